@@ -1,0 +1,73 @@
+"""Circuit partition oracle (test infrastructure only).
+
+Paper Section 4.1, Algorithm 1: the circuit is cut, in gate order, into
+stages; a gate joins the current stage unless the set of global indices
+(qubits >= b, the high c = n - b bits of the amplitude index) touched by
+the stage plus that gate would exceed ``threshold = max(inner size, 2)``, in
+which case the current stage is closed first.  The global indices a stage
+touches are its *inner* indices; the other global indices are *outer*.  All
+blocks that agree on the outer bits form one SV group; a stage with m inner
+indices has 2^(c-m) independent groups of 2^m blocks each.
+
+Readings where the pseudo-code is silent: "exceed" means strictly greater
+than the threshold; a stage is never emitted empty; a gate that alone touches
+more global indices than the threshold is rejected; gates are never
+reordered.
+"""
+from __future__ import annotations
+
+from typing import List, Sequence, Tuple
+
+
+def global_qubits(qubits, b: int):
+    return {q for q in qubits if q >= b}
+
+
+def partition(gates: Sequence, b: int, inner_size: int) -> List[Tuple[int, int]]:
+    """Algorithm 1.  Returns stages as half-open gate index ranges."""
+    threshold = max(inner_size, 2)
+    stages: List[Tuple[int, int]] = []
+    start = 0
+    cur_globals: set = set()
+    for i, (_, q, _) in enumerate(gates):
+        g = global_qubits(q, b)
+        if len(g) > threshold:
+            raise ValueError(f"gate {i} touches {len(g)} global qubits > {threshold}")
+        if len(cur_globals | g) > threshold:
+            if i > start:                 # never emit an empty stage
+                stages.append((start, i))
+            start = i
+            cur_globals = set()
+        cur_globals |= g
+    if len(gates) > start:
+        stages.append((start, len(gates)))
+    return stages
+
+
+def inner_indices(gates: Sequence, stage: Tuple[int, int], b: int) -> List[int]:
+    s = set()
+    for _, q, _ in gates[stage[0]:stage[1]]:
+        s |= global_qubits(q, b)
+    return sorted(s)
+
+
+def groups(n: int, b: int, inner: Sequence[int]) -> List[List[int]]:
+    """SV groups of a stage: group g deposits its bits, in ascending order,
+    into the outer global positions; within a group the blocks are ordered by
+    their inner bits ascending.  Returns block ids (global index >> b)."""
+    c = n - b
+    inner_rel = [q - b for q in inner]
+    outer_rel = [j for j in range(c) if j not in inner_rel]
+    out = []
+    for g in range(2 ** len(outer_rel)):
+        base = 0
+        for i, pos in enumerate(outer_rel):
+            base |= ((g >> i) & 1) << pos
+        blocks = []
+        for m in range(2 ** len(inner_rel)):
+            blk = base
+            for i, pos in enumerate(inner_rel):
+                blk |= ((m >> i) & 1) << pos
+            blocks.append(blk)
+        out.append(blocks)
+    return out

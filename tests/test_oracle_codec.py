@@ -1,0 +1,269 @@
+"""Pins for the CPU reference codec (CPU only).
+
+The codec follows paper Section 4.3 / Algorithm 2 (sign bitmap, log2
+transform, absolute-error-bounded lossy encode, bitmap pre-scan) with an
+SZ-style linear-scaling quantizer and Lorenzo predictor.  Pins:
+
+* the own log2/exp2 against libm (error bounds) and exact at powers of two;
+* two hand-derived golden records (tests/golden, derivation in its README);
+* the point-wise bound: |x'-x| <= eb (LIN) and |x'/x - 1| <= 2^eb - 1 plus
+  the transform error (LOG, Eq. 1-2), on random and adversarial inputs;
+* the stream layout decoded by an independent pure-Python parser written
+  from the format definition;
+* try-all optimality: the chosen mode is never larger than any alternative
+  sized independently from the per-value codes.
+"""
+import math
+import os
+import struct
+
+import numpy as np
+import pytest
+
+from oracle import native as N
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+LIN, LOG = 0, 1
+# |log2_own - log2| and |exp2_own/exp2 - 1| measured bounds (fits of degree 8
+# and 6, see the stream-format section of the design notes)
+E_LOG2 = 2.0e-7
+E_EXP2 = 1.0e-7
+
+
+def log_rel_bound(eb, v=0.0):
+    """Relative bound of the LOG domain for a value with log2|x| = v: eb
+    (Eq. 1-2) plus the transform error: the fit error of log2, one float32
+    rounding of v (half an ulp, <= |v| 2^-24) and the exp2 fit error."""
+    return 2.0 ** (eb + E_LOG2 + np.abs(v) * 2.0 ** -24) * (1 + E_EXP2) - 1
+
+
+def test_log2_exp2_against_libm():
+    rng = np.random.default_rng(0)
+    x = (2.0 ** rng.uniform(-125, 126, 200000)).astype(np.float32)
+    x = x[np.isfinite(x) & (x > 0)]
+    v = np.log2(x.astype(np.float64))
+    err = np.abs(N.log2_own(x).astype(np.float64) - v)
+    # fit error plus one float32 rounding of the result
+    assert np.all(err <= E_LOG2 + np.abs(v) * 2.0 ** -24)
+    p2 = (2.0 ** np.arange(-126, 127)).astype(np.float32)
+    assert np.array_equal(N.log2_own(p2), np.arange(-126, 127).astype(np.float32))
+    y = rng.uniform(-120, 120, 200000).astype(np.float32)
+    r = np.abs(N.exp2_own(y).astype(np.float64) / np.exp2(y.astype(np.float64)) - 1)
+    assert r.max() < E_EXP2
+    ints = np.arange(-120, 121).astype(np.float32)
+    assert np.array_equal(N.exp2_own(ints), (2.0 ** np.arange(-120, 121)).astype(np.float32))
+
+
+def _golden(name):
+    return bytes.fromhex(open(os.path.join(GOLD, name)).read().strip())
+
+
+def test_golden_lin_ramp():
+    eb = 2.0 ** -10
+    re = (np.arange(64) * 2.0 ** -9).astype(np.float32)
+    im = np.zeros(64, np.float32)
+    s = N.encode_block(re, im, LIN, eb)
+    assert s == _golden("lin_ramp_chunk.hex")
+    r2, i2 = N.decode_block(s, 64)
+    assert np.array_equal(r2, re) and np.array_equal(i2, im)
+
+
+def test_golden_log_alternating_powers_of_two():
+    eb = 2.0 ** -10
+    j = np.arange(64)
+    re = ((-1.0) ** j * 2.0 ** (-j)).astype(np.float32)
+    im = np.zeros(64, np.float32)
+    s = N.encode_block(re, im, LOG, eb)
+    assert s == _golden("log_alternating_pow2_chunk.hex")
+    r2, i2 = N.decode_block(s, 64)
+    assert np.array_equal(r2, re) and np.array_equal(i2, im)
+
+
+def _check_bound(re, im, domain, eb):
+    s = N.encode_block(re, im, domain, eb)
+    r2, i2 = N.decode_block(s, re.size)
+    for x, y in ((re, r2), (im, i2)):
+        x64, y64 = x.astype(np.float64), y.astype(np.float64)
+        fin = np.isfinite(x64)
+        assert np.array_equal(np.isnan(x64), np.isnan(y64))
+        if domain == LIN:
+            assert np.all(np.abs(x64[fin] - y64[fin]) <= np.float32(eb))
+        else:
+            tiny = np.abs(x64) < 2.0 ** -126
+            # zero class decodes to exactly 0; a VERBATIM chunk keeps the bits
+            t = tiny & fin
+            assert np.all((y64[t] == 0.0) | (y64[t] == x64[t]))
+            m = fin & ~tiny
+            rel = np.abs(y64[m] / x64[m] - 1)
+            v = np.log2(np.abs(x64[m]))
+            assert np.all(rel <= log_rel_bound(float(np.float32(eb)), v))
+            assert np.all(np.sign(y64[m]) == np.sign(x64[m]))
+    return s
+
+
+@pytest.mark.parametrize("domain", [LIN, LOG])
+@pytest.mark.parametrize("eb", [1e-6, 1e-5, 1e-3, math.log2(1.001)])
+def test_pointwise_bound_random(domain, eb):
+    rng = np.random.default_rng(int(eb * 1e9) + domain)
+    n = 64 * 37 + 13           # several chunks and a ragged tail
+    scale = 2.0 ** rng.uniform(-20, 0, n)
+    re = (rng.standard_normal(n) * scale).astype(np.float32)
+    im = (rng.standard_normal(n) * scale).astype(np.float32)
+    _check_bound(re, im, domain, eb)
+
+
+@pytest.mark.parametrize("domain", [LIN, LOG])
+def test_adversarial_inputs(domain):
+    eb = 1e-5
+    ebf = np.float32(eb)
+    delta = np.float32(2) * ebf
+    ks = np.arange(-40, 40)
+    half = ((ks + 0.5) * delta.astype(np.float64)).astype(np.float32)   # k + 1/2 boundaries
+    specials = np.array([0.0, -0.0, 1e-45, -1e-45, 1.1754942e-38, -1.1754942e-38,
+                         1.0, -1.0, 0.5, -0.5, 3.4e38, -3.4e38], np.float32)
+    alt = np.where(np.arange(64) % 2, 1e-3, -1e-3).astype(np.float32)
+    eq = np.full(64, 0.123456, np.float32)
+    re = np.concatenate([half, specials, alt, eq, np.zeros(64, np.float32)])
+    im = np.concatenate([specials, half, eq, alt, -np.ones(64, np.float32) * 1e-40])
+    n = min(re.size, im.size)
+    _check_bound(re[:n], im[:n], domain, eb)
+
+
+def test_zero_and_verbatim_are_exact():
+    z = np.zeros(128, np.float32)
+    s = N.encode_block(z, z, LOG, 1e-5)
+    assert s[16:] == bytes(16)                # two ZERO records of 8 bytes
+    x = np.linspace(-1, 1, 64).astype(np.float32)
+    x[7] = np.nan
+    x[9] = np.inf
+    s = N.encode_block(x, x.copy(), LIN, 1e-5)
+    h0, h1 = struct.unpack_from("<II", s, 16)
+    assert h0 == 3 and h1 == 3                # VERBATIM
+    r2, i2 = N.decode_block(s, 64)
+    assert np.array_equal(r2.view(np.uint32), x.view(np.uint32))
+
+
+def test_eq2_relative_bound_regime_of_the_paper():
+    # Eq. 2: b_a = log2(1 + b_r); the paper runs b_r = 1e-3
+    br = 1e-3
+    ba = math.log2(1 + br)
+    assert ba == pytest.approx(1.441974e-3, rel=1e-6)
+    rng = np.random.default_rng(9)
+    x = (rng.standard_normal(4096) * 2.0 ** rng.uniform(-30, 0, 4096)).astype(np.float32)
+    s = N.encode_block(x, x[::-1].copy(), LOG, ba)
+    r2, _ = N.decode_block(s, x.size)
+    rel = np.abs(r2.astype(np.float64) / x - 1)
+    assert rel.max() <= br * (1 + 2e-3)
+
+
+# ---------------------------------------------------------------- parser
+def py_parse(stream):
+    """Independent pure-Python reading of the block stream format."""
+    magic, ver, dom, l2 = stream[:4]
+    eb, nv, nc = struct.unpack_from("<fII", stream, 4)
+    assert (magic, ver, l2) == (0x51, 1, 6)
+    pos = 16
+    recs = []
+    for _ in range(nc):
+        h = struct.unpack_from("<II", stream, pos)
+        pos += 8
+        planes = []
+        for c in range(2):
+            planes.append(dict(mode=h[c] & 3, w=(h[c] >> 2) & 63, sc=(h[c] >> 8) & 3, zc=(h[c] >> 10) & 3))
+        for c in range(2):
+            if planes[c]["mode"] == 1:
+                planes[c]["anchor"] = struct.unpack_from("<i", stream, pos)[0]
+                pos += 4
+        for c in range(2):
+            if planes[c]["mode"] in (1, 2):
+                if planes[c]["sc"] == 2:
+                    planes[c]["smask"] = struct.unpack_from("<Q", stream, pos)[0]
+                    pos += 8
+                if planes[c]["zc"] == 2:
+                    planes[c]["zmask"] = struct.unpack_from("<Q", stream, pos)[0]
+                    pos += 8
+        for c in range(2):
+            p = planes[c]
+            if p["mode"] in (1, 2):
+                nb = 8 * p["w"]
+                bits = int.from_bytes(stream[pos:pos + nb], "little")
+                p["fields"] = [(bits >> (j * p["w"])) & ((1 << p["w"]) - 1) for j in range(64)]
+                pos += nb
+            elif p["mode"] == 3:
+                p["raw"] = struct.unpack_from("<64I", stream, pos)
+                pos += 256
+        recs.append(planes)
+    assert pos == len(stream)
+    return dom, eb, nv, recs
+
+
+def unzz(z):
+    return (z >> 1) ^ -(z & 1)
+
+
+def zz(d):
+    """zigzag: 0, -1, 1, -2, 2, ... -> 0, 1, 2, 3, 4, ..."""
+    return 2 * d if d >= 0 else -2 * d - 1
+
+
+@pytest.mark.parametrize("domain", [LIN, LOG])
+def test_stream_matches_independent_parser_and_codes(domain):
+    rng = np.random.default_rng(4 + domain)
+    n = 64 * 9
+    re = (rng.standard_normal(n) * 1e-3).astype(np.float32)
+    im = (rng.standard_normal(n) * 1e-3).astype(np.float32)
+    re[64:128] = 0                                 # an all-zero plane chunk
+    im[130:140] = 0                                # a mixed-zero chunk
+    eb = 1e-5
+    s = N.encode_block(re, im, domain, eb)
+    dom, ebf, nv, recs = py_parse(s)
+    assert dom == domain and nv == n and ebf == np.float32(eb)
+    kre, fre = N.codes(re, domain, eb)
+    kim, fim = N.codes(im, domain, eb)
+    for ci, planes in enumerate(recs):
+        for c, (k, x) in enumerate(((kre, re), (kim, im))):
+            p = planes[c]
+            ks = k[ci * 64:(ci + 1) * 64].astype(np.int64)
+            xs = x[ci * 64:(ci + 1) * 64]
+            if domain == LOG:
+                zero = (xs.view(np.uint32) & 0x7F800000) == 0
+            else:
+                zero = np.zeros(64, bool)
+            if p["mode"] == 0:
+                assert np.all(zero) if domain == LOG else np.all(ks == 0)
+                continue
+            assert p["mode"] in (1, 2)
+            # substitute codes of zeros the way the format defines
+            nz = np.flatnonzero(~zero)
+            kp = ks.copy()
+            last = ks[nz[0]]
+            for j in range(64):
+                if not zero[j]:
+                    last = ks[j]
+                kp[j] = last
+            if p["mode"] == 1:
+                dec = p["anchor"] + np.cumsum([0] + [unzz(f) for f in p["fields"][1:]])
+            else:
+                dec = np.array([unzz(f) for f in p["fields"]])
+            assert np.array_equal(dec, kp)
+            # try-all: the chosen size is the minimum over the alternatives
+            masks = 8 * ((p["sc"] == 2) + (p["zc"] == 2))
+            d = np.diff(kp, prepend=kp[0])
+            w_lz = max(int(zz(int(v))).bit_length() for v in d)
+            w_q0 = max(int(zz(int(v))).bit_length() for v in kp)
+            sizes = {1: 4 + masks + 8 * w_lz, 2: masks + 8 * w_q0}
+            chosen = sizes[p["mode"]]
+            assert chosen <= min(sizes.values()) and chosen <= 256
+            assert p["w"] == (w_lz if p["mode"] == 1 else w_q0)
+            if domain == LOG:
+                negs = (xs.view(np.uint32) >> 31).astype(bool) & ~zero
+                smask = sum(1 << j for j in range(64) if negs[j])
+                if p["sc"] == 2:
+                    assert p["smask"] == smask
+                else:
+                    assert p["sc"] == (1 if smask else 0)
+                zmask = sum(1 << j for j in range(64) if zero[j])
+                if p["zc"] == 2:
+                    assert p["zmask"] == zmask
+                else:
+                    assert zmask == 0

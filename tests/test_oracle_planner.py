@@ -1,0 +1,105 @@
+"""Pins for the Algorithm 1 partition oracle (CPU only).
+
+* invariants of Algorithm 1 (Section 4.1): the stages concatenate to the
+  circuit in order, none is empty, each touches at most max(inner, 2) global
+  indices, and each is maximal (its successor's first gate would overflow it);
+* a brute-force greedy written differently (by trying every cut point);
+* the SV-group structure of the Fig. 5 example (n = 6, b = 2, inner {3, 5},
+  outer {2, 4}: 4 groups of 4 blocks);
+* the paper's central claim that groups are independent: simulating every
+  group of every stage as a separate small state reproduces the full
+  simulation exactly.
+"""
+import numpy as np
+import pytest
+
+from oracle import planner as P
+from oracle import sim
+from paper_2410_14088_amd import circuits as C
+
+
+def circuits():
+    yield C.random_layers(10, 6, 3), 10
+    yield C.qft_on_ry(10, 4)[0], 10
+    yield C.qaoa_ring(10, 2, 5)[0], 10
+    yield C.ghz(10), 10
+
+
+@pytest.mark.parametrize("b", [3, 5, 7])
+@pytest.mark.parametrize("inner", [0, 2, 3, 4])
+def test_alg1_invariants(b, inner):
+    T = max(inner, 2)
+    for gates, n in circuits():
+        st = P.partition(gates, b, inner)
+        assert st[0][0] == 0 and st[-1][1] == len(gates)
+        for (a0, a1), (b0, b1) in zip(st, st[1:]):
+            assert a1 == b0
+        for s0, s1 in st:
+            assert s1 > s0
+            assert len(P.inner_indices(gates, (s0, s1), b)) <= T
+        for (s0, s1), (t0, _) in zip(st, st[1:]):
+            g = set(P.inner_indices(gates, (s0, s1), b)) | P.global_qubits(gates[t0][1], b)
+            assert len(g) > T                      # maximal: next gate overflows
+
+
+def brute_partition(gates, b, T):
+    """Greedy by exhaustive search of the longest admissible next stage."""
+    out, i = [], 0
+    while i < len(gates):
+        best = i + 1
+        for j in range(i + 1, len(gates) + 1):
+            g = set()
+            for _, q, _ in gates[i:j]:
+                g |= {x for x in q if x >= b}
+            if len(g) <= T:
+                best = j
+            else:
+                break
+        out.append((i, best))
+        i = best
+    return out
+
+
+def test_alg1_matches_bruteforce_greedy():
+    for gates, n in circuits():
+        for b in (2, 4, 6):
+            for inner in (1, 2, 3):
+                assert P.partition(gates, b, inner) == brute_partition(gates, b, max(inner, 2))
+
+
+def test_fig5_group_structure():
+    n, b = 6, 2
+    gr = P.groups(n, b, [3, 5])
+    assert len(gr) == 4 and all(len(g) == 4 for g in gr)
+    allb = sorted(x for g in gr for x in g)
+    assert allb == list(range(16))
+    for g in gr:
+        # blocks of a group agree on the outer indices 2 and 4 (block bits 0, 2)
+        outer = {((blk >> 0) & 1, (blk >> 2) & 1) for blk in g}
+        assert len(outer) == 1
+
+
+def simulate_by_groups(n, b, inner_size, gates):
+    psi = np.zeros(2 ** n, dtype=complex)
+    psi[0] = 1
+    for s in P.partition(gates, b, inner_size):
+        inner = P.inner_indices(gates, s, b)
+        m = len(inner)
+        # relabel: local qubits stay, inner global qubit inner[i] -> b + i
+        relabel = {q: q for q in range(b)}
+        relabel.update({q: b + i for i, q in enumerate(inner)})
+        sub_gates = [(k, tuple(relabel[x] for x in q), p) for k, q, p in gates[s[0]:s[1]]]
+        for blocks in P.groups(n, b, inner):
+            idx = np.concatenate([np.arange(2 ** b) + (blk << b) for blk in blocks])
+            sub = sim.simulate(b + m, sub_gates, psi[idx])
+            psi[idx] = sub
+    return psi
+
+
+@pytest.mark.parametrize("inner", [2, 3])
+def test_groups_are_independent(inner):
+    n, b = 8, 4
+    for gates in (C.random_layers(n, 3, 8), C.qft_on_ry(n, 2)[0], C.qaoa_ring(n, 2, 1)[0]):
+        ref = sim.simulate(n, gates)
+        got = simulate_by_groups(n, b, inner, gates)
+        assert np.abs(ref - got).max() < 1e-12
