@@ -20,6 +20,14 @@
  *     quantization with a Lorenzo predictor, the SZ family the paper cites in
  *     Section 2.2) with fixed-length packing per chunk.
  *
+ * Quantization step.  The absolute bound eb on f(x) admits any step
+ * delta <= 2 eb; the codec takes the largest power of two, delta = 2^-s, so
+ * that scaling by 2^s is exact in binary floating point and rounding to the
+ * nearest code never leaves an error above delta/2 <= eb.  In the LOG domain
+ * the code is formed from the two parts of log2|x| = e + p (e the binary
+ * exponent, p = log2 of the significand folded into [sqrt(1/2), sqrt(2)]):
+ * k = e 2^s + rint(p 2^s), so log2|x| is never rounded to float32 as a whole.
+ *
  * Stream format (little-endian), one "record" per chunk of 64 values of a
  * complex block (two planes: re, im):
  *   u32 hdr_re, u32 hdr_im
@@ -48,11 +56,24 @@ enum { DOM_LIN = 0, DOM_LOG = 1 };
 static uint32_t f2u(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
 static float u2f(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
 
-/* log2 of a positive normal float: x = m * 2^e with m folded into
- * [sqrt(1/2), sqrt(2)], t = m - 1 (exact), log2(1+t) ~ t * P(t) with P a
- * degree-8 Chebyshev fit of log2(1+t)/t on that interval, evaluated by
- * Horner's rule with fused multiply-adds. */
-float o_log2(float x)
+/* 2^i for an integer i in the float32 normal range, built from its bits. */
+static float pow2i(int i) { return u2f((uint32_t)(i + 127) << 23); }
+
+/* Quantization exponent s: delta = 2^-s is the largest power of two that is
+ * <= 2*eb (eb as float32). */
+int o_step_shift(float ebf)
+{
+    int ex;
+    (void)frexpf(2.0f * ebf, &ex);   /* 2 eb = m 2^ex, m in [1/2, 1) */
+    return 1 - ex;                   /* 2^(ex-1) <= 2 eb < 2^ex */
+}
+
+/* Split a positive normal float32 x into log2 x = e + p: the significand m is
+ * folded into [sqrt(1/2), sqrt(2)], t = m - 1 (exact), and
+ * p = log2(1 + t) ~ t * P(t) with P a degree-8 Chebyshev fit of
+ * log2(1+t)/t on that interval, evaluated by Horner's rule with fused
+ * multiply-adds and one final rounding of t * P. */
+void o_log2_split(float x, int *e_out, float *p_out)
 {
     static const float C[9] = {
         1.4426950216293335f, -0.7213473320007324f, 0.48091059923171997f,
@@ -61,50 +82,78 @@ float o_log2(float x)
     uint32_t u = f2u(x);
     int ef = (int)(u >> 23);
     uint32_t mant = u & 0x007FFFFFu;
-    int e;
     float m;
     if (mant > 0x003504F3u) {           /* 1.mant > sqrt(2): use m/2 */
         m = u2f(mant | 0x3F000000u);
-        e = ef - 126;
+        *e_out = ef - 126;
     } else {
         m = u2f(mant | 0x3F800000u);
-        e = ef - 127;
+        *e_out = ef - 127;
     }
     float t = m - 1.0f;
     float p = C[8];
     for (int i = 7; i >= 0; --i) p = fmaf(p, t, C[i]);
-    return fmaf(t, p, (float)e);
+    *p_out = t * p;
 }
 
-/* 2^y: y = i + f with i = nearest integer, f in [-1/2, 1/2]; 2^f by a
- * degree-6 Chebyshev fit, 2^i applied as two exact power-of-two scalings. */
-float o_exp2(float y)
+/* log2 as one float32 (e + p rounded once), for pinning against libm. */
+float o_log2(float x)
+{
+    int e;
+    float p;
+    o_log2_split(x, &e, &p);
+    return (float)e + p;
+}
+
+/* 2^f for f in [-1/2, 1/2]: degree-6 Chebyshev fit, Horner with fmaf. */
+static float exp2_frac(float f)
 {
     static const float E[7] = {
         1.0f, 0.6931471824645996f, 0.24022650718688965f, 0.05550327152013779f,
         0.00961802527308464f, 0.0013400432653725147f, 0.00015469732170458883f};
-    float fi = rintf(y);
-    int i = (int)fi;
-    float f = y - fi;
     float p = E[6];
     for (int k = 5; k >= 0; --k) p = fmaf(p, f, E[k]);
+    return p;
+}
+
+/* 2^(i + f) with the integer power applied as two exact scalings. */
+static float scale2(float p, int i)
+{
     if (i < -250) i = -250;
     if (i > 250) i = 250;
     int i1 = i >> 1, i2 = i - i1;
-    float s1 = u2f((uint32_t)(i1 + 127) << 23);
-    float s2 = u2f((uint32_t)(i2 + 127) << 23);
-    return (p * s1) * s2;
+    return (p * pow2i(i1)) * pow2i(i2);
+}
+
+/* 2^y for a float32 y (nearest integer i, f = y - i), for pinning. */
+float o_exp2(float y)
+{
+    float fi = rintf(y);
+    return scale2(exp2_frac(y - fi), (int)fi);
+}
+
+/* magnitude of a LOG-domain code k with step 2^-s: 2^(k 2^-s), with the
+ * nearest integer i = round(k / 2^s) taken in integers and the remainder
+ * f = (k - i 2^s) 2^-s in [-1/2, 1/2) exact in float32 */
+float o_log_decode(int32_t k, int s)
+{
+    int32_t half = (int32_t)1 << (s - 1);
+    int32_t i = (int32_t)(((int64_t)k + half) >> s);
+    int32_t r = k - (int32_t)((uint32_t)i << s);
+    float f = (float)r * pow2i(-s);
+    return scale2(exp2_frac(f), i);
 }
 
 static uint32_t zigzag(int32_t d) { return ((uint32_t)d << 1) ^ (d < 0 ? 0xFFFFFFFFu : 0u); }
 static int32_t unzigzag(uint32_t z) { return (int32_t)((z >> 1) ^ (0u - (z & 1u))); }
 static int bitlen(uint32_t v) { int b = 0; while (v) { ++b; v >>= 1; } return b; }
 
-/* Quantize one value v with the verify-and-correct rule: k = rint(v*r),
- * accept if |v - k*delta| <= eb (in float), else try the neighbour toward v.
- * Returns 0 on failure (caller falls back to VERBATIM). */
-int o_quantize(float v, float ebf, float delta, float r, int32_t *kout)
+/* Quantize v with step delta = 2^-s and verify |v - k delta| <= eb in float32
+ * (try the neighbour toward v once if not).  Returns 0 on failure (the chunk
+ * then falls back to VERBATIM). */
+int o_quantize(float v, float ebf, int s, int32_t *kout)
 {
+    float delta = pow2i(-s), r = pow2i(s);
     float t = v * r;
     if (!(fabsf(t) < 1073741824.0f)) return 0;
     int32_t k = (int32_t)rintf(t);
@@ -118,6 +167,30 @@ int o_quantize(float v, float ebf, float delta, float r, int32_t *kout)
     return 1;
 }
 
+/* Code of one value; returns 0 if it cannot be coded (VERBATIM), sets *zero
+ * for LOG-domain zeros and subnormals. */
+static int code_value(float x, int domain, float ebf, int s, int32_t *k, int *zero, int *neg)
+{
+    *zero = 0;
+    *neg = 0;
+    *k = 0;
+    if (s < -100 || s > 100) return 0;            /* step outside float32's range */
+    if (domain == DOM_LIN) return o_quantize(x, ebf, s, k);
+    if (s < 1 || s > 22) return 0;                /* LOG codes must fit 30 bits */
+    uint32_t u = f2u(x);
+    uint32_t ef = (u >> 23) & 0xFFu;
+    if (ef == 0) { *zero = 1; return 1; }        /* 0 or subnormal */
+    if (ef >= 254) return 0;                     /* |x| >= 2^127, inf, nan */
+    *neg = (int)(u >> 31);
+    int e;
+    float p;
+    o_log2_split(u2f(u & 0x7FFFFFFFu), &e, &p);
+    int32_t j;
+    if (!o_quantize(p, ebf, s, &j)) return 0;
+    *k = (int32_t)((uint32_t)e << s) + j;
+    return 1;
+}
+
 typedef struct {
     uint32_t hdr;
     int32_t anchor;
@@ -128,19 +201,9 @@ typedef struct {
     int mode;
 } plane_rec;
 
-static size_t plane_extra_bytes(const plane_rec *p)
-{
-    switch (p->mode) {
-    case M_ZERO: return 0;
-    case M_LZ:   return 4 + 8u * (size_t)(p->has_smask + p->has_zmask) + 8u * (size_t)p->w;
-    case M_Q0:   return 8u * (size_t)(p->has_smask + p->has_zmask) + 8u * (size_t)p->w;
-    default:     return 256;
-    }
-}
-
 /* Encode one plane of one chunk: x[0..nvalid-1] valid, the rest absent. */
-static void encode_plane_chunk(const float *x, int nvalid, int domain,
-                               float ebf, float delta, float r, plane_rec *out)
+static void encode_plane_chunk(const float *x, int nvalid, int domain, float ebf, int s,
+                               plane_rec *out)
 {
     int32_t k[CH];
     int zero[CH], neg[CH];
@@ -150,19 +213,8 @@ static void encode_plane_chunk(const float *x, int nvalid, int domain,
     memset(neg, 0, sizeof(neg));
 
     /* 1. transform and quantize (Algorithm 2: sign bitmap, |x|, log2) */
-    for (int j = 0; j < nvalid; ++j) {
-        if (domain == DOM_LOG) {
-            uint32_t u = f2u(x[j]);
-            uint32_t ef = (u >> 23) & 0xFFu;
-            if (ef == 0) { zero[j] = 1; k[j] = 0; continue; }   /* 0 or subnormal */
-            if (ef >= 254) { ok = 0; k[j] = 0; continue; }      /* |x| >= 2^127, inf, nan */
-            neg[j] = (int)(u >> 31);
-            float v = o_log2(u2f(u & 0x7FFFFFFFu));
-            if (!o_quantize(v, ebf, delta, r, &k[j])) { ok = 0; k[j] = 0; }
-        } else {
-            if (!o_quantize(x[j], ebf, delta, r, &k[j])) { ok = 0; k[j] = 0; }
-        }
-    }
+    for (int j = 0; j < nvalid; ++j)
+        if (!code_value(x[j], domain, ebf, s, &k[j], &zero[j], &neg[j])) ok = 0;
 
     /* raw bits for VERBATIM */
     uint32_t raw[CH];
@@ -276,11 +328,10 @@ static void put64(uint8_t **p, uint64_t v) { memcpy(*p, &v, 8); *p += 8; }
 size_t o_encode_chunk(const float *re, const float *im, int nvalid, int domain,
                       float ebf, uint8_t *dst)
 {
-    float delta = 2.0f * ebf;
-    float r = 1.0f / delta;
+    int s = o_step_shift(ebf);
     plane_rec P[2];
-    encode_plane_chunk(re, nvalid, domain, ebf, delta, r, &P[0]);
-    encode_plane_chunk(im, nvalid, domain, ebf, delta, r, &P[1]);
+    encode_plane_chunk(re, nvalid, domain, ebf, s, &P[0]);
+    encode_plane_chunk(im, nvalid, domain, ebf, s, &P[1]);
     uint8_t *p = dst;
     put32(&p, P[0].hdr);
     put32(&p, P[1].hdr);
@@ -298,9 +349,7 @@ size_t o_encode_chunk(const float *re, const float *im, int nvalid, int domain,
             for (int j = 0; j < CH; ++j) put32(&p, P[c].fields[j]);
         }
     }
-    size_t sz = (size_t)(p - dst);
-    (void)plane_extra_bytes;
-    return sz;
+    return (size_t)(p - dst);
 }
 
 /* Size of a record from its two headers (format parse, no arithmetic). */
@@ -322,7 +371,8 @@ static size_t record_size_from_headers(uint32_t h0, uint32_t h1)
 size_t o_decode_chunk(const uint8_t *src, int nvalid, int domain, float ebf,
                       float *re, float *im)
 {
-    float delta = 2.0f * ebf;
+    int s = o_step_shift(ebf);
+    float delta = pow2i(-s);
     uint32_t h[2];
     memcpy(&h[0], src, 4);
     memcpy(&h[1], src + 4, 4);
@@ -364,14 +414,13 @@ size_t o_decode_chunk(const uint8_t *src, int nvalid, int domain, float ebf,
                     kj = unzigzag(z);
                 }
                 if (j >= nvalid) continue;
-                float q = (float)kj * delta;
                 if (domain == DOM_LIN) {
-                    x[j] = q;
+                    x[j] = (float)kj * delta;
                 } else {
                     int isz = (zc[c] == 2) ? (int)((zm[c] >> j) & 1u) : 0;
                     int isn = (sc[c] == 2) ? (int)((sm[c] >> j) & 1u) : (sc[c] == 1);
                     if (isz) x[j] = 0.0f;
-                    else { float mag = o_exp2(q); x[j] = isn ? -mag : mag; }
+                    else { float mag = o_log_decode(kj, s); x[j] = isn ? -mag : mag; }
                 }
             }
             p += 8u * (size_t)w[c];
@@ -435,22 +484,15 @@ int o_decode_block(const uint8_t *src, size_t len, float *re, float *im, uint64_
 }
 
 /* Per-value quantization codes of one plane, for the code-level parity
- * checks: writes k (or 0) and a per-chunk "quantization failed" flag. */
+ * checks: writes k (0 for LOG zeros) and a "cannot be coded" flag. */
 void o_codes(const float *x, uint64_t n, int domain, double eb, int32_t *k, uint8_t *fail)
 {
-    float ebf = (float)eb, delta = 2.0f * ebf, r = 1.0f / delta;
+    float ebf = (float)eb;
+    int s = o_step_shift(ebf);
     for (uint64_t i = 0; i < n; ++i) {
+        int z, ng;
         int32_t kk = 0;
-        int ok = 1;
-        if (domain == DOM_LOG) {
-            uint32_t u = f2u(x[i]);
-            uint32_t ef = (u >> 23) & 0xFFu;
-            if (ef == 0) ok = 1;
-            else if (ef >= 254) ok = 0;
-            else ok = o_quantize(o_log2(u2f(u & 0x7FFFFFFFu)), ebf, delta, r, &kk);
-        } else {
-            ok = o_quantize(x[i], ebf, delta, r, &kk);
-        }
+        int ok = code_value(x[i], domain, ebf, s, &kk, &z, &ng);
         k[i] = kk;
         fail[i] = (uint8_t)!ok;
     }
@@ -459,3 +501,4 @@ void o_codes(const float *x, uint64_t n, int domain, double eb, int32_t *k, uint
 /* Vectorised transforms for pinning o_log2/o_exp2 against libm. */
 void o_log2_vec(const float *x, float *y, uint64_t n) { for (uint64_t i = 0; i < n; ++i) y[i] = o_log2(x[i]); }
 void o_exp2_vec(const float *x, float *y, uint64_t n) { for (uint64_t i = 0; i < n; ++i) y[i] = o_exp2(x[i]); }
+void o_log_decode_vec(const int32_t *k, int s, float *y, uint64_t n) { for (uint64_t i = 0; i < n; ++i) y[i] = o_log_decode(k[i], s); }

@@ -52,6 +52,9 @@ def lib():
         L.o_codes.restype = None
         L.o_codes.argtypes = [P, C.c_uint64, C.c_int, C.c_double, P, P]
         L.o_log2_vec.argtypes = [P, P, C.c_uint64]
+        L.o_log_decode_vec.argtypes = [P, C.c_int, P, C.c_uint64]
+        L.o_step_shift.restype = C.c_int
+        L.o_step_shift.argtypes = [C.c_float]
         L.o_exp2_vec.argtypes = [P, P, C.c_uint64]
         L.o_gate_matrix.restype = C.c_int
         L.o_gate_matrix.argtypes = [C.c_int, P, P]
@@ -80,6 +83,18 @@ def exp2_own(x: np.ndarray) -> np.ndarray:
     x = np.ascontiguousarray(x, dtype=np.float32)
     y = np.empty_like(x)
     lib().o_exp2_vec(_p(x), _p(y), x.size)
+    return y
+
+
+def step_shift(eb: float) -> int:
+    """s such that the quantization step is 2^-s (largest power of two <= 2 eb)."""
+    return lib().o_step_shift(float(np.float32(eb)))
+
+
+def log_decode(k: np.ndarray, s: int) -> np.ndarray:
+    k = np.ascontiguousarray(k, dtype=np.int32)
+    y = np.empty(k.size, dtype=np.float32)
+    lib().o_log_decode_vec(_p(k), s, _p(y), k.size)
     return y
 
 
