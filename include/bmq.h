@@ -1,0 +1,229 @@
+/*
+ * bmq.h -- C ABI of the MI355X compressed state-vector stage loop.
+ *
+ * The library simulates a quantum circuit on a state vector that is kept
+ * compressed in device memory between stages (paper: Zhang et al., "Overcoming
+ * Memory Constraints in Quantum Circuit Simulation with a High-Fidelity
+ * Compression Framework", arXiv 2410.14088).  The problem statement the calls
+ * follow: the input is a circuit, the SV block size and the inner size
+ * (Algorithm 1's "Require" line, Section 4.1) plus a codec error bound
+ * (Section 5.1); the state starts at |0...0> (Section 4.2); the outputs are
+ * the final state's fidelity (Section 5.3) and memory footprint (Section 5.4).
+ *
+ * Conventions shared by every call
+ *   - Status: every int-returning call returns SV_OK (0) or a negative SV_ERR_*
+ *     code; sv_last_error() gives a thread-local message.  No call throws.
+ *   - Device pointers are HIP device addresses on the current device; host
+ *     pointers are ordinary process memory.  Every call names which it takes.
+ *   - Work is enqueued on the HIP stream given to sv_create (a hipStream_t
+ *     passed as void*; NULL = the default stream).  Calls that return values
+ *     to the host synchronise that stream before returning.
+ *   - Ownership: the caller owns every buffer it passes (the device arena, the
+ *     stream, input and output arrays) and keeps them alive while a handle
+ *     that uses them exists.  The library owns the sv_t and sv_plan_t handles
+ *     (host heap) and only sub-allocates inside the caller's arena.
+ *   - Qubit q is bit q of the amplitude index (qubit 0 = least significant,
+ *     Section 2.1).  With block size b the low b bits are the local index and
+ *     the high c = n - b bits the global index (Section 3, Fig. 1).
+ *   - Complex arrays are interleaved (re, im) pairs: complex64 = 2 x float32,
+ *     complex128 = 2 x float64, amplitude i at element i.
+ *   - After SV_ERR_CAPACITY or SV_ERR_CORRUPT a handle is poisoned: only
+ *     sv_destroy is valid.  SV_ERR_INVALID leaves every argument untouched.
+ */
+#ifndef BMQ_H
+#define BMQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SV_OK = 0,
+    SV_ERR_INVALID = -1,      /* bad argument or configuration */
+    SV_ERR_OOM = -2,          /* the caller's arena is smaller than required */
+    SV_ERR_CAPACITY = -3,     /* a compressed pool overflowed during a stage */
+    SV_ERR_HIP = -4,          /* a HIP runtime call failed */
+    SV_ERR_CORRUPT = -5,      /* a stream or directory entry is malformed */
+    SV_ERR_UNSUPPORTED = -6   /* valid request the library does not implement */
+};
+
+/* Codec domains (Section 4.3).  LIN: the error bound applies to each real
+ * and imaginary part directly (point-wise absolute).  LOG: Algorithm 2 --
+ * sign bitmap, magnitude, log2, absolute bound eb on log2|x|, which is the
+ * point-wise relative bound 2^eb - 1 of Eq. 1-2. */
+enum { SV_DOMAIN_LIN = 0, SV_DOMAIN_LOG = 1 };
+
+/* Gate kinds.  1-qubit matrices as usual; for 2-qubit gates the 4x4 matrix
+ * index is 2*bit(q[0]) + bit(q[1]), the row order of Section 2.1.
+ *   U3(t,p,l) = [[cos t/2, -e^{il} sin t/2], [e^{ip} sin t/2, e^{i(p+l)} cos t/2]]
+ *   RX(b) = [[c, -i s], [-i s, c]], RY(t) = [[c, -s], [s, c]],
+ *   RZ(t) = diag(e^{-it/2}, e^{it/2}), CX: control q[0], target q[1],
+ *   CZ = diag(1,1,1,-1), CP(l) = diag(1,1,1,e^{il}),
+ *   RZZ(g) = diag(e^{-ig/2}, e^{ig/2}, e^{ig/2}, e^{-ig/2}). */
+enum {
+    SV_GATE_H = 0, SV_GATE_X, SV_GATE_Y, SV_GATE_Z, SV_GATE_S, SV_GATE_T,
+    SV_GATE_RX, SV_GATE_RY, SV_GATE_RZ, SV_GATE_U3,
+    SV_GATE_CX, SV_GATE_CZ, SV_GATE_CP, SV_GATE_RZZ, SV_GATE_COUNT
+};
+
+typedef struct {
+    int32_t kind;      /* SV_GATE_* */
+    int32_t q[2];      /* qubits; q[1] unused for 1-qubit gates */
+    int32_t pad;
+    double p[3];       /* angles in radians (U3: theta, phi, lambda) */
+} sv_gate_t;
+
+typedef struct {
+    int32_t n_qubits;     /* n, 7..40 */
+    int32_t block_qubits; /* b: SV block = 2^b amplitudes, 6 <= b <= n */
+    int32_t inner_size;   /* Algorithm 1 inner size; threshold = max(inner, 2) */
+    int32_t fuse_qubits;  /* widest dense fused gate, 1..5 */
+    int32_t domain;       /* SV_DOMAIN_LIN or SV_DOMAIN_LOG */
+    int32_t tile_qubits;  /* amplitudes per on-chip tile = 2^tile_qubits; 0 = default (12) */
+    double eb;            /* absolute bound in the codec domain, > 0 */
+    uint64_t pool_bytes;  /* capacity of each compressed pool; 0 = worst case */
+} sv_config_t;
+
+/* Per-stage statistics (all counts over the whole state). */
+typedef struct {
+    uint64_t bytes_in;        /* compressed record bytes the stage read */
+    uint64_t bytes_out;       /* compressed record bytes the stage wrote */
+    uint64_t dir_bytes;       /* directory bytes read + written */
+    uint64_t scratch_bytes;   /* uncompressed scratch bytes read + written */
+    uint64_t zero_chunks_out; /* 64-amplitude chunks that are entirely zero */
+    uint64_t mode_hist[4];    /* plane-chunks per mode: ZERO, LZ, Q0, VERBATIM */
+    uint32_t passes;          /* on-chip tile passes of the stage */
+    uint32_t n_ops;           /* fused operations applied */
+    uint32_t n_gates;         /* circuit gates in the stage */
+    uint32_t n_inner;         /* inner (global) indices of the stage */
+    float ms;                 /* device time of the stage's kernels (HIP events) */
+    uint32_t pad;
+} sv_stage_stats_t;
+
+typedef struct sv_plan sv_plan_t;
+typedef struct sv_state sv_t;
+
+/* Thread-local text of the last error (never NULL). */
+const char *sv_last_error(void);
+
+/* ---------------------------------------------------------------- planning
+ * stage_plan -- Algorithm 1 (Section 4.1): cut the gate list, in order, into
+ * stages whose gates touch at most max(inner_size, 2) global indices; the
+ * global indices a stage touches are its inner indices, the rest are outer,
+ * and the blocks sharing the outer bits form an SV group (2^(c-m) groups of
+ * 2^m blocks for m inner indices).  Then, per stage, lay out the on-chip tile
+ * passes and fuse consecutive gates into dense (<= fuse_qubits) and diagonal
+ * operations.  Host only, deterministic.
+ *   gates: host array of n_gates gates, copied.  cfg: host, copied.
+ *   out:   receives a new plan; free with plan_destroy.
+ * Errors: SV_ERR_INVALID for a bad config, a bad gate or a gate that touches
+ * more global indices than the threshold. */
+int stage_plan(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg,
+               sv_plan_t **out);
+
+/* Plan summary: stages, fused operations and tile passes (any may be NULL). */
+int plan_info(const sv_plan_t *p, size_t *n_stages, size_t *n_ops, size_t *n_passes);
+
+/* Stage s: its gate range [gate_begin, gate_end), its inner indices (up to 8
+ * written to inner_out, count in n_inner) and its number of tile passes. */
+int plan_stage(const sv_plan_t *p, size_t s, size_t *gate_begin, size_t *gate_end,
+               int32_t *inner_out, int32_t *n_inner, int32_t *n_passes);
+
+void plan_destroy(sv_plan_t *p);
+
+/* ---------------------------------------------------------------- state
+ * sv_mem_required -- bytes of device arena sv_create needs for cfg:
+ * two chunk directories and two compressed record pools (the stage loop reads
+ * one and writes the other), the uncompressed scratch planes for multi-pass
+ * stages, the operation arena and reduction buffers. */
+int sv_mem_required(const sv_config_t *cfg, uint64_t *bytes);
+
+/* sv_create -- bind the caller's device arena (dev_arena, dev_bytes; 256-byte
+ * aligned) and stream, and set the state to |0...0> (Section 4.2): the first
+ * 64-amplitude chunk (amplitude 0 = 1) is encoded on the device and every
+ * other chunk's directory entry points at the shared all-zero record, the
+ * directory analogue of compressing one zero block and copying it.
+ * Errors: SV_ERR_INVALID (config), SV_ERR_OOM (arena too small), SV_ERR_HIP. */
+int sv_create(const sv_config_t *cfg, void *dev_arena, uint64_t dev_bytes,
+              void *hip_stream, sv_t **out);
+
+void sv_destroy(sv_t *sv);
+
+/* sv_reset -- set an existing state back to |0...0> (as sv_create does),
+ * enqueued on its stream without synchronising. */
+int sv_reset(sv_t *sv);
+
+/* stage_apply_compressed -- the per-stage block loop: for stages
+ * [first, first+count) of plan p, every tile of every SV group is decoded from
+ * the compressed pool into on-chip memory, every fused operation of the stage
+ * is applied, and the tile is re-encoded by the point-wise error-bounded codec
+ * into the other pool (Sections 4.1-4.3).  One compression per stage.
+ * stats: NULL, or host array of count entries; when given, each stage's
+ * kernels are bracketed by HIP events and the call synchronises.
+ * The plan must have been made with a config whose n, b, domain and eb equal
+ * the state's.  Errors: SV_ERR_INVALID, SV_ERR_CAPACITY (a pool overflowed:
+ * raise pool_bytes), SV_ERR_HIP. */
+int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t count,
+                           sv_stage_stats_t *stats);
+
+/* sv_fidelity -- FP64 reductions on the device (Section 5.3 fidelity):
+ *   fidelity    = |<ref|psi>|^2 / (|ref|^2 |psi|^2)   (the squared form;
+ *                 the paper prints the unsquared |<ref|psi>|)
+ *   max_abs_err = max over amplitudes and over re/im of |psi - ref|
+ *   norm2       = |psi|^2
+ * ref_dev: device array of 2^n complex128 (interleaved), or NULL to compute
+ * norm2 only (fidelity and max_abs_err then set to NaN).  Synchronises. */
+int sv_fidelity(const sv_t *sv, const double *ref_dev, double *fidelity,
+                double *max_abs_err, double *norm2);
+
+/* sv_export -- decode amplitudes [start, start+count) into dst_dev
+ * (device, count complex64).  start and count must be multiples of 64. */
+int sv_export(const sv_t *sv, uint64_t start, uint64_t count, void *dst_dev);
+
+/* sv_amplitudes -- decode the k amplitudes at idx_dev[0..k) (device uint64)
+ * into out_dev (device, k complex64). */
+int sv_amplitudes(const sv_t *sv, const uint64_t *idx_dev, uint64_t k, void *out_dev);
+
+/* sv_footprint -- current compressed footprint (Section 5.4 memory metric):
+ * record bytes in the live pool and directory bytes.  Synchronises. */
+int sv_footprint(const sv_t *sv, uint64_t *record_bytes, uint64_t *dir_bytes);
+
+/* sv_block_stream -- the canonical stream of SV block `block` (2^b
+ * amplitudes): a 16-byte block header (u8 0x51, u8 version 1, u8 domain,
+ * u8 log2 chunk = 6, u32 eb float bits, u32 n_values, u32 n_chunks) followed
+ * by the records of its chunks in index order (an all-zero chunk is the
+ * 8-byte record of two zero headers).  dst_host: host buffer of cap bytes;
+ * *bytes receives the stream size (also when cap is too small, which returns
+ * SV_ERR_INVALID).  For bit-exact comparison with a reference codec. */
+int sv_block_stream(const sv_t *sv, uint64_t block, void *dst_host, uint64_t cap,
+                    uint64_t *bytes);
+
+/* sv_debug_dump -- test hook: when re_dev/im_dev are non-NULL (device arrays
+ * of 2^n float32 each), every later stage also stores the values it is about
+ * to encode (after the last fused operation, before quantization) there.
+ * NULL, NULL turns it off. */
+int sv_debug_dump(sv_t *sv, float *re_dev, float *im_dev);
+
+/* ---------------------------------------------------------------- codec
+ * Stand-alone codec on device arrays, for bit-exact checks against a
+ * reference implementation.  Values are cut into chunks of 64; chunk i is
+ * encoded into slots_dev + i*SV_CHUNK_SLOT_BYTES (device) as one record and
+ * its record size is written to sizes_dev[i] (device uint32).  The last chunk
+ * may be partial (n_values not a multiple of 64).  Uses cfg->domain and
+ * cfg->eb only.  Enqueued on hip_stream; does not synchronise. */
+#define SV_CHUNK_SLOT_BYTES 576
+int codec_encode_chunks(const float *re_dev, const float *im_dev, uint64_t n_values,
+                        const sv_config_t *cfg, void *slots_dev, uint32_t *sizes_dev,
+                        void *hip_stream);
+
+/* Inverse of codec_encode_chunks: decode every slot into re_dev / im_dev. */
+int codec_decode_chunks(const void *slots_dev, uint64_t n_values, const sv_config_t *cfg,
+                        float *re_dev, float *im_dev, void *hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BMQ_H */

@@ -1,0 +1,278 @@
+"""Thin Python binding of the C ABI in ``include/bmq.h`` (argument
+marshalling only: every step of the stage loop runs in the HIP library).
+
+PyTorch provides device memory (the arena and I/O tensors) and the stream.
+The library is loaded from ``_build/libbmq.so`` next to this file; if it is
+missing, :func:`lib` raises -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SO = os.path.join(HERE, "_build", "libbmq.so")
+
+SV_DOMAIN_LIN, SV_DOMAIN_LOG = 0, 1
+SV_CHUNK_SLOT_BYTES = 576
+KIND = {k: i for i, k in enumerate(
+    ["H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "U3", "CX", "CZ", "CP", "RZZ"])}
+ERRORS = {-1: "SV_ERR_INVALID", -2: "SV_ERR_OOM", -3: "SV_ERR_CAPACITY", -4: "SV_ERR_HIP",
+          -5: "SV_ERR_CORRUPT", -6: "SV_ERR_UNSUPPORTED"}
+
+
+class BmqError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class sv_gate_t(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("q", C.c_int32 * 2), ("pad", C.c_int32), ("p", C.c_double * 3)]
+
+
+class sv_config_t(C.Structure):
+    _fields_ = [("n_qubits", C.c_int32), ("block_qubits", C.c_int32), ("inner_size", C.c_int32),
+                ("fuse_qubits", C.c_int32), ("domain", C.c_int32), ("tile_qubits", C.c_int32),
+                ("eb", C.c_double), ("pool_bytes", C.c_uint64)]
+
+
+class sv_stage_stats_t(C.Structure):
+    _fields_ = [("bytes_in", C.c_uint64), ("bytes_out", C.c_uint64), ("dir_bytes", C.c_uint64),
+                ("scratch_bytes", C.c_uint64), ("zero_chunks_out", C.c_uint64),
+                ("mode_hist", C.c_uint64 * 4), ("passes", C.c_uint32), ("n_ops", C.c_uint32),
+                ("n_gates", C.c_uint32), ("n_inner", C.c_uint32), ("ms", C.c_float), ("pad", C.c_uint32)]
+
+
+EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_destroy",
+           "sv_mem_required", "sv_create", "sv_destroy", "sv_reset", "stage_apply_compressed",
+           "sv_fidelity", "sv_export", "sv_amplitudes", "sv_footprint", "sv_block_stream",
+           "sv_debug_dump", "codec_encode_chunks", "codec_decode_chunks"]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO):
+            raise RuntimeError(f"HIP library {SO} is not built; run __graft_entry__.build()")
+        L = C.CDLL(SO)
+        P, V = C.POINTER, C.c_void_p
+        L.sv_last_error.restype = C.c_char_p
+        L.stage_plan.argtypes = [V, C.c_size_t, P(sv_config_t), P(V)]
+        L.plan_info.argtypes = [V, P(C.c_size_t), P(C.c_size_t), P(C.c_size_t)]
+        L.plan_stage.argtypes = [V, C.c_size_t, P(C.c_size_t), P(C.c_size_t), P(C.c_int32),
+                                 P(C.c_int32), P(C.c_int32)]
+        L.plan_destroy.argtypes = [V]
+        L.plan_destroy.restype = None
+        L.sv_mem_required.argtypes = [P(sv_config_t), P(C.c_uint64)]
+        L.sv_create.argtypes = [P(sv_config_t), V, C.c_uint64, V, P(V)]
+        L.sv_destroy.argtypes = [V]
+        L.sv_destroy.restype = None
+        L.sv_reset.argtypes = [V]
+        L.stage_apply_compressed.argtypes = [V, V, C.c_size_t, C.c_size_t, V]
+        L.sv_fidelity.argtypes = [V, V, P(C.c_double), P(C.c_double), P(C.c_double)]
+        L.sv_export.argtypes = [V, C.c_uint64, C.c_uint64, V]
+        L.sv_amplitudes.argtypes = [V, V, C.c_uint64, V]
+        L.sv_footprint.argtypes = [V, P(C.c_uint64), P(C.c_uint64)]
+        L.sv_block_stream.argtypes = [V, C.c_uint64, V, C.c_uint64, P(C.c_uint64)]
+        L.sv_debug_dump.argtypes = [V, V, V]
+        L.codec_encode_chunks.argtypes = [V, V, C.c_uint64, P(sv_config_t), V, V, V]
+        L.codec_decode_chunks.argtypes = [V, C.c_uint64, P(sv_config_t), V, V, V]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise BmqError(rc, lib().sv_last_error().decode())
+
+
+@dataclass
+class Config:
+    n: int
+    b: int
+    inner: int = 2
+    fuse: int = 2
+    domain: int = SV_DOMAIN_LIN
+    eb: float = 1e-6
+    tile: int = 0
+    pool_bytes: int = 0
+
+    def c(self) -> sv_config_t:
+        return sv_config_t(self.n, self.b, self.inner, self.fuse, self.domain, self.tile,
+                           float(self.eb), int(self.pool_bytes))
+
+
+def gate_array(gates) -> "C.Array":
+    arr = (sv_gate_t * max(1, len(gates)))()
+    for i, (k, q, p) in enumerate(gates):
+        arr[i].kind = KIND[k]
+        arr[i].q[0] = q[0]
+        arr[i].q[1] = q[1] if len(q) > 1 else 0
+        for j, v in enumerate(p):
+            arr[i].p[j] = float(v)
+    return arr
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Plan:
+    """stage_plan: Algorithm 1 stages, tile passes and fused operations."""
+
+    def __init__(self, gates: Sequence, cfg: Config):
+        self.cfg = cfg
+        self.n_gates = len(gates)
+        arr = gate_array(gates)
+        h = C.c_void_p()
+        _check(lib().stage_plan(C.cast(arr, C.c_void_p), len(gates), C.byref(cfg.c()), C.byref(h)))
+        self.h = h
+
+    def info(self):
+        a, b, c = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        _check(lib().plan_info(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return dict(stages=a.value, ops=b.value, passes=c.value)
+
+    def stage(self, s: int):
+        g0, g1 = C.c_size_t(), C.c_size_t()
+        inner = (C.c_int32 * 8)()
+        ni, npass = C.c_int32(), C.c_int32()
+        _check(lib().plan_stage(self.h, s, C.byref(g0), C.byref(g1), inner, C.byref(ni), C.byref(npass)))
+        return dict(gates=(g0.value, g1.value), inner=list(inner[:ni.value]), passes=npass.value)
+
+    @property
+    def n_stages(self) -> int:
+        return self.info()["stages"]
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.plan_destroy(self.h)
+            self.h = None
+
+
+class State:
+    """A compressed state vector in a torch-owned device arena."""
+
+    def __init__(self, cfg: Config, device: str = "cuda:0"):
+        import torch
+        self.cfg = cfg
+        need = C.c_uint64()
+        _check(lib().sv_mem_required(C.byref(cfg.c()), C.byref(need)))
+        self.arena = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=device)
+        base = _ptr(self.arena)
+        off = (-base) % 256
+        h = C.c_void_p()
+        _check(lib().sv_create(C.byref(cfg.c()), C.c_void_p(base + off), int(need.value), _stream(), C.byref(h)))
+        self.h = h
+
+    def apply(self, plan: Plan, first: int = 0, count: Optional[int] = None, stats: bool = False):
+        if count is None:
+            count = plan.n_stages - first
+        st = (sv_stage_stats_t * max(1, count))() if stats else None
+        _check(lib().stage_apply_compressed(self.h, plan.h, first, count,
+                                            C.cast(st, C.c_void_p) if stats else None))
+        if not stats:
+            return None
+        out = []
+        for s in st[:count]:
+            out.append(dict(bytes_in=s.bytes_in, bytes_out=s.bytes_out, dir_bytes=s.dir_bytes,
+                            scratch_bytes=s.scratch_bytes, zero_chunks_out=s.zero_chunks_out,
+                            mode_hist=list(s.mode_hist), passes=s.passes, n_ops=s.n_ops,
+                            n_gates=s.n_gates, n_inner=s.n_inner, ms=s.ms))
+        return out
+
+    def reset(self):
+        _check(lib().sv_reset(self.h))
+
+    def fidelity(self, ref=None):
+        """ref: torch complex128 tensor on the device (2^n) or None."""
+        f, m, n2 = C.c_double(), C.c_double(), C.c_double()
+        _check(lib().sv_fidelity(self.h, C.c_void_p(_ptr(ref)) if ref is not None else None,
+                                 C.byref(f), C.byref(m), C.byref(n2)))
+        return f.value, m.value, n2.value
+
+    def export(self, start: int = 0, count: Optional[int] = None):
+        import torch
+        if count is None:
+            count = (1 << self.cfg.n) - start
+        out = torch.empty(count, dtype=torch.complex64, device=self.arena.device)
+        _check(lib().sv_export(self.h, start, count, C.c_void_p(_ptr(out))))
+        return out
+
+    def amplitudes(self, idx):
+        import torch
+        idx = idx.to(device=self.arena.device, dtype=torch.int64).contiguous()
+        out = torch.empty(idx.numel(), dtype=torch.complex64, device=self.arena.device)
+        _check(lib().sv_amplitudes(self.h, C.c_void_p(_ptr(idx)), idx.numel(), C.c_void_p(_ptr(out))))
+        return out
+
+    def footprint(self):
+        r, d = C.c_uint64(), C.c_uint64()
+        _check(lib().sv_footprint(self.h, C.byref(r), C.byref(d)))
+        return r.value, d.value
+
+    def block_stream(self, block: int) -> bytes:
+        nb = C.c_uint64()
+        rc = lib().sv_block_stream(self.h, block, None, 0, C.byref(nb))
+        if rc != 0 and nb.value == 0:
+            _check(rc)
+        buf = (C.c_uint8 * nb.value)()
+        _check(lib().sv_block_stream(self.h, block, C.cast(buf, C.c_void_p), nb.value, C.byref(nb)))
+        return bytes(buf)
+
+    def debug_dump(self, re=None, im=None):
+        _check(lib().sv_debug_dump(self.h, C.c_void_p(_ptr(re)) if re is not None else None,
+                                   C.c_void_p(_ptr(im)) if im is not None else None))
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def codec_encode_chunks(re, im, cfg: Config):
+    """Encode device float32 planes; returns (slots uint8 tensor, sizes int32 tensor)."""
+    import torch
+    n = re.numel()
+    nch = (n + 63) // 64
+    slots = torch.zeros(nch * SV_CHUNK_SLOT_BYTES, dtype=torch.uint8, device=re.device)
+    sizes = torch.zeros(nch, dtype=torch.int32, device=re.device)
+    _check(lib().codec_encode_chunks(C.c_void_p(_ptr(re)), C.c_void_p(_ptr(im)), n, C.byref(cfg.c()),
+                                     C.c_void_p(_ptr(slots)), C.c_void_p(_ptr(sizes)), _stream()))
+    return slots, sizes
+
+
+def codec_decode_chunks(slots, n: int, cfg: Config):
+    import torch
+    re = torch.empty(n, dtype=torch.float32, device=slots.device)
+    im = torch.empty(n, dtype=torch.float32, device=slots.device)
+    _check(lib().codec_decode_chunks(C.c_void_p(_ptr(slots)), n, C.byref(cfg.c()),
+                                     C.c_void_p(_ptr(re)), C.c_void_p(_ptr(im)), _stream()))
+    return re, im
+
+
+def slots_to_stream(slots_host: np.ndarray, sizes_host: np.ndarray, n: int, domain: int, eb: float) -> bytes:
+    """Concatenate per-chunk records into the canonical block stream (16-byte
+    header + records in order).  Pure byte framing, no codec arithmetic."""
+    import struct
+    nch = (n + 63) // 64
+    hdr = bytes([0x51, 1, domain, 6]) + struct.pack("<fII", float(np.float32(eb)), n, nch)
+    parts = [hdr]
+    for c in range(nch):
+        parts.append(slots_host[c * SV_CHUNK_SLOT_BYTES: c * SV_CHUNK_SLOT_BYTES + int(sizes_host[c])].tobytes())
+    return b"".join(parts)

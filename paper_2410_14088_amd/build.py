@@ -1,0 +1,56 @@
+"""Build the gfx950 HIP library ``_build/libbmq.so`` in-tree with hipcc.
+
+Flags that matter for the result:
+* ``-ffp-contract=off``: the codec's float32 steps must round exactly as
+  written (its own log2/exp2 use explicit fused multiply-adds), so the
+  compiler may not contract other multiply-adds.
+* ``-Xclang -target-feature -Xclang -packed-fp32-ops``: no packed FP32 math.
+* ``-fno-gpu-flush-denormals-to-zero``: IEEE float32 denormals on the device.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+SO = os.path.join(BUILD, "libbmq.so")
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc" if os.path.exists("/opt/rocm/bin/hipcc") else "hipcc")
+ARCH = "gfx950"
+COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", "-I", os.path.join(ROOT, "include")]
+DEVICE = [f"--offload-arch={ARCH}", "-fno-gpu-flush-denormals-to-zero",
+          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(" ".join(cmd) + "\n" + r.stdout + r.stderr)
+        raise RuntimeError(f"hipcc failed ({r.returncode})")
+    return r
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    k_obj = os.path.join(BUILD, "bmq_kernels.o")
+    _run([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "bmq_kernels.hip"), "-o", k_obj])
+    objs.append(k_obj)
+    r_obj = os.path.join(BUILD, "bmq_runtime.o")
+    _run([HIPCC] + COMMON + ["-Wall", "-c", os.path.join(CSRC, "bmq_runtime.cpp"), "-o", r_obj])
+    objs.append(r_obj)
+    tmp = SO + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
+    os.replace(tmp, SO)
+    if verbose:
+        print("built", SO)
+    return SO
+
+
+if __name__ == "__main__":
+    build(verbose=True)

@@ -1,0 +1,87 @@
+// Internal declarations shared by the host runtime (bmq_runtime.cpp) and the
+// gfx950 kernels (bmq_kernels.hip).  Plain data only: descriptors that the
+// host planner fills and the kernels read, and the kernel launch wrappers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bmq {
+
+constexpr int kChunk = 64;                      // values per codec chunk (one wavefront)
+constexpr int kMaxOpQubits = 10;                // widest diagonal operation
+constexpr int kMaxTile = 13;                    // largest on-chip tile, log2 amplitudes
+constexpr uint64_t kDirZero = 0;                // directory: chunk is entirely zero
+constexpr uint64_t kDirInvalid = ~0ull;         // directory: body lost to an overflow
+constexpr uint64_t kDirOffsetMask = (1ull << 40) - 1;   // body offset bits of an entry
+constexpr uint32_t kSlotBytes = 576;            // one canonical chunk record, worst case 560
+
+enum OpType : int32_t { OP_DENSE = 0, OP_DIAG = 1 };
+enum IoMode : int32_t { IO_COMPRESSED = 0, IO_SCRATCH = 1 };
+enum Mode : uint32_t { M_ZERO = 0, M_LZ = 1, M_Q0 = 2, M_VERB = 3 };
+
+// One fused operation.  Operation qubit j is bit j of the matrix / table
+// index.  DENSE: 2^k x 2^k complex64 matrix, row major, every qubit inside
+// the tile.  DIAG: 2^k complex64 phases; a qubit outside the tile (pos < 0)
+// is constant over the tile and read from the tile's base index.
+struct OpDesc {
+    int32_t type;
+    int32_t k;
+    int32_t pos[kMaxOpQubits];   // tile position of operation qubit j, or -1
+    int32_t gq[kMaxOpQubits];    // global qubit of operation qubit j
+    uint32_t data;               // offset into the complex64 data array
+    uint32_t pad;
+};
+
+// Per-stage device counters (one block of 8 per stage of a call).
+enum Counter : int { C_CURSOR = 0, C_OVERFLOW = 1, C_ZERO_CHUNKS = 2, C_MODE0 = 3, C_NUM = 8 };
+
+// Codec parameters: quantization step delta = 2^-s (the largest power of two
+// <= 2 eb), scale = 2^s, eb as float32; code_ok is false when the step cannot
+// code values at all (every chunk then stays VERBATIM).
+struct CodecParams {
+    int32_t domain;
+    int32_t s;
+    float ebf, delta, scale;
+    int32_t code_ok;
+};
+
+struct PassArgs {
+    int32_t n, t;
+    int32_t tileq[16];        // tile position -> global qubit (positions 0..5 are qubits 0..5)
+    int32_t nontile[48];      // non-tile qubits, ascending; tile id bit i -> qubit nontile[i]
+    int32_t n_nontile;
+    int32_t op_begin, op_end;
+    int32_t in_mode, out_mode;
+    CodecParams cp;
+    const uint64_t *dir_in;
+    const uint8_t *pool_in;
+    uint64_t *dir_out;
+    uint8_t *pool_out;
+    uint64_t cap_out;
+    unsigned long long *counters;
+    float *scr_re, *scr_im;
+    const OpDesc *ops;
+    const float2 *opdata;
+    float *dump_re, *dump_im;
+};
+
+// ---- launch wrappers (bmq_kernels.hip) ----
+hipError_t launch_pass(const PassArgs &a, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_init_state(uint64_t *dir, uint64_t n_chunks, uint8_t *pool,
+                             unsigned long long *counters, CodecParams cp, hipStream_t s);
+hipError_t launch_export(const uint64_t *dir, const uint8_t *pool, CodecParams cp,
+                         uint64_t chunk0, uint64_t n_chunks, float2 *dst, hipStream_t s);
+hipError_t launch_amplitudes(const uint64_t *dir, const uint8_t *pool, CodecParams cp,
+                             const uint64_t *idx, uint64_t k, uint64_t n_chunks, float2 *dst,
+                             hipStream_t s);
+hipError_t launch_fidelity(const uint64_t *dir, const uint8_t *pool, CodecParams cp,
+                           uint64_t n_chunks, const double2 *ref, double *partials,
+                           int n_partials, double *out5, hipStream_t s);
+hipError_t launch_codec_encode(const float *re, const float *im, uint64_t n, CodecParams cp,
+                               uint8_t *slots, uint32_t *sizes, hipStream_t s);
+hipError_t launch_codec_decode(const uint8_t *slots, uint64_t n, CodecParams cp,
+                               float *re, float *im, hipStream_t s);
+
+}  // namespace bmq

@@ -1,0 +1,960 @@
+// gfx950 kernels of the compressed stage loop.
+//
+// Layout in HBM (two copies, used in ping-pong by consecutive stages):
+//   directory: one u64 per 64-amplitude chunk:
+//              bits 39:0  byte offset of the chunk's record body in the pool
+//              bits 51:40 header of the real plane, bits 63:52 of the imaginary
+//              plane.  0 means an all-zero chunk (both planes ZERO, no body);
+//              all ones marks a body lost to a pool overflow.
+//   pool:      record bodies appended by workgroups (one atomic bump per tile).
+// A header holds mode (1:0: ZERO, LZ, Q0, VERBATIM), width w (7:2), sign class
+// (9:8: 0 all >= 0, 1 all < 0, 2 mixed) and zero class (11:10: 0 none, 2
+// mixed).  A body holds [i32 anchor_re] [i32 anchor_im] [u64 sign_re]
+// [u64 zero_re] [u64 sign_im] [u64 zero_im] payload_re payload_im; LZ/Q0
+// payloads are 64 fields of w bits, LSB-first (8w bytes), VERBATIM payloads 64
+// raw float32.  The canonical record of a chunk is its two 32-bit headers
+// followed by its body.
+//
+// The codec is the point-wise error-bounded compressor of Section 4.3
+// (Algorithm 2): LOG domain = sign bitmap + log2 of the magnitude + absolute
+// bound eb on the logarithm (relative bound 2^eb - 1, Eq. 1-2); the bitmap
+// pre-scan classifies each 64-bit chunk of the sign/zero bitmaps with wave
+// votes and keeps only mixed chunks.  The lossy part is linear-scaling
+// quantization with a Lorenzo predictor and fixed-width packing per chunk.
+// The quantization step is the largest power of two 2^-s <= 2 eb, so scaling
+// is exact; in the LOG domain the code is e 2^s + rint(p 2^s) for
+// log2|x| = e + p.  Every float32 step is written out (no contraction, own
+// log2 and exp2), so codes and streams are reproducible bit for bit.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "bmq_internal.h"
+
+namespace bmq {
+
+// ------------------------------------------------------------------ wave helpers
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+
+// DPP controls of the GFX9 family
+constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
+constexpr int DPP_WAVE_SHR1 = 0x138, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+
+// inclusive prefix sum over the 64 lanes (wrapping 32-bit arithmetic)
+__device__ __forceinline__ uint32_t wave_scan_add(uint32_t v)
+{
+    v += dpp<DPP_ROW_SHR1, 0xf>(v);
+    v += dpp<DPP_ROW_SHR2, 0xf>(v);
+    v += dpp<DPP_ROW_SHR4, 0xf>(v);
+    v += dpp<DPP_ROW_SHR8, 0xf>(v);
+    v += dpp<DPP_ROW_BCAST15, 0xa>(v);
+    v += dpp<DPP_ROW_BCAST31, 0xc>(v);
+    return v;
+}
+
+// OR over the 64 lanes, returned to every lane
+__device__ __forceinline__ uint32_t wave_or(uint32_t v)
+{
+    v |= dpp<DPP_ROW_SHR1, 0xf>(v);
+    v |= dpp<DPP_ROW_SHR2, 0xf>(v);
+    v |= dpp<DPP_ROW_SHR4, 0xf>(v);
+    v |= dpp<DPP_ROW_SHR8, 0xf>(v);
+    v |= dpp<DPP_ROW_BCAST15, 0xa>(v);
+    v |= dpp<DPP_ROW_BCAST31, 0xc>(v);
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
+
+// value of lane - 1 (0 in lane 0).  The shifted copy is pinned to its own
+// register: when the compiler folds the DPP move into a following
+// subtraction (v_subrev_u32_dpp) the device returned the negated difference,
+// so only commutative operations (add, or) may absorb a DPP source.
+__device__ __forceinline__ uint32_t wave_prev(uint32_t v)
+{
+    uint32_t p = dpp<DPP_WAVE_SHR1, 0xf>(v);
+    asm volatile("" : "+v"(p));
+    return p;
+}
+
+__device__ __forceinline__ uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// A wave-uniform 64-bit value made scalar.  readfirstlane returns a signed
+// int, so each half is zero-extended explicitly.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v)
+{
+    return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | (uint64_t)rfl((uint32_t)v);
+}
+
+__device__ __forceinline__ uint64_t lane_u64(uint64_t v, int lane)
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | (uint64_t)lo;
+}
+
+__device__ __forceinline__ void wave_sync_lds()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t zigzag(int32_t d) { return ((uint32_t)d << 1) ^ (uint32_t)(d >> 31); }
+__device__ __forceinline__ int32_t unzigzag(uint32_t z) { return (int32_t)((z >> 1) ^ (0u - (z & 1u))); }
+__device__ __forceinline__ uint32_t bitlen(uint32_t v) { return v ? 32u - (uint32_t)__clz((int)v) : 0u; }
+__device__ __forceinline__ float pow2i(int i) { return __uint_as_float((uint32_t)(i + 127) << 23); }
+
+// ------------------------------------------------------------------ codec arithmetic
+
+// log2|x| = e + p for a positive normal float32: significand folded into
+// [sqrt(1/2), sqrt(2)], t = m - 1 exactly, p = t * P(t) with P the degree-8
+// Chebyshev fit of log2(1+t)/t (Horner, fused multiply-add, one final
+// rounding of t * P).
+__device__ __forceinline__ float log2_split(uint32_t u, int &e)
+{
+    const uint32_t mant = u & 0x007FFFFFu;
+    const bool fold = mant > 0x003504F3u;
+    const float m = __uint_as_float(mant | (fold ? 0x3F000000u : 0x3F800000u));
+    e = (int)(u >> 23) - (fold ? 126 : 127);
+    const float t = m - 1.0f;
+    float p = 0.12614846229553223f;
+    p = __builtin_fmaf(p, t, -0.20742103457450867f);
+    p = __builtin_fmaf(p, t, 0.21566985547542572f);
+    p = __builtin_fmaf(p, t, -0.23892034590244293f);
+    p = __builtin_fmaf(p, t, 0.2879183292388916f);
+    p = __builtin_fmaf(p, t, -0.36070483922958374f);
+    p = __builtin_fmaf(p, t, 0.48091059923171997f);
+    p = __builtin_fmaf(p, t, -0.7213473320007324f);
+    p = __builtin_fmaf(p, t, 1.4426950216293335f);
+    return t * p;
+}
+
+// 2^(k 2^-s): nearest integer i = round(k / 2^s) in integers, remainder
+// f = (k - i 2^s) 2^-s in [-1/2, 1/2) exact, 2^f by the degree-6 Chebyshev
+// fit, 2^i applied as two exact power-of-two scalings.
+__device__ __forceinline__ float log_decode(int32_t k, int s, float delta)
+{
+    const int32_t i = (int32_t)(((int64_t)k + (int64_t)(1 << (s - 1))) >> s);
+    const int32_t r = k - (int32_t)((uint32_t)i << s);
+    const float f = (float)r * delta;
+    float p = 0.00015469732170458883f;
+    p = __builtin_fmaf(p, f, 0.0013400432653725147f);
+    p = __builtin_fmaf(p, f, 0.00961802527308464f);
+    p = __builtin_fmaf(p, f, 0.05550327152013779f);
+    p = __builtin_fmaf(p, f, 0.24022650718688965f);
+    p = __builtin_fmaf(p, f, 0.6931471824645996f);
+    p = __builtin_fmaf(p, f, 1.0f);
+    const int ic = i < -250 ? -250 : (i > 250 ? 250 : i);
+    const int i1 = ic >> 1, i2 = ic - i1;
+    return (p * pow2i(i1)) * pow2i(i2);
+}
+
+// quantize v with step 2^-s and verify |v - k 2^-s| <= eb in float32 (one
+// retry toward v); false if the bound cannot be met
+__device__ __forceinline__ bool quantize(float v, const CodecParams &cp, int32_t &k)
+{
+    const float t = v * cp.scale;
+    if (!(__builtin_fabsf(t) < 1073741824.0f)) return false;
+    int32_t kk = (int32_t)__builtin_rintf(t);
+    float q = (float)kk * cp.delta;
+    if (!(__builtin_fabsf(v - q) <= cp.ebf)) {
+        kk += (v > q) ? 1 : -1;
+        q = (float)kk * cp.delta;
+        if (!(__builtin_fabsf(v - q) <= cp.ebf)) return false;
+    }
+    k = kk;
+    return true;
+}
+
+// wave-uniform description of one encoded plane of a chunk
+struct PlaneInfo {
+    uint32_t hdr;
+    int32_t anchor;
+    uint64_t smask, zmask;
+};
+
+__device__ __forceinline__ uint32_t body_bytes(uint32_t hdr)
+{
+    const uint32_t mode = hdr & 3u, w = (hdr >> 2) & 63u;
+    const uint32_t sc = (hdr >> 8) & 3u, zc = (hdr >> 10) & 3u;
+    if (mode == M_ZERO) return 0;
+    if (mode == M_VERB) return 256;
+    return (mode == M_LZ ? 4u : 0u) + 8u * ((sc == 2u) + (zc == 2u)) + 8u * w;
+}
+
+// Encode one plane of one chunk held one value per lane; lanes >= nvalid are
+// absent.  Returns the lane's field (zigzag code, or raw bits for VERBATIM)
+// and the wave-uniform plane description.
+__device__ uint32_t encode_plane(float x, int nvalid, const CodecParams &cp, PlaneInfo &pi)
+{
+    const int lane = lane_id();
+    const bool valid = lane < nvalid;
+    const uint32_t u = __float_as_uint(x);
+    const bool log_dom = cp.domain == 1;
+    bool isz = false, neg = false, ok = true;
+    int32_t k = 0;
+    pi.anchor = 0;
+    pi.smask = 0;
+    pi.zmask = 0;
+    if (log_dom) {
+        const uint32_t ef = (u >> 23) & 0xFFu;
+        isz = ef == 0u;
+        neg = !isz && (u >> 31);
+        int e;
+        const float p = log2_split(u & 0x7FFFFFFFu, e);
+        int32_t j = 0;
+        ok = cp.code_ok && (isz || (ef < 254u && quantize(p, cp, j)));
+        k = isz ? 0 : (int32_t)((uint32_t)e << cp.s) + j;
+    } else {
+        ok = cp.code_ok && quantize(x, cp, k);
+    }
+    if (__ballot(valid && !ok)) {
+        pi.hdr = M_VERB;
+        return valid ? u : 0u;
+    }
+    const uint64_t nzm = __ballot(valid && !isz);
+    const bool allzero = log_dom ? (nzm == 0) : (__ballot(valid && k != 0) == 0);
+    if (allzero) {
+        pi.hdr = M_ZERO;
+        return 0u;
+    }
+    // zeros take the code of the last non-zero value at or before them, or of
+    // the first non-zero value; absent lanes repeat the last valid lane
+    int32_t kp = k;
+    if (nzm != ~0ull) {           // some lane is zero or absent
+        int src;
+        if (log_dom) {
+            const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
+            const uint64_t m = nzm & upto;
+            src = m ? 63 - __clzll((long long)m) : __ffsll((long long)nzm) - 1;
+        } else {
+            src = valid ? lane : nvalid - 1;
+        }
+        kp = __shfl(k, src, 64);
+    }
+    const uint32_t prev = wave_prev((uint32_t)kp);
+    const int32_t d = lane ? (int32_t)((uint32_t)kp - prev) : 0;
+    const uint32_t zl = zigzag(d), zq = zigzag(kp);
+    const uint32_t wl = bitlen(wave_or(zl)), wq = bitlen(wave_or(zq));
+    uint32_t sc = 0, zc = 0;
+    uint64_t smask = 0, zmask = 0;
+    if (log_dom) {
+        smask = __ballot(valid && neg);
+        zmask = __ballot(valid && isz);
+        sc = smask == 0 ? 0u : (smask == nzm ? 1u : 2u);
+        zc = zmask ? 2u : 0u;
+    }
+    const uint32_t masks = 8u * ((sc == 2u) + (zc == 2u));
+    const uint32_t s_lz = 4u + masks + 8u * wl, s_q0 = masks + 8u * wq;
+    uint32_t mode = M_LZ, best = s_lz;
+    if (s_q0 < best) { mode = M_Q0; best = s_q0; }
+    if (256u < best) {
+        pi.hdr = M_VERB;
+        return valid ? u : 0u;
+    }
+    const uint32_t w = (mode == M_LZ) ? wl : wq;
+    pi.hdr = mode | (w << 2) | (sc << 8) | (zc << 10);
+    pi.anchor = __builtin_amdgcn_readlane(kp, 0);
+    pi.smask = (sc == 2u) ? smask : 0ull;
+    pi.zmask = (zc == 2u) ? zmask : 0ull;
+    return (mode == M_LZ) ? zl : zq;
+}
+
+// Register image of one chunk's compressed data, loaded before decoding so
+// that the loads of several chunks are in flight together.
+struct ChunkRegs {
+    uint32_t h0, h1;                 // uniform headers
+    int32_t a0, a1;                  // uniform anchors
+    uint64_t sm0, zm0, sm1, zm1;     // uniform masks
+    uint32_t lo0, hi0, lo1, hi1;     // this lane's payload words
+};
+
+__device__ __forceinline__ void load_plane_words(uint32_t h, const uint32_t *pay, uint32_t &lo, uint32_t &hi)
+{
+    const int lane = lane_id();
+    const uint32_t mode = h & 3u;
+    lo = 0;
+    hi = 0;
+    if (mode == M_VERB) {
+        lo = pay[lane];
+    } else if (mode != M_ZERO) {
+        uint32_t w = (h >> 2) & 63u;
+        w = w > 32u ? 32u : w;            // a malformed header cannot read past the body
+        if (w) {
+            const uint32_t p = (uint32_t)lane * w, a = p >> 5, s = p & 31u;
+            lo = pay[a];
+            if (s + w > 32u) hi = pay[a + 1];
+        }
+    }
+}
+
+// Load a chunk given its two headers and the (uniform) address of its body.
+__device__ __forceinline__ ChunkRegs load_body(uint32_t h0, uint32_t h1, const uint8_t *body)
+{
+    ChunkRegs R;
+    R.h0 = h0;
+    R.h1 = h1;
+    R.a0 = R.a1 = 0;
+    R.sm0 = R.zm0 = R.sm1 = R.zm1 = 0;
+    const uint32_t m0 = h0 & 3u, m1 = h1 & 3u;
+    uint32_t off = 0;
+    const uint32_t *b32 = (const uint32_t *)body;
+    if (m0 == M_LZ) { R.a0 = (int32_t)b32[0]; off += 4; }
+    if (m1 == M_LZ) { R.a1 = (int32_t)b32[off >> 2]; off += 4; }
+    if (m0 == M_LZ || m0 == M_Q0) {
+        if (((h0 >> 8) & 3u) == 2u) { R.sm0 = (uint64_t)b32[off >> 2] | ((uint64_t)b32[(off >> 2) + 1] << 32); off += 8; }
+        if (((h0 >> 10) & 3u) == 2u) { R.zm0 = (uint64_t)b32[off >> 2] | ((uint64_t)b32[(off >> 2) + 1] << 32); off += 8; }
+    }
+    if (m1 == M_LZ || m1 == M_Q0) {
+        if (((h1 >> 8) & 3u) == 2u) { R.sm1 = (uint64_t)b32[off >> 2] | ((uint64_t)b32[(off >> 2) + 1] << 32); off += 8; }
+        if (((h1 >> 10) & 3u) == 2u) { R.zm1 = (uint64_t)b32[off >> 2] | ((uint64_t)b32[(off >> 2) + 1] << 32); off += 8; }
+    }
+    load_plane_words(h0, (const uint32_t *)(body + off), R.lo0, R.hi0);
+    uint32_t w0 = (h0 >> 2) & 63u;
+    w0 = w0 > 32u ? 32u : w0;
+    const uint32_t pay1 = off + (m0 == M_VERB ? 256u : (m0 == M_ZERO ? 0u : 8u * w0));
+    load_plane_words(h1, (const uint32_t *)(body + pay1), R.lo1, R.hi1);
+    return R;
+}
+
+__device__ __forceinline__ float decode_plane(uint32_t h, int32_t anchor, uint64_t smask, uint64_t zmask,
+                                              uint32_t lo, uint32_t hi, const CodecParams &cp)
+{
+    const int lane = lane_id();
+    const uint32_t mode = h & 3u;
+    if (mode == M_ZERO) return 0.0f;
+    if (mode == M_VERB) return __uint_as_float(lo);
+    uint32_t w = (h >> 2) & 63u;
+    w = w > 32u ? 32u : w;
+    uint32_t field = 0;
+    if (w) {
+        const uint32_t s = ((uint32_t)lane * w) & 31u;
+        field = (uint32_t)((((uint64_t)hi << 32) | lo) >> s);
+        if (w < 32u) field &= (1u << w) - 1u;
+    }
+    int32_t k;
+    if (mode == M_LZ) {
+        const int32_t d = lane ? unzigzag(field) : 0;
+        k = (int32_t)((uint32_t)anchor + wave_scan_add((uint32_t)d));
+    } else {
+        k = unzigzag(field);
+    }
+    if (cp.domain == 0) return (float)k * cp.delta;
+    const uint32_t sc = (h >> 8) & 3u, zc = (h >> 10) & 3u;
+    const bool isz = (zc == 2u) && ((zmask >> lane) & 1ull);
+    const bool isn = (sc == 2u) ? (((smask >> lane) & 1ull) != 0) : (sc == 1u);
+    if (isz) return 0.0f;
+    const float mag = log_decode(k, cp.s, cp.delta);
+    return isn ? -mag : mag;
+}
+
+__device__ __forceinline__ void decode_regs(const ChunkRegs &R, const CodecParams &cp, float &re, float &im)
+{
+    re = decode_plane(R.h0, R.a0, R.sm0, R.zm0, R.lo0, R.hi0, cp);
+    im = decode_plane(R.h1, R.a1, R.sm1, R.zm1, R.lo1, R.hi1, cp);
+}
+
+__device__ __forceinline__ ChunkRegs load_entry(uint64_t e, const uint8_t *pool)
+{
+    if (e == kDirInvalid) e = 0;          // a lost chunk reads as zero
+    const uint32_t h0 = (uint32_t)(e >> 40) & 0xFFFu, h1 = (uint32_t)(e >> 52);
+    return load_body(h0, h1, pool + (e & kDirOffsetMask));
+}
+
+// Assemble a body (and optionally the two headers in front of it) in the
+// wave's LDS staging area (>= 140 words) and copy it to gdst (4-byte
+// aligned).  f0/f1 are this lane's fields of the two planes.  Returns the
+// bytes written.
+__device__ uint32_t write_body(uint32_t *stage, const PlaneInfo &p0, const PlaneInfo &p1, uint32_t f0,
+                               uint32_t f1, uint32_t *gdst, bool with_headers)
+{
+    const int lane = lane_id();
+    const uint32_t hw = with_headers ? 2u : 0u;
+    const uint32_t words = hw + ((body_bytes(p0.hdr) + body_bytes(p1.hdr)) >> 2);
+    for (uint32_t i = lane; i < words; i += 64) stage[i] = 0u;
+    wave_sync_lds();
+    uint32_t idx = hw;
+    const uint32_t m0 = p0.hdr & 3u, m1 = p1.hdr & 3u;
+    if (lane == 0 && with_headers) { stage[0] = p0.hdr; stage[1] = p1.hdr; }
+    if (m0 == M_LZ) { if (lane == 0) stage[idx] = (uint32_t)p0.anchor; idx++; }
+    if (m1 == M_LZ) { if (lane == 0) stage[idx] = (uint32_t)p1.anchor; idx++; }
+    const PlaneInfo *ps[2] = {&p0, &p1};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const uint32_t h = ps[c]->hdr, m = h & 3u;
+        if (m == M_LZ || m == M_Q0) {
+            if (((h >> 8) & 3u) == 2u) {
+                if (lane == 0) { stage[idx] = (uint32_t)ps[c]->smask; stage[idx + 1] = (uint32_t)(ps[c]->smask >> 32); }
+                idx += 2;
+            }
+            if (((h >> 10) & 3u) == 2u) {
+                if (lane == 0) { stage[idx] = (uint32_t)ps[c]->zmask; stage[idx + 1] = (uint32_t)(ps[c]->zmask >> 32); }
+                idx += 2;
+            }
+        }
+    }
+    const uint32_t fs[2] = {f0, f1};
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const uint32_t h = ps[c]->hdr, m = h & 3u;
+        if (m == M_VERB) {
+            stage[idx + lane] = fs[c];
+            idx += 64;
+        } else if (m != M_ZERO) {
+            const uint32_t w = (h >> 2) & 63u;
+            if (w) {
+                const uint32_t p = (uint32_t)lane * w, a = p >> 5, s = p & 31u;
+                atomicOr(&stage[idx + a], fs[c] << s);
+                if (s + w > 32u) atomicOr(&stage[idx + a + 1], fs[c] >> (32u - s));
+            }
+            idx += 2u * w;
+        }
+    }
+    wave_sync_lds();
+    for (uint32_t i = lane; i < words; i += 64) gdst[i] = stage[i];
+    return words * 4u;
+}
+
+// bits of v deposited at positions q[0..nq) (bit i of v -> position q[i])
+__device__ __forceinline__ uint64_t deposit(uint64_t v, const int32_t *q, int nq)
+{
+    uint64_t r = 0;
+    for (int i = 0; i < nq; ++i) r |= ((v >> i) & 1ull) << q[i];
+    return r;
+}
+
+// ------------------------------------------------------------------ fused operations
+
+// Dense 2^K x 2^K complex operation on the LDS tile.  Every thread takes
+// groups of 2^K amplitudes whose indices differ only in the operation's bits.
+template <int K, int TILE, int NT>
+__device__ void apply_dense(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M)
+{
+    constexpr int D = 1 << K;
+    int pos[K], sp[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) { pos[j] = op.pos[j]; sp[j] = pos[j]; }
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = 0; j + 1 < K - i; ++j)
+            if (sp[j] > sp[j + 1]) { const int t = sp[j]; sp[j] = sp[j + 1]; sp[j + 1] = t; }
+    for (int g = threadIdx.x; g < (TILE >> K); g += NT) {
+        uint32_t i0 = (uint32_t)g;
+#pragma unroll
+        for (int j = 0; j < K; ++j) i0 = ((i0 >> sp[j]) << (sp[j] + 1)) | (i0 & ((1u << sp[j]) - 1u));
+        float ar[D], ai[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) {
+            uint32_t o = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) o |= (uint32_t)((c >> j) & 1) << pos[j];
+            ar[c] = sre[i0 + o];
+            ai[c] = sim[i0 + o];
+        }
+#pragma unroll(K <= 3 ? D : 1)
+        for (int r = 0; r < D; ++r) {
+            float br = 0.0f, bi = 0.0f;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const float2 m = M[r * D + c];
+                br = __builtin_fmaf(m.x, ar[c], br);
+                br = __builtin_fmaf(-m.y, ai[c], br);
+                bi = __builtin_fmaf(m.x, ai[c], bi);
+                bi = __builtin_fmaf(m.y, ar[c], bi);
+            }
+            uint32_t o = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) o |= (uint32_t)((r >> j) & 1) << pos[j];
+            sre[i0 + o] = br;
+            sim[i0 + o] = bi;
+        }
+    }
+}
+
+// Diagonal operation: multiply every amplitude by a phase from a 2^k table
+// staged in LDS.  The table index of amplitude i = tid + m NT splits into a
+// per-thread part (bits of tid and the tile-constant bits) and a per-m part
+// built from wave-uniform words, so each amplitude costs one OR and a lookup.
+template <int T, int NT>
+__device__ void apply_diag(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ tab, uint64_t base,
+                           float2 *s_tab)
+{
+    constexpr int TILE = 1 << T;
+    constexpr int LNT = __builtin_ctz(NT);
+    constexpr int MB = T - LNT;
+    const int k = op.k;
+    for (int i = threadIdx.x; i < (1 << k); i += NT) s_tab[i] = tab[i];
+    const int tid = (int)threadIdx.x;
+    uint32_t it = 0;
+    uint32_t W[MB];
+#pragma unroll
+    for (int b = 0; b < MB; ++b) W[b] = 0;
+    for (int j = 0; j < k; ++j) {
+        const int p = op.pos[j];
+        if (p < 0) {
+            it |= (uint32_t)((base >> op.gq[j]) & 1ull) << j;
+        } else if (p < LNT) {
+            it |= (uint32_t)((tid >> p) & 1) << j;
+        } else {
+#pragma unroll
+            for (int b = 0; b < MB; ++b)
+                if (p == LNT + b) W[b] |= 1u << j;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < TILE / NT; ++m) {
+        uint32_t idx = it;
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+            if ((m >> b) & 1) idx |= W[b];
+        const int i = tid + m * NT;
+        const float2 ph = s_tab[idx];
+        const float ar = sre[i], ai = sim[i];
+        sre[i] = __builtin_fmaf(ph.x, ar, -ph.y * ai);
+        sim[i] = __builtin_fmaf(ph.x, ai, ph.y * ar);
+    }
+}
+
+// ------------------------------------------------------------------ pass kernel
+//
+// One workgroup = one tile of 2^T amplitudes: qubits 0..5 (one codec chunk)
+// plus T-6 more qubits chosen by the planner.  The tile is decoded (or read
+// from scratch) into LDS, every fused operation of the pass is applied in
+// LDS, and the tile is re-encoded (or written to scratch).  Each wave owns a
+// contiguous run of CPW chunks of the tile.
+
+template <int T, int NT>
+struct PassLds {
+    static constexpr int TILE = 1 << T, NCH = TILE / kChunk, NW = NT / 64;
+    float re[TILE];
+    float im[TILE];
+    union {
+        float2 tab[1 << kMaxOpQubits];    // apply phase: diagonal table
+        struct {                          // store phase
+            uint32_t info[NCH][11];       // headers, anchors, masks per chunk
+            uint32_t off[NCH];            // body size, then offset in the tile
+            uint32_t stage[NW][140];      // per-wave body assembly
+        } st;
+    } u;
+    unsigned long long base;
+    uint32_t hist[6];
+};
+
+template <int T, int NT>
+__global__ __launch_bounds__(NT) void pass_kernel(PassArgs a)
+{
+    using L = PassLds<T, NT>;
+    constexpr int NCH = L::NCH, NW = L::NW, CPW = NCH / NW;
+    static_assert(CPW >= 1 && CPW <= 64, "chunks per wave");
+    __shared__ L s;
+
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const CodecParams cp = a.cp;
+    const uint64_t base = deposit((uint64_t)blockIdx.x, a.nontile, a.n_nontile);
+    const int c0 = wave * CPW;
+
+    // global index of the chunk this lane stands for (lane < CPW); used for
+    // the directory loads and stores and to address scratch and dumps
+    uint64_t my_g = 0;
+    if (lane < CPW) my_g = base | deposit((uint64_t)(c0 + lane), a.tileq + 6, T - 6);
+
+    // ---- load
+    if (a.in_mode == IO_COMPRESSED) {
+        const uint64_t my_e = (lane < CPW) ? a.dir_in[my_g >> 6] : 0ull;
+        constexpr int G = CPW < 4 ? CPW : 4;
+        for (int i0 = 0; i0 < CPW; i0 += G) {
+            ChunkRegs R[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) R[u] = load_entry(lane_u64(my_e, i0 + u), a.pool_in);
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                float re, im;
+                decode_regs(R[u], cp, re, im);
+                s.re[((c0 + i0 + u) << 6) + lane] = re;
+                s.im[((c0 + i0 + u) << 6) + lane] = im;
+            }
+        }
+    } else {
+        for (int i = 0; i < CPW; ++i) {
+            const uint64_t g = lane_u64(my_g, i);
+            s.re[((c0 + i) << 6) + lane] = a.scr_re[g + lane];
+            s.im[((c0 + i) << 6) + lane] = a.scr_im[g + lane];
+        }
+    }
+    __syncthreads();
+
+    // ---- apply the pass's fused operations
+    for (int o = a.op_begin; o < a.op_end; ++o) {
+        const OpDesc &op = a.ops[o];
+        const float2 *data = a.opdata + op.data;
+        if (op.type == OP_DIAG) {
+            apply_diag<T, NT>(s.re, s.im, op, data, base, s.u.tab);
+        } else {
+            switch (op.k) {
+            case 1: apply_dense<1, L::TILE, NT>(s.re, s.im, op, data); break;
+            case 2: apply_dense<2, L::TILE, NT>(s.re, s.im, op, data); break;
+            case 3: apply_dense<3, L::TILE, NT>(s.re, s.im, op, data); break;
+            case 4: apply_dense<4, L::TILE, NT>(s.re, s.im, op, data); break;
+            default: apply_dense<5, L::TILE, NT>(s.re, s.im, op, data); break;
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- store
+    if (a.out_mode == IO_SCRATCH) {
+        for (int i = 0; i < CPW; ++i) {
+            const uint64_t g = lane_u64(my_g, i);
+            a.scr_re[g + lane] = s.re[((c0 + i) << 6) + lane];
+            a.scr_im[g + lane] = s.im[((c0 + i) << 6) + lane];
+        }
+        return;
+    }
+
+    if (threadIdx.x < 6) s.hist[threadIdx.x] = 0;
+    __syncthreads();
+    // phase A: encode every chunk; the fields replace the values in LDS
+    uint32_t hist[4] = {0, 0, 0, 0}, zeros = 0;
+    for (int i = 0; i < CPW; ++i) {
+        const int c = c0 + i;
+        const float xr = s.re[(c << 6) + lane], xi = s.im[(c << 6) + lane];
+        if (a.dump_re) {
+            const uint64_t g = lane_u64(my_g, i);
+            a.dump_re[g + lane] = xr;
+            a.dump_im[g + lane] = xi;
+        }
+        PlaneInfo p0, p1;
+        const uint32_t f0 = encode_plane(xr, 64, cp, p0);
+        const uint32_t f1 = encode_plane(xi, 64, cp, p1);
+        s.re[(c << 6) + lane] = __uint_as_float(f0);
+        s.im[(c << 6) + lane] = __uint_as_float(f1);
+        if (lane == 0) {
+            uint32_t *in = s.u.st.info[c];
+            in[0] = p0.hdr | (p1.hdr << 12);
+            in[1] = (uint32_t)p0.anchor;
+            in[2] = (uint32_t)p1.anchor;
+            in[3] = (uint32_t)p0.smask;
+            in[4] = (uint32_t)(p0.smask >> 32);
+            in[5] = (uint32_t)p0.zmask;
+            in[6] = (uint32_t)(p0.zmask >> 32);
+            in[7] = (uint32_t)p1.smask;
+            in[8] = (uint32_t)(p1.smask >> 32);
+            in[9] = (uint32_t)p1.zmask;
+            in[10] = (uint32_t)(p1.zmask >> 32);
+            s.u.st.off[c] = body_bytes(p0.hdr) + body_bytes(p1.hdr);
+        }
+        hist[p0.hdr & 3u]++;
+        hist[p1.hdr & 3u]++;
+        zeros += (p0.hdr == M_ZERO) && (p1.hdr == M_ZERO);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) atomicAdd(&s.hist[m], hist[m]);
+        atomicAdd(&s.hist[4], zeros);
+    }
+    __syncthreads();
+    // exclusive scan of body sizes (wave 0); one pool allocation per tile
+    if (wave == 0) {
+        constexpr int PER = (NCH + 63) / 64;
+        uint32_t loc[PER];
+        uint32_t sum = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int c = lane * PER + i;
+            loc[i] = (c < NCH) ? s.u.st.off[c] : 0u;
+            sum += loc[i];
+        }
+        const uint32_t incl = wave_scan_add(sum);
+        uint32_t run = incl - sum;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const int c = lane * PER + i;
+            if (c < NCH) s.u.st.off[c] = run;
+            run += loc[i];
+        }
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        if (lane == 0) {
+            unsigned long long b = 0;
+            if (total) b = atomicAdd(&a.counters[C_CURSOR], (unsigned long long)total);
+            if (total && b + total > a.cap_out) {
+                atomicOr(&a.counters[C_OVERFLOW], 1ull);
+                b = ~0ull;
+            }
+            s.base = b;
+            atomicAdd(&a.counters[C_ZERO_CHUNKS], (unsigned long long)s.hist[4]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) atomicAdd(&a.counters[C_MODE0 + m], (unsigned long long)s.hist[m]);
+        }
+    }
+    __syncthreads();
+    const unsigned long long pbase = s.base;
+    // phase B: write bodies; lane i collects the directory entry of chunk i
+    uint64_t my_entry = 0;
+    for (int i = 0; i < CPW; ++i) {
+        const int c = c0 + i;
+        const uint32_t *in = s.u.st.info[c];
+        PlaneInfo p0, p1;
+        p0.hdr = in[0] & 0xFFFu;
+        p1.hdr = in[0] >> 12;
+        p0.anchor = (int32_t)in[1];
+        p1.anchor = (int32_t)in[2];
+        p0.smask = (uint64_t)in[3] | ((uint64_t)in[4] << 32);
+        p0.zmask = (uint64_t)in[5] | ((uint64_t)in[6] << 32);
+        p1.smask = (uint64_t)in[7] | ((uint64_t)in[8] << 32);
+        p1.zmask = (uint64_t)in[9] | ((uint64_t)in[10] << 32);
+        uint64_t entry;
+        if (p0.hdr == M_ZERO && p1.hdr == M_ZERO) {
+            entry = 0;
+        } else if (pbase == ~0ull) {
+            entry = kDirInvalid;
+        } else {
+            const uint64_t off = pbase + s.u.st.off[c];
+            const uint32_t f0 = __float_as_uint(s.re[(c << 6) + lane]);
+            const uint32_t f1 = __float_as_uint(s.im[(c << 6) + lane]);
+            write_body(s.u.st.stage[wave], p0, p1, f0, f1, (uint32_t *)(a.pool_out + off), false);
+            entry = off | ((uint64_t)p0.hdr << 40) | ((uint64_t)p1.hdr << 52);
+        }
+        if (lane == i) my_entry = entry;
+    }
+    if (lane < CPW) a.dir_out[my_g >> 6] = my_entry;
+}
+
+// ------------------------------------------------------------------ utility kernels
+
+__global__ void fill_u64_kernel(uint64_t *p, uint64_t n, uint64_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// |0...0>: chunk 0 holds amplitude 1 at index 0; every other chunk is zero
+// (directory entry 0, no body).
+__global__ void init_state_kernel(uint64_t *dir, uint8_t *pool, unsigned long long *counters, CodecParams cp)
+{
+    __shared__ uint32_t stage[144];
+    const int lane = lane_id();
+    PlaneInfo p0, p1;
+    const uint32_t f0 = encode_plane(lane == 0 ? 1.0f : 0.0f, 64, cp, p0);
+    const uint32_t f1 = encode_plane(0.0f, 64, cp, p1);
+    const uint32_t bytes = write_body(stage, p0, p1, f0, f1, (uint32_t *)pool, false);
+    if (lane == 0) {
+        dir[0] = ((uint64_t)p0.hdr << 40) | ((uint64_t)p1.hdr << 52);
+        counters[C_CURSOR] = bytes;
+    }
+}
+
+__device__ __forceinline__ void decode_chunk(const uint64_t *dir, const uint8_t *pool, const CodecParams &cp,
+                                             uint64_t chunk, float &re, float &im)
+{
+    const ChunkRegs R = load_entry(uniform_u64(dir[chunk]), pool);
+    decode_regs(R, cp, re, im);
+}
+
+__global__ void export_kernel(const uint64_t *dir, const uint8_t *pool, CodecParams cp, uint64_t chunk0,
+                              uint64_t n_chunks, float2 *dst)
+{
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks; c += nw) {
+        float re, im;
+        decode_chunk(dir, pool, cp, chunk0 + c, re, im);
+        dst[c * 64 + lane_id()] = make_float2(re, im);
+    }
+}
+
+__global__ void amplitudes_kernel(const uint64_t *dir, const uint8_t *pool, CodecParams cp, const uint64_t *idx,
+                                  uint64_t k, uint64_t n_chunks, float2 *dst)
+{
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t j = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); j < k; j += nw) {
+        const uint64_t xu = uniform_u64(idx[j]);
+        if ((xu >> 6) >= n_chunks) {          // index outside the state
+            if (lane_id() == 0) dst[j] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+            continue;
+        }
+        float re, im;
+        decode_chunk(dir, pool, cp, xu >> 6, re, im);
+        if ((uint64_t)lane_id() == (xu & 63ull)) dst[j] = make_float2(re, im);
+    }
+}
+
+// FP64 reductions: <ref|psi>, |psi|^2, |ref|^2, max |psi - ref| (componentwise).
+// Each block writes 5 partials; one block sums them in a fixed order.
+__global__ void fidelity_partial_kernel(const uint64_t *dir, const uint8_t *pool, CodecParams cp, uint64_t n_chunks,
+                                        const double2 *ref, double *partials)
+{
+    __shared__ double sh[5][16];
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    double sr = 0, si = 0, np = 0, nr = 0, mx = 0;
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; c < n_chunks; c += nw) {
+        float re, im;
+        decode_chunk(dir, pool, cp, c, re, im);
+        const double pr = re, pi = im;
+        np += pr * pr + pi * pi;
+        if (ref) {
+            const double2 r = ref[c * 64 + lane];
+            sr += r.x * pr + r.y * pi;
+            si += r.x * pi - r.y * pr;
+            nr += r.x * r.x + r.y * r.y;
+            mx = fmax(mx, fmax(fabs(pr - r.x), fabs(pi - r.y)));
+        }
+    }
+    double v[5] = {sr, si, np, nr, mx};
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+        double x = v[q];
+        for (int m = 32; m >= 1; m >>= 1) {
+            const double y = __shfl_xor(x, m, 64);
+            x = (q == 4) ? fmax(x, y) : x + y;
+        }
+        if (lane == 0) sh[q][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int q = (int)threadIdx.x;
+        double x = sh[q][0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) x = (q == 4) ? fmax(x, sh[q][w]) : x + sh[q][w];
+        partials[(uint64_t)blockIdx.x * 5 + q] = x;
+    }
+}
+
+__global__ void fidelity_final_kernel(const double *partials, int n, double *out5)
+{
+    if (threadIdx.x < 5) {
+        const int q = (int)threadIdx.x;
+        double x = partials[q];
+        for (int i = 1; i < n; ++i)
+            x = (q == 4) ? fmax(x, partials[(uint64_t)i * 5 + q]) : x + partials[(uint64_t)i * 5 + q];
+        out5[q] = x;
+    }
+}
+
+// stand-alone codec: canonical records (headers + body) in fixed slots
+__global__ void codec_encode_kernel(const float *re, const float *im, uint64_t n, CodecParams cp, uint8_t *slots,
+                                    uint32_t *sizes)
+{
+    __shared__ uint32_t stage[4][144];
+    const int lane = lane_id();
+    const int wave = (int)(threadIdx.x >> 6);
+    const uint64_t nch = (n + 63) / 64;
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; c < nch; c += nw) {
+        const int nvalid = (int)((n - c * 64) < 64 ? (n - c * 64) : 64);
+        const uint64_t i = c * 64 + lane;
+        const float xr = lane < nvalid ? re[i] : 0.0f;
+        const float xi = lane < nvalid ? im[i] : 0.0f;
+        PlaneInfo p0, p1;
+        const uint32_t f0 = encode_plane(xr, nvalid, cp, p0);
+        const uint32_t f1 = encode_plane(xi, nvalid, cp, p1);
+        const uint32_t bytes = write_body(stage[wave], p0, p1, f0, f1, (uint32_t *)(slots + c * kSlotBytes), true);
+        if (lane == 0) sizes[c] = bytes;
+    }
+}
+
+__global__ void codec_decode_kernel(const uint8_t *slots, uint64_t n, CodecParams cp, float *re, float *im)
+{
+    const int lane = lane_id();
+    const uint64_t nch = (n + 63) / 64;
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nch; c += nw) {
+        const uint8_t *rec = slots + c * kSlotBytes;
+        const uint32_t h0 = rfl(*(const uint32_t *)rec), h1 = rfl(*(const uint32_t *)(rec + 4));
+        const ChunkRegs R = load_body(h0 & 0xFFFu, h1 & 0xFFFu, rec + 8);
+        float xr, xi;
+        decode_regs(R, cp, xr, xi);
+        const uint64_t i = c * 64 + lane;
+        if (i < n) { re[i] = xr; im[i] = xi; }
+    }
+}
+
+// ------------------------------------------------------------------ launchers
+
+static inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap = 65536)
+{
+    uint64_t g = (work + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+hipError_t launch_pass(const PassArgs &a, hipStream_t s)
+{
+    const uint64_t tiles = 1ull << (a.n - a.t);
+    if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)tiles);
+    switch (a.t) {
+    case 10: hipLaunchKernelGGL((pass_kernel<10, 256>), grid, dim3(256), 0, s, a); break;
+    case 11: hipLaunchKernelGGL((pass_kernel<11, 256>), grid, dim3(256), 0, s, a); break;
+    case 12: hipLaunchKernelGGL((pass_kernel<12, 256>), grid, dim3(256), 0, s, a); break;
+    case 13: hipLaunchKernelGGL((pass_kernel<13, 512>), grid, dim3(512), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_state(uint64_t *dir, uint64_t n_chunks, uint8_t *pool, unsigned long long *counters,
+                             CodecParams cp, hipStream_t s)
+{
+    hipError_t e = launch_fill_u64(dir, n_chunks, 0ull, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, dir, pool, counters, cp);
+    return hipGetLastError();
+}
+
+hipError_t launch_export(const uint64_t *dir, const uint8_t *pool, CodecParams cp, uint64_t chunk0,
+                         uint64_t n_chunks, float2 *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(export_kernel, dim3(grid_for(n_chunks, 4)), dim3(256), 0, s, dir, pool, cp, chunk0,
+                       n_chunks, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_amplitudes(const uint64_t *dir, const uint8_t *pool, CodecParams cp, const uint64_t *idx,
+                             uint64_t k, uint64_t n_chunks, float2 *dst, hipStream_t s)
+{
+    hipLaunchKernelGGL(amplitudes_kernel, dim3(grid_for(k, 4)), dim3(256), 0, s, dir, pool, cp, idx, k, n_chunks,
+                       dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_fidelity(const uint64_t *dir, const uint8_t *pool, CodecParams cp, uint64_t n_chunks,
+                           const double2 *ref, double *partials, int n_partials, double *out5, hipStream_t s)
+{
+    hipLaunchKernelGGL(fidelity_partial_kernel, dim3((unsigned)n_partials), dim3(256), 0, s, dir, pool, cp,
+                       n_chunks, ref, partials);
+    hipLaunchKernelGGL(fidelity_final_kernel, dim3(1), dim3(64), 0, s, partials, n_partials, out5);
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_encode(const float *re, const float *im, uint64_t n, CodecParams cp, uint8_t *slots,
+                               uint32_t *sizes, hipStream_t s)
+{
+    hipLaunchKernelGGL(codec_encode_kernel, dim3(grid_for((n + 63) / 64, 4)), dim3(256), 0, s, re, im, n, cp,
+                       slots, sizes);
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_decode(const uint8_t *slots, uint64_t n, CodecParams cp, float *re, float *im,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(codec_decode_kernel, dim3(grid_for((n + 63) / 64, 4)), dim3(256), 0, s, slots, n, cp, re,
+                       im);
+    return hipGetLastError();
+}
+
+}  // namespace bmq

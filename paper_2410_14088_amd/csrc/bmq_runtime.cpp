@@ -1,0 +1,881 @@
+// Host runtime of the compressed stage loop: the C ABI of include/bmq.h,
+// the planner (Algorithm 1, tile passes, gate fusion) and the device-arena
+// layout.  All codec and simulation arithmetic runs in bmq_kernels.hip; this
+// file only plans, lays out memory and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <complex>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/bmq.h"
+#include "bmq_internal.h"
+
+using bmq::OpDesc;
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (expr);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(SV_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+    } while (0)
+
+constexpr int kDefaultTile = 12;
+constexpr int kMaxDiagQubits = 10;
+constexpr size_t kMaxStagesPerBatch = 4096;
+constexpr int kPartials = 1024;
+constexpr uint64_t kOpsArenaBytes = 64ull << 20;
+
+// ------------------------------------------------------------------ gates
+
+struct GateRec {
+    int kind, nq, q[2];
+    double p[3];
+    bool diag;
+};
+
+bool gate_is_diagonal(int kind)
+{
+    switch (kind) {
+    case SV_GATE_Z: case SV_GATE_S: case SV_GATE_T: case SV_GATE_RZ:
+    case SV_GATE_CZ: case SV_GATE_CP: case SV_GATE_RZZ: return true;
+    default: return false;
+    }
+}
+
+int gate_nq(int kind) { return kind >= SV_GATE_CX ? 2 : 1; }
+
+// Gate matrix, row major, dimension 2^nq (1-qubit: 2x2 in u[0..3]).
+void gate_unitary(const GateRec &g, cd *u)
+{
+    const double c = std::cos(g.p[0] / 2), s = std::sin(g.p[0] / 2);
+    const cd I(0, 1);
+    auto ph = [](double a) { return std::polar(1.0, a); };
+    for (int i = 0; i < 16; ++i) u[i] = 0;
+    const double r2 = 1.0 / std::sqrt(2.0);
+    switch (g.kind) {
+    case SV_GATE_H: u[0] = r2; u[1] = r2; u[2] = r2; u[3] = -r2; break;
+    case SV_GATE_X: u[1] = 1; u[2] = 1; break;
+    case SV_GATE_Y: u[1] = -I; u[2] = I; break;
+    case SV_GATE_Z: u[0] = 1; u[3] = -1; break;
+    case SV_GATE_S: u[0] = 1; u[3] = I; break;
+    case SV_GATE_T: u[0] = 1; u[3] = ph(M_PI / 4); break;
+    case SV_GATE_RX: u[0] = c; u[1] = -I * s; u[2] = -I * s; u[3] = c; break;
+    case SV_GATE_RY: u[0] = c; u[1] = -s; u[2] = s; u[3] = c; break;
+    case SV_GATE_RZ: u[0] = ph(-g.p[0] / 2); u[3] = ph(g.p[0] / 2); break;
+    case SV_GATE_U3:
+        u[0] = c; u[1] = -ph(g.p[2]) * s; u[2] = ph(g.p[1]) * s; u[3] = ph(g.p[1] + g.p[2]) * c; break;
+    case SV_GATE_CX: u[0] = 1; u[5] = 1; u[11] = 1; u[14] = 1; break;
+    case SV_GATE_CZ: u[0] = 1; u[5] = 1; u[10] = 1; u[15] = -1; break;
+    case SV_GATE_CP: u[0] = 1; u[5] = 1; u[10] = 1; u[15] = ph(g.p[0]); break;
+    case SV_GATE_RZZ:
+        u[0] = ph(-g.p[0] / 2); u[5] = ph(g.p[0] / 2); u[10] = ph(g.p[0] / 2); u[15] = ph(-g.p[0] / 2); break;
+    default: break;
+    }
+}
+
+// index of the gate's own matrix for an operation index x over qubits Q
+int gate_sub_index(const GateRec &g, const std::vector<int> &Q, uint32_t x)
+{
+    auto bit = [&](int qubit) {
+        const int j = (int)(std::find(Q.begin(), Q.end(), qubit) - Q.begin());
+        return (int)((x >> j) & 1u);
+    };
+    if (g.nq == 1) return bit(g.q[0]);
+    return 2 * bit(g.q[0]) + bit(g.q[1]);
+}
+
+uint32_t gate_mask(const GateRec &g, const std::vector<int> &Q)
+{
+    uint32_t m = 0;
+    for (int i = 0; i < g.nq; ++i)
+        m |= 1u << (int)(std::find(Q.begin(), Q.end(), g.q[i]) - Q.begin());
+    return m;
+}
+
+// ------------------------------------------------------------------ plan
+
+struct FusedOp {
+    int type;                    // bmq::OP_DENSE / OP_DIAG
+    std::vector<int> qubits;     // ascending
+    std::vector<size_t> gates;   // circuit gate indices, in order
+};
+
+struct PassPlan {
+    std::vector<int> tileq;      // t qubits: 0..5, then the rest ascending
+    int op_begin = 0, op_end = 0;
+};
+
+struct StagePlan {
+    size_t g0 = 0, g1 = 0;
+    std::vector<int> inner;
+    std::vector<PassPlan> passes;
+};
+
+}  // namespace
+
+struct sv_plan {
+    sv_config_t cfg{};
+    int t = kDefaultTile;
+    std::vector<GateRec> gates;
+    std::vector<StagePlan> stages;
+    std::vector<OpDesc> ops;
+    std::vector<float2> data;
+    uint64_t uid = 0;
+};
+
+struct sv_state {
+    sv_config_t cfg{};
+    int n = 0, b = 0;
+    hipStream_t stream = nullptr;
+    uint8_t *arena = nullptr;
+    uint64_t arena_bytes = 0;
+    uint64_t *dir[2] = {nullptr, nullptr};
+    uint8_t *pool[2] = {nullptr, nullptr};
+    uint64_t pool_cap = 0;
+    float *scr_re = nullptr, *scr_im = nullptr;
+    unsigned long long *counters = nullptr;
+    double *partials = nullptr;
+    double *out5 = nullptr;
+    uint8_t *ops_arena = nullptr;
+    int cur = 0;
+    uint64_t live_bytes = 0;
+    uint64_t uploaded_uid = 0;
+    float *dump_re = nullptr, *dump_im = nullptr;
+    bool poisoned = false;
+    bool reset_pending = false;                 // live_bytes is in the init counters
+    std::vector<hipEvent_t> events;             // per-stage timing, created on demand
+};
+
+namespace {
+
+std::atomic<uint64_t> g_plan_uid{1};
+
+int step_shift(float ebf);
+bool step_ok(int domain, int s);
+
+int validate_cfg(const sv_config_t *c)
+{
+    if (!c) return fail(SV_ERR_INVALID, "config is NULL");
+    if (c->n_qubits < 10 || c->n_qubits > 40)
+        return fail(SV_ERR_INVALID, "n_qubits %d outside [10, 40]", c->n_qubits);
+    if (c->block_qubits < 6 || c->block_qubits > c->n_qubits)
+        return fail(SV_ERR_INVALID, "block_qubits %d outside [6, n]", c->block_qubits);
+    if (c->fuse_qubits < 1 || c->fuse_qubits > 5)
+        return fail(SV_ERR_INVALID, "fuse_qubits %d outside [1, 5]", c->fuse_qubits);
+    if (c->domain != SV_DOMAIN_LIN && c->domain != SV_DOMAIN_LOG)
+        return fail(SV_ERR_INVALID, "domain %d", c->domain);
+    const int t = c->tile_qubits ? c->tile_qubits : kDefaultTile;
+    if (t < 10 || t > bmq::kMaxTile || t > c->n_qubits)
+        return fail(SV_ERR_INVALID, "tile_qubits %d outside [10, min(13, n)]", t);
+    if (!(c->eb > 0) || !std::isfinite(c->eb) || !std::isfinite((float)c->eb) || (float)c->eb <= 0)
+        return fail(SV_ERR_INVALID, "eb must be a positive finite float32");
+    if (!step_ok(c->domain, step_shift((float)c->eb)))
+        return fail(SV_ERR_INVALID, "eb %g outside the codec's range for this domain (LOG: 2^-23 <= eb < 1/2)", c->eb);
+    return SV_OK;
+}
+
+int tile_of(const sv_config_t *c) { return c->tile_qubits ? c->tile_qubits : kDefaultTile; }
+
+// Quantization step delta = 2^-s: the largest power of two <= 2 eb (eb
+// rounded to float32), so that scaling by 2^s is exact.
+int step_shift(float ebf)
+{
+    int ex;
+    (void)std::frexp(2.0f * ebf, &ex);   // 2 eb = m 2^ex, m in [1/2, 1)
+    return 1 - ex;
+}
+
+bool step_ok(int domain, int s)
+{
+    return domain == SV_DOMAIN_LOG ? (s >= 1 && s <= 22) : (s >= -100 && s <= 100);
+}
+
+bmq::CodecParams codec_params(const sv_config_t &c)
+{
+    bmq::CodecParams cp;
+    cp.domain = c.domain;
+    cp.ebf = (float)c.eb;
+    cp.s = step_shift(cp.ebf);
+    cp.code_ok = step_ok(c.domain, cp.s) ? 1 : 0;
+    const int s = cp.code_ok ? cp.s : 0;
+    cp.s = s;
+    cp.delta = std::ldexp(1.0f, -s);
+    cp.scale = std::ldexp(1.0f, s);
+    return cp;
+}
+
+// Algorithm 1: greedy in gate order, close the stage when its global indices
+// would exceed threshold = max(inner, 2).  Never emits an empty stage.
+int partition(const std::vector<GateRec> &gates, int b, int inner, std::vector<StagePlan> &out)
+{
+    const int threshold = std::max(inner, 2);
+    size_t start = 0;
+    std::vector<int> cur;
+    for (size_t i = 0; i < gates.size(); ++i) {
+        std::vector<int> gq;
+        for (int j = 0; j < gates[i].nq; ++j)
+            if (gates[i].q[j] >= b) gq.push_back(gates[i].q[j]);
+        if ((int)gq.size() > threshold)
+            return fail(SV_ERR_INVALID, "gate %zu touches %zu global qubits > threshold %d", i, gq.size(), threshold);
+        std::vector<int> uni = cur;
+        for (int q : gq)
+            if (std::find(uni.begin(), uni.end(), q) == uni.end()) uni.push_back(q);
+        if ((int)uni.size() > threshold) {
+            if (i > start) {
+                StagePlan s;
+                s.g0 = start;
+                s.g1 = i;
+                s.inner = cur;
+                std::sort(s.inner.begin(), s.inner.end());
+                out.push_back(s);
+            }
+            start = i;
+            uni = gq;
+        }
+        cur = uni;
+    }
+    if (gates.size() > start) {
+        StagePlan s;
+        s.g0 = start;
+        s.g1 = gates.size();
+        s.inner = cur;
+        std::sort(s.inner.begin(), s.inner.end());
+        out.push_back(s);
+    }
+    return SV_OK;
+}
+
+// Cut a stage into on-chip passes: every qubit >= 6 that a non-diagonal gate
+// acts on must be one of the pass's t-6 free tile qubits.  Greedy, in order.
+bool plan_passes(sv_plan &P, StagePlan &st)
+{
+    const int n = P.cfg.n_qubits, b = P.cfg.block_qubits, t = P.t;
+    const int free_slots = t - 6;
+    std::vector<std::vector<size_t>> pass_gates;
+    std::vector<std::vector<int>> pass_need;
+    std::vector<size_t> cur;
+    std::vector<int> need;
+    for (size_t g = st.g0; g < st.g1; ++g) {
+        const GateRec &gr = P.gates[g];
+        std::vector<int> add = need;
+        if (!gr.diag)
+            for (int j = 0; j < gr.nq; ++j)
+                if (gr.q[j] >= 6 && std::find(add.begin(), add.end(), gr.q[j]) == add.end()) add.push_back(gr.q[j]);
+        if ((int)add.size() > free_slots && !cur.empty()) {
+            pass_gates.push_back(cur);
+            pass_need.push_back(need);
+            cur.clear();
+            add.clear();
+            if (!gr.diag)
+                for (int j = 0; j < gr.nq; ++j)
+                    if (gr.q[j] >= 6 && std::find(add.begin(), add.end(), gr.q[j]) == add.end()) add.push_back(gr.q[j]);
+        }
+        need = add;
+        cur.push_back(g);
+    }
+    pass_gates.push_back(cur);
+    pass_need.push_back(need);
+
+    for (size_t pi = 0; pi < pass_gates.size(); ++pi) {
+        // tile qubits: 0..5, the needed ones, then fill with local qubits,
+        // the stage's inner qubits and finally any other qubit, ascending
+        std::vector<int> tq = pass_need[pi];
+        auto has = [&](int q) { return q < 6 || std::find(tq.begin(), tq.end(), q) != tq.end(); };
+        for (int q = 6; q < b && (int)tq.size() < free_slots; ++q)
+            if (!has(q)) tq.push_back(q);
+        for (int q : st.inner)
+            if ((int)tq.size() < free_slots && !has(q)) tq.push_back(q);
+        for (int q = 6; q < n && (int)tq.size() < free_slots; ++q)
+            if (!has(q)) tq.push_back(q);
+        std::sort(tq.begin(), tq.end());
+        PassPlan pp;
+        for (int q = 0; q < 6; ++q) pp.tileq.push_back(q);
+        for (int q : tq) pp.tileq.push_back(q);
+        auto in_tile = [&](int q) { return std::find(pp.tileq.begin(), pp.tileq.end(), q) != pp.tileq.end(); };
+
+        // greedy order-preserving fusion
+        const int K = P.cfg.fuse_qubits;
+        std::vector<FusedOp> fused;
+        FusedOp curop{-1, {}, {}};
+        auto flush = [&]() {
+            if (curop.type >= 0) fused.push_back(curop);
+            curop = FusedOp{-1, {}, {}};
+        };
+        for (size_t g : pass_gates[pi]) {
+            const GateRec &gr = P.gates[g];
+            std::vector<int> uni = curop.qubits;
+            bool subset = true;
+            for (int j = 0; j < gr.nq; ++j)
+                if (std::find(uni.begin(), uni.end(), gr.q[j]) == uni.end()) { uni.push_back(gr.q[j]); subset = false; }
+            std::sort(uni.begin(), uni.end());
+            if (gr.diag) {
+                if (curop.type == bmq::OP_DENSE && subset) { curop.gates.push_back(g); continue; }
+                if (curop.type == bmq::OP_DIAG && (int)uni.size() <= kMaxDiagQubits) {
+                    curop.qubits = uni; curop.gates.push_back(g); continue;
+                }
+                flush();
+                curop.type = bmq::OP_DIAG;
+            } else {
+                bool all_in = true;
+                for (int q : curop.qubits) all_in = all_in && in_tile(q);
+                if (curop.type == bmq::OP_DENSE && (int)uni.size() <= K) {
+                    curop.qubits = uni; curop.gates.push_back(g); continue;
+                }
+                if (curop.type == bmq::OP_DIAG && all_in && (int)uni.size() <= K) {
+                    curop.type = bmq::OP_DENSE; curop.qubits = uni; curop.gates.push_back(g); continue;
+                }
+                flush();
+                curop.type = bmq::OP_DENSE;
+            }
+            for (int j = 0; j < gr.nq; ++j) curop.qubits.push_back(gr.q[j]);
+            std::sort(curop.qubits.begin(), curop.qubits.end());
+            curop.gates.push_back(g);
+        }
+        flush();
+
+        pp.op_begin = (int)P.ops.size();
+        for (const FusedOp &f : fused) {
+            OpDesc d;
+            std::memset(&d, 0, sizeof(d));
+            d.type = f.type;
+            d.k = (int)f.qubits.size();
+            for (int j = 0; j < d.k; ++j) {
+                d.gq[j] = f.qubits[j];
+                const auto it = std::find(pp.tileq.begin(), pp.tileq.end(), f.qubits[j]);
+                d.pos[j] = it == pp.tileq.end() ? -1 : (int)(it - pp.tileq.begin());
+            }
+            d.data = (uint32_t)P.data.size();
+            const uint32_t D = 1u << d.k;
+            if (f.type == bmq::OP_DENSE)
+                for (int j = 0; j < d.k; ++j)
+                    if (d.pos[j] < 0) return false;   // a dense operation must lie inside the tile
+            if (f.type == bmq::OP_DIAG) {
+                std::vector<cd> tab(D, cd(1, 0));
+                for (size_t g : f.gates) {
+                    cd u[16];
+                    gate_unitary(P.gates[g], u);
+                    const int dim = 1 << P.gates[g].nq;
+                    for (uint32_t x = 0; x < D; ++x) {
+                        const int s = gate_sub_index(P.gates[g], f.qubits, x);
+                        tab[x] *= u[s * dim + s];
+                    }
+                }
+                for (uint32_t x = 0; x < D; ++x) P.data.push_back(make_float2((float)tab[x].real(), (float)tab[x].imag()));
+            } else {
+                std::vector<cd> M(D * D, cd(0, 0));
+                for (uint32_t x = 0; x < D; ++x) M[x * D + x] = 1;
+                for (size_t g : f.gates) {
+                    cd u[16];
+                    gate_unitary(P.gates[g], u);
+                    const int dim = 1 << P.gates[g].nq;
+                    const uint32_t gm = gate_mask(P.gates[g], f.qubits);
+                    std::vector<cd> E(D * D, cd(0, 0));
+                    for (uint32_t r = 0; r < D; ++r)
+                        for (uint32_t c = 0; c < D; ++c)
+                            if ((r & ~gm) == (c & ~gm))
+                                E[r * D + c] = u[gate_sub_index(P.gates[g], f.qubits, r) * dim +
+                                                 gate_sub_index(P.gates[g], f.qubits, c)];
+                    std::vector<cd> R(D * D, cd(0, 0));
+                    for (uint32_t r = 0; r < D; ++r)
+                        for (uint32_t k = 0; k < D; ++k) {
+                            const cd e = E[r * D + k];
+                            if (e == cd(0, 0)) continue;
+                            for (uint32_t c = 0; c < D; ++c) R[r * D + c] += e * M[k * D + c];
+                        }
+                    M.swap(R);
+                }
+                for (uint32_t x = 0; x < D * D; ++x) P.data.push_back(make_float2((float)M[x].real(), (float)M[x].imag()));
+            }
+            P.ops.push_back(d);
+        }
+        pp.op_end = (int)P.ops.size();
+        st.passes.push_back(pp);
+    }
+    return true;
+}
+
+struct ArenaLayout {
+    uint64_t dir_bytes, pool_cap, scr_bytes, counters_bytes, partials_bytes, ops_bytes, total;
+    uint64_t off_dir0, off_dir1, off_pool0, off_pool1, off_scr_re, off_scr_im, off_counters,
+        off_partials, off_out5, off_ops;
+};
+
+uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+
+ArenaLayout layout_for(const sv_config_t &c)
+{
+    ArenaLayout L{};
+    const uint64_t nch = 1ull << (c.n_qubits - 6);
+    L.dir_bytes = align256(nch * 8);
+    const uint64_t worst = nch * 560ull + 1024;
+    L.pool_cap = c.pool_bytes ? c.pool_bytes : worst;
+    const uint64_t pool_alloc = align256(L.pool_cap + 256);     // slack after the last record
+    L.scr_bytes = align256((1ull << c.n_qubits) * 4ull);
+    L.counters_bytes = align256((kMaxStagesPerBatch + 2) * bmq::C_NUM * 8ull);
+    L.partials_bytes = align256(kPartials * 5 * 8ull);
+    L.ops_bytes = kOpsArenaBytes;
+    uint64_t o = 0;
+    L.off_dir0 = o; o += L.dir_bytes;
+    L.off_dir1 = o; o += L.dir_bytes;
+    L.off_pool0 = o; o += pool_alloc;
+    L.off_pool1 = o; o += pool_alloc;
+    L.off_scr_re = o; o += L.scr_bytes;
+    L.off_scr_im = o; o += L.scr_bytes;
+    L.off_counters = o; o += L.counters_bytes;
+    L.off_partials = o; o += L.partials_bytes;
+    L.off_out5 = o; o += 256;
+    L.off_ops = o; o += L.ops_bytes;
+    L.total = o;
+    return L;
+}
+
+// body bytes of one plane from its 12-bit header (stream format parse)
+uint32_t body_bytes_host(uint32_t hdr)
+{
+    const uint32_t mode = hdr & 3u, w = (hdr >> 2) & 63u, sc = (hdr >> 8) & 3u, zc = (hdr >> 10) & 3u;
+    if (mode == 0) return 0;
+    if (mode == 3) return 256;
+    return (mode == 1 ? 4u : 0u) + 8u * ((sc == 2u) + (zc == 2u)) + 8u * w;
+}
+
+int check_state(const sv_t *sv)
+{
+    if (!sv) return fail(SV_ERR_INVALID, "state is NULL");
+    if (sv->poisoned) return fail(SV_ERR_CAPACITY, "state is poisoned by an earlier overflow");
+    return SV_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char *sv_last_error(void) { return g_err.c_str(); }
+
+int stage_plan(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, sv_plan_t **out)
+{
+    if (!out) return fail(SV_ERR_INVALID, "out is NULL");
+    if (int rc = validate_cfg(cfg)) return rc;
+    if (n_gates && !gates) return fail(SV_ERR_INVALID, "gates is NULL");
+    sv_plan *P = new (std::nothrow) sv_plan;
+    if (!P) return fail(SV_ERR_OOM, "host allocation failed");
+    P->cfg = *cfg;
+    P->t = tile_of(cfg);
+    const int n = cfg->n_qubits;
+    for (size_t i = 0; i < n_gates; ++i) {
+        const sv_gate_t &g = gates[i];
+        if (g.kind < 0 || g.kind >= SV_GATE_COUNT) { delete P; return fail(SV_ERR_INVALID, "gate %zu: bad kind %d", i, g.kind); }
+        GateRec r;
+        r.kind = g.kind;
+        r.nq = gate_nq(g.kind);
+        r.q[0] = g.q[0];
+        r.q[1] = r.nq == 2 ? g.q[1] : -1;
+        for (int j = 0; j < 3; ++j) r.p[j] = g.p[j];
+        r.diag = gate_is_diagonal(g.kind);
+        for (int j = 0; j < r.nq; ++j)
+            if (r.q[j] < 0 || r.q[j] >= n) { delete P; return fail(SV_ERR_INVALID, "gate %zu: qubit %d out of range", i, r.q[j]); }
+        if (r.nq == 2 && r.q[0] == r.q[1]) { delete P; return fail(SV_ERR_INVALID, "gate %zu: repeated qubit", i); }
+        P->gates.push_back(r);
+    }
+    if (int rc = partition(P->gates, cfg->block_qubits, cfg->inner_size, P->stages)) { delete P; return rc; }
+    for (StagePlan &st : P->stages)
+        if (!plan_passes(*P, st)) { delete P; return fail(SV_ERR_INVALID, "internal: dense operation outside its tile"); }
+    if ((uint64_t)P->ops.size() * sizeof(OpDesc) + P->data.size() * sizeof(float2) + 256 > kOpsArenaBytes) {
+        delete P;
+        return fail(SV_ERR_UNSUPPORTED, "plan too large for the operation arena");
+    }
+    P->uid = g_plan_uid.fetch_add(1);
+    *out = P;
+    return SV_OK;
+}
+
+int plan_info(const sv_plan_t *p, size_t *n_stages, size_t *n_ops, size_t *n_passes)
+{
+    if (!p) return fail(SV_ERR_INVALID, "plan is NULL");
+    if (n_stages) *n_stages = p->stages.size();
+    if (n_ops) *n_ops = p->ops.size();
+    if (n_passes) {
+        size_t np = 0;
+        for (const auto &s : p->stages) np += s.passes.size();
+        *n_passes = np;
+    }
+    return SV_OK;
+}
+
+int plan_stage(const sv_plan_t *p, size_t s, size_t *gate_begin, size_t *gate_end,
+               int32_t *inner_out, int32_t *n_inner, int32_t *n_passes)
+{
+    if (!p) return fail(SV_ERR_INVALID, "plan is NULL");
+    if (s >= p->stages.size()) return fail(SV_ERR_INVALID, "stage %zu out of range", s);
+    const StagePlan &st = p->stages[s];
+    if (gate_begin) *gate_begin = st.g0;
+    if (gate_end) *gate_end = st.g1;
+    if (n_inner) *n_inner = (int32_t)st.inner.size();
+    if (inner_out)
+        for (size_t i = 0; i < st.inner.size() && i < 8; ++i) inner_out[i] = st.inner[i];
+    if (n_passes) *n_passes = (int32_t)st.passes.size();
+    return SV_OK;
+}
+
+void plan_destroy(sv_plan_t *p) { delete p; }
+
+int sv_mem_required(const sv_config_t *cfg, uint64_t *bytes)
+{
+    if (int rc = validate_cfg(cfg)) return rc;
+    if (!bytes) return fail(SV_ERR_INVALID, "bytes is NULL");
+    *bytes = layout_for(*cfg).total;
+    return SV_OK;
+}
+
+int sv_create(const sv_config_t *cfg, void *dev_arena, uint64_t dev_bytes, void *hip_stream, sv_t **out)
+{
+    if (int rc = validate_cfg(cfg)) return rc;
+    if (!out) return fail(SV_ERR_INVALID, "out is NULL");
+    if (!dev_arena || ((uintptr_t)dev_arena & 255u)) return fail(SV_ERR_INVALID, "arena must be non-NULL and 256-byte aligned");
+    const ArenaLayout L = layout_for(*cfg);
+    if (dev_bytes < L.total)
+        return fail(SV_ERR_OOM, "arena of %llu bytes < %llu required", (unsigned long long)dev_bytes,
+                    (unsigned long long)L.total);
+    sv_state *S = new (std::nothrow) sv_state;
+    if (!S) return fail(SV_ERR_OOM, "host allocation failed");
+    S->cfg = *cfg;
+    S->n = cfg->n_qubits;
+    S->b = cfg->block_qubits;
+    S->stream = (hipStream_t)hip_stream;
+    S->arena = (uint8_t *)dev_arena;
+    S->arena_bytes = dev_bytes;
+    S->dir[0] = (uint64_t *)(S->arena + L.off_dir0);
+    S->dir[1] = (uint64_t *)(S->arena + L.off_dir1);
+    S->pool[0] = S->arena + L.off_pool0;
+    S->pool[1] = S->arena + L.off_pool1;
+    S->pool_cap = L.pool_cap;
+    S->scr_re = (float *)(S->arena + L.off_scr_re);
+    S->scr_im = (float *)(S->arena + L.off_scr_im);
+    S->counters = (unsigned long long *)(S->arena + L.off_counters);
+    S->partials = (double *)(S->arena + L.off_partials);
+    S->out5 = (double *)(S->arena + L.off_out5);
+    S->ops_arena = S->arena + L.off_ops;
+    S->cur = 0;
+    const uint64_t nch = 1ull << (S->n - 6);
+    unsigned long long *ic = S->counters + kMaxStagesPerBatch * bmq::C_NUM;
+    hipError_t e = bmq::launch_fill_u64((uint64_t *)ic, bmq::C_NUM, 0, S->stream);
+    if (e == hipSuccess) e = bmq::launch_init_state(S->dir[0], nch, S->pool[0], ic, codec_params(*cfg), S->stream);
+    unsigned long long cursor = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&cursor, ic + bmq::C_CURSOR, 8, hipMemcpyDeviceToHost, S->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+    if (e != hipSuccess) {
+        delete S;
+        return fail(SV_ERR_HIP, "sv_create: %s", hipGetErrorString(e));
+    }
+    S->live_bytes = cursor;
+    *out = S;
+    return SV_OK;
+}
+
+void sv_destroy(sv_t *sv)
+{
+    if (!sv) return;
+    (void)hipStreamSynchronize(sv->stream);
+    for (hipEvent_t e : sv->events) (void)hipEventDestroy(e);
+    delete sv;
+}
+
+int sv_reset(sv_t *sv)
+{
+    if (!sv) return fail(SV_ERR_INVALID, "state is NULL");
+    const uint64_t nch = 1ull << (sv->n - 6);
+    unsigned long long *ic = sv->counters + kMaxStagesPerBatch * bmq::C_NUM;
+    HIP_TRY(bmq::launch_fill_u64((uint64_t *)ic, bmq::C_NUM, 0, sv->stream));
+    HIP_TRY(bmq::launch_init_state(sv->dir[0], nch, sv->pool[0], ic, codec_params(sv->cfg), sv->stream));
+    sv->cur = 0;
+    sv->poisoned = false;
+    sv->reset_pending = true;
+    return SV_OK;
+}
+
+int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t count, sv_stage_stats_t *stats)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (!p) return fail(SV_ERR_INVALID, "plan is NULL");
+    if (p->cfg.n_qubits != sv->cfg.n_qubits || p->cfg.block_qubits != sv->cfg.block_qubits ||
+        p->cfg.domain != sv->cfg.domain || p->cfg.eb != sv->cfg.eb)
+        return fail(SV_ERR_INVALID, "plan and state configurations differ");
+    if (first > p->stages.size() || count > p->stages.size() - first)
+        return fail(SV_ERR_INVALID, "stage range [%zu, %zu) outside the plan's %zu stages", first, first + count,
+                    p->stages.size());
+    if (count == 0) return SV_OK;
+    if (sv->uploaded_uid != p->uid) {
+        const uint64_t ob = p->ops.size() * sizeof(OpDesc);
+        if (ob) HIP_TRY(hipMemcpyAsync(sv->ops_arena, p->ops.data(), ob, hipMemcpyHostToDevice, sv->stream));
+        if (!p->data.empty())
+            HIP_TRY(hipMemcpyAsync(sv->ops_arena + align256(ob), p->data.data(), p->data.size() * sizeof(float2),
+                                   hipMemcpyHostToDevice, sv->stream));
+        HIP_TRY(hipStreamSynchronize(sv->stream));   // host vectors are pageable
+        sv->uploaded_uid = p->uid;
+    }
+    const OpDesc *dops = (const OpDesc *)sv->ops_arena;
+    const float2 *ddata = (const float2 *)(sv->ops_arena + align256(p->ops.size() * sizeof(OpDesc)));
+    const bmq::CodecParams cp = codec_params(sv->cfg);
+    const int n = sv->n;
+    const uint64_t nch = 1ull << (n - 6);
+
+    size_t done = 0;
+    while (done < count) {
+        const size_t batch = std::min(count - done, kMaxStagesPerBatch);
+        HIP_TRY(bmq::launch_fill_u64((uint64_t *)sv->counters, batch * bmq::C_NUM, 0, sv->stream));
+        if (stats)
+            while (sv->events.size() < 2 * batch) {
+                hipEvent_t e;
+                HIP_TRY(hipEventCreate(&e));
+                sv->events.push_back(e);
+            }
+        for (size_t i = 0; i < batch; ++i) {
+            const StagePlan &st = p->stages[first + done + i];
+            if (stats) HIP_TRY(hipEventRecord(sv->events[2 * i], sv->stream));
+            const int np = (int)st.passes.size();
+            for (int pi = 0; pi < np; ++pi) {
+                const PassPlan &pp = st.passes[pi];
+                bmq::PassArgs a;
+                std::memset(&a, 0, sizeof(a));
+                a.n = n;
+                a.t = p->t;
+                for (int j = 0; j < p->t; ++j) a.tileq[j] = pp.tileq[j];
+                int nn = 0;
+                for (int q = 0; q < n; ++q)
+                    if (std::find(pp.tileq.begin(), pp.tileq.end(), q) == pp.tileq.end()) a.nontile[nn++] = q;
+                a.n_nontile = nn;
+                a.op_begin = pp.op_begin;
+                a.op_end = pp.op_end;
+                a.in_mode = pi == 0 ? bmq::IO_COMPRESSED : bmq::IO_SCRATCH;
+                a.out_mode = pi == np - 1 ? bmq::IO_COMPRESSED : bmq::IO_SCRATCH;
+                a.cp = cp;
+                a.dir_in = sv->dir[sv->cur];
+                a.pool_in = sv->pool[sv->cur];
+                a.dir_out = sv->dir[sv->cur ^ 1];
+                a.pool_out = sv->pool[sv->cur ^ 1];
+                a.cap_out = sv->pool_cap;
+                a.counters = sv->counters + i * bmq::C_NUM;
+                a.scr_re = sv->scr_re;
+                a.scr_im = sv->scr_im;
+                a.ops = dops;
+                a.opdata = ddata;
+                a.dump_re = sv->dump_re;
+                a.dump_im = sv->dump_im;
+                HIP_TRY(bmq::launch_pass(a, sv->stream));
+            }
+            if (stats) HIP_TRY(hipEventRecord(sv->events[2 * i + 1], sv->stream));
+            sv->cur ^= 1;
+        }
+        std::vector<unsigned long long> hc(batch * bmq::C_NUM);
+        HIP_TRY(hipMemcpyAsync(hc.data(), sv->counters, hc.size() * 8, hipMemcpyDeviceToHost, sv->stream));
+        unsigned long long init_cursor = 0;
+        if (sv->reset_pending)
+            HIP_TRY(hipMemcpyAsync(&init_cursor, sv->counters + kMaxStagesPerBatch * bmq::C_NUM + bmq::C_CURSOR, 8,
+                                   hipMemcpyDeviceToHost, sv->stream));
+        HIP_TRY(hipStreamSynchronize(sv->stream));
+        if (sv->reset_pending) {
+            sv->live_bytes = init_cursor;
+            sv->reset_pending = false;
+        }
+        uint64_t prev = sv->live_bytes;
+        for (size_t i = 0; i < batch; ++i) {
+            const unsigned long long *c = &hc[i * bmq::C_NUM];
+            if (c[bmq::C_OVERFLOW]) {
+                sv->poisoned = true;
+                return fail(SV_ERR_CAPACITY, "stage %zu overflowed the compressed pool (%llu bytes needed, capacity %llu)",
+                            first + done + i, c[bmq::C_CURSOR], (unsigned long long)sv->pool_cap);
+            }
+            if (stats) {
+                const StagePlan &st = p->stages[first + done + i];
+                sv_stage_stats_t &s = stats[done + i];
+                std::memset(&s, 0, sizeof(s));
+                s.bytes_in = prev;
+                s.bytes_out = c[bmq::C_CURSOR];
+                s.dir_bytes = 2ull * nch * 8ull;
+                s.scratch_bytes = (uint64_t)(st.passes.size() - 1) * 2ull * (1ull << n) * 8ull;
+                s.zero_chunks_out = c[bmq::C_ZERO_CHUNKS];
+                for (int m = 0; m < 4; ++m) s.mode_hist[m] = c[bmq::C_MODE0 + m];
+                s.passes = (uint32_t)st.passes.size();
+                uint32_t nops = 0;
+                for (const auto &pp : st.passes) nops += (uint32_t)(pp.op_end - pp.op_begin);
+                s.n_ops = nops;
+                s.n_gates = (uint32_t)(st.g1 - st.g0);
+                s.n_inner = (uint32_t)st.inner.size();
+                float ms = 0.0f;
+                HIP_TRY(hipEventElapsedTime(&ms, sv->events[2 * i], sv->events[2 * i + 1]));
+                s.ms = ms;
+            }
+            prev = c[bmq::C_CURSOR];
+        }
+        sv->live_bytes = prev;
+        done += batch;
+    }
+    return SV_OK;
+}
+
+int sv_fidelity(const sv_t *sv, const double *ref_dev, double *fidelity, double *max_abs_err, double *norm2)
+{
+    if (int rc = check_state(sv)) return rc;
+    const uint64_t nch = 1ull << (sv->n - 6);
+    const int np = (int)std::min<uint64_t>(kPartials, (nch + 3) / 4);
+    HIP_TRY(bmq::launch_fidelity(sv->dir[sv->cur], sv->pool[sv->cur], codec_params(sv->cfg), nch,
+                                 (const double2 *)ref_dev, sv->partials, np, sv->out5, sv->stream));
+    double h[5];
+    HIP_TRY(hipMemcpyAsync(h, sv->out5, sizeof(h), hipMemcpyDeviceToHost, sv->stream));
+    HIP_TRY(hipStreamSynchronize(sv->stream));
+    if (norm2) *norm2 = h[2];
+    if (ref_dev) {
+        const double ov2 = h[0] * h[0] + h[1] * h[1];
+        if (fidelity) *fidelity = ov2 / (h[2] * h[3]);
+        if (max_abs_err) *max_abs_err = h[4];
+    } else {
+        if (fidelity) *fidelity = NAN;
+        if (max_abs_err) *max_abs_err = NAN;
+    }
+    return SV_OK;
+}
+
+int sv_export(const sv_t *sv, uint64_t start, uint64_t count, void *dst_dev)
+{
+    if (int rc = check_state(sv)) return rc;
+    const uint64_t dim = 1ull << sv->n;
+    if ((start & 63) || (count & 63) || start > dim || count > dim - start || (count && !dst_dev))
+        return fail(SV_ERR_INVALID, "export range must be 64-aligned and inside the state");
+    if (!count) return SV_OK;
+    HIP_TRY(bmq::launch_export(sv->dir[sv->cur], sv->pool[sv->cur], codec_params(sv->cfg), start >> 6, count >> 6,
+                               (float2 *)dst_dev, sv->stream));
+    return SV_OK;
+}
+
+int sv_amplitudes(const sv_t *sv, const uint64_t *idx_dev, uint64_t k, void *out_dev)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (k && (!idx_dev || !out_dev)) return fail(SV_ERR_INVALID, "NULL pointer");
+    if (!k) return SV_OK;
+    HIP_TRY(bmq::launch_amplitudes(sv->dir[sv->cur], sv->pool[sv->cur], codec_params(sv->cfg), idx_dev, k,
+                                   1ull << (sv->n - 6), (float2 *)out_dev, sv->stream));
+    return SV_OK;
+}
+
+int sv_footprint(const sv_t *sv, uint64_t *record_bytes, uint64_t *dir_bytes)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (sv->reset_pending) {
+        unsigned long long c = 0;
+        HIP_TRY(hipMemcpyAsync(&c, sv->counters + kMaxStagesPerBatch * bmq::C_NUM + bmq::C_CURSOR, 8,
+                               hipMemcpyDeviceToHost, sv->stream));
+        HIP_TRY(hipStreamSynchronize(sv->stream));
+        const_cast<sv_t *>(sv)->live_bytes = c;
+        const_cast<sv_t *>(sv)->reset_pending = false;
+    }
+    if (record_bytes) *record_bytes = sv->live_bytes;
+    if (dir_bytes) *dir_bytes = (1ull << (sv->n - 6)) * 8ull;
+    return SV_OK;
+}
+
+int sv_block_stream(const sv_t *sv, uint64_t block, void *dst_host, uint64_t cap, uint64_t *bytes)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (!bytes) return fail(SV_ERR_INVALID, "bytes is NULL");
+    const int b = sv->b;
+    if (block >= (1ull << (sv->n - b))) return fail(SV_ERR_INVALID, "block %llu out of range", (unsigned long long)block);
+    const uint64_t nchb = 1ull << (b - 6);
+    const uint64_t chunk0 = block * nchb;
+    // the directory holds each chunk's two headers and its body offset; the
+    // canonical record is the headers followed by the body
+    std::vector<uint64_t> dir(nchb);
+    HIP_TRY(hipMemcpyAsync(dir.data(), sv->dir[sv->cur] + chunk0, nchb * 8, hipMemcpyDeviceToHost, sv->stream));
+    HIP_TRY(hipStreamSynchronize(sv->stream));
+    std::vector<uint32_t> sizes(nchb);
+    uint64_t total = 16;
+    for (uint64_t c = 0; c < nchb; ++c) {
+        if (dir[c] == bmq::kDirInvalid) return fail(SV_ERR_CORRUPT, "chunk %llu lost to an overflow", (unsigned long long)(chunk0 + c));
+        sizes[c] = body_bytes_host((uint32_t)(dir[c] >> 40) & 0xFFFu) + body_bytes_host((uint32_t)(dir[c] >> 52));
+        total += 8 + sizes[c];
+    }
+    *bytes = total;
+    if (!dst_host || cap < total) return fail(SV_ERR_INVALID, "buffer of %llu bytes < stream of %llu", (unsigned long long)cap,
+                                             (unsigned long long)total);
+    uint8_t *d = (uint8_t *)dst_host;
+    const float ebf = (float)sv->cfg.eb;
+    uint32_t ebbits;
+    std::memcpy(&ebbits, &ebf, 4);
+    const uint32_t nv = (uint32_t)(1ull << b), nc = (uint32_t)nchb;
+    d[0] = 0x51; d[1] = 1; d[2] = (uint8_t)sv->cfg.domain; d[3] = 6;
+    std::memcpy(d + 4, &ebbits, 4);
+    std::memcpy(d + 8, &nv, 4);
+    std::memcpy(d + 12, &nc, 4);
+    uint64_t o = 16;
+    for (uint64_t c = 0; c < nchb; ++c) {
+        const uint32_t h0 = (uint32_t)(dir[c] >> 40) & 0xFFFu, h1 = (uint32_t)(dir[c] >> 52);
+        std::memcpy(d + o, &h0, 4);
+        std::memcpy(d + o + 4, &h1, 4);
+        o += 8;
+        if (sizes[c]) {
+            HIP_TRY(hipMemcpy(d + o, sv->pool[sv->cur] + (dir[c] & bmq::kDirOffsetMask), sizes[c],
+                              hipMemcpyDeviceToHost));
+            o += sizes[c];
+        }
+    }
+    return SV_OK;
+}
+
+int sv_debug_dump(sv_t *sv, float *re_dev, float *im_dev)
+{
+    if (int rc = check_state(sv)) return rc;
+    if ((re_dev == nullptr) != (im_dev == nullptr)) return fail(SV_ERR_INVALID, "give both planes or neither");
+    sv->dump_re = re_dev;
+    sv->dump_im = im_dev;
+    return SV_OK;
+}
+
+int codec_encode_chunks(const float *re_dev, const float *im_dev, uint64_t n_values, const sv_config_t *cfg,
+                        void *slots_dev, uint32_t *sizes_dev, void *hip_stream)
+{
+    if (!cfg || !(cfg->eb > 0) || (cfg->domain != SV_DOMAIN_LIN && cfg->domain != SV_DOMAIN_LOG))
+        return fail(SV_ERR_INVALID, "bad codec config");
+    if (!n_values) return SV_OK;
+    if (!re_dev || !im_dev || !slots_dev || !sizes_dev) return fail(SV_ERR_INVALID, "NULL pointer");
+    HIP_TRY(bmq::launch_codec_encode(re_dev, im_dev, n_values, codec_params(*cfg), (uint8_t *)slots_dev, sizes_dev,
+                                     (hipStream_t)hip_stream));
+    return SV_OK;
+}
+
+int codec_decode_chunks(const void *slots_dev, uint64_t n_values, const sv_config_t *cfg, float *re_dev, float *im_dev,
+                        void *hip_stream)
+{
+    if (!cfg || !(cfg->eb > 0) || (cfg->domain != SV_DOMAIN_LIN && cfg->domain != SV_DOMAIN_LOG))
+        return fail(SV_ERR_INVALID, "bad codec config");
+    if (!n_values) return SV_OK;
+    if (!re_dev || !im_dev || !slots_dev) return fail(SV_ERR_INVALID, "NULL pointer");
+    HIP_TRY(bmq::launch_codec_decode((const uint8_t *)slots_dev, n_values, codec_params(*cfg), re_dev, im_dev,
+                                     (hipStream_t)hip_stream));
+    return SV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,77 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/bmq.h declares, and its host-only planner (stage_plan) reproduces
+Algorithm 1's stages from the independent oracle planner.  No GPU needed:
+planning makes no HIP calls."""
+import os
+import re
+
+import pytest
+
+from oracle import planner as OP
+from paper_2410_14088_amd import circuits as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bmq():
+    from paper_2410_14088_amd import bmq as B
+    if not os.path.exists(B.SO):
+        from paper_2410_14088_amd import build
+        build.build()
+    B.lib()
+    return B
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "bmq.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", txt, flags=re.M)))
+
+
+def test_exports_every_declared_symbol(bmq):
+    names = header_functions()
+    assert "stage_apply_compressed" in names and "sv_create" in names
+    L = bmq.lib()
+    for nm in names:
+        assert hasattr(L, nm), f"{nm} not exported"
+    assert sorted(bmq.EXPORTS) == names
+
+
+@pytest.mark.parametrize("inner", [0, 2, 3, 4])
+def test_planner_matches_oracle_alg1(bmq, inner):
+    cases = [(C.config(0)["gates"], 16, 10), (C.config(1, n=20)["gates"], 20, 14),
+             (C.qaoa_ring(16, 3, 2)[0], 16, 11), (C.random_layers(18, 5, 9), 18, 12)]
+    for gates, n, b in cases:
+        cfg = bmq.Config(n=n, b=b, inner=inner, fuse=4, domain=1, eb=1e-5)
+        plan = bmq.Plan(gates, cfg)
+        want = OP.partition(gates, b, inner)
+        assert plan.n_stages == len(want)
+        for s, (g0, g1) in enumerate(want):
+            st = plan.stage(s)
+            assert st["gates"] == (g0, g1)
+            assert st["inner"] == OP.inner_indices(gates, (g0, g1), b)
+            assert st["passes"] >= 1
+
+
+def test_config_stage_counts(bmq):
+    d = C.config(0)
+    assert bmq.Plan(d["gates"], bmq.Config(n=16, b=10)).n_stages == len(OP.partition(d["gates"], 10, 2))
+
+
+@pytest.mark.parametrize("bad", [dict(n=9), dict(n=41), dict(b=5), dict(b=17), dict(fuse=0),
+                                 dict(fuse=6), dict(domain=2), dict(eb=0.0), dict(eb=-1.0),
+                                 dict(tile=9), dict(tile=14), dict(eb=float("nan"))])
+def test_invalid_configs_rejected(bmq, bad):
+    kw = dict(n=16, b=10, inner=2, fuse=2, domain=0, eb=1e-6)
+    kw.update(bad)
+    with pytest.raises(bmq.BmqError) as e:
+        bmq.Plan(C.ghz(16), bmq.Config(**kw))
+    assert e.value.code == -1
+
+
+def test_invalid_gates_rejected(bmq):
+    cfg = bmq.Config(n=12, b=8)
+    for g in ([("CX", (3, 3), ())], [("H", (12,), ())], [("X", (-1,), ())]):
+        with pytest.raises(bmq.BmqError):
+            bmq.Plan(g, cfg)

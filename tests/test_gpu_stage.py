@@ -1,0 +1,219 @@
+"""GPU stage-loop parity against the CPU oracle.
+
+* every stage's re-encoded blocks equal the CPU codec's stream on the values
+  the stage was about to encode (dump hook), bit for bit;
+* every decoded amplitude lies within eb of those values (LIN) or within the
+  relative bound of Eq. 1-2 (LOG);
+* the final state matches the FP64 oracle: F^2 = |<psi_o|psi_g>|^2 >= 0.99
+  (the paper's fidelity, Section 5.3, squared), max amplitude error printed;
+* determinism, overflow handling and edge cases.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import native as N
+from oracle import sim as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2410_14088_amd import bmq  # noqa: E402
+from paper_2410_14088_amd import circuits as C  # noqa: E402
+
+DEV = "cuda:0"
+E_LOG2, E_EXP2 = 2.0e-7, 1.0e-7
+
+
+def log_rel_bound(eb, v):
+    return 2.0 ** (eb + E_LOG2 + np.abs(v) * 2.0 ** -24) * (1 + E_EXP2) - 1
+
+
+def run(gates, n, b, domain, eb, fuse=2, inner=2, tile=0, ref=None, label=""):
+    print(f"stage run {label} n={n} b={b} dom={domain} eb={eb} fuse={fuse} inner={inner} tile={tile}", flush=True)
+    cfg = bmq.Config(n=n, b=b, inner=inner, fuse=fuse, domain=domain, eb=eb, tile=tile)
+    plan = bmq.Plan(gates, cfg)
+    sv = bmq.State(cfg, DEV)
+    stats = sv.apply(plan, stats=True)
+    if ref is None:
+        ref = N.simulate(n, gates)
+    f2, mx, n2 = sv.fidelity(torch.from_numpy(np.ascontiguousarray(ref)).to(DEV))
+    print(f"  stages={plan.n_stages} F2={f2:.10f} max|d|={mx:.3e} norm2={n2:.10f}", flush=True)
+    return sv, plan, stats, f2, mx, n2
+
+
+def test_config0_random16_lin():
+    d = C.config(0)
+    sv, plan, stats, f2, mx, n2 = run(d["gates"], d["n"], d["b"], d["domain"], d["eb"], fuse=d["fuse"], label="cfg0")
+    from oracle import planner as OP
+    assert plan.n_stages == len(OP.partition(d["gates"], d["b"], 2))
+    assert f2 >= 0.99 and abs(n2 - 1) < 0.01
+    assert all(s["bytes_out"] > 0 for s in stats)
+
+
+def test_config0_random16_log():
+    d = C.config(0)
+    sv, plan, stats, f2, mx, n2 = run(d["gates"], d["n"], d["b"], 1, 1e-5, fuse=2, label="cfg0-log")
+    assert f2 >= 0.9999 and mx < 1e-4
+
+
+@pytest.mark.parametrize("domain,eb", [(0, 1e-6), (1, 1e-5)])
+def test_per_stage_bitexact_and_pointwise(domain, eb):
+    n, b = 14, 8
+    gates = C.random_layers(n, 3, 77) + C.qft_ladder(n)[:40]
+    cfg = bmq.Config(n=n, b=b, inner=2, fuse=3, domain=domain, eb=eb)
+    plan = bmq.Plan(gates, cfg)
+    sv = bmq.State(cfg, DEV)
+    dre = torch.empty(1 << n, dtype=torch.float32, device=DEV)
+    dim = torch.empty_like(dre)
+    sv.debug_dump(dre, dim)
+    ebf = float(np.float32(eb))
+    rng = np.random.default_rng(0)
+    for s in range(plan.n_stages):
+        print(f"stage {s}", flush=True)
+        sv.apply(plan, s, 1)
+        pre_re = dre.cpu().numpy()
+        pre_im = dim.cpu().numpy()
+        out = sv.export().cpu().numpy()
+        for x, y in ((pre_re, out.real), (pre_im, out.imag)):
+            x64, y64 = x.astype(np.float64), y.astype(np.float64)
+            if domain == 0:
+                assert np.all(np.abs(x64 - y64) <= ebf)
+            else:
+                tiny = np.abs(x64) < 2.0 ** -126
+                assert np.all((y64[tiny] == 0) | (y64[tiny] == x64[tiny]))
+                m = ~tiny
+                assert np.all(np.abs(y64[m] / x64[m] - 1) <= log_rel_bound(ebf, np.log2(np.abs(x64[m]))))
+        for blk in rng.choice(1 << (n - b), 4, replace=False):
+            lo, hi = int(blk) << b, (int(blk) + 1) << b
+            cpu = N.encode_block(pre_re[lo:hi], pre_im[lo:hi], domain, eb)
+            gpu = sv.block_stream(int(blk))
+            assert gpu == cpu, f"stage {s} block {blk}: streams differ"
+            r2, i2 = N.decode_block(cpu, hi - lo)
+            assert np.array_equal(r2.view(np.uint32), out.real[lo:hi].astype(np.float32).view(np.uint32))
+            assert np.array_equal(i2.view(np.uint32), out.imag[lo:hi].astype(np.float32).view(np.uint32))
+    ref = N.simulate(n, gates)
+    f2, mx, _ = sv.fidelity(torch.from_numpy(ref).to(DEV))
+    assert f2 >= 0.99
+
+
+ALL = [("H", 1, 0), ("X", 1, 0), ("Y", 1, 0), ("Z", 1, 0), ("S", 1, 0), ("T", 1, 0),
+       ("RX", 1, 1), ("RY", 1, 1), ("RZ", 1, 1), ("U3", 1, 3),
+       ("CX", 2, 0), ("CZ", 2, 0), ("CP", 2, 1), ("RZZ", 2, 1)]
+
+
+def mixed(n, m, seed):
+    rng = np.random.default_rng(seed)
+    g = []
+    for _ in range(m):
+        k, nq, npar = ALL[rng.integers(len(ALL))]
+        q = tuple(int(x) for x in rng.choice(n, nq, replace=False))
+        g.append((k, q, tuple(float(x) for x in rng.uniform(0, 2 * math.pi, npar))))
+    return g
+
+
+@pytest.mark.parametrize("fuse", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("tile", [10, 12, 13])
+def test_all_gate_kinds_fusion_and_tiles(fuse, tile):
+    n, b = 14, 9
+    gates = mixed(n, 300, 10 * fuse + tile)
+    sv, plan, stats, f2, mx, n2 = run(gates, n, b, 1, 1e-5, fuse=fuse, tile=tile, label="mixed")
+    assert f2 >= 0.9999 and mx < 1e-4
+    assert plan.info()["passes"] >= plan.n_stages
+
+
+@pytest.mark.parametrize("inner", [0, 1, 3, 4])
+def test_inner_sizes_and_block_sizes(inner):
+    n = 15
+    gates = C.random_layers(n, 4, 3)
+    for b in (6, 9, 15):
+        sv, plan, stats, f2, mx, n2 = run(gates, n, b, 1, 1e-5, fuse=2, inner=inner, label="inner")
+        assert f2 >= 0.9999
+
+
+def test_qft_reduced_against_closed_form():
+    d = C.config(1, n=20)
+    ref = N.qft_ry_state(d["n"], d["thetas"])
+    sv, plan, stats, f2, mx, n2 = run(d["gates"], d["n"], 14, d["domain"], d["eb"], fuse=4, ref=ref, label="qft20")
+    assert f2 >= 0.9999 and mx < 1e-5
+
+
+def test_qaoa_reduced_against_oracle():
+    g, ga, be = C.qaoa_ring(18, 3, 1003)
+    sv, plan, stats, f2, mx, n2 = run(g, 18, 12, 1, 1e-5, fuse=4, label="qaoa18")
+    assert f2 >= 0.9999
+    idx = np.array([0, 1, 12345, (1 << 18) - 1], dtype=np.int64)
+    got = sv.amplitudes(torch.from_numpy(idx)).cpu().numpy()
+    want = [S.qaoa_ring_amplitude(18, ga, be, int(x)) for x in idx]
+    assert np.abs(got - np.array(want)).max() < 1e-5
+
+
+def test_ghz_zero_chunks_and_ratio():
+    n = 20
+    g = C.ghz(n)
+    sv, plan, stats, f2, mx, n2 = run(g, n, 14, 1, 1e-5, fuse=2, label="ghz")
+    assert f2 >= 0.999999
+    rec, dirb = sv.footprint()
+    assert rec < 1024          # two non-zero chunks
+    assert stats[-1]["zero_chunks_out"] == (1 << (n - 6)) - 2
+
+
+def test_empty_circuit_and_initial_state():
+    n = 12
+    cfg = bmq.Config(n=n, b=8, domain=1, eb=1e-5)
+    sv = bmq.State(cfg, DEV)
+    v = sv.export().cpu().numpy()
+    assert v[0] == 1 and np.all(v[1:] == 0)          # LOG: log2(1) = 0 exactly
+    plan = bmq.Plan([], cfg)
+    assert plan.n_stages == 0
+    sv.apply(plan)
+    cfg0 = bmq.Config(n=n, b=8, domain=0, eb=1e-6)
+    sv0 = bmq.State(cfg0, DEV)
+    v0 = sv0.export().cpu().numpy()
+    assert abs(v0[0] - 1) <= np.float32(1e-6) and np.all(v0[1:] == 0)
+
+
+def test_deterministic_streams():
+    d = C.config(0)
+    outs = []
+    for _ in range(2):
+        sv, plan, *_ = run(d["gates"][:200], 16, 10, 1, 1e-5, fuse=2, label="det")
+        outs.append([sv.block_stream(k) for k in range(64)])
+    assert outs[0] == outs[1]
+
+
+def test_pool_overflow_reports_capacity():
+    n = 14
+    cfg = bmq.Config(n=n, b=8, domain=1, eb=1e-5, pool_bytes=4096)
+    plan = bmq.Plan(C.random_layers(n, 2, 1), cfg)
+    sv = bmq.State(cfg, DEV)
+    with pytest.raises(bmq.BmqError) as e:
+        sv.apply(plan)
+    assert e.value.code == -3
+    with pytest.raises(bmq.BmqError):
+        sv.export()                                       # poisoned handle
+
+
+def test_config1_full_size_sampled():
+    """30-qubit QFT on an Ry product state, 2^22-amplitude blocks, LOG
+    eb=1e-5, fused 4-qubit gates: sampled amplitudes against the closed form."""
+    d = C.config(1)
+    n = d["n"]
+    cfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=4, domain=1, eb=1e-5)
+    plan = bmq.Plan(d["gates"], cfg)
+    sv = bmq.State(cfg, DEV)
+    stats = sv.apply(plan, stats=True)
+    rng = np.random.default_rng(1)
+    idx = rng.integers(0, 1 << n, 4096).astype(np.uint64)
+    want = N.qft_ry_amplitudes(n, d["thetas"], idx)
+    got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy()
+    err = np.abs(got - want)
+    rel = err / np.abs(want)
+    print(f"cfg1 stages={plan.n_stages} max|d|={err.max():.3e} max rel={rel.max():.3e} "
+          f"ratio={(8 << n) / stats[-1]['bytes_out']:.3f}", flush=True)
+    assert err.max() < 1e-6
+    f_est = abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real)
+    assert f_est >= 0.99
+    _, _, n2 = sv.fidelity(None)
+    assert abs(n2 - 1) < 1e-3
