@@ -9,7 +9,8 @@
 namespace bmq {
 
 constexpr int kChunk = 64;                      // values per codec chunk (one wavefront)
-constexpr int kMaxOpQubits = 10;                // widest diagonal operation
+constexpr int kMaxOpQubits = 10;                // qubit slots of an operation descriptor
+constexpr int kMaxDiagQubits = 9;               // widest diagonal operation (2^9-entry LDS table)
 constexpr int kMaxTile = 13;                    // largest on-chip tile, log2 amplitudes
 constexpr uint64_t kDirZero = 0;                // directory: chunk is entirely zero
 constexpr uint64_t kDirInvalid = ~0ull;         // directory: body lost to an overflow
@@ -33,8 +34,13 @@ struct OpDesc {
     uint32_t pad;
 };
 
-// Per-stage device counters (one block of 8 per stage of a call).
+// Per-stage device counters.  The output pool of a stage is split into
+// n_seg segments (workgroup i uses segment i mod n_seg), each with its own
+// cursor and statistics, so that no single address takes every workgroup's
+// atomics.  A stage's counter block is kSegments x C_NUM words.
 enum Counter : int { C_CURSOR = 0, C_OVERFLOW = 1, C_ZERO_CHUNKS = 2, C_MODE0 = 3, C_NUM = 8 };
+constexpr int kSegments = 256;
+constexpr uint32_t kMaxBodyBytes = 552;         // two planes, worst case
 
 // Codec parameters: quantization step delta = 2^-s (the largest power of two
 // <= 2 eb), scale = 2^s, eb as float32; code_ok is false when the step cannot
@@ -58,8 +64,9 @@ struct PassArgs {
     const uint8_t *pool_in;
     uint64_t *dir_out;
     uint8_t *pool_out;
-    uint64_t cap_out;
-    unsigned long long *counters;
+    uint64_t seg_cap;               // bytes per output pool segment
+    int32_t n_seg;                  // segments in use (power of two <= kSegments)
+    unsigned long long *counters;   // this stage's block of kSegments x C_NUM
     float *scr_re, *scr_im;
     const OpDesc *ops;
     const float2 *opdata;

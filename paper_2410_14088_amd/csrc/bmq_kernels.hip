@@ -97,6 +97,16 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int lane)
     return ((uint64_t)hi << 32) | (uint64_t)lo;
 }
 
+// v with lane `lane` (wave-uniform) replaced by the uniform value x
+__device__ __forceinline__ uint32_t set_lane(uint32_t v, int lane, uint32_t x)
+{
+    const uint32_t xs = rfl(x);
+    const uint32_t ls = rfl((uint32_t)lane);
+    // GFX9 reads one SGPR over the constant bus; the lane select goes in M0
+    asm volatile("v_writelane_b32 %0, %1, m0" : "+v"(v) : "s"(xs), "{m0}"(ls));
+    return v;
+}
+
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -139,7 +149,8 @@ __device__ __forceinline__ float log2_split(uint32_t u, int &e)
 // fit, 2^i applied as two exact power-of-two scalings.
 __device__ __forceinline__ float log_decode(int32_t k, int s, float delta)
 {
-    const int32_t i = (int32_t)(((int64_t)k + (int64_t)(1 << (s - 1))) >> s);
+    // |k| < 2^30 and 1 <= s <= 22, so k + 2^(s-1) cannot overflow 32 bits
+    const int32_t i = (k + (1 << (s - 1))) >> s;
     const int32_t r = k - (int32_t)((uint32_t)i << s);
     const float f = (float)r * delta;
     float p = 0.00015469732170458883f;
@@ -207,8 +218,11 @@ __device__ uint32_t encode_plane(float x, int nvalid, const CodecParams &cp, Pla
         neg = !isz && (u >> 31);
         int e;
         const float p = log2_split(u & 0x7FFFFFFFu, e);
-        int32_t j = 0;
-        ok = cp.code_ok && (isz || (ef < 254u && quantize(p, cp, j)));
+        // |p| <= 1/2 and 1 <= s <= 22: p 2^s is exact and below 2^21, so the
+        // range test and the verify step of quantize() always pass here and
+        // the code is just the rounded scaled value
+        const int32_t j = (int32_t)__builtin_rintf(p * cp.scale);
+        ok = cp.code_ok && (isz || ef < 254u);
         k = isz ? 0 : (int32_t)((uint32_t)e << cp.s) + j;
     } else {
         ok = cp.code_ok && quantize(x, cp, k);
@@ -322,15 +336,15 @@ __device__ __forceinline__ ChunkRegs load_body(uint32_t h0, uint32_t h1, const u
     return R;
 }
 
-__device__ __forceinline__ float decode_plane(uint32_t h, int32_t anchor, uint64_t smask, uint64_t zmask,
-                                              uint32_t lo, uint32_t hi, const CodecParams &cp)
+// Decode this lane's value of one plane.  mode, w (<= 32) and anchor are
+// wave-uniform; lo/hi are the two payload words holding the lane's field (for
+// VERBATIM, lo is the raw value); neg/zero are the lane's sign and zero flags.
+__device__ __forceinline__ float decode_value(uint32_t mode, uint32_t w, int32_t anchor, uint32_t lo, uint32_t hi,
+                                              bool neg, bool zero, const CodecParams &cp)
 {
     const int lane = lane_id();
-    const uint32_t mode = h & 3u;
     if (mode == M_ZERO) return 0.0f;
     if (mode == M_VERB) return __uint_as_float(lo);
-    uint32_t w = (h >> 2) & 63u;
-    w = w > 32u ? 32u : w;
     uint32_t field = 0;
     if (w) {
         const uint32_t s = ((uint32_t)lane * w) & 31u;
@@ -345,12 +359,21 @@ __device__ __forceinline__ float decode_plane(uint32_t h, int32_t anchor, uint64
         k = unzigzag(field);
     }
     if (cp.domain == 0) return (float)k * cp.delta;
+    if (zero) return 0.0f;
+    const float mag = log_decode(k, cp.s, cp.delta);
+    return neg ? -mag : mag;
+}
+
+__device__ __forceinline__ float decode_plane(uint32_t h, int32_t anchor, uint64_t smask, uint64_t zmask,
+                                              uint32_t lo, uint32_t hi, const CodecParams &cp)
+{
+    const int lane = lane_id();
+    uint32_t w = (h >> 2) & 63u;
+    w = w > 32u ? 32u : w;
     const uint32_t sc = (h >> 8) & 3u, zc = (h >> 10) & 3u;
     const bool isz = (zc == 2u) && ((zmask >> lane) & 1ull);
     const bool isn = (sc == 2u) ? (((smask >> lane) & 1ull) != 0) : (sc == 1u);
-    if (isz) return 0.0f;
-    const float mag = log_decode(k, cp.s, cp.delta);
-    return isn ? -mag : mag;
+    return decode_value(h & 3u, w, anchor, lo, hi, isn, isz, cp);
 }
 
 __device__ __forceinline__ void decode_regs(const ChunkRegs &R, const CodecParams &cp, float &re, float &im)
@@ -432,10 +455,20 @@ __device__ __forceinline__ uint64_t deposit(uint64_t v, const int32_t *q, int nq
 
 // Dense 2^K x 2^K complex operation on the LDS tile.  Every thread takes
 // groups of 2^K amplitudes whose indices differ only in the operation's bits.
+// Read of operation data that no kernel writes while it runs: through the
+// constant address space, so that a wave-uniform index becomes a scalar load
+// into SGPRs instead of a vector load the compiler hoists into VGPRs.
+__device__ __forceinline__ float2 const_ld(const float2 *p, int i)
+{
+    const __attribute__((address_space(4))) float *c = (const __attribute__((address_space(4))) float *)p;
+    return make_float2(c[2 * i], c[2 * i + 1]);
+}
+
 template <int K, int TILE, int NT>
 __device__ void apply_dense(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M)
 {
     constexpr int D = 1 << K;
+    constexpr int UNR = K <= 3 ? D : 1;
     int pos[K], sp[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) { pos[j] = op.pos[j]; sp[j] = pos[j]; }
@@ -457,12 +490,12 @@ __device__ void apply_dense(float *sre, float *sim, const OpDesc &op, const floa
             ar[c] = sre[i0 + o];
             ai[c] = sim[i0 + o];
         }
-#pragma unroll(K <= 3 ? D : 1)
+#pragma unroll UNR
         for (int r = 0; r < D; ++r) {
             float br = 0.0f, bi = 0.0f;
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                const float2 m = M[r * D + c];
+                const float2 m = const_ld(M, r * D + c);
                 br = __builtin_fmaf(m.x, ar[c], br);
                 br = __builtin_fmaf(-m.y, ai[c], br);
                 bi = __builtin_fmaf(m.x, ai[c], bi);
@@ -528,7 +561,59 @@ __device__ void apply_diag(float *sre, float *sim, const OpDesc &op, const float
 // plus T-6 more qubits chosen by the planner.  The tile is decoded (or read
 // from scratch) into LDS, every fused operation of the pass is applied in
 // LDS, and the tile is re-encoded (or written to scratch).  Each wave owns a
-// contiguous run of CPW chunks of the tile.
+// contiguous run of CPW chunks; lane i of a wave stands for its chunk i in
+// all per-chunk bookkeeping (directory entries, headers, layouts, offsets), so
+// that the bookkeeping of a wave's chunks costs one vector instruction, not
+// one scalar sequence per chunk.
+
+// Layout of a record body from its two 12-bit headers (see the file head),
+// computed for one chunk per lane.
+struct Layout {
+    uint32_t m0, m1, w0, w1;                       // modes, widths (w <= 32)
+    bool lz0, lz1, hs0, hz0, hs1, hz1;             // anchor / sign mask / zero mask present
+    uint32_t off_sm0, off_zm0, off_sm1, off_zm1;   // byte offsets in the body
+    uint32_t off_p0, off_p1, size;
+};
+
+__device__ __forceinline__ Layout layout_of(uint32_t h0, uint32_t h1)
+{
+    Layout L;
+    L.m0 = h0 & 3u;
+    L.m1 = h1 & 3u;
+    L.w0 = min((h0 >> 2) & 63u, 32u);
+    L.w1 = min((h1 >> 2) & 63u, 32u);
+    const bool pk0 = L.m0 == M_LZ || L.m0 == M_Q0, pk1 = L.m1 == M_LZ || L.m1 == M_Q0;
+    L.lz0 = L.m0 == M_LZ;
+    L.lz1 = L.m1 == M_LZ;
+    L.hs0 = pk0 && ((h0 >> 8) & 3u) == 2u;
+    L.hz0 = pk0 && ((h0 >> 10) & 3u) == 2u;
+    L.hs1 = pk1 && ((h1 >> 8) & 3u) == 2u;
+    L.hz1 = pk1 && ((h1 >> 10) & 3u) == 2u;
+    uint32_t o = 4u * ((uint32_t)L.lz0 + (uint32_t)L.lz1);
+    L.off_sm0 = o; o += 8u * L.hs0;
+    L.off_zm0 = o; o += 8u * L.hz0;
+    L.off_sm1 = o; o += 8u * L.hs1;
+    L.off_zm1 = o; o += 8u * L.hz1;
+    L.off_p0 = o; o += (L.m0 == M_VERB) ? 256u : (pk0 ? 8u * L.w0 : 0u);
+    L.off_p1 = o; o += (L.m1 == M_VERB) ? 256u : (pk1 ? 8u * L.w1 : 0u);
+    L.size = o;
+    return L;
+}
+
+// payload layout word: off_p0 [5:0], off_p1 [15:6], w0 [21:16], w1 [27:22],
+// m0 [29:28], m1 [31:30]
+__device__ __forceinline__ uint32_t pack_pay(const Layout &L)
+{
+    return L.off_p0 | (L.off_p1 << 6) | (L.w0 << 16) | (L.w1 << 22) | (L.m0 << 28) | (L.m1 << 30);
+}
+
+// Pack this lane's w-bit field at bit lane*w of stage[] (LSB-first).
+__device__ __forceinline__ void pack_field(uint32_t *stage, uint32_t f, uint32_t w)
+{
+    const uint32_t p = (uint32_t)lane_id() * w, a = p >> 5, s = p & 31u;
+    atomicOr(&stage[a], f << s);
+    if (s + w > 32u) atomicOr(&stage[a + 1], f >> (32u - s));
+}
 
 template <int T, int NT>
 struct PassLds {
@@ -536,19 +621,14 @@ struct PassLds {
     float re[TILE];
     float im[TILE];
     union {
-        float2 tab[1 << kMaxOpQubits];    // apply phase: diagonal table
-        struct {                          // store phase
-            uint32_t info[NCH][11];       // headers, anchors, masks per chunk
-            uint32_t off[NCH];            // body size, then offset in the tile
-            uint32_t stage[NW][140];      // per-wave body assembly
-        } st;
+        float2 tab[1 << kMaxDiagQubits];  // apply phase: diagonal table
+        uint32_t stage[NW][128];          // store phase: payload packing per wave
     } u;
-    unsigned long long base;
     uint32_t hist[6];
 };
 
 template <int T, int NT>
-__global__ __launch_bounds__(NT) void pass_kernel(PassArgs a)
+__global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
 {
     using L = PassLds<T, NT>;
     constexpr int NCH = L::NCH, NW = L::NW, CPW = NCH / NW;
@@ -561,25 +641,59 @@ __global__ __launch_bounds__(NT) void pass_kernel(PassArgs a)
     const uint64_t base = deposit((uint64_t)blockIdx.x, a.nontile, a.n_nontile);
     const int c0 = wave * CPW;
 
-    // global index of the chunk this lane stands for (lane < CPW); used for
-    // the directory loads and stores and to address scratch and dumps
+    // global index of the chunk this lane stands for (lane < CPW)
     uint64_t my_g = 0;
     if (lane < CPW) my_g = base | deposit((uint64_t)(c0 + lane), a.tileq + 6, T - 6);
 
     // ---- load
     if (a.in_mode == IO_COMPRESSED) {
-        const uint64_t my_e = (lane < CPW) ? a.dir_in[my_g >> 6] : 0ull;
+        uint64_t e = (lane < CPW) ? a.dir_in[my_g >> 6] : 0ull;
+        if (e == kDirInvalid) e = 0;                      // a lost chunk reads as zero
+        const uint32_t eh0 = (uint32_t)(e >> 40) & 0xFFFu, eh1 = (uint32_t)(e >> 52);
+        const Layout Lv = layout_of(eh0, eh1);
+        const uint64_t boff = e & kDirOffsetMask;
+        const uint32_t *bv = (const uint32_t *)(a.pool_in + boff);
+        const int32_t av0 = Lv.lz0 ? (int32_t)bv[0] : 0;              // anchors, one chunk per lane
+        const int32_t av1 = Lv.lz1 ? (int32_t)bv[Lv.lz0 ? 1 : 0] : 0;
+        const uint32_t pay = pack_pay(Lv);
+        const uint32_t msk = Lv.off_sm0 | (Lv.off_zm0 << 6) | (Lv.off_sm1 << 12) | (Lv.off_zm1 << 18) |
+                             ((uint32_t)Lv.hs0 << 24) | ((uint32_t)Lv.hz0 << 25) | ((uint32_t)Lv.hs1 << 26) |
+                             ((uint32_t)Lv.hz1 << 27) | ((((eh0 >> 8) & 3u) == 1u) << 28) |
+                             ((((eh1 >> 8) & 3u) == 1u) << 29);
         constexpr int G = CPW < 4 ? CPW : 4;
         for (int i0 = 0; i0 < CPW; i0 += G) {
-            ChunkRegs R[G];
-#pragma unroll
-            for (int u = 0; u < G; ++u) R[u] = load_entry(lane_u64(my_e, i0 + u), a.pool_in);
+            uint32_t lo0[G], hi0[G], lo1[G], hi1[G], sw0[G], zw0[G], sw1[G], zw1[G], P[G], M[G];
 #pragma unroll
             for (int u = 0; u < G; ++u) {
-                float re, im;
-                decode_regs(R[u], cp, re, im);
-                s.re[((c0 + i0 + u) << 6) + lane] = re;
-                s.im[((c0 + i0 + u) << 6) + lane] = im;
+                const int i = i0 + u;
+                const uint32_t *b = (const uint32_t *)(a.pool_in + lane_u64(boff, i));
+                const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)pay, i);
+                const uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)msk, i);
+                P[u] = p;
+                M[u] = m;
+                const uint32_t w0 = (p >> 16) & 63u, w1 = (p >> 22) & 63u;
+                const uint32_t j0 = ((p >> 28) & 3u) == M_VERB ? (uint32_t)lane : (((uint32_t)lane * w0) >> 5);
+                const uint32_t j1 = ((p >> 30) & 3u) == M_VERB ? (uint32_t)lane : (((uint32_t)lane * w1) >> 5);
+                const uint32_t *p0 = b + ((p & 63u) >> 2) + j0;
+                const uint32_t *p1 = b + (((p >> 6) & 1023u) >> 2) + j1;
+                lo0[u] = p0[0]; hi0[u] = p0[1];
+                lo1[u] = p1[0]; hi1[u] = p1[1];
+                const uint32_t hw = (uint32_t)lane >> 5;
+                sw0[u] = b[((m & 63u) >> 2) + hw];
+                sw1[u] = b[(((m >> 12) & 63u) >> 2) + hw];
+                zw0[u] = (m & (1u << 25)) ? b[(((m >> 6) & 63u) >> 2) + hw] : 0u;
+                zw1[u] = (m & (1u << 27)) ? b[(((m >> 18) & 63u) >> 2) + hw] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int i = i0 + u;
+                const uint32_t p = P[u], m = M[u], bit = (uint32_t)lane & 31u;
+                const bool n0 = (m & (1u << 24)) ? ((sw0[u] >> bit) & 1u) : ((m >> 28) & 1u);
+                const bool n1 = (m & (1u << 26)) ? ((sw1[u] >> bit) & 1u) : ((m >> 29) & 1u);
+                const bool z0 = (zw0[u] >> bit) & 1u, z1 = (zw1[u] >> bit) & 1u;
+                const int32_t a0 = __builtin_amdgcn_readlane(av0, i), a1 = __builtin_amdgcn_readlane(av1, i);
+                s.re[((c0 + i) << 6) + lane] = decode_value((p >> 28) & 3u, (p >> 16) & 63u, a0, lo0[u], hi0[u], n0, z0, cp);
+                s.im[((c0 + i) << 6) + lane] = decode_value((p >> 30) & 3u, (p >> 22) & 63u, a1, lo1[u], hi1[u], n1, z1, cp);
             }
         }
     } else {
@@ -619,9 +733,10 @@ __global__ __launch_bounds__(NT) void pass_kernel(PassArgs a)
         return;
     }
 
+    // encode every chunk; the fields replace the values in LDS and the
+    // chunk's headers, anchors and masks go to lane i of the wave
     if (threadIdx.x < 6) s.hist[threadIdx.x] = 0;
-    __syncthreads();
-    // phase A: encode every chunk; the fields replace the values in LDS
+    uint32_t hv = 0, av0 = 0, av1 = 0, s0l = 0, s0h = 0, z0l = 0, z0h = 0, s1l = 0, s1h = 0, z1l = 0, z1h = 0;
     uint32_t hist[4] = {0, 0, 0, 0}, zeros = 0;
     for (int i = 0; i < CPW; ++i) {
         const int c = c0 + i;
@@ -636,95 +751,100 @@ __global__ __launch_bounds__(NT) void pass_kernel(PassArgs a)
         const uint32_t f1 = encode_plane(xi, 64, cp, p1);
         s.re[(c << 6) + lane] = __uint_as_float(f0);
         s.im[(c << 6) + lane] = __uint_as_float(f1);
-        if (lane == 0) {
-            uint32_t *in = s.u.st.info[c];
-            in[0] = p0.hdr | (p1.hdr << 12);
-            in[1] = (uint32_t)p0.anchor;
-            in[2] = (uint32_t)p1.anchor;
-            in[3] = (uint32_t)p0.smask;
-            in[4] = (uint32_t)(p0.smask >> 32);
-            in[5] = (uint32_t)p0.zmask;
-            in[6] = (uint32_t)(p0.zmask >> 32);
-            in[7] = (uint32_t)p1.smask;
-            in[8] = (uint32_t)(p1.smask >> 32);
-            in[9] = (uint32_t)p1.zmask;
-            in[10] = (uint32_t)(p1.zmask >> 32);
-            s.u.st.off[c] = body_bytes(p0.hdr) + body_bytes(p1.hdr);
+        hv = set_lane(hv, i, (uint32_t)((int)(p0.hdr | (p1.hdr << 12))));
+        av0 = set_lane(av0, i, (uint32_t)(p0.anchor));
+        av1 = set_lane(av1, i, (uint32_t)(p1.anchor));
+        if (p0.smask) {
+            s0l = set_lane(s0l, i, (uint32_t)((int)(uint32_t)p0.smask));
+            s0h = set_lane(s0h, i, (uint32_t)((int)(uint32_t)(p0.smask >> 32)));
+        }
+        if (p0.zmask) {
+            z0l = set_lane(z0l, i, (uint32_t)((int)(uint32_t)p0.zmask));
+            z0h = set_lane(z0h, i, (uint32_t)((int)(uint32_t)(p0.zmask >> 32)));
+        }
+        if (p1.smask) {
+            s1l = set_lane(s1l, i, (uint32_t)((int)(uint32_t)p1.smask));
+            s1h = set_lane(s1h, i, (uint32_t)((int)(uint32_t)(p1.smask >> 32)));
+        }
+        if (p1.zmask) {
+            z1l = set_lane(z1l, i, (uint32_t)((int)(uint32_t)p1.zmask));
+            z1h = set_lane(z1h, i, (uint32_t)((int)(uint32_t)(p1.zmask >> 32)));
         }
         hist[p0.hdr & 3u]++;
         hist[p1.hdr & 3u]++;
         zeros += (p0.hdr == M_ZERO) && (p1.hdr == M_ZERO);
     }
+
+    // per-chunk body sizes and offsets (lane = chunk), one allocation per wave
+    const bool mine = lane < CPW;
+    const uint32_t h0 = mine ? (hv & 0xFFFu) : 0u, h1 = mine ? (hv >> 12) : 0u;
+    const Layout Lv = layout_of(h0, h1);
+    const uint32_t incl = wave_scan_add(Lv.size);
+    const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+    const uint32_t seg = ((uint32_t)blockIdx.x * NW + (uint32_t)wave) & (uint32_t)(a.n_seg - 1);
+    unsigned long long *cnt = a.counters + seg * C_NUM;
+    unsigned long long got = 0;
+    if (lane == 0 && total) got = atomicAdd(&cnt[C_CURSOR], (unsigned long long)total);
+    const uint64_t b = uniform_u64(got);
+    const bool overflow = total && b + total > a.seg_cap;
+    if (lane == 0 && overflow) atomicOr(&cnt[C_OVERFLOW], 1ull);
+    const uint64_t off = (uint64_t)seg * a.seg_cap + b + (incl - Lv.size);
+    uint64_t entry = 0;
+    if (h0 | h1) entry = overflow ? kDirInvalid : (off | ((uint64_t)h0 << 40) | ((uint64_t)h1 << 52));
+
+    if (!overflow) {
+        // anchors and masks: each lane writes its own chunk's
+        uint32_t *bw = (uint32_t *)(a.pool_out + off);
+        if (mine && Lv.lz0) bw[0] = av0;
+        if (mine && Lv.lz1) bw[Lv.lz0 ? 1 : 0] = av1;
+        if (mine && Lv.hs0) { bw[Lv.off_sm0 >> 2] = s0l; bw[(Lv.off_sm0 >> 2) + 1] = s0h; }
+        if (mine && Lv.hz0) { bw[Lv.off_zm0 >> 2] = z0l; bw[(Lv.off_zm0 >> 2) + 1] = z0h; }
+        if (mine && Lv.hs1) { bw[Lv.off_sm1 >> 2] = s1l; bw[(Lv.off_sm1 >> 2) + 1] = s1h; }
+        if (mine && Lv.hz1) { bw[Lv.off_zm1 >> 2] = z1l; bw[(Lv.off_zm1 >> 2) + 1] = z1h; }
+        // payloads, chunk by chunk: VERBATIM planes store straight from the
+        // lanes, packed planes go through the wave's LDS stage
+        const uint32_t pay = pack_pay(Lv);
+        uint32_t *stage = s.u.stage[wave];
+        for (int i = 0; i < CPW; ++i) {
+            const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)pay, i);
+            const uint32_t m0 = (p >> 28) & 3u, m1 = (p >> 30) & 3u;
+            if (m0 == M_ZERO && m1 == M_ZERO) continue;
+            const int c = c0 + i;
+            uint32_t *dst = (uint32_t *)(a.pool_out + lane_u64(off, i));
+            const uint32_t f0 = __float_as_uint(s.re[(c << 6) + lane]);
+            const uint32_t f1 = __float_as_uint(s.im[(c << 6) + lane]);
+            const uint32_t w0 = (p >> 16) & 63u, w1 = (p >> 22) & 63u;
+            const uint32_t q0 = (m0 == M_LZ || m0 == M_Q0) ? 2u * w0 : 0u;   // packed words
+            const uint32_t q1 = (m1 == M_LZ || m1 == M_Q0) ? 2u * w1 : 0u;
+            const uint32_t op0 = (p & 63u) >> 2, op1 = ((p >> 6) & 1023u) >> 2;
+            if (m0 == M_VERB) dst[op0 + lane] = f0;
+            if (m1 == M_VERB) dst[op1 + lane] = f1;
+            if (q0 + q1) {
+                for (uint32_t k = lane; k < q0 + q1; k += 64) stage[k] = 0u;
+                wave_sync_lds();
+                if (q0) pack_field(stage, f0, w0);
+                if (q1) pack_field(stage + q0, f1, w1);
+                wave_sync_lds();
+                const uint32_t ob = q0 ? op0 : op1;        // packed planes are contiguous
+                for (uint32_t k = lane; k < q0 + q1; k += 64) dst[ob + k] = stage[k];
+                wave_sync_lds();
+            }
+        }
+    }
+    if (mine) a.dir_out[my_g >> 6] = entry;
+
     if (lane == 0) {
 #pragma unroll
         for (int m = 0; m < 4; ++m) atomicAdd(&s.hist[m], hist[m]);
         atomicAdd(&s.hist[4], zeros);
     }
     __syncthreads();
-    // exclusive scan of body sizes (wave 0); one pool allocation per tile
-    if (wave == 0) {
-        constexpr int PER = (NCH + 63) / 64;
-        uint32_t loc[PER];
-        uint32_t sum = 0;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int c = lane * PER + i;
-            loc[i] = (c < NCH) ? s.u.st.off[c] : 0u;
-            sum += loc[i];
-        }
-        const uint32_t incl = wave_scan_add(sum);
-        uint32_t run = incl - sum;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const int c = lane * PER + i;
-            if (c < NCH) s.u.st.off[c] = run;
-            run += loc[i];
-        }
-        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-        if (lane == 0) {
-            unsigned long long b = 0;
-            if (total) b = atomicAdd(&a.counters[C_CURSOR], (unsigned long long)total);
-            if (total && b + total > a.cap_out) {
-                atomicOr(&a.counters[C_OVERFLOW], 1ull);
-                b = ~0ull;
-            }
-            s.base = b;
-            atomicAdd(&a.counters[C_ZERO_CHUNKS], (unsigned long long)s.hist[4]);
-#pragma unroll
-            for (int m = 0; m < 4; ++m) atomicAdd(&a.counters[C_MODE0 + m], (unsigned long long)s.hist[m]);
-        }
+    if (threadIdx.x == 0) {
+        unsigned long long *c = a.counters + (blockIdx.x & (uint32_t)(a.n_seg - 1)) * C_NUM;
+        if (s.hist[4]) atomicAdd(&c[C_ZERO_CHUNKS], (unsigned long long)s.hist[4]);
+        atomicAdd(&c[C_MODE0], (unsigned long long)s.hist[0] | ((unsigned long long)s.hist[1] << 32));
+        atomicAdd(&c[C_MODE0 + 2], (unsigned long long)s.hist[2] | ((unsigned long long)s.hist[3] << 32));
     }
-    __syncthreads();
-    const unsigned long long pbase = s.base;
-    // phase B: write bodies; lane i collects the directory entry of chunk i
-    uint64_t my_entry = 0;
-    for (int i = 0; i < CPW; ++i) {
-        const int c = c0 + i;
-        const uint32_t *in = s.u.st.info[c];
-        PlaneInfo p0, p1;
-        p0.hdr = in[0] & 0xFFFu;
-        p1.hdr = in[0] >> 12;
-        p0.anchor = (int32_t)in[1];
-        p1.anchor = (int32_t)in[2];
-        p0.smask = (uint64_t)in[3] | ((uint64_t)in[4] << 32);
-        p0.zmask = (uint64_t)in[5] | ((uint64_t)in[6] << 32);
-        p1.smask = (uint64_t)in[7] | ((uint64_t)in[8] << 32);
-        p1.zmask = (uint64_t)in[9] | ((uint64_t)in[10] << 32);
-        uint64_t entry;
-        if (p0.hdr == M_ZERO && p1.hdr == M_ZERO) {
-            entry = 0;
-        } else if (pbase == ~0ull) {
-            entry = kDirInvalid;
-        } else {
-            const uint64_t off = pbase + s.u.st.off[c];
-            const uint32_t f0 = __float_as_uint(s.re[(c << 6) + lane]);
-            const uint32_t f1 = __float_as_uint(s.im[(c << 6) + lane]);
-            write_body(s.u.st.stage[wave], p0, p1, f0, f1, (uint32_t *)(a.pool_out + off), false);
-            entry = off | ((uint64_t)p0.hdr << 40) | ((uint64_t)p1.hdr << 52);
-        }
-        if (lane == i) my_entry = entry;
-    }
-    if (lane < CPW) a.dir_out[my_g >> 6] = my_entry;
 }
 
 // ------------------------------------------------------------------ utility kernels

@@ -44,8 +44,9 @@ int fail(int code, const char *fmt, ...)
     } while (0)
 
 constexpr int kDefaultTile = 12;
-constexpr int kMaxDiagQubits = 10;
-constexpr size_t kMaxStagesPerBatch = 4096;
+constexpr int kMaxDiagQubits = bmq::kMaxDiagQubits;
+constexpr size_t kMaxStagesPerBatch = 1024;
+constexpr size_t kStageCounters = (size_t)bmq::kSegments * bmq::C_NUM;   // words per stage
 constexpr int kPartials = 1024;
 constexpr uint64_t kOpsArenaBytes = 64ull << 20;
 
@@ -431,11 +432,11 @@ ArenaLayout layout_for(const sv_config_t &c)
     ArenaLayout L{};
     const uint64_t nch = 1ull << (c.n_qubits - 6);
     L.dir_bytes = align256(nch * 8);
-    const uint64_t worst = nch * 560ull + 1024;
+    const uint64_t worst = nch * bmq::kMaxBodyBytes + bmq::kSegments * 256ull;
     L.pool_cap = c.pool_bytes ? c.pool_bytes : worst;
-    const uint64_t pool_alloc = align256(L.pool_cap + 256);     // slack after the last record
+    const uint64_t pool_alloc = align256(L.pool_cap + 1024);    // decoders read a little past a body
     L.scr_bytes = align256((1ull << c.n_qubits) * 4ull);
-    L.counters_bytes = align256((kMaxStagesPerBatch + 2) * bmq::C_NUM * 8ull);
+    L.counters_bytes = align256((kMaxStagesPerBatch + 1) * kStageCounters * 8ull);
     L.partials_bytes = align256(kPartials * 5 * 8ull);
     L.ops_bytes = kOpsArenaBytes;
     uint64_t o = 0;
@@ -582,8 +583,8 @@ int sv_create(const sv_config_t *cfg, void *dev_arena, uint64_t dev_bytes, void 
     S->ops_arena = S->arena + L.off_ops;
     S->cur = 0;
     const uint64_t nch = 1ull << (S->n - 6);
-    unsigned long long *ic = S->counters + kMaxStagesPerBatch * bmq::C_NUM;
-    hipError_t e = bmq::launch_fill_u64((uint64_t *)ic, bmq::C_NUM, 0, S->stream);
+    unsigned long long *ic = S->counters + kMaxStagesPerBatch * kStageCounters;
+    hipError_t e = bmq::launch_fill_u64((uint64_t *)ic, kStageCounters, 0, S->stream);
     if (e == hipSuccess) e = bmq::launch_init_state(S->dir[0], nch, S->pool[0], ic, codec_params(*cfg), S->stream);
     unsigned long long cursor = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(&cursor, ic + bmq::C_CURSOR, 8, hipMemcpyDeviceToHost, S->stream);
@@ -609,8 +610,8 @@ int sv_reset(sv_t *sv)
 {
     if (!sv) return fail(SV_ERR_INVALID, "state is NULL");
     const uint64_t nch = 1ull << (sv->n - 6);
-    unsigned long long *ic = sv->counters + kMaxStagesPerBatch * bmq::C_NUM;
-    HIP_TRY(bmq::launch_fill_u64((uint64_t *)ic, bmq::C_NUM, 0, sv->stream));
+    unsigned long long *ic = sv->counters + kMaxStagesPerBatch * kStageCounters;
+    HIP_TRY(bmq::launch_fill_u64((uint64_t *)ic, kStageCounters, 0, sv->stream));
     HIP_TRY(bmq::launch_init_state(sv->dir[0], nch, sv->pool[0], ic, codec_params(sv->cfg), sv->stream));
     sv->cur = 0;
     sv->poisoned = false;
@@ -643,11 +644,16 @@ int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t co
     const bmq::CodecParams cp = codec_params(sv->cfg);
     const int n = sv->n;
     const uint64_t nch = 1ull << (n - 6);
+    // output pool segments: as many as tiles, at most kSegments; each holds
+    // the worst case of its tiles when the pool has its default size
+    const uint64_t waves = (1ull << (n - p->t)) * (p->t == 13 ? 8u : 4u);   // allocations per pass
+    const int n_seg = (int)std::min<uint64_t>((uint64_t)bmq::kSegments, waves);
+    const uint64_t seg_cap = (sv->pool_cap / (uint64_t)n_seg) & ~3ull;
 
     size_t done = 0;
     while (done < count) {
         const size_t batch = std::min(count - done, kMaxStagesPerBatch);
-        HIP_TRY(bmq::launch_fill_u64((uint64_t *)sv->counters, batch * bmq::C_NUM, 0, sv->stream));
+        HIP_TRY(bmq::launch_fill_u64((uint64_t *)sv->counters, batch * kStageCounters, 0, sv->stream));
         if (stats)
             while (sv->events.size() < 2 * batch) {
                 hipEvent_t e;
@@ -678,8 +684,9 @@ int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t co
                 a.pool_in = sv->pool[sv->cur];
                 a.dir_out = sv->dir[sv->cur ^ 1];
                 a.pool_out = sv->pool[sv->cur ^ 1];
-                a.cap_out = sv->pool_cap;
-                a.counters = sv->counters + i * bmq::C_NUM;
+                a.n_seg = n_seg;
+                a.seg_cap = seg_cap;
+                a.counters = sv->counters + i * kStageCounters;
                 a.scr_re = sv->scr_re;
                 a.scr_im = sv->scr_im;
                 a.ops = dops;
@@ -691,11 +698,11 @@ int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t co
             if (stats) HIP_TRY(hipEventRecord(sv->events[2 * i + 1], sv->stream));
             sv->cur ^= 1;
         }
-        std::vector<unsigned long long> hc(batch * bmq::C_NUM);
+        std::vector<unsigned long long> hc(batch * kStageCounters);
         HIP_TRY(hipMemcpyAsync(hc.data(), sv->counters, hc.size() * 8, hipMemcpyDeviceToHost, sv->stream));
         unsigned long long init_cursor = 0;
         if (sv->reset_pending)
-            HIP_TRY(hipMemcpyAsync(&init_cursor, sv->counters + kMaxStagesPerBatch * bmq::C_NUM + bmq::C_CURSOR, 8,
+            HIP_TRY(hipMemcpyAsync(&init_cursor, sv->counters + kMaxStagesPerBatch * kStageCounters + bmq::C_CURSOR, 8,
                                    hipMemcpyDeviceToHost, sv->stream));
         HIP_TRY(hipStreamSynchronize(sv->stream));
         if (sv->reset_pending) {
@@ -704,7 +711,18 @@ int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t co
         }
         uint64_t prev = sv->live_bytes;
         for (size_t i = 0; i < batch; ++i) {
-            const unsigned long long *c = &hc[i * bmq::C_NUM];
+            // per segment: cursor, overflow flag, zero chunks, and the mode
+            // histogram packed two 32-bit counts per word (ZERO|LZ, Q0|VERBATIM)
+            unsigned long long c[bmq::C_NUM] = {0, 0, 0, 0, 0, 0, 0, 0};
+            uint64_t mh[4] = {0, 0, 0, 0};
+            for (int g = 0; g < bmq::kSegments; ++g) {
+                const unsigned long long *sg = &hc[i * kStageCounters + (size_t)g * bmq::C_NUM];
+                for (int q = 0; q < bmq::C_NUM; ++q) c[q] += sg[q];
+                mh[0] += sg[bmq::C_MODE0] & 0xFFFFFFFFull;
+                mh[1] += sg[bmq::C_MODE0] >> 32;
+                mh[2] += sg[bmq::C_MODE0 + 2] & 0xFFFFFFFFull;
+                mh[3] += sg[bmq::C_MODE0 + 2] >> 32;
+            }
             if (c[bmq::C_OVERFLOW]) {
                 sv->poisoned = true;
                 return fail(SV_ERR_CAPACITY, "stage %zu overflowed the compressed pool (%llu bytes needed, capacity %llu)",
@@ -719,7 +737,7 @@ int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t co
                 s.dir_bytes = 2ull * nch * 8ull;
                 s.scratch_bytes = (uint64_t)(st.passes.size() - 1) * 2ull * (1ull << n) * 8ull;
                 s.zero_chunks_out = c[bmq::C_ZERO_CHUNKS];
-                for (int m = 0; m < 4; ++m) s.mode_hist[m] = c[bmq::C_MODE0 + m];
+                s.mode_hist[0] = mh[0]; s.mode_hist[1] = mh[1]; s.mode_hist[2] = mh[2]; s.mode_hist[3] = mh[3];
                 s.passes = (uint32_t)st.passes.size();
                 uint32_t nops = 0;
                 for (const auto &pp : st.passes) nops += (uint32_t)(pp.op_end - pp.op_begin);
@@ -787,7 +805,7 @@ int sv_footprint(const sv_t *sv, uint64_t *record_bytes, uint64_t *dir_bytes)
     if (int rc = check_state(sv)) return rc;
     if (sv->reset_pending) {
         unsigned long long c = 0;
-        HIP_TRY(hipMemcpyAsync(&c, sv->counters + kMaxStagesPerBatch * bmq::C_NUM + bmq::C_CURSOR, 8,
+        HIP_TRY(hipMemcpyAsync(&c, sv->counters + kMaxStagesPerBatch * kStageCounters + bmq::C_CURSOR, 8,
                                hipMemcpyDeviceToHost, sv->stream));
         HIP_TRY(hipStreamSynchronize(sv->stream));
         const_cast<sv_t *>(sv)->live_bytes = c;
