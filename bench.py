@@ -41,7 +41,45 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=21, help="qubits of the CPU-baseline sample")
     ap.add_argument("--stats-out", default="")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device-to-device copy of 1 GiB, three times: the reference
+    for scaling the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
+
+
+def counter_traffic(n: int, tile: int, fuse: int):
+    """HBM bytes per pass-kernel launch from the committed FETCH_SIZE /
+    WRITE_SIZE profile of the default workload, or None when the workload
+    differs or the kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+    if (n, tile or 12, fuse) != (30, 12, 4):
+        return None
+    prof = os.path.join(ROOT, "profiles", "pass_kernel_qft30_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_2410_14088_amd", "csrc", "bmq_kernels.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_sha = re.search(r"^kernel_sha256: ([0-9a-f]{64})$", text, re.M)
+    m_val = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
+    if not m_sha or not m_val or m_sha.group(1) != sha:
+        return None
+    return int(m_val.group(1))
 
 
 def cpu_baseline(n: int):
@@ -86,6 +124,9 @@ def cpu_baseline(n: int):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding of the "
               "stage loop is a design note, not implemented", file=sys.stderr)
@@ -169,9 +210,11 @@ def main():
                    "domain": "log", "eb": d["eb"], "fuse_qubits": args.fuse,
                    "tile_qubits": args.tile or 12},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(n, args.tile, args.fuse)},
         "gbps_algorithmic": achieved,
         "kernel_ms_per_step": kern_ms / args.steps,
+        "pass_launch_avg_ms": kern_ms / launches,
+        "alg_bytes_per_launch": alg_bytes / launches,
         "pass_launches_per_step": launches // args.steps,
         "compression_ratio_vs_complex64": ratio64,
         "compression_ratio_vs_complex128": ratio128,
