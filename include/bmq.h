@@ -223,6 +223,72 @@ int codec_encode_chunks(const float *re_dev, const float *im_dev, uint64_t n_val
 int codec_decode_chunks(const void *slots_dev, uint64_t n_values, const sv_config_t *cfg,
                         float *re_dev, float *im_dev, void *hip_stream);
 
+/* ---------------------------------------------------------------- predictor
+ * The compression ratio of a block is unknown until it is compressed, which
+ * makes device memory hard to plan (Section 3 feasibility analysis, Section
+ * 4.4 two-level memory management).  A small multilayer perceptron predicts,
+ * per SV block and before a stage runs, log2 of the block's stream bytes
+ * after the stage and its most frequent codec mode, from features of the
+ * block's current compressed form and of the stage.  It is trained online
+ * with Adam on the labels each stage produces.
+ *
+ * Features (SV_FEATURES floats per block, from the directory headers only):
+ *   0 log2 stream bytes; 1-4 fraction of planes in mode ZERO, LZ, Q0,
+ *   VERBATIM; 5-12 / 13-20 width histogram (bins of 4 bits, last bin 28-32)
+ *   of packed real / imaginary planes; 21 all-zero chunk fraction; 22
+ *   mixed-sign fraction of packed planes; 23 / 24 mean width / 32 of packed
+ *   real / imaginary planes; 25 non-diagonal gates / 64; 26 diagonal gates /
+ *   64; 27 gates touching a global qubit / 64; 28 distinct local qubits
+ *   touched / b; 29 fused operations / 16; 30 stage index / stages;
+ *   31 log2(eb) / 32.
+ * A block's stream bytes are those of sv_block_stream without its 16-byte
+ * header (two 4-byte headers per chunk plus the record bodies). */
+#define SV_FEATURES 32
+#define SV_MLP_IN 32
+#define SV_MLP_HIDDEN 64
+#define SV_MLP_OUT 5
+/* parameters, float32: W1[64][32] b1[64] W2[64][64] b2[64] W3[5][64] b3[5]
+ * (row = output unit); ReLU after layers 1 and 2; output 0 also adds input 0
+ * (the block's current log2 bytes), so the untrained net predicts no change */
+#define SV_MLP_NPARAM 6597
+#define SV_MLP_BETA1 0.9f
+#define SV_MLP_BETA2 0.999f
+#define SV_MLP_EPS 1e-8f
+
+/* sv_block_features -- features of every block of the current state for the
+ * upcoming stage `stage` of plan p.  feats_dev: device float32 array of
+ * 2^(n-b) x SV_FEATURES.  Enqueued on the state's stream. */
+int sv_block_features(const sv_t *sv, const sv_plan_t *p, size_t stage, float *feats_dev);
+
+/* sv_block_labels -- per block of the current state: log2 of its stream
+ * bytes (log2_bytes_dev, float32) and its most frequent plane mode
+ * (mode_dev, int32 0..3; ties go to the lower mode).  Device arrays of
+ * 2^(n-b) entries.  Enqueued on the state's stream. */
+int sv_block_labels(const sv_t *sv, float *log2_bytes_dev, int32_t *mode_dev);
+
+/* mlp_forward -- out_dev[batch][5] = MLP(x_dev[batch][32]).  Device arrays;
+ * batch <= 2^30. */
+int mlp_forward(const float *params_dev, const float *x_dev, uint32_t batch, float *out_dev,
+                void *hip_stream);
+
+/* mlp_work_floats -- floats of work space mlp_loss_grad needs for a batch. */
+uint64_t mlp_work_floats(uint32_t batch);
+
+/* mlp_loss_grad -- mean loss over the batch, 0.5 (out0 - y)^2 + cross
+ * entropy of out1..4 against mode (clamped to 0..3), into loss_dev[0], and
+ * its gradient with respect to the parameters into grad_dev[SV_MLP_NPARAM].
+ * work_dev: mlp_work_floats(batch) floats.  1 <= batch <= 2^30.  Sums over
+ * the batch run in sample order (reproducible). */
+int mlp_loss_grad(const float *params_dev, const float *x_dev, const float *y_log2_bytes_dev,
+                  const int32_t *y_mode_dev, uint32_t batch, float *work_dev, float *grad_dev,
+                  float *loss_dev, void *hip_stream);
+
+/* mlp_adam_update -- one Adam step (beta1 SV_MLP_BETA1, beta2 SV_MLP_BETA2,
+ * eps SV_MLP_EPS, bias-corrected with step t >= 1) of params_dev with
+ * grad_dev; m_dev and v_dev are the moment arrays (zero before step 1). */
+int mlp_adam_update(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev,
+                    uint32_t step, float lr, void *hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,7 +51,9 @@ class sv_stage_stats_t(C.Structure):
 EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_destroy",
            "sv_mem_required", "sv_create", "sv_destroy", "sv_reset", "stage_apply_compressed",
            "sv_fidelity", "sv_export", "sv_amplitudes", "sv_footprint", "sv_block_stream",
-           "sv_debug_dump", "codec_encode_chunks", "codec_decode_chunks"]
+           "sv_debug_dump", "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
+           "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update"]
+SV_FEATURES, SV_MLP_NPARAM = 32, 6597
 
 _lib = None
 
@@ -84,6 +86,13 @@ def lib():
         L.sv_debug_dump.argtypes = [V, V, V]
         L.codec_encode_chunks.argtypes = [V, V, C.c_uint64, P(sv_config_t), V, V, V]
         L.codec_decode_chunks.argtypes = [V, C.c_uint64, P(sv_config_t), V, V, V]
+        L.sv_block_features.argtypes = [V, V, C.c_size_t, V]
+        L.sv_block_labels.argtypes = [V, V, V]
+        L.mlp_forward.argtypes = [V, V, C.c_uint32, V, V]
+        L.mlp_work_floats.argtypes = [C.c_uint32]
+        L.mlp_work_floats.restype = C.c_uint64
+        L.mlp_loss_grad.argtypes = [V, V, V, V, C.c_uint32, V, V, V, V]
+        L.mlp_adam_update.argtypes = [V, V, V, V, C.c_uint32, C.c_float, V]
         _lib = L
     return _lib
 
@@ -236,6 +245,25 @@ class State:
         _check(lib().sv_debug_dump(self.h, C.c_void_p(_ptr(re)) if re is not None else None,
                                    C.c_void_p(_ptr(im)) if im is not None else None))
 
+    @property
+    def n_blocks(self) -> int:
+        return 1 << (self.cfg.n - self.cfg.b)
+
+    def block_features(self, plan: Plan, stage: int):
+        """Predictor features of every block for the upcoming `stage`: [blocks][32]."""
+        import torch
+        out = torch.empty((self.n_blocks, SV_FEATURES), dtype=torch.float32, device=self.arena.device)
+        _check(lib().sv_block_features(self.h, plan.h, stage, C.c_void_p(_ptr(out))))
+        return out
+
+    def block_labels(self):
+        """(log2 stream bytes, most frequent plane mode) per block of the current state."""
+        import torch
+        lb = torch.empty(self.n_blocks, dtype=torch.float32, device=self.arena.device)
+        md = torch.empty(self.n_blocks, dtype=torch.int32, device=self.arena.device)
+        _check(lib().sv_block_labels(self.h, C.c_void_p(_ptr(lb)), C.c_void_p(_ptr(md))))
+        return lb, md
+
     def close(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.sv_destroy(self.h)
@@ -276,3 +304,56 @@ def slots_to_stream(slots_host: np.ndarray, sizes_host: np.ndarray, n: int, doma
     for c in range(nch):
         parts.append(slots_host[c * SV_CHUNK_SLOT_BYTES: c * SV_CHUNK_SLOT_BYTES + int(sizes_host[c])].tobytes())
     return b"".join(parts)
+
+
+# ---------------------------------------------------------------- block predictor
+
+def mlp_forward(params, X):
+    """[B][5] outputs of the block predictor for device features X [B][32]."""
+    import torch
+    X = X.contiguous()
+    out = torch.empty((X.shape[0], 5), dtype=torch.float32, device=X.device)
+    _check(lib().mlp_forward(C.c_void_p(_ptr(params)), C.c_void_p(_ptr(X)), X.shape[0],
+                             C.c_void_p(_ptr(out)), _stream()))
+    return out
+
+
+def mlp_loss_grad(params, X, y, mode):
+    """(mean loss [1], gradient [SV_MLP_NPARAM]) on device tensors."""
+    import torch
+    B = X.shape[0]
+    work = torch.empty(int(lib().mlp_work_floats(B)), dtype=torch.float32, device=X.device)
+    grad = torch.empty(SV_MLP_NPARAM, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    X, y, mode = X.contiguous(), y.contiguous(), mode.to(torch.int32).contiguous()
+    _check(lib().mlp_loss_grad(C.c_void_p(_ptr(params)), C.c_void_p(_ptr(X)), C.c_void_p(_ptr(y)),
+                               C.c_void_p(_ptr(mode)), B, C.c_void_p(_ptr(work)), C.c_void_p(_ptr(grad)),
+                               C.c_void_p(_ptr(loss)), _stream()))
+    return loss, grad
+
+
+def mlp_adam_update(params, grad, m, v, step: int, lr: float):
+    _check(lib().mlp_adam_update(C.c_void_p(_ptr(params)), C.c_void_p(_ptr(grad)), C.c_void_p(_ptr(m)),
+                                 C.c_void_p(_ptr(v)), step, float(lr), _stream()))
+
+
+class Predictor:
+    """Block-size / mode predictor trained online (device parameters and Adam
+    moments; every step runs in the library's kernels)."""
+
+    def __init__(self, params_host: np.ndarray, device: str = "cuda:0", lr: float = 1e-3):
+        import torch
+        self.params = torch.from_numpy(np.asarray(params_host, dtype=np.float32).copy()).to(device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self.lr = lr
+
+    def predict(self, X):
+        return mlp_forward(self.params, X)
+
+    def train_step(self, X, y, mode):
+        loss, grad = mlp_loss_grad(self.params, X, y, mode)
+        self.step += 1
+        mlp_adam_update(self.params, grad, self.m, self.v, self.step, self.lr)
+        return loss

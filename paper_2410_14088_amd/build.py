@@ -41,6 +41,9 @@ def build(verbose: bool = False) -> str:
     k_obj = os.path.join(BUILD, "bmq_kernels.o")
     _run([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "bmq_kernels.hip"), "-o", k_obj])
     objs.append(k_obj)
+    m_obj = os.path.join(BUILD, "bmq_mlp.o")
+    _run([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "bmq_mlp.hip"), "-o", m_obj])
+    objs.append(m_obj)
     r_obj = os.path.join(BUILD, "bmq_runtime.o")
     _run([HIPCC] + COMMON + ["-Wall", "-c", os.path.join(CSRC, "bmq_runtime.cpp"), "-o", r_obj])
     objs.append(r_obj)

@@ -157,5 +157,21 @@ def batch_mix(count: int = 512, seed0: int = 5000, nmin: int = 18, nmax: int = 2
     return out
 
 
+def mlp_init_params(seed: int) -> np.ndarray:
+    """Seeded initial parameters of the block predictor (32 -> 64 -> 64 -> 5):
+    hidden-layer weights U(-sqrt(6/fan_in), +sqrt(6/fan_in)) drawn layer by
+    layer in row-major order, output layer and biases zero (so the untrained
+    predictor says "same size as now, all modes equally likely"); float32,
+    packed W1 b1 W2 b2 W3 b3."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for rows, cols in ((64, 32), (64, 64)):
+        lim = math.sqrt(6.0 / cols)
+        parts.append(rng.uniform(-lim, lim, size=rows * cols))
+        parts.append(np.zeros(rows))
+    parts.append(np.zeros(5 * 64 + 5))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def count_gates(gates: Sequence[Gate]) -> int:
     return len(gates)

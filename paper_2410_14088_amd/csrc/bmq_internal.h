@@ -86,9 +86,26 @@ hipError_t launch_amplitudes(const uint64_t *dir, const uint8_t *pool, CodecPara
 hipError_t launch_fidelity(const uint64_t *dir, const uint8_t *pool, CodecParams cp,
                            uint64_t n_chunks, const double2 *ref, double *partials,
                            int n_partials, double *out5, hipStream_t s);
+// the 7 stage features of the block predictor (features 25..31)
+struct StageFeats {
+    float v[7];
+};
+// feats: n_blocks x 32 (or NULL); label_bytes / label_mode: n_blocks each
+// (both or neither); n_blocks < 2^31
+hipError_t launch_block_stats(const uint64_t *dir, uint64_t chunks_per_block, uint64_t n_blocks,
+                              const StageFeats &sf, float *feats, float *label_bytes,
+                              int32_t *label_mode, hipStream_t s);
 hipError_t launch_codec_encode(const float *re, const float *im, uint64_t n, CodecParams cp,
                                uint8_t *slots, uint32_t *sizes, hipStream_t s);
 hipError_t launch_codec_decode(const uint8_t *slots, uint64_t n, CodecParams cp,
                                float *re, float *im, hipStream_t s);
+
+// ---- block predictor (bmq_mlp.hip) ----
+uint64_t mlp_work_floats(uint32_t batch);
+hipError_t launch_mlp_forward(const float *P, const float *X, uint32_t batch, float *out, hipStream_t s);
+hipError_t launch_mlp_loss_grad(const float *P, const float *X, const float *y_bytes, const int32_t *y_mode,
+                                uint32_t batch, float *work, float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_adam(float *P, const float *grad, float *m, float *v, float lr, float beta1, float beta2,
+                           float eps, float c1, float c2, hipStream_t s);
 
 }  // namespace bmq

@@ -905,6 +905,90 @@ __global__ void amplitudes_kernel(const uint64_t *dir, const uint8_t *pool, Code
     }
 }
 
+// Per-block statistics of the compressed state, read from the directory
+// headers only (no decode): one workgroup per SV block.  Integer counts are
+// summed with LDS atomics (exact, so the result does not depend on order) and
+// turned into the predictor's 32 features, or into the labels of a block
+// (log2 of its stream bytes, most frequent plane mode).
+//   features: [0] log2 bytes  [1..4] mode fractions over planes
+//             [5..12] / [13..20] width histograms (bins of 4 bits) of the
+//             real / imaginary packed planes  [21] all-zero chunk fraction
+//             [22] mixed-sign fraction of packed planes  [23], [24] mean
+//             width / 32 of packed real / imaginary planes  [25..31] stage
+//             features supplied by the host
+enum { BS_MODE = 0, BS_WH_RE = 4, BS_WH_IM = 12, BS_PACKED_RE = 20, BS_PACKED_IM = 21, BS_ZERO = 22,
+       BS_MIXED = 23, BS_WSUM_RE = 24, BS_WSUM_IM = 25, BS_N = 26 };
+
+__global__ void block_stats_kernel(const uint64_t *dir, uint64_t chunks_per_block, StageFeats sf,
+                                   float *feats, float *label_bytes, int32_t *label_mode)
+{
+    __shared__ uint32_t cnt[BS_N];
+    __shared__ unsigned long long body;
+    if (threadIdx.x < BS_N) cnt[threadIdx.x] = 0;
+    if (threadIdx.x == 0) body = 0;
+    __syncthreads();
+    uint32_t c[BS_N];
+#pragma unroll
+    for (int i = 0; i < BS_N; ++i) c[i] = 0;
+    unsigned long long bytes = 0;
+    const uint64_t c0 = (uint64_t)blockIdx.x * chunks_per_block;
+    for (uint64_t j = threadIdx.x; j < chunks_per_block; j += blockDim.x) {
+        uint64_t e = dir[c0 + j];
+        if (e == kDirInvalid) e = 0;
+        const uint32_t h0 = (uint32_t)(e >> 40) & 0xFFFu, h1 = (uint32_t)(e >> 52);
+        const Layout L = layout_of(h0, h1);
+        bytes += L.size;
+        c[BS_MODE + L.m0]++;
+        c[BS_MODE + L.m1]++;
+        c[BS_ZERO] += (h0 | h1) == 0u;
+        const bool pk0 = L.m0 == M_LZ || L.m0 == M_Q0, pk1 = L.m1 == M_LZ || L.m1 == M_Q0;
+        if (pk0) {
+            c[BS_WH_RE + min(L.w0 >> 2, 7u)]++;
+            c[BS_PACKED_RE]++;
+            c[BS_WSUM_RE] += L.w0;
+            c[BS_MIXED] += ((h0 >> 8) & 3u) == 2u;
+        }
+        if (pk1) {
+            c[BS_WH_IM + min(L.w1 >> 2, 7u)]++;
+            c[BS_PACKED_IM]++;
+            c[BS_WSUM_IM] += L.w1;
+            c[BS_MIXED] += ((h1 >> 8) & 3u) == 2u;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < BS_N; ++i)
+        if (c[i]) atomicAdd(&cnt[i], c[i]);
+    if (bytes) atomicAdd(&body, bytes);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    // a chunk's record is its two 32-bit headers plus its body
+    const double total = (double)body + 8.0 * (double)chunks_per_block;
+    const float lb = (float)::log2(total);
+    if (label_bytes) {
+        uint32_t best = 0;
+        for (uint32_t m = 1; m < 4; ++m)
+            if (cnt[BS_MODE + m] > cnt[BS_MODE + best]) best = m;
+        label_bytes[blockIdx.x] = lb;
+        label_mode[blockIdx.x] = (int32_t)best;
+    }
+    if (feats) {
+        float *f = feats + (uint64_t)blockIdx.x * 32u;
+        const float planes = (float)(2 * chunks_per_block);
+        const float pre = (float)max(cnt[BS_PACKED_RE], 1u), pim = (float)max(cnt[BS_PACKED_IM], 1u);
+        f[0] = lb;
+        for (int m = 0; m < 4; ++m) f[1 + m] = (float)cnt[BS_MODE + m] / planes;
+        for (int i = 0; i < 8; ++i) {
+            f[5 + i] = (float)cnt[BS_WH_RE + i] / pre;
+            f[13 + i] = (float)cnt[BS_WH_IM + i] / pim;
+        }
+        f[21] = (float)cnt[BS_ZERO] / (float)chunks_per_block;
+        f[22] = (float)cnt[BS_MIXED] / (float)max(cnt[BS_PACKED_RE] + cnt[BS_PACKED_IM], 1u);
+        f[23] = (float)cnt[BS_WSUM_RE] / (32.0f * pre);
+        f[24] = (float)cnt[BS_WSUM_IM] / (32.0f * pim);
+        for (int i = 0; i < 7; ++i) f[25 + i] = sf.v[i];
+    }
+}
+
 // FP64 reductions: <ref|psi>, |psi|^2, |ref|^2, max |psi - ref| (componentwise).
 // Each block writes 5 partials; one block sums them in a fixed order.
 __global__ void fidelity_partial_kernel(const uint64_t *dir, const uint8_t *pool, CodecParams cp, uint64_t n_chunks,
@@ -1058,6 +1142,15 @@ hipError_t launch_fidelity(const uint64_t *dir, const uint8_t *pool, CodecParams
     hipLaunchKernelGGL(fidelity_partial_kernel, dim3((unsigned)n_partials), dim3(256), 0, s, dir, pool, cp,
                        n_chunks, ref, partials);
     hipLaunchKernelGGL(fidelity_final_kernel, dim3(1), dim3(64), 0, s, partials, n_partials, out5);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_stats(const uint64_t *dir, uint64_t chunks_per_block, uint64_t n_blocks,
+                              const StageFeats &sf, float *feats, float *label_bytes, int32_t *label_mode,
+                              hipStream_t s)
+{
+    hipLaunchKernelGGL(block_stats_kernel, dim3((unsigned)n_blocks), dim3(256), 0, s, dir, chunks_per_block, sf,
+                       feats, label_bytes, label_mode);
     return hipGetLastError();
 }
 

@@ -816,6 +816,89 @@ int sv_footprint(const sv_t *sv, uint64_t *record_bytes, uint64_t *dir_bytes)
     return SV_OK;
 }
 
+int sv_block_features(const sv_t *sv, const sv_plan_t *p, size_t stage, float *feats_dev)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (!p || !feats_dev) return fail(SV_ERR_INVALID, "NULL argument");
+    if (p->cfg.n_qubits != sv->cfg.n_qubits || p->cfg.block_qubits != sv->cfg.block_qubits)
+        return fail(SV_ERR_INVALID, "plan and state configurations differ");
+    if (stage >= p->stages.size()) return fail(SV_ERR_INVALID, "stage %zu outside the plan", stage);
+    if (sv->n - sv->b > 30) return fail(SV_ERR_UNSUPPORTED, "more than 2^30 blocks");
+    const StagePlan &st = p->stages[stage];
+    int nondiag = 0, diag = 0, global = 0;
+    uint64_t local_mask = 0;
+    for (size_t g = st.g0; g < st.g1; ++g) {
+        const GateRec &gr = p->gates[g];
+        (gr.diag ? diag : nondiag)++;
+        bool touches_global = false;
+        for (int i = 0; i < gr.nq; ++i) {
+            if (gr.q[i] >= sv->b) touches_global = true;
+            else local_mask |= 1ull << gr.q[i];
+        }
+        global += touches_global;
+    }
+    int nops = 0;
+    for (const auto &pp : st.passes) nops += pp.op_end - pp.op_begin;
+    bmq::StageFeats sf;
+    sf.v[0] = (float)(nondiag / 64.0);
+    sf.v[1] = (float)(diag / 64.0);
+    sf.v[2] = (float)(global / 64.0);
+    sf.v[3] = (float)((double)__builtin_popcountll(local_mask) / sv->b);
+    sf.v[4] = (float)(nops / 16.0);
+    sf.v[5] = (float)((double)stage / (double)p->stages.size());
+    sf.v[6] = (float)(std::log2(sv->cfg.eb) / 32.0);
+    HIP_TRY(bmq::launch_block_stats(sv->dir[sv->cur], 1ull << (sv->b - 6), 1ull << (sv->n - sv->b), sf, feats_dev,
+                                    nullptr, nullptr, sv->stream));
+    return SV_OK;
+}
+
+int sv_block_labels(const sv_t *sv, float *log2_bytes_dev, int32_t *mode_dev)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (!log2_bytes_dev || !mode_dev) return fail(SV_ERR_INVALID, "NULL argument");
+    if (sv->n - sv->b > 30) return fail(SV_ERR_UNSUPPORTED, "more than 2^30 blocks");
+    bmq::StageFeats sf{};
+    HIP_TRY(bmq::launch_block_stats(sv->dir[sv->cur], 1ull << (sv->b - 6), 1ull << (sv->n - sv->b), sf, nullptr,
+                                    log2_bytes_dev, mode_dev, sv->stream));
+    return SV_OK;
+}
+
+int mlp_forward(const float *params_dev, const float *x_dev, uint32_t batch, float *out_dev, void *hip_stream)
+{
+    if (!params_dev || (batch && (!x_dev || !out_dev))) return fail(SV_ERR_INVALID, "NULL pointer");
+    if (batch > (1u << 30)) return fail(SV_ERR_INVALID, "batch above 2^30");
+    if (!batch) return SV_OK;
+    HIP_TRY(bmq::launch_mlp_forward(params_dev, x_dev, batch, out_dev, (hipStream_t)hip_stream));
+    return SV_OK;
+}
+
+uint64_t mlp_work_floats(uint32_t batch) { return bmq::mlp_work_floats(batch); }
+
+int mlp_loss_grad(const float *params_dev, const float *x_dev, const float *y_log2_bytes_dev,
+                  const int32_t *y_mode_dev, uint32_t batch, float *work_dev, float *grad_dev, float *loss_dev,
+                  void *hip_stream)
+{
+    if (!params_dev || !x_dev || !y_log2_bytes_dev || !y_mode_dev || !work_dev || !grad_dev || !loss_dev)
+        return fail(SV_ERR_INVALID, "NULL pointer");
+    if (batch == 0 || batch > (1u << 30)) return fail(SV_ERR_INVALID, "batch must be in [1, 2^30]");
+    HIP_TRY(bmq::launch_mlp_loss_grad(params_dev, x_dev, y_log2_bytes_dev, y_mode_dev, batch, work_dev, grad_dev,
+                                      loss_dev, (hipStream_t)hip_stream));
+    return SV_OK;
+}
+
+int mlp_adam_update(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev, uint32_t step, float lr,
+                    void *hip_stream)
+{
+    if (!params_dev || !grad_dev || !m_dev || !v_dev) return fail(SV_ERR_INVALID, "NULL pointer");
+    if (step == 0) return fail(SV_ERR_INVALID, "Adam steps count from 1");
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(SV_ERR_INVALID, "learning rate must be finite and >= 0");
+    const double c1 = 1.0 / (1.0 - std::pow((double)SV_MLP_BETA1, (double)step));
+    const double c2 = 1.0 / (1.0 - std::pow((double)SV_MLP_BETA2, (double)step));
+    HIP_TRY(bmq::launch_mlp_adam(params_dev, grad_dev, m_dev, v_dev, lr, SV_MLP_BETA1, SV_MLP_BETA2, SV_MLP_EPS,
+                                 (float)c1, (float)c2, (hipStream_t)hip_stream));
+    return SV_OK;
+}
+
 int sv_block_stream(const sv_t *sv, uint64_t block, void *dst_host, uint64_t cap, uint64_t *bytes)
 {
     if (int rc = check_state(sv)) return rc;
