@@ -77,20 +77,33 @@ typedef struct {
 } sv_gate_t;
 
 typedef struct {
-    int32_t n_qubits;     /* n, 7..40 */
+    int32_t n_qubits;     /* n, 10..40 */
     int32_t block_qubits; /* b: SV block = 2^b amplitudes, 6 <= b <= n */
     int32_t inner_size;   /* Algorithm 1 inner size; threshold = max(inner, 2) */
     int32_t fuse_qubits;  /* widest dense fused gate, 1..5 */
     int32_t domain;       /* SV_DOMAIN_LIN or SV_DOMAIN_LOG */
     int32_t tile_qubits;  /* amplitudes per on-chip tile = 2^tile_qubits; 0 = default (12) */
     double eb;            /* absolute bound in the codec domain, > 0 */
-    uint64_t pool_bytes;  /* capacity of each compressed pool; 0 = worst case */
+    uint64_t pool_bytes;  /* device capacity of each compressed pool; 0 = worst case */
+    uint32_t flags;       /* SV_FLAG_* */
+    uint32_t reserved;    /* 0 */
 } sv_config_t;
+
+/* SV_FLAG_NO_SCRATCH: no uncompressed scratch planes in the arena (they are
+ * as large as the uncompressed state).  A stage that needs several tile
+ * passes then recompresses between passes, i.e. runs as several compressed
+ * sub-stages: less device memory, one more compression per extra pass. */
+#define SV_FLAG_NO_SCRATCH 1u
+/* SV_FLAG_NO_MFMA: apply dense 4- and 5-qubit fused operations with vector
+ * FMAs instead of the matrix cores (for comparison; both are float32). */
+#define SV_FLAG_NO_MFMA 2u
 
 /* Per-stage statistics (all counts over the whole state). */
 typedef struct {
-    uint64_t bytes_in;        /* compressed record bytes the stage read */
-    uint64_t bytes_out;       /* compressed record bytes the stage wrote */
+    uint64_t bytes_in;        /* compressed record bytes the stage read (first pass) */
+    uint64_t bytes_out;       /* compressed record bytes the stage wrote (last pass) */
+    uint64_t bytes_out_host;  /* of bytes_out, those placed in the host pool */
+    uint64_t inter_bytes;     /* compressed bytes written and read back between passes */
     uint64_t dir_bytes;       /* directory bytes read + written */
     uint64_t scratch_bytes;   /* uncompressed scratch bytes read + written */
     uint64_t zero_chunks_out; /* 64-amplitude chunks that are entirely zero */
@@ -105,6 +118,7 @@ typedef struct {
 
 typedef struct sv_plan sv_plan_t;
 typedef struct sv_state sv_t;
+typedef struct sv_graph sv_graph_t;
 
 /* Thread-local text of the last error (never NULL). */
 const char *sv_last_error(void);
@@ -136,9 +150,10 @@ void plan_destroy(sv_plan_t *p);
 
 /* ---------------------------------------------------------------- state
  * sv_mem_required -- bytes of device arena sv_create needs for cfg:
- * two chunk directories and two compressed record pools (the stage loop reads
- * one and writes the other), the uncompressed scratch planes for multi-pass
- * stages, the operation arena and reduction buffers. */
+ * two chunk directories and two compressed record pools of pool_bytes each
+ * (the stage loop reads one and writes the other), the uncompressed scratch
+ * planes for multi-pass stages (none with SV_FLAG_NO_SCRATCH), the operation
+ * arena and reduction buffers. */
 int sv_mem_required(const sv_config_t *cfg, uint64_t *bytes);
 
 /* sv_create -- bind the caller's device arena (dev_arena, dev_bytes; 256-byte
@@ -152,6 +167,18 @@ int sv_create(const sv_config_t *cfg, void *dev_arena, uint64_t dev_bytes,
 
 void sv_destroy(sv_t *sv);
 
+/* sv_attach_host_pool -- the second memory level (Section 4.4 two-level
+ * memory management): host_pinned is page-locked host memory the device can
+ * address (hipHostMalloc, or a pinned torch tensor), of host_bytes; it is
+ * split into two halves that pair with the two device pools.  When a device
+ * pool segment is full, a wave's record bodies go to the host half instead;
+ * directory offsets at and above pool_bytes address the host half.  Kernels
+ * read and write it in place over the host link.  The caller owns the memory
+ * and keeps it alive while the state exists.  Passing NULL, 0 detaches it.
+ * Errors: SV_ERR_INVALID (not device-addressable, too small, or the live
+ * state still has records in the attached host pool). */
+int sv_attach_host_pool(sv_t *sv, void *host_pinned, uint64_t host_bytes);
+
 /* sv_reset -- set an existing state back to |0...0> (as sv_create does),
  * enqueued on its stream without synchronising. */
 int sv_reset(sv_t *sv);
@@ -164,10 +191,42 @@ int sv_reset(sv_t *sv);
  * stats: NULL, or host array of count entries; when given, each stage's
  * kernels are bracketed by HIP events and the call synchronises.
  * The plan must have been made with a config whose n, b, domain and eb equal
- * the state's.  Errors: SV_ERR_INVALID, SV_ERR_CAPACITY (a pool overflowed:
- * raise pool_bytes), SV_ERR_HIP. */
+ * the state's.  Errors: SV_ERR_INVALID, SV_ERR_CAPACITY (the device pool and
+ * the host pool, if any, overflowed: raise pool_bytes or attach a larger host
+ * pool), SV_ERR_HIP. */
 int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t count,
                            sv_stage_stats_t *stats);
+
+/* sv_autotune -- choose tile_qubits (10..13, <= n) and fuse_qubits (1..5)
+ * for a circuit by measurement: each candidate is planned, run from |0...0>
+ * for its first probe_stages stages (all if 0) on the caller's arena and
+ * stream (once to warm up, once timed with HIP events), and the fastest wins.
+ * Candidates that overflow the pools are skipped.  The arena must hold
+ * sv_mem_required(cfg) bytes (the same for every candidate); its contents are
+ * overwritten.  best: receives cfg with the winning tile_qubits and
+ * fuse_qubits.  ms_all: NULL or 20 floats, entry (tile-10)*5 + (fuse-1) = the
+ * candidate's time in ms, NaN when not run.  Synchronises. */
+int sv_autotune(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, void *dev_arena,
+                uint64_t dev_bytes, void *hip_stream, size_t probe_stages, sv_config_t *best,
+                float *ms_all);
+
+/* ---------------------------------------------------------------- graphs
+ * sv_graph_capture -- record the stage loop of stages [first, first+count)
+ * of plan p on state sv (counter clearing plus every tile pass, as
+ * stage_apply_compressed would enqueue them) into a HIP graph, without running
+ * it.  At most 1024 pass launches.  The graph is tied to sv, to p's uploaded
+ * operations and to the state's current pool copy: it may be replayed when
+ * the state is in that copy again (after sv_reset, or after an even number
+ * of compressed passes).  Not available while a debug dump is set.
+ * sv_graph_launch -- replay on the state's stream, asynchronously.  The
+ * replay's overflow check and footprint update happen at the next
+ * sv_graph_sync, stage_apply_compressed, sv_footprint or another replay.
+ * sv_graph_sync -- synchronise and run that check (SV_ERR_CAPACITY on
+ * overflow).  sv_graph_destroy -- free the graph (p and sv must still exist). */
+int sv_graph_capture(sv_t *sv, const sv_plan_t *p, size_t first, size_t count, sv_graph_t **out);
+int sv_graph_launch(sv_t *sv, sv_graph_t *g);
+int sv_graph_sync(sv_t *sv);
+void sv_graph_destroy(sv_graph_t *g);
 
 /* sv_fidelity -- FP64 reductions on the device (Section 5.3 fidelity):
  *   fidelity    = |<ref|psi>|^2 / (|ref|^2 |psi|^2)   (the squared form;
@@ -188,8 +247,10 @@ int sv_export(const sv_t *sv, uint64_t start, uint64_t count, void *dst_dev);
 int sv_amplitudes(const sv_t *sv, const uint64_t *idx_dev, uint64_t k, void *out_dev);
 
 /* sv_footprint -- current compressed footprint (Section 5.4 memory metric):
- * record bytes in the live pool and directory bytes.  Synchronises. */
-int sv_footprint(const sv_t *sv, uint64_t *record_bytes, uint64_t *dir_bytes);
+ * record bytes of the live state copy (device and host pools together), of
+ * those the bytes in the host pool, and directory bytes.  Synchronises.
+ * Any output pointer may be NULL. */
+int sv_footprint(const sv_t *sv, uint64_t *record_bytes, uint64_t *host_bytes, uint64_t *dir_bytes);
 
 /* sv_block_stream -- the canonical stream of SV block `block` (2^b
  * amplitudes): a 16-byte block header (u8 0x51, u8 version 1, u8 domain,

@@ -18,6 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "_build", "libbmq.so")
 
 SV_DOMAIN_LIN, SV_DOMAIN_LOG = 0, 1
+SV_FLAG_NO_SCRATCH = 1
+SV_FLAG_NO_MFMA = 2
 SV_CHUNK_SLOT_BYTES = 576
 KIND = {k: i for i, k in enumerate(
     ["H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "U3", "CX", "CZ", "CP", "RZZ"])}
@@ -38,21 +40,23 @@ class sv_gate_t(C.Structure):
 class sv_config_t(C.Structure):
     _fields_ = [("n_qubits", C.c_int32), ("block_qubits", C.c_int32), ("inner_size", C.c_int32),
                 ("fuse_qubits", C.c_int32), ("domain", C.c_int32), ("tile_qubits", C.c_int32),
-                ("eb", C.c_double), ("pool_bytes", C.c_uint64)]
+                ("eb", C.c_double), ("pool_bytes", C.c_uint64), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class sv_stage_stats_t(C.Structure):
-    _fields_ = [("bytes_in", C.c_uint64), ("bytes_out", C.c_uint64), ("dir_bytes", C.c_uint64),
+    _fields_ = [("bytes_in", C.c_uint64), ("bytes_out", C.c_uint64), ("bytes_out_host", C.c_uint64),
+                ("inter_bytes", C.c_uint64), ("dir_bytes", C.c_uint64),
                 ("scratch_bytes", C.c_uint64), ("zero_chunks_out", C.c_uint64),
                 ("mode_hist", C.c_uint64 * 4), ("passes", C.c_uint32), ("n_ops", C.c_uint32),
                 ("n_gates", C.c_uint32), ("n_inner", C.c_uint32), ("ms", C.c_float), ("pad", C.c_uint32)]
 
 
 EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_destroy",
-           "sv_mem_required", "sv_create", "sv_destroy", "sv_reset", "stage_apply_compressed",
+           "sv_mem_required", "sv_create", "sv_destroy", "sv_attach_host_pool", "sv_reset", "stage_apply_compressed",
            "sv_fidelity", "sv_export", "sv_amplitudes", "sv_footprint", "sv_block_stream",
            "sv_debug_dump", "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
-           "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update"]
+           "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
+           "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune"]
 SV_FEATURES, SV_MLP_NPARAM = 32, 6597
 
 _lib = None
@@ -77,16 +81,24 @@ def lib():
         L.sv_destroy.argtypes = [V]
         L.sv_destroy.restype = None
         L.sv_reset.argtypes = [V]
+        L.sv_attach_host_pool.argtypes = [V, V, C.c_uint64]
         L.stage_apply_compressed.argtypes = [V, V, C.c_size_t, C.c_size_t, V]
         L.sv_fidelity.argtypes = [V, V, P(C.c_double), P(C.c_double), P(C.c_double)]
         L.sv_export.argtypes = [V, C.c_uint64, C.c_uint64, V]
         L.sv_amplitudes.argtypes = [V, V, C.c_uint64, V]
-        L.sv_footprint.argtypes = [V, P(C.c_uint64), P(C.c_uint64)]
+        L.sv_footprint.argtypes = [V, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
         L.sv_block_stream.argtypes = [V, C.c_uint64, V, C.c_uint64, P(C.c_uint64)]
         L.sv_debug_dump.argtypes = [V, V, V]
         L.codec_encode_chunks.argtypes = [V, V, C.c_uint64, P(sv_config_t), V, V, V]
         L.codec_decode_chunks.argtypes = [V, C.c_uint64, P(sv_config_t), V, V, V]
         L.sv_block_features.argtypes = [V, V, C.c_size_t, V]
+        L.sv_graph_capture.argtypes = [V, V, C.c_size_t, C.c_size_t, P(V)]
+        L.sv_autotune.argtypes = [V, C.c_size_t, P(sv_config_t), V, C.c_uint64, V, C.c_size_t, P(sv_config_t),
+                                  P(C.c_float)]
+        L.sv_graph_launch.argtypes = [V, V]
+        L.sv_graph_sync.argtypes = [V]
+        L.sv_graph_destroy.argtypes = [V]
+        L.sv_graph_destroy.restype = None
         L.sv_block_labels.argtypes = [V, V, V]
         L.mlp_forward.argtypes = [V, V, C.c_uint32, V, V]
         L.mlp_work_floats.argtypes = [C.c_uint32]
@@ -112,10 +124,11 @@ class Config:
     eb: float = 1e-6
     tile: int = 0
     pool_bytes: int = 0
+    flags: int = 0
 
     def c(self) -> sv_config_t:
         return sv_config_t(self.n, self.b, self.inner, self.fuse, self.domain, self.tile,
-                           float(self.eb), int(self.pool_bytes))
+                           float(self.eb), int(self.pool_bytes), int(self.flags), 0)
 
 
 def gate_array(gates) -> "C.Array":
@@ -196,7 +209,8 @@ class State:
             return None
         out = []
         for s in st[:count]:
-            out.append(dict(bytes_in=s.bytes_in, bytes_out=s.bytes_out, dir_bytes=s.dir_bytes,
+            out.append(dict(bytes_in=s.bytes_in, bytes_out=s.bytes_out, bytes_out_host=s.bytes_out_host,
+                            inter_bytes=s.inter_bytes, dir_bytes=s.dir_bytes,
                             scratch_bytes=s.scratch_bytes, zero_chunks_out=s.zero_chunks_out,
                             mode_hist=list(s.mode_hist), passes=s.passes, n_ops=s.n_ops,
                             n_gates=s.n_gates, n_inner=s.n_inner, ms=s.ms))
@@ -204,6 +218,17 @@ class State:
 
     def reset(self):
         _check(lib().sv_reset(self.h))
+
+    def capture(self, plan: Plan, first: int = 0, count: Optional[int] = None) -> "Graph":
+        """Record stages [first, first+count) as a HIP graph (nothing runs)."""
+        if count is None:
+            count = plan.n_stages - first
+        h = C.c_void_p()
+        _check(lib().sv_graph_capture(self.h, plan.h, first, count, C.byref(h)))
+        return Graph(h, self, plan)
+
+    def graph_sync(self):
+        _check(lib().sv_graph_sync(self.h))
 
     def fidelity(self, ref=None):
         """ref: torch complex128 tensor on the device (2^n) or None."""
@@ -228,9 +253,21 @@ class State:
         return out
 
     def footprint(self):
-        r, d = C.c_uint64(), C.c_uint64()
-        _check(lib().sv_footprint(self.h, C.byref(r), C.byref(d)))
-        return r.value, d.value
+        """(record bytes, of those in the host pool, directory bytes)"""
+        r, h, d = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(lib().sv_footprint(self.h, C.byref(r), C.byref(h), C.byref(d)))
+        return r.value, h.value, d.value
+
+    def attach_host_pool(self, nbytes: int):
+        """Second memory level: a pinned host buffer of nbytes (0 detaches)."""
+        import torch
+        if nbytes:
+            buf = torch.empty(int(nbytes), dtype=torch.uint8, pin_memory=True)
+            _check(lib().sv_attach_host_pool(self.h, C.c_void_p(buf.data_ptr()), int(nbytes)))
+        else:
+            buf = None
+            _check(lib().sv_attach_host_pool(self.h, None, 0))
+        self.host_pool = buf
 
     def block_stream(self, block: int) -> bytes:
         nb = C.c_uint64()
@@ -267,6 +304,44 @@ class State:
     def close(self):
         if getattr(self, "h", None) and _lib is not None:
             _lib.sv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+
+def autotune(gates, cfg: Config, probe_stages: int = 0, device: str = "cuda:0"):
+    """Measure tile / fusion candidates on the device; returns (best Config,
+    {(tile, fuse): ms})."""
+    import torch
+    need = C.c_uint64()
+    _check(lib().sv_mem_required(C.byref(cfg.c()), C.byref(need)))
+    arena = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=device)
+    base = _ptr(arena)
+    off = (-base) % 256
+    arr = gate_array(gates)
+    best = sv_config_t()
+    ms = (C.c_float * 20)()
+    _check(lib().sv_autotune(C.cast(arr, C.c_void_p), len(gates), C.byref(cfg.c()), C.c_void_p(base + off),
+                             int(need.value), _stream(), probe_stages, C.byref(best), ms))
+    table = {(10 + i // 5, 1 + i % 5): ms[i] for i in range(20) if ms[i] == ms[i]}
+    out = Config(n=best.n_qubits, b=best.block_qubits, inner=best.inner_size, fuse=best.fuse_qubits,
+                 domain=best.domain, eb=best.eb, tile=best.tile_qubits, pool_bytes=best.pool_bytes, flags=best.flags)
+    return out, table
+
+
+class Graph:
+    """A captured stage loop; replay with launch()."""
+
+    def __init__(self, h, state: "State", plan: Plan):
+        self.h, self.state, self.plan = h, state, plan
+
+    def launch(self):
+        _check(lib().sv_graph_launch(self.state.h, self.h))
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.sv_graph_destroy(self.h)
             self.h = None
 
     def __del__(self):

@@ -34,11 +34,17 @@ struct OpDesc {
     uint32_t pad;
 };
 
-// Per-stage device counters.  The output pool of a stage is split into
+// Per-launch device counters.  The device pool a pass writes is split into
 // n_seg segments (workgroup i uses segment i mod n_seg), each with its own
 // cursor and statistics, so that no single address takes every workgroup's
-// atomics.  A stage's counter block is kSegments x C_NUM words.
-enum Counter : int { C_CURSOR = 0, C_OVERFLOW = 1, C_ZERO_CHUNKS = 2, C_MODE0 = 3, C_NUM = 8 };
+// atomics.  A wave whose segment is full spills its bodies to the host pool
+// (second memory level) through one cursor, C_HOST_CURSOR of segment 0.
+// A launch's counter block is kSegments x C_NUM words; C_MODE0 packs the
+// ZERO | LZ counts, C_MODE0 + 2 the Q0 | VERBATIM counts (32 bits each).
+enum Counter : int {
+    C_CURSOR = 0, C_OVERFLOW = 1, C_ZERO_CHUNKS = 2, C_MODE0 = 3, C_DEV_BYTES = 4, C_HOST_BYTES = 6,
+    C_HOST_CURSOR = 7, C_NUM = 8
+};
 constexpr int kSegments = 256;
 constexpr uint32_t kMaxBodyBytes = 552;         // two planes, worst case
 
@@ -52,6 +58,15 @@ struct CodecParams {
     int32_t code_ok;
 };
 
+// Where the record bodies of one state copy live: directory offsets below
+// cap address the device pool, offsets cap + h address byte h of the host
+// pool (pinned host memory the device reads and writes directly).
+struct PoolView {
+    const uint8_t *dev;
+    const uint8_t *host;
+    uint64_t cap;
+};
+
 struct PassArgs {
     int32_t n, t;
     int32_t tileq[16];        // tile position -> global qubit (positions 0..5 are qubits 0..5)
@@ -62,8 +77,12 @@ struct PassArgs {
     CodecParams cp;
     const uint64_t *dir_in;
     const uint8_t *pool_in;
+    const uint8_t *host_in;
     uint64_t *dir_out;
     uint8_t *pool_out;
+    uint8_t *host_out;
+    uint64_t pool_cap;              // device pool bytes (offsets at and above go to the host pool)
+    uint64_t host_cap;              // host pool bytes per state copy (0: no host level)
     uint64_t seg_cap;               // bytes per output pool segment
     int32_t n_seg;                  // segments in use (power of two <= kSegments)
     unsigned long long *counters;   // this stage's block of kSegments x C_NUM
@@ -71,6 +90,7 @@ struct PassArgs {
     const OpDesc *ops;
     const float2 *opdata;
     float *dump_re, *dump_im;
+    int32_t mfma;                   // dense 4- and 5-qubit operations on the matrix cores
 };
 
 // ---- launch wrappers (bmq_kernels.hip) ----
@@ -78,12 +98,12 @@ hipError_t launch_pass(const PassArgs &a, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_init_state(uint64_t *dir, uint64_t n_chunks, uint8_t *pool,
                              unsigned long long *counters, CodecParams cp, hipStream_t s);
-hipError_t launch_export(const uint64_t *dir, const uint8_t *pool, CodecParams cp,
+hipError_t launch_export(const uint64_t *dir, const PoolView &pv, CodecParams cp,
                          uint64_t chunk0, uint64_t n_chunks, float2 *dst, hipStream_t s);
-hipError_t launch_amplitudes(const uint64_t *dir, const uint8_t *pool, CodecParams cp,
+hipError_t launch_amplitudes(const uint64_t *dir, const PoolView &pv, CodecParams cp,
                              const uint64_t *idx, uint64_t k, uint64_t n_chunks, float2 *dst,
                              hipStream_t s);
-hipError_t launch_fidelity(const uint64_t *dir, const uint8_t *pool, CodecParams cp,
+hipError_t launch_fidelity(const uint64_t *dir, const PoolView &pv, CodecParams cp,
                            uint64_t n_chunks, const double2 *ref, double *partials,
                            int n_partials, double *out5, hipStream_t s);
 // the 7 stage features of the block predictor (features 25..31)

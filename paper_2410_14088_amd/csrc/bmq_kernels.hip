@@ -382,11 +382,17 @@ __device__ __forceinline__ void decode_regs(const ChunkRegs &R, const CodecParam
     im = decode_plane(R.h1, R.a1, R.sm1, R.zm1, R.lo1, R.hi1, cp);
 }
 
-__device__ __forceinline__ ChunkRegs load_entry(uint64_t e, const uint8_t *pool)
+__device__ __forceinline__ const uint8_t *body_ptr(const uint8_t *dev, const uint8_t *host, uint64_t cap,
+                                                   uint64_t off)
+{
+    return off < cap ? dev + off : host + (off - cap);
+}
+
+__device__ __forceinline__ ChunkRegs load_entry(uint64_t e, const PoolView &pv)
 {
     if (e == kDirInvalid) e = 0;          // a lost chunk reads as zero
     const uint32_t h0 = (uint32_t)(e >> 40) & 0xFFFu, h1 = (uint32_t)(e >> 52);
-    return load_body(h0, h1, pool + (e & kDirOffsetMask));
+    return load_body(h0, h1, body_ptr(pv.dev, pv.host, pv.cap, e & kDirOffsetMask));
 }
 
 // Assemble a body (and optionally the two headers in front of it) in the
@@ -507,6 +513,80 @@ __device__ void apply_dense(float *sre, float *sim, const OpDesc &op, const floa
             sre[i0 + o] = br;
             sim[i0 + o] = bi;
         }
+    }
+}
+
+// Dense operation of K = 4 or 5 qubits on the matrix cores.  Over a tile the
+// operation is the real product [Re out; Im out] = A [Re in; Im in] with the
+// 2D x 2D block matrix A = [[Re M, -Im M], [Im M, Re M]] (D = 2^K) and one
+// column per group of D amplitudes.  v_mfma_f32_32x32x2_f32 multiplies a
+// 32 x 2 slice of A (lane l: row l % 32, column l / 32) by a 2 x 32 slice of
+// the columns (lane l: row l / 32, column l % 32) into a 32 x 32 block (lane
+// l, register v: row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32), full
+// float32 arithmetic.  Each wave takes column blocks of 32 groups; a group's
+// amplitudes are read from LDS before any of them is written back, and the
+// groups of different waves are disjoint, so the update is in place.
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+
+// element (i, k) of A for a D x D complex matrix M (row major)
+template <int D>
+__device__ __forceinline__ float block_elem(const float2 *__restrict__ M, int i, int k)
+{
+    const int r = i & (D - 1), c = k & (D - 1);
+    const float2 m = M[r * D + c];
+    if (i < D) return k < D ? m.x : -m.y;
+    return k < D ? m.y : m.x;
+}
+
+template <int K, int TILE, int NT>
+__device__ void apply_dense_mfma(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M)
+{
+    constexpr int D = 1 << K, G = TILE >> K, RB = 2 * D / 32, STEPS = D;   // row blocks, k-steps of 2
+    static_assert(G % 32 == 0, "column blocks of 32 groups");
+    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
+    const int hi = lane >> 5, col = lane & 31;
+    int pos[K], sp[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) { pos[j] = op.pos[j]; sp[j] = pos[j]; }
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+#pragma unroll
+        for (int j = 0; j + 1 < K - i; ++j)
+            if (sp[j] > sp[j + 1]) { const int t = sp[j]; sp[j] = sp[j + 1]; sp[j + 1] = t; }
+    // amplitude offset of row r of a group: r's bits deposited at the op positions
+    auto row_off = [&](int r) {
+        uint32_t o = 0;
+#pragma unroll
+        for (int j = 0; j < K; ++j) o |= (uint32_t)((r >> j) & 1) << pos[j];
+        return o;
+    };
+    for (int cb = wave * 32; cb < G; cb += (NT / 64) * 32) {
+        uint32_t base = (uint32_t)(cb + col);
+#pragma unroll
+        for (int j = 0; j < K; ++j) base = ((base >> sp[j]) << (sp[j] + 1)) | (base & ((1u << sp[j]) - 1u));
+        floatx16 acc[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[rb][v] = 0.0f;
+#pragma unroll 4
+        for (int st = 0; st < STEPS; ++st) {
+            const int k = 2 * st + hi;                     // k < D exactly when st < D / 2
+            const uint32_t idx = base | row_off(k & (D - 1));
+            const float bv = (st < D / 2) ? sre[idx] : sim[idx];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(block_elem<D>(M, rb * 32 + col, k), bv, acc[rb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = rb * 32 + 8 * (v >> 2) + 4 * hi + (v & 3);   // output row of A
+                const uint32_t idx = base | row_off(i & (D - 1));
+                if (i < D) sre[idx] = acc[rb][v];
+                else sim[idx] = acc[rb][v];
+            }
     }
 }
 
@@ -651,8 +731,8 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
         if (e == kDirInvalid) e = 0;                      // a lost chunk reads as zero
         const uint32_t eh0 = (uint32_t)(e >> 40) & 0xFFFu, eh1 = (uint32_t)(e >> 52);
         const Layout Lv = layout_of(eh0, eh1);
-        const uint64_t boff = e & kDirOffsetMask;
-        const uint32_t *bv = (const uint32_t *)(a.pool_in + boff);
+        const uint64_t boff = (uint64_t)body_ptr(a.pool_in, a.host_in, a.pool_cap, e & kDirOffsetMask);
+        const uint32_t *bv = (const uint32_t *)boff;
         const int32_t av0 = Lv.lz0 ? (int32_t)bv[0] : 0;              // anchors, one chunk per lane
         const int32_t av1 = Lv.lz1 ? (int32_t)bv[Lv.lz0 ? 1 : 0] : 0;
         const uint32_t pay = pack_pay(Lv);
@@ -666,7 +746,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
 #pragma unroll
             for (int u = 0; u < G; ++u) {
                 const int i = i0 + u;
-                const uint32_t *b = (const uint32_t *)(a.pool_in + lane_u64(boff, i));
+                const uint32_t *b = (const uint32_t *)lane_u64(boff, i);
                 const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)pay, i);
                 const uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)msk, i);
                 P[u] = p;
@@ -716,8 +796,14 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
             case 1: apply_dense<1, L::TILE, NT>(s.re, s.im, op, data); break;
             case 2: apply_dense<2, L::TILE, NT>(s.re, s.im, op, data); break;
             case 3: apply_dense<3, L::TILE, NT>(s.re, s.im, op, data); break;
-            case 4: apply_dense<4, L::TILE, NT>(s.re, s.im, op, data); break;
-            default: apply_dense<5, L::TILE, NT>(s.re, s.im, op, data); break;
+            case 4:
+                if (a.mfma) apply_dense_mfma<4, L::TILE, NT>(s.re, s.im, op, data);
+                else apply_dense<4, L::TILE, NT>(s.re, s.im, op, data);
+                break;
+            default:
+                if (a.mfma) apply_dense_mfma<5, L::TILE, NT>(s.re, s.im, op, data);
+                else apply_dense<5, L::TILE, NT>(s.re, s.im, op, data);
+                break;
             }
         }
         __syncthreads();
@@ -786,15 +872,26 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
     unsigned long long got = 0;
     if (lane == 0 && total) got = atomicAdd(&cnt[C_CURSOR], (unsigned long long)total);
     const uint64_t b = uniform_u64(got);
-    const bool overflow = total && b + total > a.seg_cap;
+    uint64_t wave_off = (uint64_t)seg * a.seg_cap + b;       // directory offset of the wave's first body
+    bool overflow = false;
+    if (total && b + total > a.seg_cap) {
+        // segment full: the wave's bodies go to the host pool, or are lost
+        unsigned long long goth = 0;
+        if (lane == 0 && a.host_cap) goth = atomicAdd(&a.counters[C_HOST_CURSOR], (unsigned long long)total);
+        const uint64_t hb = uniform_u64(goth);
+        overflow = !a.host_cap || hb + total > a.host_cap;
+        wave_off = a.pool_cap + hb;
+    }
     if (lane == 0 && overflow) atomicOr(&cnt[C_OVERFLOW], 1ull);
-    const uint64_t off = (uint64_t)seg * a.seg_cap + b + (incl - Lv.size);
+    if (lane == 0 && total && !overflow)
+        atomicAdd(&cnt[wave_off < a.pool_cap ? C_DEV_BYTES : C_HOST_BYTES], (unsigned long long)total);
+    const uint64_t off = wave_off + (incl - Lv.size);
     uint64_t entry = 0;
     if (h0 | h1) entry = overflow ? kDirInvalid : (off | ((uint64_t)h0 << 40) | ((uint64_t)h1 << 52));
 
     if (!overflow) {
         // anchors and masks: each lane writes its own chunk's
-        uint32_t *bw = (uint32_t *)(a.pool_out + off);
+        uint32_t *bw = (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, off);
         if (mine && Lv.lz0) bw[0] = av0;
         if (mine && Lv.lz1) bw[Lv.lz0 ? 1 : 0] = av1;
         if (mine && Lv.hs0) { bw[Lv.off_sm0 >> 2] = s0l; bw[(Lv.off_sm0 >> 2) + 1] = s0h; }
@@ -810,7 +907,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
             const uint32_t m0 = (p >> 28) & 3u, m1 = (p >> 30) & 3u;
             if (m0 == M_ZERO && m1 == M_ZERO) continue;
             const int c = c0 + i;
-            uint32_t *dst = (uint32_t *)(a.pool_out + lane_u64(off, i));
+            uint32_t *dst = (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, lane_u64(off, i));
             const uint32_t f0 = __float_as_uint(s.re[(c << 6) + lane]);
             const uint32_t f1 = __float_as_uint(s.im[(c << 6) + lane]);
             const uint32_t w0 = (p >> 16) & 63u, w1 = (p >> 22) & 63u;
@@ -871,25 +968,25 @@ __global__ void init_state_kernel(uint64_t *dir, uint8_t *pool, unsigned long lo
     }
 }
 
-__device__ __forceinline__ void decode_chunk(const uint64_t *dir, const uint8_t *pool, const CodecParams &cp,
+__device__ __forceinline__ void decode_chunk(const uint64_t *dir, const PoolView &pv, const CodecParams &cp,
                                              uint64_t chunk, float &re, float &im)
 {
-    const ChunkRegs R = load_entry(uniform_u64(dir[chunk]), pool);
+    const ChunkRegs R = load_entry(uniform_u64(dir[chunk]), pv);
     decode_regs(R, cp, re, im);
 }
 
-__global__ void export_kernel(const uint64_t *dir, const uint8_t *pool, CodecParams cp, uint64_t chunk0,
+__global__ void export_kernel(const uint64_t *dir, PoolView pv, CodecParams cp, uint64_t chunk0,
                               uint64_t n_chunks, float2 *dst)
 {
     const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
     for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks; c += nw) {
         float re, im;
-        decode_chunk(dir, pool, cp, chunk0 + c, re, im);
+        decode_chunk(dir, pv, cp, chunk0 + c, re, im);
         dst[c * 64 + lane_id()] = make_float2(re, im);
     }
 }
 
-__global__ void amplitudes_kernel(const uint64_t *dir, const uint8_t *pool, CodecParams cp, const uint64_t *idx,
+__global__ void amplitudes_kernel(const uint64_t *dir, PoolView pv, CodecParams cp, const uint64_t *idx,
                                   uint64_t k, uint64_t n_chunks, float2 *dst)
 {
     const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
@@ -900,7 +997,7 @@ __global__ void amplitudes_kernel(const uint64_t *dir, const uint8_t *pool, Code
             continue;
         }
         float re, im;
-        decode_chunk(dir, pool, cp, xu >> 6, re, im);
+        decode_chunk(dir, pv, cp, xu >> 6, re, im);
         if ((uint64_t)lane_id() == (xu & 63ull)) dst[j] = make_float2(re, im);
     }
 }
@@ -991,7 +1088,7 @@ __global__ void block_stats_kernel(const uint64_t *dir, uint64_t chunks_per_bloc
 
 // FP64 reductions: <ref|psi>, |psi|^2, |ref|^2, max |psi - ref| (componentwise).
 // Each block writes 5 partials; one block sums them in a fixed order.
-__global__ void fidelity_partial_kernel(const uint64_t *dir, const uint8_t *pool, CodecParams cp, uint64_t n_chunks,
+__global__ void fidelity_partial_kernel(const uint64_t *dir, PoolView pv, CodecParams cp, uint64_t n_chunks,
                                         const double2 *ref, double *partials)
 {
     __shared__ double sh[5][16];
@@ -1001,7 +1098,7 @@ __global__ void fidelity_partial_kernel(const uint64_t *dir, const uint8_t *pool
     const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
     for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; c < n_chunks; c += nw) {
         float re, im;
-        decode_chunk(dir, pool, cp, c, re, im);
+        decode_chunk(dir, pv, cp, c, re, im);
         const double pr = re, pi = im;
         np += pr * pr + pi * pi;
         if (ref) {
@@ -1120,26 +1217,26 @@ hipError_t launch_init_state(uint64_t *dir, uint64_t n_chunks, uint8_t *pool, un
     return hipGetLastError();
 }
 
-hipError_t launch_export(const uint64_t *dir, const uint8_t *pool, CodecParams cp, uint64_t chunk0,
+hipError_t launch_export(const uint64_t *dir, const PoolView &pv, CodecParams cp, uint64_t chunk0,
                          uint64_t n_chunks, float2 *dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(export_kernel, dim3(grid_for(n_chunks, 4)), dim3(256), 0, s, dir, pool, cp, chunk0,
+    hipLaunchKernelGGL(export_kernel, dim3(grid_for(n_chunks, 4)), dim3(256), 0, s, dir, pv, cp, chunk0,
                        n_chunks, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_amplitudes(const uint64_t *dir, const uint8_t *pool, CodecParams cp, const uint64_t *idx,
+hipError_t launch_amplitudes(const uint64_t *dir, const PoolView &pv, CodecParams cp, const uint64_t *idx,
                              uint64_t k, uint64_t n_chunks, float2 *dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(amplitudes_kernel, dim3(grid_for(k, 4)), dim3(256), 0, s, dir, pool, cp, idx, k, n_chunks,
+    hipLaunchKernelGGL(amplitudes_kernel, dim3(grid_for(k, 4)), dim3(256), 0, s, dir, pv, cp, idx, k, n_chunks,
                        dst);
     return hipGetLastError();
 }
 
-hipError_t launch_fidelity(const uint64_t *dir, const uint8_t *pool, CodecParams cp, uint64_t n_chunks,
+hipError_t launch_fidelity(const uint64_t *dir, const PoolView &pv, CodecParams cp, uint64_t n_chunks,
                            const double2 *ref, double *partials, int n_partials, double *out5, hipStream_t s)
 {
-    hipLaunchKernelGGL(fidelity_partial_kernel, dim3((unsigned)n_partials), dim3(256), 0, s, dir, pool, cp,
+    hipLaunchKernelGGL(fidelity_partial_kernel, dim3((unsigned)n_partials), dim3(256), 0, s, dir, pv, cp,
                        n_chunks, ref, partials);
     hipLaunchKernelGGL(fidelity_final_kernel, dim3(1), dim3(64), 0, s, partials, n_partials, out5);
     return hipGetLastError();

@@ -45,8 +45,8 @@ int fail(int code, const char *fmt, ...)
 
 constexpr int kDefaultTile = 12;
 constexpr int kMaxDiagQubits = bmq::kMaxDiagQubits;
-constexpr size_t kMaxStagesPerBatch = 1024;
-constexpr size_t kStageCounters = (size_t)bmq::kSegments * bmq::C_NUM;   // words per stage
+constexpr size_t kMaxLaunchesPerBatch = 1024;   // counter blocks of one batch of pass launches
+constexpr size_t kStageCounters = (size_t)bmq::kSegments * bmq::C_NUM;   // words per launch
 constexpr int kPartials = 1024;
 constexpr uint64_t kOpsArenaBytes = 64ull << 20;
 
@@ -157,7 +157,11 @@ struct sv_state {
     uint64_t *dir[2] = {nullptr, nullptr};
     uint8_t *pool[2] = {nullptr, nullptr};
     uint64_t pool_cap = 0;
-    float *scr_re = nullptr, *scr_im = nullptr;
+    float *scr_re = nullptr, *scr_im = nullptr;   // NULL with SV_FLAG_NO_SCRATCH
+    uint8_t *host[2] = {nullptr, nullptr};        // host pool halves (second memory level), device view
+    uint8_t *host_h[2] = {nullptr, nullptr};      // the same halves, host view
+    uint64_t host_cap = 0;                        // usable bytes per half
+    uint64_t live_host = 0;                       // of live_bytes, those in the host pool
     unsigned long long *counters = nullptr;
     double *partials = nullptr;
     double *out5 = nullptr;
@@ -168,11 +172,23 @@ struct sv_state {
     float *dump_re = nullptr, *dump_im = nullptr;
     bool poisoned = false;
     bool reset_pending = false;                 // live_bytes is in the init counters
+    sv_graph *pending_graph = nullptr;          // replayed graph whose counters are unread
     std::vector<hipEvent_t> events;             // per-stage timing, created on demand
+};
+
+struct sv_graph {
+    sv_state *sv = nullptr;
+    const sv_plan *plan = nullptr;
+    uint64_t plan_uid = 0;
+    size_t first = 0, count = 0, launches = 0;
+    int cur_begin = 0, cur_end = 0;
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
 };
 
 namespace {
 
+int resolve_graph(sv_t *sv);
 std::atomic<uint64_t> g_plan_uid{1};
 
 int step_shift(float ebf);
@@ -194,6 +210,8 @@ int validate_cfg(const sv_config_t *c)
         return fail(SV_ERR_INVALID, "tile_qubits %d outside [10, min(13, n)]", t);
     if (!(c->eb > 0) || !std::isfinite(c->eb) || !std::isfinite((float)c->eb) || (float)c->eb <= 0)
         return fail(SV_ERR_INVALID, "eb must be a positive finite float32");
+    if (c->flags & ~(SV_FLAG_NO_SCRATCH | SV_FLAG_NO_MFMA)) return fail(SV_ERR_INVALID, "unknown flags 0x%x", c->flags);
+    if (c->reserved) return fail(SV_ERR_INVALID, "reserved must be 0");
     if (!step_ok(c->domain, step_shift((float)c->eb)))
         return fail(SV_ERR_INVALID, "eb %g outside the codec's range for this domain (LOG: 2^-23 <= eb < 1/2)", c->eb);
     return SV_OK;
@@ -435,8 +453,8 @@ ArenaLayout layout_for(const sv_config_t &c)
     const uint64_t worst = nch * bmq::kMaxBodyBytes + bmq::kSegments * 256ull;
     L.pool_cap = c.pool_bytes ? c.pool_bytes : worst;
     const uint64_t pool_alloc = align256(L.pool_cap + 1024);    // decoders read a little past a body
-    L.scr_bytes = align256((1ull << c.n_qubits) * 4ull);
-    L.counters_bytes = align256((kMaxStagesPerBatch + 1) * kStageCounters * 8ull);
+    L.scr_bytes = (c.flags & SV_FLAG_NO_SCRATCH) ? 0 : align256((1ull << c.n_qubits) * 4ull);
+    L.counters_bytes = align256((kMaxLaunchesPerBatch + 1) * kStageCounters * 8ull);
     L.partials_bytes = align256(kPartials * 5 * 8ull);
     L.ops_bytes = kOpsArenaBytes;
     uint64_t o = 0;
@@ -461,6 +479,11 @@ uint32_t body_bytes_host(uint32_t hdr)
     if (mode == 0) return 0;
     if (mode == 3) return 256;
     return (mode == 1 ? 4u : 0u) + 8u * ((sc == 2u) + (zc == 2u)) + 8u * w;
+}
+
+bmq::PoolView pool_view(const sv_t *sv, int which)
+{
+    return bmq::PoolView{sv->pool[which], sv->host[which], sv->pool_cap};
 }
 
 int check_state(const sv_t *sv)
@@ -575,15 +598,17 @@ int sv_create(const sv_config_t *cfg, void *dev_arena, uint64_t dev_bytes, void 
     S->pool[0] = S->arena + L.off_pool0;
     S->pool[1] = S->arena + L.off_pool1;
     S->pool_cap = L.pool_cap;
-    S->scr_re = (float *)(S->arena + L.off_scr_re);
-    S->scr_im = (float *)(S->arena + L.off_scr_im);
+    if (L.scr_bytes) {
+        S->scr_re = (float *)(S->arena + L.off_scr_re);
+        S->scr_im = (float *)(S->arena + L.off_scr_im);
+    }
     S->counters = (unsigned long long *)(S->arena + L.off_counters);
     S->partials = (double *)(S->arena + L.off_partials);
     S->out5 = (double *)(S->arena + L.off_out5);
     S->ops_arena = S->arena + L.off_ops;
     S->cur = 0;
     const uint64_t nch = 1ull << (S->n - 6);
-    unsigned long long *ic = S->counters + kMaxStagesPerBatch * kStageCounters;
+    unsigned long long *ic = S->counters + kMaxLaunchesPerBatch * kStageCounters;
     hipError_t e = bmq::launch_fill_u64((uint64_t *)ic, kStageCounters, 0, S->stream);
     if (e == hipSuccess) e = bmq::launch_init_state(S->dir[0], nch, S->pool[0], ic, codec_params(*cfg), S->stream);
     unsigned long long cursor = 0;
@@ -606,11 +631,42 @@ void sv_destroy(sv_t *sv)
     delete sv;
 }
 
+int sv_attach_host_pool(sv_t *sv, void *host_pinned, uint64_t host_bytes)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (int rc = resolve_graph(sv)) return rc;
+    if (!sv->reset_pending && sv->live_host)
+        return fail(SV_ERR_INVALID, "the live state still has %llu bytes in the attached host pool",
+                    (unsigned long long)sv->live_host);
+    HIP_TRY(hipStreamSynchronize(sv->stream));     // no kernel may still use the old pool
+    if (!host_pinned || !host_bytes) {
+        sv->host[0] = sv->host[1] = sv->host_h[0] = sv->host_h[1] = nullptr;
+        sv->host_cap = 0;
+        return SV_OK;
+    }
+    void *dptr = nullptr;
+    const hipError_t e = hipHostGetDevicePointer(&dptr, host_pinned, 0);
+    if (e != hipSuccess || !dptr)
+        return fail(SV_ERR_INVALID, "host pool is not pinned device-addressable memory (%s)", hipGetErrorString(e));
+    const uint64_t half = (host_bytes / 2) & ~255ull;
+    if (half < 4096) return fail(SV_ERR_INVALID, "host pool of %llu bytes is too small", (unsigned long long)host_bytes);
+    const uint64_t cap = half - 1024;              // decoders read a little past a body
+    if (sv->pool_cap + cap > bmq::kDirOffsetMask)
+        return fail(SV_ERR_INVALID, "device + host pool exceed the directory's 40-bit offsets");
+    sv->host[0] = (uint8_t *)dptr;
+    sv->host[1] = (uint8_t *)dptr + half;
+    sv->host_h[0] = (uint8_t *)host_pinned;
+    sv->host_h[1] = (uint8_t *)host_pinned + half;
+    sv->host_cap = cap;
+    return SV_OK;
+}
+
 int sv_reset(sv_t *sv)
 {
     if (!sv) return fail(SV_ERR_INVALID, "state is NULL");
+    sv->pending_graph = nullptr;          // the replay's result is discarded
     const uint64_t nch = 1ull << (sv->n - 6);
-    unsigned long long *ic = sv->counters + kMaxStagesPerBatch * kStageCounters;
+    unsigned long long *ic = sv->counters + kMaxLaunchesPerBatch * kStageCounters;
     HIP_TRY(bmq::launch_fill_u64((uint64_t *)ic, kStageCounters, 0, sv->stream));
     HIP_TRY(bmq::launch_init_state(sv->dir[0], nch, sv->pool[0], ic, codec_params(sv->cfg), sv->stream));
     sv->cur = 0;
@@ -619,9 +675,12 @@ int sv_reset(sv_t *sv)
     return SV_OK;
 }
 
-int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t count, sv_stage_stats_t *stats)
+}  // extern "C"
+
+namespace {
+
+int check_plan(const sv_t *sv, const sv_plan_t *p, size_t first, size_t count)
 {
-    if (int rc = check_state(sv)) return rc;
     if (!p) return fail(SV_ERR_INVALID, "plan is NULL");
     if (p->cfg.n_qubits != sv->cfg.n_qubits || p->cfg.block_qubits != sv->cfg.block_qubits ||
         p->cfg.domain != sv->cfg.domain || p->cfg.eb != sv->cfg.eb)
@@ -629,131 +688,367 @@ int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t co
     if (first > p->stages.size() || count > p->stages.size() - first)
         return fail(SV_ERR_INVALID, "stage range [%zu, %zu) outside the plan's %zu stages", first, first + count,
                     p->stages.size());
-    if (count == 0) return SV_OK;
-    if (sv->uploaded_uid != p->uid) {
-        const uint64_t ob = p->ops.size() * sizeof(OpDesc);
-        if (ob) HIP_TRY(hipMemcpyAsync(sv->ops_arena, p->ops.data(), ob, hipMemcpyHostToDevice, sv->stream));
-        if (!p->data.empty())
-            HIP_TRY(hipMemcpyAsync(sv->ops_arena + align256(ob), p->data.data(), p->data.size() * sizeof(float2),
-                                   hipMemcpyHostToDevice, sv->stream));
-        HIP_TRY(hipStreamSynchronize(sv->stream));   // host vectors are pageable
-        sv->uploaded_uid = p->uid;
-    }
-    const OpDesc *dops = (const OpDesc *)sv->ops_arena;
-    const float2 *ddata = (const float2 *)(sv->ops_arena + align256(p->ops.size() * sizeof(OpDesc)));
-    const bmq::CodecParams cp = codec_params(sv->cfg);
+    return SV_OK;
+}
+
+int upload_plan(sv_t *sv, const sv_plan_t *p)
+{
+    if (sv->uploaded_uid == p->uid) return SV_OK;
+    const uint64_t ob = p->ops.size() * sizeof(OpDesc);
+    if (align256(ob) + p->data.size() * sizeof(float2) > kOpsArenaBytes)
+        return fail(SV_ERR_UNSUPPORTED, "plan's fused operations exceed the %llu-byte operation arena",
+                    (unsigned long long)kOpsArenaBytes);
+    if (ob) HIP_TRY(hipMemcpyAsync(sv->ops_arena, p->ops.data(), ob, hipMemcpyHostToDevice, sv->stream));
+    if (!p->data.empty())
+        HIP_TRY(hipMemcpyAsync(sv->ops_arena + align256(ob), p->data.data(), p->data.size() * sizeof(float2),
+                               hipMemcpyHostToDevice, sv->stream));
+    HIP_TRY(hipStreamSynchronize(sv->stream));   // host vectors are pageable
+    sv->uploaded_uid = p->uid;
+    return SV_OK;
+}
+
+// Enqueue pass pi of stage st on stream s with counter block li; flips the
+// state's current copy when the pass writes compressed output.
+int enqueue_pass(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, size_t li, hipStream_t s)
+{
+    const int n = sv->n;
+    const bool scratch = sv->scr_re != nullptr;
+    const int np = (int)st.passes.size();
+    // output pool segments: as many as waves, at most kSegments; each holds
+    // the worst case of its tiles when the pool has its default size
+    const uint64_t waves = (1ull << (n - p->t)) * (p->t == 13 ? 8u : 4u);
+    const int n_seg = (int)std::min<uint64_t>((uint64_t)bmq::kSegments, waves);
+    const PassPlan &pp = st.passes[pi];
+    bmq::PassArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.n = n;
+    a.t = p->t;
+    for (int j = 0; j < p->t; ++j) a.tileq[j] = pp.tileq[j];
+    int nn = 0;
+    for (int q = 0; q < n; ++q)
+        if (std::find(pp.tileq.begin(), pp.tileq.end(), q) == pp.tileq.end()) a.nontile[nn++] = q;
+    a.n_nontile = nn;
+    a.op_begin = pp.op_begin;
+    a.op_end = pp.op_end;
+    // with scratch planes, passes between the first and the last stay
+    // uncompressed; without, every pass is a compressed round
+    a.in_mode = (!scratch || pi == 0) ? bmq::IO_COMPRESSED : bmq::IO_SCRATCH;
+    a.out_mode = (!scratch || pi == np - 1) ? bmq::IO_COMPRESSED : bmq::IO_SCRATCH;
+    a.cp = codec_params(sv->cfg);
+    a.dir_in = sv->dir[sv->cur];
+    a.pool_in = sv->pool[sv->cur];
+    a.host_in = sv->host[sv->cur];
+    a.dir_out = sv->dir[sv->cur ^ 1];
+    a.pool_out = sv->pool[sv->cur ^ 1];
+    a.host_out = sv->host[sv->cur ^ 1];
+    a.pool_cap = sv->pool_cap;
+    a.host_cap = sv->host_cap;
+    a.n_seg = n_seg;
+    a.seg_cap = (sv->pool_cap / (uint64_t)n_seg) & ~3ull;
+    a.counters = sv->counters + li * kStageCounters;
+    a.scr_re = sv->scr_re;
+    a.scr_im = sv->scr_im;
+    a.ops = (const OpDesc *)sv->ops_arena;
+    a.opdata = (const float2 *)(sv->ops_arena + align256(p->ops.size() * sizeof(OpDesc)));
+    a.dump_re = sv->dump_re;
+    a.dump_im = sv->dump_im;
+    a.mfma = (sv->cfg.flags & SV_FLAG_NO_MFMA) ? 0 : 1;
+    HIP_TRY(bmq::launch_pass(a, s));
+    if (a.out_mode == bmq::IO_COMPRESSED) sv->cur ^= 1;
+    return SV_OK;
+}
+
+// Launches and counter blocks of the stage run [first, first + batch).
+size_t launches_of(const sv_plan_t *p, size_t first, size_t batch)
+{
+    size_t l = 0;
+    for (size_t i = 0; i < batch; ++i) l += p->stages[first + i].passes.size();
+    return l;
+}
+
+// Read the counter blocks of stages [first, first + batch) (host copy hc),
+// check for overflow, fill stats (without ms) and advance the footprint.
+int collect_stages(sv_t *sv, const sv_plan_t *p, size_t first, size_t batch,
+                   const std::vector<unsigned long long> &hc, sv_stage_stats_t *stats)
+{
+    const bool scratch = sv->scr_re != nullptr;
     const int n = sv->n;
     const uint64_t nch = 1ull << (n - 6);
-    // output pool segments: as many as tiles, at most kSegments; each holds
-    // the worst case of its tiles when the pool has its default size
-    const uint64_t waves = (1ull << (n - p->t)) * (p->t == 13 ? 8u : 4u);   // allocations per pass
-    const int n_seg = (int)std::min<uint64_t>((uint64_t)bmq::kSegments, waves);
-    const uint64_t seg_cap = (sv->pool_cap / (uint64_t)n_seg) & ~3ull;
+    size_t li = 0;
+    for (size_t i = 0; i < batch; ++i) {
+        const StagePlan &st = p->stages[first + i];
+        const size_t np = st.passes.size();
+        uint64_t inter = 0, out_dev = 0, out_host = 0, zero = 0, mh[4] = {0, 0, 0, 0};
+        bool overflow = false;
+        for (size_t pi = 0; pi < np; ++pi, ++li) {
+            if (scratch && pi + 1 < np) continue;          // uncompressed intermediate pass
+            // per segment: cursor, overflow flag, zero chunks, device and host
+            // bytes, and the mode histogram packed two 32-bit counts per word
+            // (ZERO|LZ, Q0|VERBATIM)
+            uint64_t dev = 0, host = 0, z = 0, m4[4] = {0, 0, 0, 0};
+            for (int g = 0; g < bmq::kSegments; ++g) {
+                const unsigned long long *sg = &hc[li * kStageCounters + (size_t)g * bmq::C_NUM];
+                overflow |= sg[bmq::C_OVERFLOW] != 0;
+                dev += sg[bmq::C_DEV_BYTES];
+                host += sg[bmq::C_HOST_BYTES];
+                z += sg[bmq::C_ZERO_CHUNKS];
+                m4[0] += sg[bmq::C_MODE0] & 0xFFFFFFFFull;
+                m4[1] += sg[bmq::C_MODE0] >> 32;
+                m4[2] += sg[bmq::C_MODE0 + 2] & 0xFFFFFFFFull;
+                m4[3] += sg[bmq::C_MODE0 + 2] >> 32;
+            }
+            if (pi + 1 < np) inter += 2 * (dev + host);
+            out_dev = dev;
+            out_host = host;
+            zero = z;
+            for (int q = 0; q < 4; ++q) mh[q] = m4[q];
+        }
+        if (overflow) {
+            sv->poisoned = true;
+            return fail(SV_ERR_CAPACITY,
+                        "stage %zu overflowed the compressed pools (device pool %llu bytes, host pool %llu bytes)",
+                        first + i, (unsigned long long)sv->pool_cap, (unsigned long long)sv->host_cap);
+        }
+        if (stats) {
+            sv_stage_stats_t &s = stats[i];
+            const float ms = s.ms;
+            std::memset(&s, 0, sizeof(s));
+            s.ms = ms;
+            s.bytes_in = sv->live_bytes;
+            s.bytes_out = out_dev + out_host;
+            s.bytes_out_host = out_host;
+            s.inter_bytes = inter;
+            s.dir_bytes = (scratch ? 1 : np) * 2ull * nch * 8ull;
+            s.scratch_bytes = scratch ? (uint64_t)(np - 1) * 2ull * (1ull << n) * 8ull : 0;
+            s.zero_chunks_out = zero;
+            s.mode_hist[0] = mh[0]; s.mode_hist[1] = mh[1]; s.mode_hist[2] = mh[2]; s.mode_hist[3] = mh[3];
+            s.passes = (uint32_t)np;
+            uint32_t nops = 0;
+            for (const auto &pp : st.passes) nops += (uint32_t)(pp.op_end - pp.op_begin);
+            s.n_ops = nops;
+            s.n_gates = (uint32_t)(st.g1 - st.g0);
+            s.n_inner = (uint32_t)st.inner.size();
+        }
+        sv->live_bytes = out_dev + out_host;
+        sv->live_host = out_host;
+    }
+    return SV_OK;
+}
 
+// Copy a batch's counters (and, after a reset, the initial footprint) to the
+// host, synchronising the stream.
+int read_counters(sv_t *sv, size_t launches, std::vector<unsigned long long> &hc)
+{
+    hc.resize(launches * kStageCounters);
+    HIP_TRY(hipMemcpyAsync(hc.data(), sv->counters, hc.size() * 8, hipMemcpyDeviceToHost, sv->stream));
+    unsigned long long init_cursor = 0;
+    if (sv->reset_pending)
+        HIP_TRY(hipMemcpyAsync(&init_cursor, sv->counters + kMaxLaunchesPerBatch * kStageCounters + bmq::C_CURSOR, 8,
+                               hipMemcpyDeviceToHost, sv->stream));
+    HIP_TRY(hipStreamSynchronize(sv->stream));
+    if (sv->reset_pending) {
+        sv->live_bytes = init_cursor;
+        sv->live_host = 0;
+        sv->reset_pending = false;
+    }
+    return SV_OK;
+}
+
+// A replayed graph leaves its counters on the device; read them before
+// anything else uses the counter blocks or the footprint.
+int resolve_graph(sv_t *sv)
+{
+    if (!sv->pending_graph) return SV_OK;
+    const sv_graph *g = sv->pending_graph;
+    sv->pending_graph = nullptr;
+    std::vector<unsigned long long> hc;
+    if (int rc = read_counters(sv, g->launches, hc)) return rc;
+    return collect_stages(sv, g->plan, g->first, g->count, hc, nullptr);
+}
+
+}  // namespace
+
+extern "C" {
+
+int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t count, sv_stage_stats_t *stats)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (int rc = check_plan(sv, p, first, count)) return rc;
+    if (count == 0) return SV_OK;
+    if (int rc = resolve_graph(sv)) return rc;
+    if (int rc = upload_plan(sv, p)) return rc;
     size_t done = 0;
+    std::vector<unsigned long long> hc;
     while (done < count) {
-        const size_t batch = std::min(count - done, kMaxStagesPerBatch);
-        HIP_TRY(bmq::launch_fill_u64((uint64_t *)sv->counters, batch * kStageCounters, 0, sv->stream));
+        // a batch: whole stages whose passes fit the counter blocks
+        size_t batch = 0, launches = 0;
+        while (done + batch < count) {
+            const size_t np = p->stages[first + done + batch].passes.size();
+            if (batch && launches + np > kMaxLaunchesPerBatch) break;
+            launches += np;
+            ++batch;
+        }
+        HIP_TRY(bmq::launch_fill_u64((uint64_t *)sv->counters, launches * kStageCounters, 0, sv->stream));
         if (stats)
             while (sv->events.size() < 2 * batch) {
                 hipEvent_t e;
                 HIP_TRY(hipEventCreate(&e));
                 sv->events.push_back(e);
             }
+        size_t li = 0;
         for (size_t i = 0; i < batch; ++i) {
             const StagePlan &st = p->stages[first + done + i];
             if (stats) HIP_TRY(hipEventRecord(sv->events[2 * i], sv->stream));
-            const int np = (int)st.passes.size();
-            for (int pi = 0; pi < np; ++pi) {
-                const PassPlan &pp = st.passes[pi];
-                bmq::PassArgs a;
-                std::memset(&a, 0, sizeof(a));
-                a.n = n;
-                a.t = p->t;
-                for (int j = 0; j < p->t; ++j) a.tileq[j] = pp.tileq[j];
-                int nn = 0;
-                for (int q = 0; q < n; ++q)
-                    if (std::find(pp.tileq.begin(), pp.tileq.end(), q) == pp.tileq.end()) a.nontile[nn++] = q;
-                a.n_nontile = nn;
-                a.op_begin = pp.op_begin;
-                a.op_end = pp.op_end;
-                a.in_mode = pi == 0 ? bmq::IO_COMPRESSED : bmq::IO_SCRATCH;
-                a.out_mode = pi == np - 1 ? bmq::IO_COMPRESSED : bmq::IO_SCRATCH;
-                a.cp = cp;
-                a.dir_in = sv->dir[sv->cur];
-                a.pool_in = sv->pool[sv->cur];
-                a.dir_out = sv->dir[sv->cur ^ 1];
-                a.pool_out = sv->pool[sv->cur ^ 1];
-                a.n_seg = n_seg;
-                a.seg_cap = seg_cap;
-                a.counters = sv->counters + i * kStageCounters;
-                a.scr_re = sv->scr_re;
-                a.scr_im = sv->scr_im;
-                a.ops = dops;
-                a.opdata = ddata;
-                a.dump_re = sv->dump_re;
-                a.dump_im = sv->dump_im;
-                HIP_TRY(bmq::launch_pass(a, sv->stream));
-            }
+            for (int pi = 0; pi < (int)st.passes.size(); ++pi, ++li)
+                if (int rc = enqueue_pass(sv, p, st, pi, li, sv->stream)) return rc;
             if (stats) HIP_TRY(hipEventRecord(sv->events[2 * i + 1], sv->stream));
-            sv->cur ^= 1;
         }
-        std::vector<unsigned long long> hc(batch * kStageCounters);
-        HIP_TRY(hipMemcpyAsync(hc.data(), sv->counters, hc.size() * 8, hipMemcpyDeviceToHost, sv->stream));
-        unsigned long long init_cursor = 0;
-        if (sv->reset_pending)
-            HIP_TRY(hipMemcpyAsync(&init_cursor, sv->counters + kMaxStagesPerBatch * kStageCounters + bmq::C_CURSOR, 8,
-                                   hipMemcpyDeviceToHost, sv->stream));
-        HIP_TRY(hipStreamSynchronize(sv->stream));
-        if (sv->reset_pending) {
-            sv->live_bytes = init_cursor;
-            sv->reset_pending = false;
-        }
-        uint64_t prev = sv->live_bytes;
-        for (size_t i = 0; i < batch; ++i) {
-            // per segment: cursor, overflow flag, zero chunks, and the mode
-            // histogram packed two 32-bit counts per word (ZERO|LZ, Q0|VERBATIM)
-            unsigned long long c[bmq::C_NUM] = {0, 0, 0, 0, 0, 0, 0, 0};
-            uint64_t mh[4] = {0, 0, 0, 0};
-            for (int g = 0; g < bmq::kSegments; ++g) {
-                const unsigned long long *sg = &hc[i * kStageCounters + (size_t)g * bmq::C_NUM];
-                for (int q = 0; q < bmq::C_NUM; ++q) c[q] += sg[q];
-                mh[0] += sg[bmq::C_MODE0] & 0xFFFFFFFFull;
-                mh[1] += sg[bmq::C_MODE0] >> 32;
-                mh[2] += sg[bmq::C_MODE0 + 2] & 0xFFFFFFFFull;
-                mh[3] += sg[bmq::C_MODE0 + 2] >> 32;
-            }
-            if (c[bmq::C_OVERFLOW]) {
-                sv->poisoned = true;
-                return fail(SV_ERR_CAPACITY, "stage %zu overflowed the compressed pool (%llu bytes needed, capacity %llu)",
-                            first + done + i, c[bmq::C_CURSOR], (unsigned long long)sv->pool_cap);
-            }
-            if (stats) {
-                const StagePlan &st = p->stages[first + done + i];
-                sv_stage_stats_t &s = stats[done + i];
-                std::memset(&s, 0, sizeof(s));
-                s.bytes_in = prev;
-                s.bytes_out = c[bmq::C_CURSOR];
-                s.dir_bytes = 2ull * nch * 8ull;
-                s.scratch_bytes = (uint64_t)(st.passes.size() - 1) * 2ull * (1ull << n) * 8ull;
-                s.zero_chunks_out = c[bmq::C_ZERO_CHUNKS];
-                s.mode_hist[0] = mh[0]; s.mode_hist[1] = mh[1]; s.mode_hist[2] = mh[2]; s.mode_hist[3] = mh[3];
-                s.passes = (uint32_t)st.passes.size();
-                uint32_t nops = 0;
-                for (const auto &pp : st.passes) nops += (uint32_t)(pp.op_end - pp.op_begin);
-                s.n_ops = nops;
-                s.n_gates = (uint32_t)(st.g1 - st.g0);
-                s.n_inner = (uint32_t)st.inner.size();
-                float ms = 0.0f;
-                HIP_TRY(hipEventElapsedTime(&ms, sv->events[2 * i], sv->events[2 * i + 1]));
-                s.ms = ms;
-            }
-            prev = c[bmq::C_CURSOR];
-        }
-        sv->live_bytes = prev;
+        if (int rc = read_counters(sv, launches, hc)) return rc;
+        if (stats)
+            for (size_t i = 0; i < batch; ++i)
+                HIP_TRY(hipEventElapsedTime(&stats[done + i].ms, sv->events[2 * i], sv->events[2 * i + 1]));
+        if (int rc = collect_stages(sv, p, first + done, batch, hc, stats ? stats + done : nullptr)) return rc;
         done += batch;
     }
     return SV_OK;
+}
+
+int sv_autotune(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, void *dev_arena,
+                uint64_t dev_bytes, void *hip_stream, size_t probe_stages, sv_config_t *best, float *ms_all)
+{
+    if (int rc = validate_cfg(cfg)) return rc;
+    if (!best) return fail(SV_ERR_INVALID, "best is NULL");
+    if (ms_all)
+        for (int i = 0; i < 20; ++i) ms_all[i] = NAN;
+    float best_ms = INFINITY;
+    sv_config_t winner = *cfg;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    int rc = SV_OK;
+    for (int t = 10; t <= bmq::kMaxTile && rc == SV_OK; ++t) {
+        if (t > cfg->n_qubits) break;
+        for (int k = 1; k <= 5 && rc == SV_OK; ++k) {
+            sv_config_t c = *cfg;
+            c.tile_qubits = t;
+            c.fuse_qubits = k;
+            sv_plan_t *p = nullptr;
+            sv_t *sv = nullptr;
+            rc = stage_plan(gates, n_gates, &c, &p);
+            if (rc == SV_OK) rc = sv_create(&c, dev_arena, dev_bytes, hip_stream, &sv);
+            const size_t ns = p ? p->stages.size() : 0;
+            const size_t cnt = probe_stages && probe_stages < ns ? probe_stages : ns;
+            float ms = 0.0f;
+            // one warm-up run (first launches load code), then the timed run
+            for (int rep = 0; rc == SV_OK && rep < 2; ++rep) {
+                rc = sv_reset(sv);
+                if (rc == SV_OK && hipEventRecord(e0, sv->stream) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
+                if (rc == SV_OK) rc = stage_apply_compressed(sv, p, 0, cnt, nullptr);
+                if (rc == SV_OK && hipEventRecord(e1, sv->stream) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
+                if (rc == SV_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
+                if (rc == SV_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
+            }
+            if (sv) sv_destroy(sv);
+            if (p) plan_destroy(p);
+            if (rc == SV_ERR_CAPACITY) rc = SV_OK;     // this candidate does not fit the pools: skip it
+            else if (rc == SV_OK) {
+                if (ms_all) ms_all[(t - 10) * 5 + (k - 1)] = ms;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    winner = c;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != SV_OK) return rc;
+    if (!(best_ms < INFINITY)) return fail(SV_ERR_CAPACITY, "no candidate fits the pools");
+    *best = winner;
+    return SV_OK;
+}
+
+int sv_graph_capture(sv_t *sv, const sv_plan_t *p, size_t first, size_t count, sv_graph_t **out)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (int rc = check_plan(sv, p, first, count)) return rc;
+    if (!out) return fail(SV_ERR_INVALID, "out is NULL");
+    if (count == 0) return fail(SV_ERR_INVALID, "empty stage range");
+    if (sv->dump_re) return fail(SV_ERR_UNSUPPORTED, "the debug dump cannot be captured");
+    const size_t launches = launches_of(p, first, count);
+    if (launches > kMaxLaunchesPerBatch)
+        return fail(SV_ERR_UNSUPPORTED, "%zu pass launches exceed the %zu counter blocks of one graph", launches,
+                    kMaxLaunchesPerBatch);
+    if (int rc = resolve_graph(sv)) return rc;
+    if (int rc = upload_plan(sv, p)) return rc;
+    sv_graph *g = new (std::nothrow) sv_graph;
+    if (!g) return fail(SV_ERR_OOM, "host allocation failed");
+    g->sv = sv;
+    g->plan = p;
+    g->plan_uid = p->uid;
+    g->first = first;
+    g->count = count;
+    g->launches = launches;
+    g->cur_begin = sv->cur;
+    // capture on a private stream (the legacy default stream cannot capture)
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    int rc = SV_OK;
+    if (e == hipSuccess) {
+        // counters are cleared by a kernel, not a memset node
+        e = bmq::launch_fill_u64((uint64_t *)sv->counters, launches * kStageCounters, 0, cs);
+        size_t li = 0;
+        for (size_t i = 0; e == hipSuccess && rc == SV_OK && i < count; ++i) {
+            const StagePlan &st = p->stages[first + i];
+            for (int pi = 0; rc == SV_OK && pi < (int)st.passes.size(); ++pi, ++li)
+                rc = enqueue_pass(sv, p, st, pi, li, cs);
+        }
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = e2;
+        g->g = graph;
+        if (e == hipSuccess && rc == SV_OK) e = hipGraphInstantiate(&g->x, g->g, nullptr, nullptr, 0);
+    }
+    g->cur_end = sv->cur;
+    sv->cur = g->cur_begin;                       // capture ran nothing
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess || rc != SV_OK) {
+        sv_graph_destroy(g);
+        return rc != SV_OK ? rc : fail(SV_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return SV_OK;
+}
+
+int sv_graph_launch(sv_t *sv, sv_graph_t *g)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (!g || g->sv != sv) return fail(SV_ERR_INVALID, "graph was not captured on this state");
+    if (g->plan_uid != sv->uploaded_uid)
+        return fail(SV_ERR_INVALID, "another plan's operations were uploaded since the capture");
+    if (sv->cur != g->cur_begin)
+        return fail(SV_ERR_INVALID, "the state is in its other pool copy; replay needs the copy it was captured on");
+    if (int rc = resolve_graph(sv)) return rc;
+    HIP_TRY(hipGraphLaunch(g->x, sv->stream));
+    sv->cur = g->cur_end;
+    sv->pending_graph = g;
+    return SV_OK;
+}
+
+int sv_graph_sync(sv_t *sv)
+{
+    if (int rc = check_state(sv)) return rc;
+    return resolve_graph(sv);
+}
+
+void sv_graph_destroy(sv_graph_t *g)
+{
+    if (!g) return;
+    if (g->sv && g->sv->pending_graph == g) (void)resolve_graph(g->sv);
+    if (g->x) (void)hipGraphExecDestroy(g->x);
+    if (g->g) (void)hipGraphDestroy(g->g);
+    delete g;
 }
 
 int sv_fidelity(const sv_t *sv, const double *ref_dev, double *fidelity, double *max_abs_err, double *norm2)
@@ -761,7 +1056,7 @@ int sv_fidelity(const sv_t *sv, const double *ref_dev, double *fidelity, double 
     if (int rc = check_state(sv)) return rc;
     const uint64_t nch = 1ull << (sv->n - 6);
     const int np = (int)std::min<uint64_t>(kPartials, (nch + 3) / 4);
-    HIP_TRY(bmq::launch_fidelity(sv->dir[sv->cur], sv->pool[sv->cur], codec_params(sv->cfg), nch,
+    HIP_TRY(bmq::launch_fidelity(sv->dir[sv->cur], pool_view(sv, sv->cur), codec_params(sv->cfg), nch,
                                  (const double2 *)ref_dev, sv->partials, np, sv->out5, sv->stream));
     double h[5];
     HIP_TRY(hipMemcpyAsync(h, sv->out5, sizeof(h), hipMemcpyDeviceToHost, sv->stream));
@@ -785,7 +1080,7 @@ int sv_export(const sv_t *sv, uint64_t start, uint64_t count, void *dst_dev)
     if ((start & 63) || (count & 63) || start > dim || count > dim - start || (count && !dst_dev))
         return fail(SV_ERR_INVALID, "export range must be 64-aligned and inside the state");
     if (!count) return SV_OK;
-    HIP_TRY(bmq::launch_export(sv->dir[sv->cur], sv->pool[sv->cur], codec_params(sv->cfg), start >> 6, count >> 6,
+    HIP_TRY(bmq::launch_export(sv->dir[sv->cur], pool_view(sv, sv->cur), codec_params(sv->cfg), start >> 6, count >> 6,
                                (float2 *)dst_dev, sv->stream));
     return SV_OK;
 }
@@ -795,23 +1090,25 @@ int sv_amplitudes(const sv_t *sv, const uint64_t *idx_dev, uint64_t k, void *out
     if (int rc = check_state(sv)) return rc;
     if (k && (!idx_dev || !out_dev)) return fail(SV_ERR_INVALID, "NULL pointer");
     if (!k) return SV_OK;
-    HIP_TRY(bmq::launch_amplitudes(sv->dir[sv->cur], sv->pool[sv->cur], codec_params(sv->cfg), idx_dev, k,
+    HIP_TRY(bmq::launch_amplitudes(sv->dir[sv->cur], pool_view(sv, sv->cur), codec_params(sv->cfg), idx_dev, k,
                                    1ull << (sv->n - 6), (float2 *)out_dev, sv->stream));
     return SV_OK;
 }
 
-int sv_footprint(const sv_t *sv, uint64_t *record_bytes, uint64_t *dir_bytes)
+int sv_footprint(const sv_t *sv, uint64_t *record_bytes, uint64_t *host_bytes, uint64_t *dir_bytes)
 {
     if (int rc = check_state(sv)) return rc;
+    if (int rc = resolve_graph(const_cast<sv_t *>(sv))) return rc;
     if (sv->reset_pending) {
         unsigned long long c = 0;
-        HIP_TRY(hipMemcpyAsync(&c, sv->counters + kMaxStagesPerBatch * kStageCounters + bmq::C_CURSOR, 8,
+        HIP_TRY(hipMemcpyAsync(&c, sv->counters + kMaxLaunchesPerBatch * kStageCounters + bmq::C_CURSOR, 8,
                                hipMemcpyDeviceToHost, sv->stream));
         HIP_TRY(hipStreamSynchronize(sv->stream));
         const_cast<sv_t *>(sv)->live_bytes = c;
         const_cast<sv_t *>(sv)->reset_pending = false;
     }
     if (record_bytes) *record_bytes = sv->live_bytes;
+    if (host_bytes) *host_bytes = sv->live_host;
     if (dir_bytes) *dir_bytes = (1ull << (sv->n - 6)) * 8ull;
     return SV_OK;
 }
@@ -938,8 +1235,11 @@ int sv_block_stream(const sv_t *sv, uint64_t block, void *dst_host, uint64_t cap
         std::memcpy(d + o + 4, &h1, 4);
         o += 8;
         if (sizes[c]) {
-            HIP_TRY(hipMemcpy(d + o, sv->pool[sv->cur] + (dir[c] & bmq::kDirOffsetMask), sizes[c],
-                              hipMemcpyDeviceToHost));
+            const uint64_t off = dir[c] & bmq::kDirOffsetMask;
+            if (off < sv->pool_cap)
+                HIP_TRY(hipMemcpy(d + o, sv->pool[sv->cur] + off, sizes[c], hipMemcpyDeviceToHost));
+            else
+                std::memcpy(d + o, sv->host_h[sv->cur] + (off - sv->pool_cap), sizes[c]);
             o += sizes[c];
         }
     }

@@ -61,7 +61,8 @@ def test_config_stage_counts(bmq):
 
 @pytest.mark.parametrize("bad", [dict(n=9), dict(n=41), dict(b=5), dict(b=17), dict(fuse=0),
                                  dict(fuse=6), dict(domain=2), dict(eb=0.0), dict(eb=-1.0),
-                                 dict(tile=9), dict(tile=14), dict(eb=float("nan"))])
+                                 dict(tile=9), dict(tile=14), dict(eb=float("nan")), dict(flags=4),
+                                 dict(flags=0x80000000)])
 def test_invalid_configs_rejected(bmq, bad):
     kw = dict(n=16, b=10, inner=2, fuse=2, domain=0, eb=1e-6)
     kw.update(bad)
@@ -75,3 +76,13 @@ def test_invalid_gates_rejected(bmq):
     for g in ([("CX", (3, 3), ())], [("H", (12,), ())], [("X", (-1,), ())]):
         with pytest.raises(bmq.BmqError):
             bmq.Plan(g, cfg)
+
+
+def test_no_scratch_flag_shrinks_the_arena(bmq):
+    import ctypes as C_
+    need = []
+    for flags in (0, bmq.SV_FLAG_NO_SCRATCH):
+        v = C_.c_uint64()
+        bmq._check(bmq.lib().sv_mem_required(C_.byref(bmq.Config(n=24, b=16, flags=flags).c()), C_.byref(v)))
+        need.append(v.value)
+    assert need[0] - need[1] >= 2 * 4 * (1 << 24)       # two float32 scratch planes

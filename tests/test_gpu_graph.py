@@ -1,0 +1,112 @@
+"""HIP-graph replay of the stage loop and the measured autotuner, on the GPU.
+Every replay, with eager work and synchronisation between replays, must
+give the eager run's streams bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import native as N
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2410_14088_amd import bmq  # noqa: E402
+from paper_2410_14088_amd import circuits as C  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _setup(gates, n, b, **kw):
+    cfg = bmq.Config(n=n, b=b, inner=2, domain=1, eb=1e-5, **kw)
+    return cfg, bmq.Plan(gates, cfg), bmq.State(cfg, DEV)
+
+
+def test_graph_replays_match_eager():
+    d = C.config(0)
+    n, b = d["n"], d["b"]
+    cfg, plan, eager = _setup(d["gates"], n, b, fuse=2)
+    eager.apply(plan)
+    want = eager.export()
+    want_streams = [eager.block_stream(k) for k in range(eager.n_blocks)]
+    want_fp = eager.footprint()
+    _, plan2, sv = _setup(d["gates"], n, b, fuse=2)
+    g = sv.capture(plan2)
+    other_cfg, other_plan, other = _setup(C.ghz(16), 16, 10, fuse=2)
+    for r in range(3):
+        print(f"replay {r}", flush=True)
+        sv.reset()
+        g.launch()
+        sv.graph_sync()
+        assert sv.footprint() == want_fp
+        assert torch.equal(sv.export(), want)
+        assert [sv.block_stream(k) for k in range(sv.n_blocks)] == want_streams
+        other.reset()                       # eager work between replays
+        other.apply(other_plan)
+        torch.cuda.synchronize()
+    g.close()
+
+
+def test_graph_of_a_stage_range_and_parity_check():
+    d = C.config(0)
+    n, b = d["n"], d["b"]
+    cfg, plan, eager = _setup(d["gates"], n, b, fuse=2)
+    eager.apply(plan, 0, 10)
+    eager.apply(plan, 10, 7)
+    _, plan2, sv = _setup(d["gates"], n, b, fuse=2)
+    sv.apply(plan2, 0, 10)
+    g = sv.capture(plan2, 10, 7)
+    g.launch()
+    passes = sum(plan2.stage(s)["passes"] for s in range(10, 17))
+    if passes % 2:
+        with pytest.raises(bmq.BmqError):
+            g.launch()                      # the state now sits in the other pool copy
+    sv.graph_sync()
+    assert torch.equal(sv.export(), eager.export())
+
+
+def test_graph_overflow_is_reported_at_sync():
+    d = C.config(0)
+    n, b = d["n"], d["b"]
+    _, plan, sv = _setup(d["gates"], n, b, fuse=2, pool_bytes=1 << 16)
+    g = sv.capture(plan)
+    g.launch()
+    with pytest.raises(bmq.BmqError) as e:
+        sv.graph_sync()
+    assert e.value.code == -3
+
+
+def test_graph_speed_small_circuit():
+    d = C.config(0)
+    n, b = d["n"], d["b"]
+    _, plan, sv = _setup(d["gates"], n, b, fuse=2)
+    g = sv.capture(plan)
+    import time
+    for mode in ("eager", "graph", "eager", "graph"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            sv.reset()
+            if mode == "graph":
+                g.launch()
+                sv.graph_sync()
+            else:
+                sv.apply(plan)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        print(f"{mode}: {dt * 1e3:.2f} ms per run of {plan.n_stages} stages", flush=True)
+
+
+def test_autotune_picks_a_measured_candidate():
+    d = C.config(0)
+    cfg = bmq.Config(n=d["n"], b=d["b"], inner=2, fuse=2, domain=1, eb=1e-5)
+    best, table = bmq.autotune(d["gates"], cfg, probe_stages=20)
+    print({k: round(v, 3) for k, v in table.items()}, "->", best.tile, best.fuse, flush=True)
+    assert (best.tile, best.fuse) in table
+    assert table[(best.tile, best.fuse)] == min(table.values())
+    assert len(table) == 4 * 5
+    # the chosen configuration runs the whole circuit within the fidelity bound
+    plan = bmq.Plan(d["gates"], best)
+    sv = bmq.State(best, DEV)
+    sv.apply(plan)
+    ref = torch.from_numpy(np.ascontiguousarray(N.simulate(d["n"], d["gates"]))).to(DEV)
+    f2, _, _ = sv.fidelity(ref)
+    assert f2 >= 0.9999

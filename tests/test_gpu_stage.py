@@ -154,7 +154,7 @@ def test_ghz_zero_chunks_and_ratio():
     g = C.ghz(n)
     sv, plan, stats, f2, mx, n2 = run(g, n, 14, 1, 1e-5, fuse=2, label="ghz")
     assert f2 >= 0.999999
-    rec, dirb = sv.footprint()
+    rec, _, dirb = sv.footprint()
     assert rec < 1024          # two non-zero chunks
     assert stats[-1]["zero_chunks_out"] == (1 << (n - 6)) - 2
 
