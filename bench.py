@@ -35,9 +35,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n", type=int, default=30, help="qubits (default: the 30-qubit workload)")
+    ap.add_argument("--workload", default="qft", choices=["qft", "random-mirror"],
+                    help="qft: QFT on an Ry product (default, 30 qubits); random-mirror: random U3/CZ layers "
+                         "(33 qubits, depth 16) followed by their inverse")
+    ap.add_argument("--n", type=int, default=0, help="qubits (default: 30 for qft, 33 for random-mirror)")
+    ap.add_argument("--flags", type=int, default=0, help="sv_config_t flags (1 no scratch, 2 no MFMA)")
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--fuse", type=int, default=4)
+    ap.add_argument("--fuse", type=int, default=0, help="fusion width (default 4 for qft, 5 for random-mirror)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=21, help="qubits of the CPU-baseline sample")
     ap.add_argument("--stats-out", default="")
@@ -60,13 +64,13 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
 
 
-def counter_traffic(n: int, tile: int, fuse: int):
+def counter_traffic(n: int, tile: int, fuse: int, flags: int = 0, workload: str = "qft"):
     """HBM bytes per pass-kernel launch from the committed FETCH_SIZE /
     WRITE_SIZE profile of the default workload, or None when the workload
     differs or the kernel source changed since the counters were taken."""
     import hashlib
     import re
-    if (n, tile or 12, fuse) != (30, 12, 4):
+    if (n, tile or 12, fuse, flags, workload) != (30, 12, 4, 0, "qft"):
         return None
     prof = os.path.join(ROOT, "profiles", "pass_kernel_qft30_hbm_counters.md")
     src = os.path.join(ROOT, "paper_2410_14088_amd", "csrc", "bmq_kernels.hip")
@@ -137,12 +141,24 @@ def main():
     from paper_2410_14088_amd import bmq
     from paper_2410_14088_amd import circuits as C
 
-    n = args.n
-    d = C.config(1, n=n)
-    cfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=args.fuse, domain=d["domain"], eb=d["eb"], tile=args.tile)
-    plan = bmq.Plan(d["gates"], cfg)
+    if args.workload == "qft":
+        n = args.n or 30
+        d = C.config(1, n=n)
+        gates = d["gates"]
+        fuse = args.fuse or 4
+        wname = f"qft-on-ry-{n}q"
+    else:
+        n = args.n or 33
+        d = C.config(2, n=n)
+        gates = C.mirror(d["gates"])
+        fuse = args.fuse or 5
+        wname = f"random-{n}q-d16-mirror"
+    args.fuse = fuse
+    cfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=fuse, domain=d["domain"], eb=d["eb"], tile=args.tile,
+                     flags=args.flags)
+    plan = bmq.Plan(gates, cfg)
     info = plan.info()
-    G = len(d["gates"])
+    G = len(gates)
     dev = "cuda:0"
     sv = bmq.State(cfg, dev)
     stream = torch.cuda.current_stream()
@@ -182,15 +198,22 @@ def main():
     ratio64 = (8 << n) / peak_bytes
     ratio128 = (16 << n) / peak_bytes
 
-    # result check outside the timed region: sampled closed-form amplitudes
-    from oracle import native as N
-    rng = np.random.default_rng(1)
-    idx = rng.integers(0, 1 << n, 4096).astype(np.uint64)
-    want = N.qft_ry_amplitudes(n, d["thetas"], idx)
-    got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy()
-    f_est = float(abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real))
-    maxerr = float(np.abs(got - want).max())
+    # result check outside the timed region
     _, _, norm2 = sv.fidelity(None)
+    if args.workload == "qft":
+        # sampled closed-form amplitudes
+        from oracle import native as N
+        rng = np.random.default_rng(1)
+        idx = rng.integers(0, 1 << n, 4096).astype(np.uint64)
+        want = N.qft_ry_amplitudes(n, d["thetas"], idx)
+        got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy()
+        f_est = float(abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real))
+        maxerr = float(np.abs(got - want).max())
+    else:
+        # the mirror circuit returns to |0...0>: F^2 = |psi(0)|^2 / |psi|^2 exactly
+        a0 = sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0]
+        f_est = float(abs(a0) ** 2 / norm2)
+        maxerr = float(abs(abs(a0) - 1.0))
 
     out = {
         "metric": METRIC,
@@ -205,12 +228,12 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"qft-on-ry-{n}q", "n_qubits": n, "block_qubits": d["b"], "gates": G,
+        "config": {"workload": wname, "n_qubits": n, "block_qubits": d["b"], "gates": G,
                    "stages": info["stages"], "passes": info["passes"], "fused_ops": info["ops"],
                    "domain": "log", "eb": d["eb"], "fuse_qubits": args.fuse,
-                   "tile_qubits": args.tile or 12},
+                   "tile_qubits": args.tile or 12, "flags": args.flags},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(n, args.tile, args.fuse)},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(n, args.tile, args.fuse, args.flags, args.workload)},
         "gbps_algorithmic": achieved,
         "kernel_ms_per_step": kern_ms / args.steps,
         "pass_launch_avg_ms": kern_ms / launches,
@@ -218,14 +241,16 @@ def main():
         "pass_launches_per_step": launches // args.steps,
         "compression_ratio_vs_complex64": ratio64,
         "compression_ratio_vs_complex128": ratio128,
-        "fidelity_sampled_f2": f_est,
+        "fidelity_f2": f_est,
+        "fidelity_check": "4096 sampled amplitudes vs closed form" if args.workload == "qft"
+                          else "exact: mirror circuit, |psi(0)|^2 / |psi|^2",
         "max_abs_err_sampled": maxerr,
         "norm2": norm2,
     }
     if args.stats_out:
         with open(args.stats_out, "w") as f:
             json.dump(last, f, indent=1)
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "qft":
         out["cpu_baseline"] = cpu_baseline(args.cpu_n)
     print(json.dumps(out))
 

@@ -100,6 +100,28 @@ def ghz(n: int) -> List[Gate]:
     return [("H", (0,), ())] + [("CX", (q - 1, q), ()) for q in range(1, n)]
 
 
+def mirror(gates: Sequence[Gate]) -> List[Gate]:
+    """The circuit followed by its inverse (gates reversed, each inverted), so
+    the state returns to |0...0> up to a global phase.  S and T are undone by
+    RZ(-pi/2) and RZ(-pi/4), which differ from their inverses by a global
+    phase only."""
+    inv = []
+    for k, q, p in reversed(list(gates)):
+        if k in ("H", "X", "Y", "Z", "CX", "CZ"):
+            inv.append((k, q, ()))
+        elif k in ("RX", "RY", "RZ", "CP", "RZZ"):
+            inv.append((k, q, (-p[0],)))
+        elif k == "U3":
+            inv.append(("U3", q, (-p[0], -p[2], -p[1])))
+        elif k == "S":
+            inv.append(("RZ", q, (-math.pi / 2,)))
+        elif k == "T":
+            inv.append(("RZ", q, (-math.pi / 4,)))
+        else:
+            raise ValueError(k)
+    return list(gates) + inv
+
+
 # --------------------------------------------------------------------------
 # The five workload configurations.  Each returns a dict with the circuit and
 # the simulation parameters (qubits n, block qubits b, inner size, fuse width,

@@ -470,6 +470,12 @@ __device__ __forceinline__ float2 const_ld(const float2 *p, int i)
     return make_float2(c[2 * i], c[2 * i + 1]);
 }
 
+// Tile layout in LDS: amplitude e of the tile sits at word e + e / 16, one
+// pad word after every 16, so that the four lanes that encode one chunk
+// (16 consecutive amplitudes each) and the 16 chunks of a wave hit 64
+// different banks.
+__device__ __forceinline__ uint32_t tix(uint32_t e) { return e + (e >> 4); }
+
 template <int K, int TILE, int NT>
 __device__ void apply_dense(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M)
 {
@@ -493,8 +499,8 @@ __device__ void apply_dense(float *sre, float *sim, const OpDesc &op, const floa
             uint32_t o = 0;
 #pragma unroll
             for (int j = 0; j < K; ++j) o |= (uint32_t)((c >> j) & 1) << pos[j];
-            ar[c] = sre[i0 + o];
-            ai[c] = sim[i0 + o];
+            ar[c] = sre[tix(i0 + o)];
+            ai[c] = sim[tix(i0 + o)];
         }
 #pragma unroll UNR
         for (int r = 0; r < D; ++r) {
@@ -510,8 +516,8 @@ __device__ void apply_dense(float *sre, float *sim, const OpDesc &op, const floa
             uint32_t o = 0;
 #pragma unroll
             for (int j = 0; j < K; ++j) o |= (uint32_t)((r >> j) & 1) << pos[j];
-            sre[i0 + o] = br;
-            sim[i0 + o] = bi;
+            sre[tix(i0 + o)] = br;
+            sim[tix(i0 + o)] = bi;
         }
     }
 }
@@ -572,7 +578,7 @@ __device__ void apply_dense_mfma(float *sre, float *sim, const OpDesc &op, const
 #pragma unroll 4
         for (int st = 0; st < STEPS; ++st) {
             const int k = 2 * st + hi;                     // k < D exactly when st < D / 2
-            const uint32_t idx = base | row_off(k & (D - 1));
+            const uint32_t idx = tix(base | row_off(k & (D - 1)));
             const float bv = (st < D / 2) ? sre[idx] : sim[idx];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
@@ -583,7 +589,7 @@ __device__ void apply_dense_mfma(float *sre, float *sim, const OpDesc &op, const
 #pragma unroll
             for (int v = 0; v < 16; ++v) {
                 const int i = rb * 32 + 8 * (v >> 2) + 4 * hi + (v & 3);   // output row of A
-                const uint32_t idx = base | row_off(i & (D - 1));
+                const uint32_t idx = tix(base | row_off(i & (D - 1)));
                 if (i < D) sre[idx] = acc[rb][v];
                 else sim[idx] = acc[rb][v];
             }
@@ -627,7 +633,7 @@ __device__ void apply_diag(float *sre, float *sim, const OpDesc &op, const float
 #pragma unroll
         for (int b = 0; b < MB; ++b)
             if ((m >> b) & 1) idx |= W[b];
-        const int i = tid + m * NT;
+        const int i = tid + (tid >> 4) + m * (NT + NT / 16);      // tix(tid + m NT), NT a multiple of 16
         const float2 ph = s_tab[idx];
         const float ar = sre[i], ai = sim[i];
         sre[i] = __builtin_fmaf(ph.x, ar, -ph.y * ai);
@@ -695,15 +701,194 @@ __device__ __forceinline__ void pack_field(uint32_t *stage, uint32_t f, uint32_t
     if (s + w > 32u) atomicOr(&stage[a + 1], f >> (32u - s));
 }
 
+// ------------------------------------------------------------------ quad-lane encoder
+//
+// In the pass kernel each chunk is encoded by four consecutive lanes of a
+// wave (a quad); lane q holds values 16q..16q+15 and works through them one
+// after another.  The chunk-wide facts the format needs (any failed code, any
+// non-zero, sign and zero classes, the widest residual) are OR reductions
+// over the quad (two DPP quad permutations each), the zero substitution and
+// the Lorenzo residual across quarter boundaries need the previous lanes'
+// last codes, and every decision is then per lane, so a wave encodes 16
+// chunks with no scalar per-chunk work.  The result is byte for byte the
+// record encode_plane produces.
+
+// DPP quad permutations: broadcast lane i of the quad, swap neighbours
+constexpr int QB0 = 0x00, QB1 = 0x55, QB2 = 0xAA, QB3 = 0xFF, QX1 = 0xB1, QX2 = 0x4E;
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t qperm(uint32_t v)
+{
+    uint32_t r = dpp<CTRL, 0xf>(v);
+    asm volatile("" : "+v"(r));           // keep the move separate (see wave_prev)
+    return r;
+}
+
+__device__ __forceinline__ uint32_t quad_or(uint32_t v)
+{
+    v |= qperm<QX1>(v);
+    v |= qperm<QX2>(v);
+    return v;
+}
+
+struct QuadPlane {
+    uint32_t hdr;       // plane header (same in the four lanes)
+    int32_t anchor;     // LZ anchor (lane 0)
+    uint32_t nzb, negb; // this lane's 16 non-zero / negative bits
+    uint32_t w;         // field width
+    int32_t carry;      // code preceding this lane's first value
+    int32_t kp[16];     // this lane's codes after the zero substitution
+};
+
+// Encode one plane of a chunk; x points at this lane's 16 values (LDS).
+__device__ __forceinline__ void encode_quad(const float *x, const CodecParams &cp, int q, QuadPlane &P)
+{
+    const bool log_dom = cp.domain == 1;
+    uint32_t nzb = 0, negb = 0, bad = 0, anynz = 0;
+    int32_t first = 0, last = 0;
+    bool seen = false;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const float v = x[j];
+        const uint32_t u = __float_as_uint(v);
+        int32_t k = 0;
+        bool isz = false, ok;
+        if (log_dom) {
+            const uint32_t ef = (u >> 23) & 0xFFu;
+            isz = ef == 0u;
+            int e;
+            const float p = log2_split(u & 0x7FFFFFFFu, e);
+            const int32_t jj = (int32_t)__builtin_rintf(p * cp.scale);
+            ok = cp.code_ok && (isz || ef < 254u);
+            k = isz ? 0 : (int32_t)((uint32_t)e << cp.s) + jj;
+            negb |= (uint32_t)(!isz && (u >> 31)) << j;
+        } else {
+            ok = cp.code_ok && quantize(v, cp, k);
+            anynz |= k != 0;
+        }
+        bad |= !ok;
+        nzb |= (uint32_t)!isz << j;
+        if (!isz) {
+            first = seen ? first : k;
+            last = k;
+            seen = true;
+        }
+        P.kp[j] = k;
+    }
+    // chunk facts: bit 0 any failed code, 1 any non-zero code (LIN), 2 any
+    // non-zero value, 3 a non-zero value that is not negative (sign class
+    // not all-negative); bits 16..31 any zero value, bits 4..15 unused
+    const uint32_t zb = ~nzb & 0xFFFFu;
+    const uint32_t f = quad_or(bad | (anynz << 1) | ((nzb != 0u) << 2) | ((negb != nzb) << 3) |
+                               ((negb != 0u) << 4) | (zb << 16));
+    P.nzb = nzb;
+    P.negb = negb;
+    P.anchor = 0;
+    P.w = 0;
+    P.carry = 0;
+    if (f & 1u) { P.hdr = M_VERB; return; }
+    const bool allzero = log_dom ? !(f & 4u) : !(f & 2u);
+    if (allzero) { P.hdr = M_ZERO; return; }
+    // zeros take the code of the last non-zero value at or before them, else
+    // the chunk's first non-zero code: carry-in from the previous lanes
+    const uint32_t hs = seen ? 1u : 0u;
+    const uint32_t h0 = qperm<QB0>(hs), h1 = qperm<QB1>(hs), h2 = qperm<QB2>(hs);
+    const int32_t f0 = (int32_t)qperm<QB0>((uint32_t)first), f1 = (int32_t)qperm<QB1>((uint32_t)first);
+    const int32_t f2 = (int32_t)qperm<QB2>((uint32_t)first), f3 = (int32_t)qperm<QB3>((uint32_t)first);
+    const int32_t l0 = (int32_t)qperm<QB0>((uint32_t)last), l1 = (int32_t)qperm<QB1>((uint32_t)last);
+    const int32_t l2 = (int32_t)qperm<QB2>((uint32_t)last);
+    const int32_t cfirst = h0 ? f0 : (h1 ? f1 : (h2 ? f2 : f3));
+    int32_t carry = cfirst;
+    if (q >= 1 && h0) carry = l0;
+    if (q >= 2 && h1) carry = l1;
+    if (q >= 3 && h2) carry = l2;
+    P.carry = carry;
+    uint32_t orl = 0, orq = 0;
+    int32_t prev = carry;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const int32_t kp = ((nzb >> j) & 1u) ? P.kp[j] : prev;
+        P.kp[j] = kp;
+        const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
+        orl |= zigzag(d);
+        orq |= zigzag(kp);
+        prev = kp;
+    }
+    const uint32_t wl = bitlen(quad_or(orl)), wq = bitlen(quad_or(orq));
+    uint32_t sc = 0, zc = 0;
+    if (log_dom) {
+        sc = !(f & 16u) ? 0u : ((f & 8u) ? 2u : 1u);
+        zc = (f >> 16) ? 2u : 0u;
+    }
+    const uint32_t masks = 8u * ((sc == 2u) + (zc == 2u));
+    const uint32_t s_lz = 4u + masks + 8u * wl, s_q0 = masks + 8u * wq;
+    uint32_t mode = M_LZ, best = s_lz;
+    if (s_q0 < best) { mode = M_Q0; best = s_q0; }
+    if (256u < best) { P.hdr = M_VERB; return; }
+    P.w = (mode == M_LZ) ? wl : wq;
+    P.hdr = mode | (P.w << 2) | (sc << 8) | (zc << 10);
+    P.anchor = P.kp[0];
+}
+
+// Store this lane's part of a plane's payload: packed planes as 16 w-bit
+// fields from bit 16 w q of the payload (LSB-first), VERBATIM planes as the
+// 16 raw values from word 16 q.  When w is odd the lanes q = 1, 3 start in
+// the middle of a word whose low half the previous lane fills; that word is
+// assembled from both lanes and stored once.
+__device__ __forceinline__ void store_quad_payload(const QuadPlane &P, const float *x, uint32_t *pay, int q)
+{
+    const uint32_t mode = P.hdr & 3u;
+    if (mode == M_VERB) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) pay[16 * q + j] = __float_as_uint(x[j]);
+        return;
+    }
+    const uint32_t w = P.w;
+    uint32_t lead = 0;
+    const bool packed = mode != M_ZERO && w != 0u;
+    uint64_t acc = 0;
+    uint32_t nb = 0, wi = 0, off = 0;
+    bool pending = false;
+    if (packed) {
+        const uint32_t start = 16u * w * (uint32_t)q;
+        wi = start >> 5;
+        off = start & 31u;
+        nb = off;
+        pending = off != 0u;
+        int32_t prev = P.carry;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int32_t kp = P.kp[j];
+            const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
+            prev = kp;
+            const uint32_t fld = (mode == M_LZ) ? zigzag(d) : zigzag(kp);
+            acc |= (uint64_t)fld << nb;
+            nb += w;
+            if (nb >= 32u) {
+                if (pending) {
+                    lead = (uint32_t)acc;
+                    pending = false;
+                } else {
+                    pay[wi] = (uint32_t)acc;
+                }
+                ++wi;
+                acc >>= 32;
+                nb -= 32u;
+            }
+        }
+    }
+    // the low half-word an even lane leaves over goes to the next lane
+    const uint32_t tail = (packed && nb) ? (uint32_t)acc : 0u;
+    const uint32_t from_prev = qperm<0x90>(tail);      // lane q takes lane q - 1's value
+    if (packed && off) pay[(16u * w * (uint32_t)q) >> 5] = lead | from_prev;
+}
+
 template <int T, int NT>
 struct PassLds {
     static constexpr int TILE = 1 << T, NCH = TILE / kChunk, NW = NT / 64;
-    float re[TILE];
-    float im[TILE];
-    union {
-        float2 tab[1 << kMaxDiagQubits];  // apply phase: diagonal table
-        uint32_t stage[NW][128];          // store phase: payload packing per wave
-    } u;
+    float re[TILE + TILE / 16];           // tile, padded layout (tix)
+    float im[TILE + TILE / 16];
+    float2 tab[1 << kMaxDiagQubits];      // apply phase: diagonal table
     uint32_t hist[6];
 };
 
@@ -772,15 +957,15 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
                 const bool n1 = (m & (1u << 26)) ? ((sw1[u] >> bit) & 1u) : ((m >> 29) & 1u);
                 const bool z0 = (zw0[u] >> bit) & 1u, z1 = (zw1[u] >> bit) & 1u;
                 const int32_t a0 = __builtin_amdgcn_readlane(av0, i), a1 = __builtin_amdgcn_readlane(av1, i);
-                s.re[((c0 + i) << 6) + lane] = decode_value((p >> 28) & 3u, (p >> 16) & 63u, a0, lo0[u], hi0[u], n0, z0, cp);
-                s.im[((c0 + i) << 6) + lane] = decode_value((p >> 30) & 3u, (p >> 22) & 63u, a1, lo1[u], hi1[u], n1, z1, cp);
+                s.re[tix(((c0 + i) << 6) + lane)] = decode_value((p >> 28) & 3u, (p >> 16) & 63u, a0, lo0[u], hi0[u], n0, z0, cp);
+                s.im[tix(((c0 + i) << 6) + lane)] = decode_value((p >> 30) & 3u, (p >> 22) & 63u, a1, lo1[u], hi1[u], n1, z1, cp);
             }
         }
     } else {
         for (int i = 0; i < CPW; ++i) {
             const uint64_t g = lane_u64(my_g, i);
-            s.re[((c0 + i) << 6) + lane] = a.scr_re[g + lane];
-            s.im[((c0 + i) << 6) + lane] = a.scr_im[g + lane];
+            s.re[tix(((c0 + i) << 6) + lane)] = a.scr_re[g + lane];
+            s.im[tix(((c0 + i) << 6) + lane)] = a.scr_im[g + lane];
         }
     }
     __syncthreads();
@@ -790,7 +975,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
         const OpDesc &op = a.ops[o];
         const float2 *data = a.opdata + op.data;
         if (op.type == OP_DIAG) {
-            apply_diag<T, NT>(s.re, s.im, op, data, base, s.u.tab);
+            apply_diag<T, NT>(s.re, s.im, op, data, base, s.tab);
         } else {
             switch (op.k) {
             case 1: apply_dense<1, L::TILE, NT>(s.re, s.im, op, data); break;
@@ -813,59 +998,34 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
     if (a.out_mode == IO_SCRATCH) {
         for (int i = 0; i < CPW; ++i) {
             const uint64_t g = lane_u64(my_g, i);
-            a.scr_re[g + lane] = s.re[((c0 + i) << 6) + lane];
-            a.scr_im[g + lane] = s.im[((c0 + i) << 6) + lane];
+            a.scr_re[g + lane] = s.re[tix(((c0 + i) << 6) + lane)];
+            a.scr_im[g + lane] = s.im[tix(((c0 + i) << 6) + lane)];
         }
         return;
     }
 
-    // encode every chunk; the fields replace the values in LDS and the
-    // chunk's headers, anchors and masks go to lane i of the wave
+    // ---- encode: four lanes per chunk, lane q holding values 16q..16q+15
+    // (see encode_quad); one allocation per wave
     if (threadIdx.x < 6) s.hist[threadIdx.x] = 0;
-    uint32_t hv = 0, av0 = 0, av1 = 0, s0l = 0, s0h = 0, z0l = 0, z0h = 0, s1l = 0, s1h = 0, z1l = 0, z1h = 0;
-    uint32_t hist[4] = {0, 0, 0, 0}, zeros = 0;
-    for (int i = 0; i < CPW; ++i) {
-        const int c = c0 + i;
-        const float xr = s.re[(c << 6) + lane], xi = s.im[(c << 6) + lane];
-        if (a.dump_re) {
-            const uint64_t g = lane_u64(my_g, i);
-            a.dump_re[g + lane] = xr;
-            a.dump_im[g + lane] = xi;
+    const int qc = lane >> 2, q = lane & 3;
+    const bool act = qc < CPW;
+    const int c = c0 + (act ? qc : 0);
+    const uint64_t g = base | deposit((uint64_t)c, a.tileq + 6, T - 6);   // chunk's first amplitude
+    const uint32_t t0 = tix((uint32_t)(c << 6) + 16u * (uint32_t)q);
+    if (a.dump_re && act) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            a.dump_re[g + 16 * q + j] = s.re[t0 + j];
+            a.dump_im[g + 16 * q + j] = s.im[t0 + j];
         }
-        PlaneInfo p0, p1;
-        const uint32_t f0 = encode_plane(xr, 64, cp, p0);
-        const uint32_t f1 = encode_plane(xi, 64, cp, p1);
-        s.re[(c << 6) + lane] = __uint_as_float(f0);
-        s.im[(c << 6) + lane] = __uint_as_float(f1);
-        hv = set_lane(hv, i, (uint32_t)((int)(p0.hdr | (p1.hdr << 12))));
-        av0 = set_lane(av0, i, (uint32_t)(p0.anchor));
-        av1 = set_lane(av1, i, (uint32_t)(p1.anchor));
-        if (p0.smask) {
-            s0l = set_lane(s0l, i, (uint32_t)((int)(uint32_t)p0.smask));
-            s0h = set_lane(s0h, i, (uint32_t)((int)(uint32_t)(p0.smask >> 32)));
-        }
-        if (p0.zmask) {
-            z0l = set_lane(z0l, i, (uint32_t)((int)(uint32_t)p0.zmask));
-            z0h = set_lane(z0h, i, (uint32_t)((int)(uint32_t)(p0.zmask >> 32)));
-        }
-        if (p1.smask) {
-            s1l = set_lane(s1l, i, (uint32_t)((int)(uint32_t)p1.smask));
-            s1h = set_lane(s1h, i, (uint32_t)((int)(uint32_t)(p1.smask >> 32)));
-        }
-        if (p1.zmask) {
-            z1l = set_lane(z1l, i, (uint32_t)((int)(uint32_t)p1.zmask));
-            z1h = set_lane(z1h, i, (uint32_t)((int)(uint32_t)(p1.zmask >> 32)));
-        }
-        hist[p0.hdr & 3u]++;
-        hist[p1.hdr & 3u]++;
-        zeros += (p0.hdr == M_ZERO) && (p1.hdr == M_ZERO);
     }
-
-    // per-chunk body sizes and offsets (lane = chunk), one allocation per wave
-    const bool mine = lane < CPW;
-    const uint32_t h0 = mine ? (hv & 0xFFFu) : 0u, h1 = mine ? (hv >> 12) : 0u;
+    QuadPlane P0, P1;
+    encode_quad(s.re + t0, cp, q, P0);
+    encode_quad(s.im + t0, cp, q, P1);
+    const uint32_t h0 = act ? P0.hdr : 0u, h1 = act ? P1.hdr : 0u;
     const Layout Lv = layout_of(h0, h1);
-    const uint32_t incl = wave_scan_add(Lv.size);
+    const uint32_t size = (q == 0) ? Lv.size : 0u;
+    const uint32_t incl = wave_scan_add(size);
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     const uint32_t seg = ((uint32_t)blockIdx.x * NW + (uint32_t)wave) & (uint32_t)(a.n_seg - 1);
     unsigned long long *cnt = a.counters + seg * C_NUM;
@@ -885,62 +1045,44 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
     if (lane == 0 && overflow) atomicOr(&cnt[C_OVERFLOW], 1ull);
     if (lane == 0 && total && !overflow)
         atomicAdd(&cnt[wave_off < a.pool_cap ? C_DEV_BYTES : C_HOST_BYTES], (unsigned long long)total);
-    const uint64_t off = wave_off + (incl - Lv.size);
-    uint64_t entry = 0;
-    if (h0 | h1) entry = overflow ? kDirInvalid : (off | ((uint64_t)h0 << 40) | ((uint64_t)h1 << 52));
-
-    if (!overflow) {
-        // anchors and masks: each lane writes its own chunk's
-        uint32_t *bw = (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, off);
-        if (mine && Lv.lz0) bw[0] = av0;
-        if (mine && Lv.lz1) bw[Lv.lz0 ? 1 : 0] = av1;
-        if (mine && Lv.hs0) { bw[Lv.off_sm0 >> 2] = s0l; bw[(Lv.off_sm0 >> 2) + 1] = s0h; }
-        if (mine && Lv.hz0) { bw[Lv.off_zm0 >> 2] = z0l; bw[(Lv.off_zm0 >> 2) + 1] = z0h; }
-        if (mine && Lv.hs1) { bw[Lv.off_sm1 >> 2] = s1l; bw[(Lv.off_sm1 >> 2) + 1] = s1h; }
-        if (mine && Lv.hz1) { bw[Lv.off_zm1 >> 2] = z1l; bw[(Lv.off_zm1 >> 2) + 1] = z1h; }
-        // payloads, chunk by chunk: VERBATIM planes store straight from the
-        // lanes, packed planes go through the wave's LDS stage
-        const uint32_t pay = pack_pay(Lv);
-        uint32_t *stage = s.u.stage[wave];
-        for (int i = 0; i < CPW; ++i) {
-            const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)pay, i);
-            const uint32_t m0 = (p >> 28) & 3u, m1 = (p >> 30) & 3u;
-            if (m0 == M_ZERO && m1 == M_ZERO) continue;
-            const int c = c0 + i;
-            uint32_t *dst = (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, lane_u64(off, i));
-            const uint32_t f0 = __float_as_uint(s.re[(c << 6) + lane]);
-            const uint32_t f1 = __float_as_uint(s.im[(c << 6) + lane]);
-            const uint32_t w0 = (p >> 16) & 63u, w1 = (p >> 22) & 63u;
-            const uint32_t q0 = (m0 == M_LZ || m0 == M_Q0) ? 2u * w0 : 0u;   // packed words
-            const uint32_t q1 = (m1 == M_LZ || m1 == M_Q0) ? 2u * w1 : 0u;
-            const uint32_t op0 = (p & 63u) >> 2, op1 = ((p >> 6) & 1023u) >> 2;
-            if (m0 == M_VERB) dst[op0 + lane] = f0;
-            if (m1 == M_VERB) dst[op1 + lane] = f1;
-            if (q0 + q1) {
-                for (uint32_t k = lane; k < q0 + q1; k += 64) stage[k] = 0u;
-                wave_sync_lds();
-                if (q0) pack_field(stage, f0, w0);
-                if (q1) pack_field(stage + q0, f1, w1);
-                wave_sync_lds();
-                const uint32_t ob = q0 ? op0 : op1;        // packed planes are contiguous
-                for (uint32_t k = lane; k < q0 + q1; k += 64) dst[ob + k] = stage[k];
-                wave_sync_lds();
-            }
+    // the chunk's body offset, from its quad's lane 0
+    const uint32_t rel = qperm<QB0>(incl - size);
+    const uint64_t off = wave_off + rel;
+    if (act && !overflow && (h0 | h1)) {
+        uint8_t *body = (uint8_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, off);
+        if (q == 0) {
+            if (Lv.lz0) *(int32_t *)body = P0.anchor;
+            if (Lv.lz1) *(int32_t *)(body + (Lv.lz0 ? 4 : 0)) = P1.anchor;
         }
+        // each lane stores its 16 bits of the mixed masks
+        if (Lv.hs0) *(uint16_t *)(body + Lv.off_sm0 + 2 * q) = (uint16_t)P0.negb;
+        if (Lv.hz0) *(uint16_t *)(body + Lv.off_zm0 + 2 * q) = (uint16_t)(~P0.nzb);
+        if (Lv.hs1) *(uint16_t *)(body + Lv.off_sm1 + 2 * q) = (uint16_t)P1.negb;
+        if (Lv.hz1) *(uint16_t *)(body + Lv.off_zm1 + 2 * q) = (uint16_t)(~P1.nzb);
+        store_quad_payload(P0, s.re + t0, (uint32_t *)(body + Lv.off_p0), q);
+        store_quad_payload(P1, s.im + t0, (uint32_t *)(body + Lv.off_p1), q);
     }
-    if (mine) a.dir_out[my_g >> 6] = entry;
+    if (act && q == 0)
+        a.dir_out[g >> 6] = (h0 | h1) == 0u ? 0ull
+                           : (overflow ? kDirInvalid : (off | ((uint64_t)h0 << 40) | ((uint64_t)h1 << 52)));
 
+    // mode histogram: 8-bit counts per mode packed in one word, summed over the wave
+    const uint32_t hw = (act && q == 0) ? ((1u << (8 * (h0 & 3u))) + (1u << (8 * (h1 & 3u)))) : 0u;
+    const uint32_t zw = (act && q == 0 && (h0 | h1) == 0u) ? 1u : 0u;
+    const uint32_t hsum = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_add(hw), 63);
+    const uint32_t zsum = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_add(zw), 63);
+    __syncthreads();
     if (lane == 0) {
 #pragma unroll
-        for (int m = 0; m < 4; ++m) atomicAdd(&s.hist[m], hist[m]);
-        atomicAdd(&s.hist[4], zeros);
+        for (int m = 0; m < 4; ++m) atomicAdd(&s.hist[m], (hsum >> (8 * m)) & 0xFFu);
+        atomicAdd(&s.hist[4], zsum);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long *c = a.counters + (blockIdx.x & (uint32_t)(a.n_seg - 1)) * C_NUM;
-        if (s.hist[4]) atomicAdd(&c[C_ZERO_CHUNKS], (unsigned long long)s.hist[4]);
-        atomicAdd(&c[C_MODE0], (unsigned long long)s.hist[0] | ((unsigned long long)s.hist[1] << 32));
-        atomicAdd(&c[C_MODE0 + 2], (unsigned long long)s.hist[2] | ((unsigned long long)s.hist[3] << 32));
+        unsigned long long *cc = a.counters + (blockIdx.x & (uint32_t)(a.n_seg - 1)) * C_NUM;
+        if (s.hist[4]) atomicAdd(&cc[C_ZERO_CHUNKS], (unsigned long long)s.hist[4]);
+        atomicAdd(&cc[C_MODE0], (unsigned long long)s.hist[0] | ((unsigned long long)s.hist[1] << 32));
+        atomicAdd(&cc[C_MODE0 + 2], (unsigned long long)s.hist[2] | ((unsigned long long)s.hist[3] << 32));
     }
 }
 

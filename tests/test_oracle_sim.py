@@ -153,3 +153,13 @@ def test_generators_deterministic():
     # controlled phase decomposed into 5 basic gates this is the 2,673 gates
     # it quotes in Section 4.1
     assert len(C.qft_ladder(33)) == 33 + 528 and 33 + 5 * 528 == 2673
+
+
+def test_mirror_returns_to_zero_state():
+    from paper_2410_14088_amd import circuits as C
+    for gates in (C.random_layers(8, 4, seed=3), C.qft_on_ry(7, seed=4)[0], C.qaoa_ring(8, 2, seed=5)[0],
+                  [("S", (0,), ()), ("T", (1,), ()), ("H", (1,), ()), ("RZZ", (0, 2), (0.3,)),
+                   ("CX", (2, 0), ()), ("RX", (1,), (0.7,)), ("Y", (2,), ())]):
+        n = 1 + max(q for _, qs, _ in gates for q in qs)
+        psi = sim.simulate(n, C.mirror(gates))
+        assert abs(abs(psi[0]) - 1) < 1e-12
