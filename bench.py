@@ -206,14 +206,14 @@ def main():
         rng = np.random.default_rng(1)
         idx = rng.integers(0, 1 << n, 4096).astype(np.uint64)
         want = N.qft_ry_amplitudes(n, d["thetas"], idx)
-        got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy()
+        got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy().astype(np.complex128)
         f_est = float(abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real))
         maxerr = float(np.abs(got - want).max())
     else:
         # the mirror circuit returns to |0...0>: F^2 = |psi(0)|^2 / |psi|^2 exactly
-        a0 = sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0]
-        f_est = float(abs(a0) ** 2 / norm2)
-        maxerr = float(abs(abs(a0) - 1.0))
+        a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
+        f_est = abs(a0) ** 2 / norm2
+        maxerr = abs(abs(a0) - 1.0)
 
     out = {
         "metric": METRIC,
