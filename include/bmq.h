@@ -228,6 +228,22 @@ int sv_graph_launch(sv_t *sv, sv_graph_t *g);
 int sv_graph_sync(sv_t *sv);
 void sv_graph_destroy(sv_graph_t *g);
 
+/* ---------------------------------------------------------------- batches
+ * sv_batch_apply -- run every stage of plans[i] on states[i] for count
+ * independent circuits together: launch k executes the k-th tile pass of
+ * every circuit that has one, in one grid over all their tiles (one grid per
+ * tile size), so small circuits share the device instead of running one
+ * after another.  Each state ends exactly as stage_apply_compressed would
+ * leave it (same kernels, same records).  All states must use hip_stream;
+ * each circuit may need at most 1024 pass launches.  workspace_dev: device
+ * memory, 256-byte aligned, of sv_batch_workspace bytes (launch arguments).
+ * Synchronises; on overflow the overflowing states are poisoned and the
+ * first error is returned. */
+int sv_batch_workspace(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
+                       uint64_t *bytes);
+int sv_batch_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
+                   void *workspace_dev, uint64_t workspace_bytes, void *hip_stream);
+
 /* sv_fidelity -- FP64 reductions on the device (Section 5.3 fidelity):
  *   fidelity    = |<ref|psi>|^2 / (|ref|^2 |psi|^2)   (the squared form;
  *                 the paper prints the unsquared |<ref|psi>|)

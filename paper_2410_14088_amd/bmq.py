@@ -56,7 +56,8 @@ EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_destr
            "sv_fidelity", "sv_export", "sv_amplitudes", "sv_footprint", "sv_block_stream",
            "sv_debug_dump", "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
            "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
-           "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune"]
+           "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune",
+           "sv_batch_workspace", "sv_batch_apply"]
 SV_FEATURES, SV_MLP_NPARAM = 32, 6597
 
 _lib = None
@@ -93,6 +94,8 @@ def lib():
         L.codec_decode_chunks.argtypes = [V, C.c_uint64, P(sv_config_t), V, V, V]
         L.sv_block_features.argtypes = [V, V, C.c_size_t, V]
         L.sv_graph_capture.argtypes = [V, V, C.c_size_t, C.c_size_t, P(V)]
+        L.sv_batch_workspace.argtypes = [V, V, C.c_size_t, P(C.c_uint64)]
+        L.sv_batch_apply.argtypes = [V, V, C.c_size_t, V, C.c_uint64, V]
         L.sv_autotune.argtypes = [V, C.c_size_t, P(sv_config_t), V, C.c_uint64, V, C.c_size_t, P(sv_config_t),
                                   P(C.c_float)]
         L.sv_graph_launch.argtypes = [V, V]
@@ -328,6 +331,20 @@ def autotune(gates, cfg: Config, probe_stages: int = 0, device: str = "cuda:0"):
     out = Config(n=best.n_qubits, b=best.block_qubits, inner=best.inner_size, fuse=best.fuse_qubits,
                  domain=best.domain, eb=best.eb, tile=best.tile_qubits, pool_bytes=best.pool_bytes, flags=best.flags)
     return out, table
+
+
+def batch_apply(states, plans):
+    """Run every circuit's stages together (sv_batch_apply)."""
+    import torch
+    n = len(states)
+    sa = (C.c_void_p * n)(*[st.h.value for st in states])
+    pa = (C.c_void_p * n)(*[pl.h.value for pl in plans])
+    need = C.c_uint64()
+    _check(lib().sv_batch_workspace(sa, pa, n, C.byref(need)))
+    ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=states[0].arena.device)
+    base = _ptr(ws)
+    off = (-base) % 256
+    _check(lib().sv_batch_apply(sa, pa, n, C.c_void_p(base + off), int(need.value), _stream()))
 
 
 class Graph:

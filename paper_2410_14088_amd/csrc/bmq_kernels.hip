@@ -450,7 +450,8 @@ __device__ uint32_t write_body(uint32_t *stage, const PlaneInfo &p0, const Plane
 }
 
 // bits of v deposited at positions q[0..nq) (bit i of v -> position q[i])
-__device__ __forceinline__ uint64_t deposit(uint64_t v, const int32_t *q, int nq)
+template <class P>
+__device__ __forceinline__ uint64_t deposit(uint64_t v, P q, int nq)
 {
     uint64_t r = 0;
     for (int i = 0; i < nq; ++i) r |= ((v >> i) & 1ull) << q[i];
@@ -477,7 +478,7 @@ __device__ __forceinline__ float2 const_ld(const float2 *p, int i)
 __device__ __forceinline__ uint32_t tix(uint32_t e) { return e + (e >> 4); }
 
 template <int K, int TILE, int NT>
-__device__ void apply_dense(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M)
+__device__ __forceinline__ void apply_dense(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M)
 {
     constexpr int D = 1 << K;
     constexpr int UNR = K <= 3 ? D : 1;
@@ -545,7 +546,7 @@ __device__ __forceinline__ float block_elem(const float2 *__restrict__ M, int i,
 }
 
 template <int K, int TILE, int NT>
-__device__ void apply_dense_mfma(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M)
+__device__ __forceinline__ void apply_dense_mfma(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M)
 {
     constexpr int D = 1 << K, G = TILE >> K, RB = 2 * D / 32, STEPS = D;   // row blocks, k-steps of 2
     static_assert(G % 32 == 0, "column blocks of 32 groups");
@@ -601,7 +602,7 @@ __device__ void apply_dense_mfma(float *sre, float *sim, const OpDesc &op, const
 // per-thread part (bits of tid and the tile-constant bits) and a per-m part
 // built from wave-uniform words, so each amplitude costs one OR and a lookup.
 template <int T, int NT>
-__device__ void apply_diag(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ tab, uint64_t base,
+__device__ __forceinline__ void apply_diag(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ tab, uint64_t base,
                            float2 *s_tab)
 {
     constexpr int TILE = 1 << T;
@@ -892,8 +893,25 @@ struct PassLds {
     uint32_t hist[6];
 };
 
-template <int T, int NT>
-__global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
+__device__ __forceinline__ CodecParams copy_cp(const CodecParams &c) { return c; }
+
+template <class C>
+__device__ __forceinline__ CodecParams copy_cp(const C &c)
+{
+    CodecParams r;
+    r.domain = c.domain;
+    r.s = c.s;
+    r.ebf = c.ebf;
+    r.delta = c.delta;
+    r.scale = c.scale;
+    r.code_ok = c.code_ok;
+    return r;
+}
+
+// A is PassArgs, or PassArgs in the constant address space (arguments that a
+// batched launch reads from device memory with scalar loads)
+template <int T, int NT, class A>
+__device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
 {
     using L = PassLds<T, NT>;
     constexpr int NCH = L::NCH, NW = L::NW, CPW = NCH / NW;
@@ -902,8 +920,8 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
 
     const int lane = lane_id();
     const int wave = (int)(threadIdx.x >> 6);
-    const CodecParams cp = a.cp;
-    const uint64_t base = deposit((uint64_t)blockIdx.x, a.nontile, a.n_nontile);
+    const CodecParams cp = copy_cp(a.cp);
+    const uint64_t base = deposit((uint64_t)tile, a.nontile, a.n_nontile);
     const int c0 = wave * CPW;
 
     // global index of the chunk this lane stands for (lane < CPW)
@@ -1027,7 +1045,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
     const uint32_t size = (q == 0) ? Lv.size : 0u;
     const uint32_t incl = wave_scan_add(size);
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    const uint32_t seg = ((uint32_t)blockIdx.x * NW + (uint32_t)wave) & (uint32_t)(a.n_seg - 1);
+    const uint32_t seg = (tile * NW + (uint32_t)wave) & (uint32_t)(a.n_seg - 1);
     unsigned long long *cnt = a.counters + seg * C_NUM;
     unsigned long long got = 0;
     if (lane == 0 && total) got = atomicAdd(&cnt[C_CURSOR], (unsigned long long)total);
@@ -1079,11 +1097,33 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        unsigned long long *cc = a.counters + (blockIdx.x & (uint32_t)(a.n_seg - 1)) * C_NUM;
+        unsigned long long *cc = a.counters + (tile & (uint32_t)(a.n_seg - 1)) * C_NUM;
         if (s.hist[4]) atomicAdd(&cc[C_ZERO_CHUNKS], (unsigned long long)s.hist[4]);
         atomicAdd(&cc[C_MODE0], (unsigned long long)s.hist[0] | ((unsigned long long)s.hist[1] << 32));
         atomicAdd(&cc[C_MODE0 + 2], (unsigned long long)s.hist[2] | ((unsigned long long)s.hist[3] << 32));
     }
+}
+
+template <int T, int NT>
+__global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
+{
+    pass_body<T, NT, PassArgs>(a, blockIdx.x);
+}
+
+// One launch over the tiles of several states (independent circuits): state
+// i owns blocks [first_block[i], first_block[i + 1]) and its own arguments.
+template <int T, int NT>
+__global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_batch(const PassArgs *__restrict__ args,
+                                                                   const uint32_t *__restrict__ first_block, int n)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (first_block[mid] <= blockIdx.x) lo = mid;
+        else hi = mid;
+    }
+    typedef const __attribute__((address_space(4))) PassArgs CArgs;
+    pass_body<T, NT, CArgs>(((CArgs *)args)[lo], blockIdx.x - first_block[lo]);
 }
 
 // ------------------------------------------------------------------ utility kernels
@@ -1339,6 +1379,20 @@ hipError_t launch_pass(const PassArgs &a, hipStream_t s)
     case 11: hipLaunchKernelGGL((pass_kernel<11, 256>), grid, dim3(256), 0, s, a); break;
     case 12: hipLaunchKernelGGL((pass_kernel<12, 256>), grid, dim3(256), 0, s, a); break;
     case 13: hipLaunchKernelGGL((pass_kernel<13, 512>), grid, dim3(512), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_batch(int t, const PassArgs *args_dev, const uint32_t *first_block_dev, int n,
+                             uint32_t blocks, hipStream_t s)
+{
+    const dim3 grid(blocks);
+    switch (t) {
+    case 10: hipLaunchKernelGGL((pass_kernel_batch<10, 256>), grid, dim3(256), 0, s, args_dev, first_block_dev, n); break;
+    case 11: hipLaunchKernelGGL((pass_kernel_batch<11, 256>), grid, dim3(256), 0, s, args_dev, first_block_dev, n); break;
+    case 12: hipLaunchKernelGGL((pass_kernel_batch<12, 256>), grid, dim3(256), 0, s, args_dev, first_block_dev, n); break;
+    case 13: hipLaunchKernelGGL((pass_kernel_batch<13, 512>), grid, dim3(512), 0, s, args_dev, first_block_dev, n); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -707,9 +707,9 @@ int upload_plan(sv_t *sv, const sv_plan_t *p)
     return SV_OK;
 }
 
-// Enqueue pass pi of stage st on stream s with counter block li; flips the
-// state's current copy when the pass writes compressed output.
-int enqueue_pass(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, size_t li, hipStream_t s)
+// Arguments of pass pi of stage st with counter block li; flips the state's
+// current copy when the pass writes compressed output.
+void build_pass_args(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, size_t li, bmq::PassArgs &a)
 {
     const int n = sv->n;
     const bool scratch = sv->scr_re != nullptr;
@@ -719,7 +719,6 @@ int enqueue_pass(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, size
     const uint64_t waves = (1ull << (n - p->t)) * (p->t == 13 ? 8u : 4u);
     const int n_seg = (int)std::min<uint64_t>((uint64_t)bmq::kSegments, waves);
     const PassPlan &pp = st.passes[pi];
-    bmq::PassArgs a;
     std::memset(&a, 0, sizeof(a));
     a.n = n;
     a.t = p->t;
@@ -753,8 +752,15 @@ int enqueue_pass(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, size
     a.dump_re = sv->dump_re;
     a.dump_im = sv->dump_im;
     a.mfma = (sv->cfg.flags & SV_FLAG_NO_MFMA) ? 0 : 1;
-    HIP_TRY(bmq::launch_pass(a, s));
     if (a.out_mode == bmq::IO_COMPRESSED) sv->cur ^= 1;
+}
+
+// Enqueue pass pi of stage st on stream s with counter block li.
+int enqueue_pass(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, size_t li, hipStream_t s)
+{
+    bmq::PassArgs a;
+    build_pass_args(sv, p, st, pi, li, a);
+    HIP_TRY(bmq::launch_pass(a, s));
     return SV_OK;
 }
 
@@ -764,6 +770,56 @@ size_t launches_of(const sv_plan_t *p, size_t first, size_t batch)
     size_t l = 0;
     for (size_t i = 0; i < batch; ++i) l += p->stages[first + i].passes.size();
     return l;
+}
+
+// The batched launches of several states: launch k runs the k-th pass of
+// every state that has one, grouped by tile size.
+struct BatchGroup {
+    size_t k;
+    int t;
+    std::vector<size_t> members;     // state indices
+    uint64_t args_off, fb_off;       // workspace offsets
+    uint32_t blocks;
+};
+
+int plan_batch(sv_t *const *states, const sv_plan_t *const *plans, size_t count, std::vector<BatchGroup> &groups,
+               uint64_t &bytes)
+{
+    if (!states || !plans || count == 0) return fail(SV_ERR_INVALID, "empty batch");
+    size_t kmax = 0;
+    for (size_t i = 0; i < count; ++i) {
+        if (int rc = check_state(states[i])) return rc;
+        if (int rc = check_plan(states[i], plans[i], 0, plans[i] ? plans[i]->stages.size() : 0)) return rc;
+        for (size_t j = 0; j < i; ++j)
+            if (states[j] == states[i]) return fail(SV_ERR_INVALID, "state %zu appears twice in the batch", i);
+        if (states[i]->dump_re) return fail(SV_ERR_UNSUPPORTED, "the debug dump cannot run in a batch");
+        const size_t l = launches_of(plans[i], 0, plans[i]->stages.size());
+        if (l > kMaxLaunchesPerBatch)
+            return fail(SV_ERR_UNSUPPORTED, "circuit %zu needs %zu pass launches (at most %zu in a batch)", i, l,
+                        kMaxLaunchesPerBatch);
+        kmax = std::max(kmax, l);
+    }
+    groups.clear();
+    bytes = 0;
+    for (size_t k = 0; k < kmax; ++k)
+        for (int t = 10; t <= bmq::kMaxTile; ++t) {
+            BatchGroup g{k, t, {}, 0, 0, 0};
+            uint64_t blocks = 0;
+            for (size_t i = 0; i < count; ++i)
+                if (plans[i]->t == t && launches_of(plans[i], 0, plans[i]->stages.size()) > k) {
+                    g.members.push_back(i);
+                    blocks += 1ull << (states[i]->n - t);
+                }
+            if (g.members.empty()) continue;
+            if (blocks > 0x7FFFFFFFull) return fail(SV_ERR_UNSUPPORTED, "a batched launch exceeds 2^31 workgroups");
+            g.blocks = (uint32_t)blocks;
+            g.args_off = bytes;
+            bytes += align256(g.members.size() * sizeof(bmq::PassArgs));
+            g.fb_off = bytes;
+            bytes += align256((g.members.size() + 1) * sizeof(uint32_t));
+            groups.push_back(std::move(g));
+        }
+    return SV_OK;
 }
 
 // Read the counter blocks of stages [first, first + batch) (host copy hc),
@@ -1049,6 +1105,79 @@ void sv_graph_destroy(sv_graph_t *g)
     if (g->x) (void)hipGraphExecDestroy(g->x);
     if (g->g) (void)hipGraphDestroy(g->g);
     delete g;
+}
+
+int sv_batch_workspace(sv_t *const *states, const sv_plan_t *const *plans, size_t count, uint64_t *bytes)
+{
+    if (!bytes) return fail(SV_ERR_INVALID, "bytes is NULL");
+    std::vector<BatchGroup> groups;
+    return plan_batch(states, plans, count, groups, *bytes);
+}
+
+int sv_batch_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t count, void *workspace_dev,
+                   uint64_t workspace_bytes, void *hip_stream)
+{
+    std::vector<BatchGroup> groups;
+    uint64_t need = 0;
+    if (int rc = plan_batch(states, plans, count, groups, need)) return rc;
+    if (!workspace_dev || ((uintptr_t)workspace_dev & 255u) || workspace_bytes < need)
+        return fail(SV_ERR_INVALID, "workspace must be 256-byte aligned and hold %llu bytes", (unsigned long long)need);
+    hipStream_t stream = (hipStream_t)hip_stream;
+    for (size_t i = 0; i < count; ++i)
+        if (states[i]->stream != stream)
+            return fail(SV_ERR_INVALID, "state %zu was created on another stream", i);
+    for (size_t i = 0; i < count; ++i) {
+        if (int rc = resolve_graph(states[i])) return rc;
+        if (int rc = upload_plan(states[i], plans[i])) return rc;
+    }
+    // every state's pass arguments in launch order (the current pool copy
+    // advances as stage_apply_compressed would advance it)
+    std::vector<std::vector<bmq::PassArgs>> args(count);
+    for (size_t i = 0; i < count; ++i) {
+        sv_t *sv = states[i];
+        const sv_plan_t *p = plans[i];
+        size_t li = 0;
+        for (const StagePlan &st : p->stages)
+            for (int pi = 0; pi < (int)st.passes.size(); ++pi, ++li) {
+                bmq::PassArgs a;
+                build_pass_args(sv, p, st, pi, li, a);
+                args[i].push_back(a);
+            }
+    }
+    std::vector<uint8_t> host(need, 0);
+    for (const BatchGroup &g : groups) {
+        bmq::PassArgs *ga = (bmq::PassArgs *)(host.data() + g.args_off);
+        uint32_t *fb = (uint32_t *)(host.data() + g.fb_off);
+        uint32_t acc = 0;
+        for (size_t m = 0; m < g.members.size(); ++m) {
+            const size_t i = g.members[m];
+            ga[m] = args[i][g.k];
+            fb[m] = acc;
+            acc += (uint32_t)(1ull << (states[i]->n - g.t));
+        }
+        fb[g.members.size()] = acc;
+    }
+    uint8_t *ws = (uint8_t *)workspace_dev;
+    HIP_TRY(hipMemcpyAsync(ws, host.data(), need, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));          // the host image is pageable
+    for (size_t i = 0; i < count; ++i)
+        HIP_TRY(bmq::launch_fill_u64((uint64_t *)states[i]->counters, args[i].size() * kStageCounters, 0, stream));
+    for (const BatchGroup &g : groups)
+        HIP_TRY(bmq::launch_pass_batch(g.t, (const bmq::PassArgs *)(ws + g.args_off), (const uint32_t *)(ws + g.fb_off),
+                                       (int)g.members.size(), g.blocks, stream));
+    std::vector<unsigned long long> hc;
+    int first_err = SV_OK;
+    std::string err;
+    for (size_t i = 0; i < count; ++i) {
+        int rc = read_counters(states[i], args[i].size(), hc);
+        if (rc == SV_OK) rc = collect_stages(states[i], plans[i], 0, plans[i]->stages.size(), hc, nullptr);
+        if (rc != SV_OK && first_err == SV_OK) {
+            first_err = rc;
+            err = g_err;
+        }
+    }
+    if (first_err != SV_OK) g_err = err;
+    return first_err;
 }
 
 int sv_fidelity(const sv_t *sv, const double *ref_dev, double *fidelity, double *max_abs_err, double *norm2)

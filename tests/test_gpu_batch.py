@@ -1,0 +1,110 @@
+"""Batched multi-circuit stage loop (sv_batch_apply) on the GPU: every
+circuit of a batch ends with exactly the records of its own eager run."""
+import time
+
+import numpy as np
+import pytest
+
+from oracle import native as N
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2410_14088_amd import bmq  # noqa: E402
+from paper_2410_14088_amd import circuits as C  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def _mix():
+    out = []
+    for j, d in enumerate(C.batch_mix(12, seed0=7000, nmin=12, nmax=16)):
+        out.append(dict(gates=d["gates"], n=d["n"], b=d["n"] - 4, domain=j % 2, eb=1e-5 if j % 2 else 1e-6,
+                        fuse=2 + j % 4, tile=10 if j % 3 == 0 else 0))
+    out.append(dict(gates=C.ghz(14), n=14, b=8, domain=1, eb=1e-5, fuse=2, tile=0))
+    return out
+
+
+def _make(d, **kw):
+    cfg = bmq.Config(n=d["n"], b=d["b"], inner=2, fuse=d["fuse"], domain=d["domain"], eb=d["eb"], tile=d["tile"],
+                     **kw)
+    return bmq.Plan(d["gates"], cfg), bmq.State(cfg, DEV)
+
+
+def test_batch_equals_individual_runs():
+    mix = _mix()
+    eager, batched, plans = [], [], []
+    for d in mix:
+        p, s = _make(d)
+        s.apply(p)
+        eager.append(s)
+        p2, s2 = _make(d)
+        plans.append(p2)
+        batched.append(s2)
+    print(f"batch of {len(mix)} circuits", flush=True)
+    bmq.batch_apply(batched, plans)
+    for i, (a, b) in enumerate(zip(eager, batched)):
+        assert a.footprint() == b.footprint(), i
+        for k in range(a.n_blocks):
+            assert a.block_stream(k) == b.block_stream(k), (i, k)
+    # one of them against the FP64 oracle
+    d = mix[1]
+    ref = torch.from_numpy(np.ascontiguousarray(N.simulate(d["n"], d["gates"]))).to(DEV)
+    f2, _, _ = batched[1].fidelity(ref)
+    assert f2 >= 0.9999
+
+
+def test_batch_twice_continues_from_the_current_state():
+    d = _mix()[2]
+    p, s = _make(d)
+    s.apply(p)
+    s.apply(p)
+    p2, s2 = _make(d)
+    bmq.batch_apply([s2], [p2])
+    bmq.batch_apply([s2], [p2])
+    assert all(s.block_stream(k) == s2.block_stream(k) for k in range(s.n_blocks))
+
+
+def test_batch_overflow_is_reported():
+    mix = _mix()
+    p0, s0 = _make(mix[0])
+    p1, s1 = _make(mix[1], pool_bytes=4096)
+    with pytest.raises(bmq.BmqError) as e:
+        bmq.batch_apply([s0, s1], [p0, p1])
+    assert e.value.code == -3
+    # the state that fit is complete and correct
+    pe, se = _make(mix[0])
+    se.apply(pe)
+    assert all(se.block_stream(k) == s0.block_stream(k) for k in range(se.n_blocks))
+
+
+def test_batch_rejects_duplicates():
+    d = _mix()[0]
+    p, s = _make(d)
+    with pytest.raises(bmq.BmqError):
+        bmq.batch_apply([s, s], [p, p])
+
+
+def test_batch_throughput_vs_sequential():
+    mix = C.batch_mix(48, seed0=5000, nmin=14, nmax=18)
+    states, plans, amp_gates = [], [], 0
+    for d in mix:
+        cfg = bmq.Config(n=d["n"], b=d["n"] - 4, inner=2, fuse=4, domain=1, eb=1e-5)
+        plans.append(bmq.Plan(d["gates"], cfg))
+        states.append(bmq.State(cfg, DEV))
+        amp_gates += (1 << d["n"]) * len(d["gates"])
+    for st, p in zip(states, plans):          # warm-up
+        st.apply(p)
+    for mode in ("sequential", "batched"):
+        for st in states:
+            st.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "batched":
+            bmq.batch_apply(states, plans)
+        else:
+            for st, p in zip(states, plans):
+                st.apply(p)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        print(f"{mode}: {dt * 1e3:.1f} ms, {amp_gates / dt:.3e} amplitude*gates/s", flush=True)
