@@ -35,9 +35,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="qft", choices=["qft", "random-mirror"],
+    ap.add_argument("--workload", default="qft", choices=["qft", "random-mirror", "batch"],
                     help="qft: QFT on an Ry product (default, 30 qubits); random-mirror: random U3/CZ layers "
-                         "(33 qubits, depth 16) followed by their inverse")
+                         "(33 qubits, depth 16) followed by their inverse; batch: 512 uneven circuits of "
+                         "18-26 qubits run together (sv_batch_apply) and one after another")
+    ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--n", type=int, default=0, help="qubits (default: 30 for qft, 33 for random-mirror)")
     ap.add_argument("--flags", type=int, default=0, help="sv_config_t flags (1 no scratch, 2 no MFMA)")
     ap.add_argument("--tile", type=int, default=0)
@@ -126,8 +128,53 @@ def cpu_baseline(n: int):
                        f"(1 thread) + FP64 OpenMP gate application, {dt:.1f} s")
 
 
+def bench_batch(args):
+    """Many independent circuits: the batched launch against the per-circuit
+    loop on the same states and plans (identical records either way)."""
+    import torch
+    from paper_2410_14088_amd import bmq
+    from paper_2410_14088_amd import circuits as C
+    mix = C.batch_mix(args.batch_count)
+    flags = args.flags or 1                     # no scratch planes: 512 arenas must fit together
+    states, plans, amp_gates = [], [], 0
+    for d in mix:
+        cfg = bmq.Config(n=d["n"], b=d["n"] - 8, inner=2, fuse=args.fuse or 4, domain=1, eb=1e-5, flags=flags)
+        plans.append(bmq.Plan(d["gates"], cfg))
+        states.append(bmq.State(cfg, "cuda:0"))
+        amp_gates += (1 << d["n"]) * len(d["gates"])
+    res = {}
+    for mode in ["batched"] * args.warmup + ["batched", "sequential"]:
+        for st in states:
+            st.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if mode == "batched":
+            bmq.batch_apply(states, plans)
+        else:
+            for st, p in zip(states, plans):
+                st.apply(p)
+        torch.cuda.synchronize()
+        res[mode] = time.perf_counter() - t0
+    fp = sum(st.footprint()[0] for st in states)
+    out = {
+        "metric": METRIC, "value": amp_gates / res["batched"], "unit": "amplitude·gates/s", "n_gpus": 1,
+        "steps": 1, "warmup": args.warmup, "ms_per_step": res["batched"] * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch-{len(mix)}-circuits-18-26q", "circuits": len(mix),
+                   "amplitudes": sum(1 << d["n"] for d in mix), "amp_gates": amp_gates, "domain": "log",
+                   "eb": 1e-5, "fuse_qubits": args.fuse or 4, "flags": flags, "block_qubits": "n-8"},
+        "sequential_value": amp_gates / res["sequential"], "sequential_ms": res["sequential"] * 1e3,
+        "speedup_vs_sequential": res["sequential"] / res["batched"],
+        "compression_ratio_vs_complex64": sum(8 << d["n"] for d in mix) / fp,
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.workload == "batch" and args.gpus == 1 and not args.copy_calibration:
+        bench_batch(args)
+        return
     if args.copy_calibration:
         copy_calibration()
         return

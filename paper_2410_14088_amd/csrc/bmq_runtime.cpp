@@ -48,7 +48,7 @@ constexpr int kMaxDiagQubits = bmq::kMaxDiagQubits;
 constexpr size_t kMaxLaunchesPerBatch = 1024;   // counter blocks of one batch of pass launches
 constexpr size_t kStageCounters = (size_t)bmq::kSegments * bmq::C_NUM;   // words per launch
 constexpr int kPartials = 1024;
-constexpr uint64_t kOpsArenaBytes = 64ull << 20;
+constexpr uint64_t kOpsArenaBytes = 16ull << 20;   // fused matrices and diagonal tables of one plan
 
 // ------------------------------------------------------------------ gates
 
