@@ -96,8 +96,8 @@ struct PassArgs {
 // ---- launch wrappers (bmq_kernels.hip) ----
 hipError_t launch_pass(const PassArgs &a, hipStream_t s);
 // first_block_dev[i]: first block of state i (ascending, first_block_dev[0] = 0);
-// blocks: the total; every state in the launch uses tile size t
-hipError_t launch_pass_batch(int t, const PassArgs *args_dev, const uint32_t *first_block_dev, int n,
+// blocks: the total; every state in the launch uses tile size t and codec domain
+hipError_t launch_pass_batch(int t, int domain, const PassArgs *args_dev, const uint32_t *first_block_dev, int n,
                              uint32_t blocks, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_init_state(uint64_t *dir, uint64_t n_chunks, uint8_t *pool,

@@ -339,8 +339,9 @@ __device__ __forceinline__ ChunkRegs load_body(uint32_t h0, uint32_t h1, const u
 // Decode this lane's value of one plane.  mode, w (<= 32) and anchor are
 // wave-uniform; lo/hi are the two payload words holding the lane's field (for
 // VERBATIM, lo is the raw value); neg/zero are the lane's sign and zero flags.
-__device__ __forceinline__ float decode_value(uint32_t mode, uint32_t w, int32_t anchor, uint32_t lo, uint32_t hi,
-                                              bool neg, bool zero, const CodecParams &cp)
+template <int DOM>
+__device__ __forceinline__ float decode_value_d(uint32_t mode, uint32_t w, int32_t anchor, uint32_t lo, uint32_t hi,
+                                                bool neg, bool zero, const CodecParams &cp)
 {
     const int lane = lane_id();
     if (mode == M_ZERO) return 0.0f;
@@ -358,10 +359,17 @@ __device__ __forceinline__ float decode_value(uint32_t mode, uint32_t w, int32_t
     } else {
         k = unzigzag(field);
     }
-    if (cp.domain == 0) return (float)k * cp.delta;
+    if (DOM == 0) return (float)k * cp.delta;
     if (zero) return 0.0f;
     const float mag = log_decode(k, cp.s, cp.delta);
     return neg ? -mag : mag;
+}
+
+__device__ __forceinline__ float decode_value(uint32_t mode, uint32_t w, int32_t anchor, uint32_t lo, uint32_t hi,
+                                              bool neg, bool zero, const CodecParams &cp)
+{
+    return cp.domain == 1 ? decode_value_d<1>(mode, w, anchor, lo, hi, neg, zero, cp)
+                          : decode_value_d<0>(mode, w, anchor, lo, hi, neg, zero, cp);
 }
 
 __device__ __forceinline__ float decode_plane(uint32_t h, int32_t anchor, uint64_t smask, uint64_t zmask,
@@ -742,9 +750,10 @@ struct QuadPlane {
 };
 
 // Encode one plane of a chunk; x points at this lane's 16 values (LDS).
+template <int DOM>
 __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &cp, int q, QuadPlane &P)
 {
-    const bool log_dom = cp.domain == 1;
+    constexpr bool log_dom = DOM == 1;
     uint32_t nzb = 0, negb = 0, bad = 0, anynz = 0;
     int32_t first = 0, last = 0;
     bool seen = false;
@@ -910,7 +919,7 @@ __device__ __forceinline__ CodecParams copy_cp(const C &c)
 
 // A is PassArgs, or PassArgs in the constant address space (arguments that a
 // batched launch reads from device memory with scalar loads)
-template <int T, int NT, class A>
+template <int T, int NT, int DOM, class A>
 __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
 {
     using L = PassLds<T, NT>;
@@ -975,8 +984,8 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
                 const bool n1 = (m & (1u << 26)) ? ((sw1[u] >> bit) & 1u) : ((m >> 29) & 1u);
                 const bool z0 = (zw0[u] >> bit) & 1u, z1 = (zw1[u] >> bit) & 1u;
                 const int32_t a0 = __builtin_amdgcn_readlane(av0, i), a1 = __builtin_amdgcn_readlane(av1, i);
-                s.re[tix(((c0 + i) << 6) + lane)] = decode_value((p >> 28) & 3u, (p >> 16) & 63u, a0, lo0[u], hi0[u], n0, z0, cp);
-                s.im[tix(((c0 + i) << 6) + lane)] = decode_value((p >> 30) & 3u, (p >> 22) & 63u, a1, lo1[u], hi1[u], n1, z1, cp);
+                s.re[tix(((c0 + i) << 6) + lane)] = decode_value_d<DOM>((p >> 28) & 3u, (p >> 16) & 63u, a0, lo0[u], hi0[u], n0, z0, cp);
+                s.im[tix(((c0 + i) << 6) + lane)] = decode_value_d<DOM>((p >> 30) & 3u, (p >> 22) & 63u, a1, lo1[u], hi1[u], n1, z1, cp);
             }
         }
     } else {
@@ -1038,8 +1047,8 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         }
     }
     QuadPlane P0, P1;
-    encode_quad(s.re + t0, cp, q, P0);
-    encode_quad(s.im + t0, cp, q, P1);
+    encode_quad<DOM>(s.re + t0, cp, q, P0);
+    encode_quad<DOM>(s.im + t0, cp, q, P1);
     const uint32_t h0 = act ? P0.hdr : 0u, h1 = act ? P1.hdr : 0u;
     const Layout Lv = layout_of(h0, h1);
     const uint32_t size = (q == 0) ? Lv.size : 0u;
@@ -1104,15 +1113,15 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     }
 }
 
-template <int T, int NT>
+template <int T, int NT, int DOM>
 __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
 {
-    pass_body<T, NT, PassArgs>(a, blockIdx.x);
+    pass_body<T, NT, DOM, PassArgs>(a, blockIdx.x);
 }
 
 // One launch over the tiles of several states (independent circuits): state
 // i owns blocks [first_block[i], first_block[i + 1]) and its own arguments.
-template <int T, int NT>
+template <int T, int NT, int DOM>
 __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_batch(const PassArgs *__restrict__ args,
                                                                    const uint32_t *__restrict__ first_block, int n)
 {
@@ -1123,7 +1132,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_batch(const PassArg
         else hi = mid;
     }
     typedef const __attribute__((address_space(4))) PassArgs CArgs;
-    pass_body<T, NT, CArgs>(((CArgs *)args)[lo], blockIdx.x - first_block[lo]);
+    pass_body<T, NT, DOM, CArgs>(((CArgs *)args)[lo], blockIdx.x - first_block[lo]);
 }
 
 // ------------------------------------------------------------------ utility kernels
@@ -1374,25 +1383,31 @@ hipError_t launch_pass(const PassArgs &a, hipStream_t s)
     const uint64_t tiles = 1ull << (a.n - a.t);
     if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
     const dim3 grid((unsigned)tiles);
-    switch (a.t) {
-    case 10: hipLaunchKernelGGL((pass_kernel<10, 256>), grid, dim3(256), 0, s, a); break;
-    case 11: hipLaunchKernelGGL((pass_kernel<11, 256>), grid, dim3(256), 0, s, a); break;
-    case 12: hipLaunchKernelGGL((pass_kernel<12, 256>), grid, dim3(256), 0, s, a); break;
-    case 13: hipLaunchKernelGGL((pass_kernel<13, 512>), grid, dim3(512), 0, s, a); break;
+    const int key = a.t * 2 + (a.cp.domain == 1 ? 1 : 0);
+    switch (key) {
+#define BMQ_PASS(T, NT, D) \
+    case T * 2 + D: hipLaunchKernelGGL((pass_kernel<T, NT, D>), grid, dim3(NT), 0, s, a); break;
+    BMQ_PASS(10, 256, 0) BMQ_PASS(10, 256, 1) BMQ_PASS(11, 256, 0) BMQ_PASS(11, 256, 1)
+    BMQ_PASS(12, 256, 0) BMQ_PASS(12, 256, 1) BMQ_PASS(13, 512, 0) BMQ_PASS(13, 512, 1)
+#undef BMQ_PASS
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_pass_batch(int t, const PassArgs *args_dev, const uint32_t *first_block_dev, int n,
+hipError_t launch_pass_batch(int t, int domain, const PassArgs *args_dev, const uint32_t *first_block_dev, int n,
                              uint32_t blocks, hipStream_t s)
 {
     const dim3 grid(blocks);
-    switch (t) {
-    case 10: hipLaunchKernelGGL((pass_kernel_batch<10, 256>), grid, dim3(256), 0, s, args_dev, first_block_dev, n); break;
-    case 11: hipLaunchKernelGGL((pass_kernel_batch<11, 256>), grid, dim3(256), 0, s, args_dev, first_block_dev, n); break;
-    case 12: hipLaunchKernelGGL((pass_kernel_batch<12, 256>), grid, dim3(256), 0, s, args_dev, first_block_dev, n); break;
-    case 13: hipLaunchKernelGGL((pass_kernel_batch<13, 512>), grid, dim3(512), 0, s, args_dev, first_block_dev, n); break;
+    const int key = t * 2 + (domain == 1 ? 1 : 0);
+    switch (key) {
+#define BMQ_PASS(T, NT, D) \
+    case T * 2 + D: \
+        hipLaunchKernelGGL((pass_kernel_batch<T, NT, D>), grid, dim3(NT), 0, s, args_dev, first_block_dev, n); \
+        break;
+    BMQ_PASS(10, 256, 0) BMQ_PASS(10, 256, 1) BMQ_PASS(11, 256, 0) BMQ_PASS(11, 256, 1)
+    BMQ_PASS(12, 256, 0) BMQ_PASS(12, 256, 1) BMQ_PASS(13, 512, 0) BMQ_PASS(13, 512, 1)
+#undef BMQ_PASS
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

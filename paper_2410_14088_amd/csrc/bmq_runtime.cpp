@@ -776,7 +776,7 @@ size_t launches_of(const sv_plan_t *p, size_t first, size_t batch)
 // every state that has one, grouped by tile size.
 struct BatchGroup {
     size_t k;
-    int t;
+    int t, dom;
     std::vector<size_t> members;     // state indices
     uint64_t args_off, fb_off;       // workspace offsets
     uint32_t blocks;
@@ -802,11 +802,13 @@ int plan_batch(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
     groups.clear();
     bytes = 0;
     for (size_t k = 0; k < kmax; ++k)
-        for (int t = 10; t <= bmq::kMaxTile; ++t) {
-            BatchGroup g{k, t, {}, 0, 0, 0};
+        for (int key = 20; key < 2 * (bmq::kMaxTile + 1); ++key) {
+            const int t = key / 2, dom = key % 2;
+            BatchGroup g{k, t, dom, {}, 0, 0, 0};
             uint64_t blocks = 0;
             for (size_t i = 0; i < count; ++i)
-                if (plans[i]->t == t && launches_of(plans[i], 0, plans[i]->stages.size()) > k) {
+                if (plans[i]->t == t && states[i]->cfg.domain == dom &&
+                    launches_of(plans[i], 0, plans[i]->stages.size()) > k) {
                     g.members.push_back(i);
                     blocks += 1ull << (states[i]->n - t);
                 }
@@ -1163,7 +1165,7 @@ int sv_batch_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t co
     for (size_t i = 0; i < count; ++i)
         HIP_TRY(bmq::launch_fill_u64((uint64_t *)states[i]->counters, args[i].size() * kStageCounters, 0, stream));
     for (const BatchGroup &g : groups)
-        HIP_TRY(bmq::launch_pass_batch(g.t, (const bmq::PassArgs *)(ws + g.args_off), (const uint32_t *)(ws + g.fb_off),
+        HIP_TRY(bmq::launch_pass_batch(g.t, g.dom, (const bmq::PassArgs *)(ws + g.args_off), (const uint32_t *)(ws + g.fb_off),
                                        (int)g.members.size(), g.blocks, stream));
     std::vector<unsigned long long> hc;
     int first_err = SV_OK;
