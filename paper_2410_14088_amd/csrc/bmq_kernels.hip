@@ -754,36 +754,60 @@ template <int DOM>
 __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &cp, int q, QuadPlane &P)
 {
     constexpr bool log_dom = DOM == 1;
-    uint32_t nzb = 0, negb = 0, bad = 0, anynz = 0;
-    int32_t first = 0, last = 0;
-    bool seen = false;
+    uint32_t nzb = 0xFFFFu, negb = 0, bad = 0, anynz = 0;
+    if (log_dom) {
+        uint32_t efmax = 0;
+        nzb = 0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const float v = x[j];
-        const uint32_t u = __float_as_uint(v);
-        int32_t k = 0;
-        bool isz = false, ok;
-        if (log_dom) {
-            const uint32_t ef = (u >> 23) & 0xFFu;
-            isz = ef == 0u;
-            int e;
-            const float p = log2_split(u & 0x7FFFFFFFu, e);
-            const int32_t jj = (int32_t)__builtin_rintf(p * cp.scale);
-            ok = cp.code_ok && (isz || ef < 254u);
-            k = isz ? 0 : (int32_t)((uint32_t)e << cp.s) + jj;
-            negb |= (uint32_t)(!isz && (u >> 31)) << j;
-        } else {
-            ok = cp.code_ok && quantize(v, cp, k);
+        for (int j = 0; j < 16; ++j) {
+            const uint32_t u = __float_as_uint(x[j]);
+            const uint32_t a = u & 0x7FFFFFFFu;
+            const uint32_t ef = a >> 23;
+            efmax = max(efmax, ef);
+            nzb |= min(ef, 1u) << j;                   // zero or subnormal: bit clear
+            negb |= (u >> 31) << j;
+            // log2|x| = e + p (as log2_split): adding 0x4AFB0C carries into
+            // the exponent exactly when the significand exceeds 0x3504F3, so
+            // one integer add folds the significand into [sqrt(1/2), sqrt(2)]
+            const uint32_t ix = a + 0x004AFB0Cu;
+            const int32_t e = (int32_t)(ix >> 23) - 127;
+            const float t = __uint_as_float((ix & 0x007FFFFFu) + 0x3F3504F4u) - 1.0f;
+            float pp = 0.12614846229553223f;
+            pp = __builtin_fmaf(pp, t, -0.20742103457450867f);
+            pp = __builtin_fmaf(pp, t, 0.21566985547542572f);
+            pp = __builtin_fmaf(pp, t, -0.23892034590244293f);
+            pp = __builtin_fmaf(pp, t, 0.2879183292388916f);
+            pp = __builtin_fmaf(pp, t, -0.36070483922958374f);
+            pp = __builtin_fmaf(pp, t, 0.48091059923171997f);
+            pp = __builtin_fmaf(pp, t, -0.7213473320007324f);
+            pp = __builtin_fmaf(pp, t, 1.4426950216293335f);
+            const int32_t jj = (int32_t)__builtin_rintf((t * pp) * cp.scale);
+            P.kp[j] = (int32_t)((uint32_t)e << cp.s) + jj;   // zeros are substituted below
+        }
+        negb &= nzb;                                   // zeros count as non-negative
+        bad = efmax >= 254u || !cp.code_ok;
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            int32_t k = 0;
+            bad |= !quantize(x[j], cp, k);
             anynz |= k != 0;
+            P.kp[j] = k;
         }
-        bad |= !ok;
-        nzb |= (uint32_t)!isz << j;
-        if (!isz) {
-            first = seen ? first : k;
-            last = k;
-            seen = true;
-        }
-        P.kp[j] = k;
+        bad |= !cp.code_ok;
+    }
+    // the lane's first and last non-zero codes (LIN has no zeros)
+    int32_t first = P.kp[0], last = P.kp[15];
+    const bool seen = nzb != 0u;
+    if (nzb != 0xFFFFu) {
+        bool sn = false;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+            if ((nzb >> j) & 1u) {
+                first = sn ? first : P.kp[j];
+                last = P.kp[j];
+                sn = true;
+            }
     }
     // chunk facts: bit 0 any failed code, 1 any non-zero code (LIN), 2 any
     // non-zero value, 3 a non-zero value that is not negative (sign class
@@ -815,14 +839,25 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     P.carry = carry;
     uint32_t orl = 0, orq = 0;
     int32_t prev = carry;
+    if (nzb != 0xFFFFu) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int32_t kp = ((nzb >> j) & 1u) ? P.kp[j] : prev;
-        P.kp[j] = kp;
-        const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
-        orl |= zigzag(d);
-        orq |= zigzag(kp);
-        prev = kp;
+        for (int j = 0; j < 16; ++j) {
+            const int32_t kp = ((nzb >> j) & 1u) ? P.kp[j] : prev;
+            P.kp[j] = kp;
+            const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
+            orl |= zigzag(d);
+            orq |= zigzag(kp);
+            prev = kp;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int32_t kp = P.kp[j];
+            const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
+            orl |= zigzag(d);
+            orq |= zigzag(kp);
+            prev = kp;
+        }
     }
     const uint32_t wl = bitlen(quad_or(orl)), wq = bitlen(quad_or(orq));
     uint32_t sc = 0, zc = 0;
