@@ -875,6 +875,75 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     P.anchor = P.kp[0];
 }
 
+// Decode one plane of a chunk, four lanes per chunk: lane q produces values
+// 16q..16q+15 into dst[0..15] (LDS).  Its fields start at bit 16 w q of the
+// payload; field j is cut from the two words holding it.  Lorenzo residuals
+// are summed within the lane, and the quad's exclusive scan of the lane
+// totals plus the anchor gives each lane its starting code.  The same
+// integer and float32 steps as decode_value, so the values are identical.
+template <int DOM>
+__device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const uint8_t *body, uint32_t off_sm,
+                                            uint32_t off_zm, uint32_t off_p, float *dst, int q, bool act,
+                                            const CodecParams &cp)
+{
+    const uint32_t mode = h & 3u;
+    if (mode == M_ZERO) {
+        if (act)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) dst[j] = 0.0f;
+        return;
+    }
+    const uint32_t *pay = (const uint32_t *)(body + off_p);
+    if (mode == M_VERB) {
+        if (act)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) dst[j] = __uint_as_float(pay[16 * q + j]);
+        return;
+    }
+    const uint32_t w = min((h >> 2) & 63u, 32u);
+    const uint32_t sc = (h >> 8) & 3u, zc = (h >> 10) & 3u;
+    const uint32_t negb = (sc == 2u) ? (uint32_t)*(const uint16_t *)(body + off_sm + 2 * q) : (sc == 1u ? 0xFFFFu : 0u);
+    const uint32_t zb = (zc == 2u) ? (uint32_t)*(const uint16_t *)(body + off_zm + 2 * q) : 0u;
+    const uint32_t fmask = w >= 32u ? ~0u : ((1u << w) - 1u);
+    const uint32_t o = 16u * w * (uint32_t)q;
+    int32_t k[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const uint32_t oj = o + (uint32_t)j * w;
+        const uint32_t lo = pay[oj >> 5], hi = pay[(oj >> 5) + 1];
+        const uint32_t f = (uint32_t)((((uint64_t)hi << 32) | lo) >> (oj & 31u)) & fmask;
+        k[j] = unzigzag(f);
+    }
+    if (mode == M_LZ) {
+        if (q == 0) k[0] = 0;                           // the first residual is the anchor's
+        uint32_t acc = 0;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            acc += (uint32_t)k[j];
+            k[j] = (int32_t)acc;
+        }
+        const uint32_t t0 = qperm<QB0>(acc), t1 = qperm<QB1>(acc), t2 = qperm<QB2>(acc);
+        uint32_t start = (uint32_t)anchor;
+        if (q >= 1) start += t0;
+        if (q >= 2) start += t1;
+        if (q >= 3) start += t2;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) k[j] = (int32_t)(start + (uint32_t)k[j]);
+    }
+    if (!act) return;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        float v;
+        if (DOM == 0) {
+            v = (float)k[j] * cp.delta;
+        } else {
+            const float mag = log_decode(k[j], cp.s, cp.delta);
+            v = ((zb >> j) & 1u) ? 0.0f : (((negb >> j) & 1u) ? -mag : mag);
+        }
+        dst[j] = v;
+    }
+}
+
 // Store this lane's part of a plane's payload: packed planes as 16 w-bit
 // fields from bit 16 w q of the payload (LSB-first), VERBATIM planes as the
 // 16 raw values from word 16 q.  When w is odd the lanes q = 1, 3 start in
@@ -974,55 +1043,21 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
 
     // ---- load
     if (a.in_mode == IO_COMPRESSED) {
-        uint64_t e = (lane < CPW) ? a.dir_in[my_g >> 6] : 0ull;
+        // four lanes per chunk (see decode_quad)
+        const int qc = lane >> 2, q = lane & 3;
+        const bool act = qc < CPW;
+        const int c = c0 + (act ? qc : 0);
+        const uint64_t gch = base | deposit((uint64_t)c, a.tileq + 6, T - 6);
+        uint64_t e = act ? a.dir_in[gch >> 6] : 0ull;
         if (e == kDirInvalid) e = 0;                      // a lost chunk reads as zero
         const uint32_t eh0 = (uint32_t)(e >> 40) & 0xFFFu, eh1 = (uint32_t)(e >> 52);
         const Layout Lv = layout_of(eh0, eh1);
-        const uint64_t boff = (uint64_t)body_ptr(a.pool_in, a.host_in, a.pool_cap, e & kDirOffsetMask);
-        const uint32_t *bv = (const uint32_t *)boff;
-        const int32_t av0 = Lv.lz0 ? (int32_t)bv[0] : 0;              // anchors, one chunk per lane
-        const int32_t av1 = Lv.lz1 ? (int32_t)bv[Lv.lz0 ? 1 : 0] : 0;
-        const uint32_t pay = pack_pay(Lv);
-        const uint32_t msk = Lv.off_sm0 | (Lv.off_zm0 << 6) | (Lv.off_sm1 << 12) | (Lv.off_zm1 << 18) |
-                             ((uint32_t)Lv.hs0 << 24) | ((uint32_t)Lv.hz0 << 25) | ((uint32_t)Lv.hs1 << 26) |
-                             ((uint32_t)Lv.hz1 << 27) | ((((eh0 >> 8) & 3u) == 1u) << 28) |
-                             ((((eh1 >> 8) & 3u) == 1u) << 29);
-        constexpr int G = CPW < 4 ? CPW : 4;
-        for (int i0 = 0; i0 < CPW; i0 += G) {
-            uint32_t lo0[G], hi0[G], lo1[G], hi1[G], sw0[G], zw0[G], sw1[G], zw1[G], P[G], M[G];
-#pragma unroll
-            for (int u = 0; u < G; ++u) {
-                const int i = i0 + u;
-                const uint32_t *b = (const uint32_t *)lane_u64(boff, i);
-                const uint32_t p = (uint32_t)__builtin_amdgcn_readlane((int)pay, i);
-                const uint32_t m = (uint32_t)__builtin_amdgcn_readlane((int)msk, i);
-                P[u] = p;
-                M[u] = m;
-                const uint32_t w0 = (p >> 16) & 63u, w1 = (p >> 22) & 63u;
-                const uint32_t j0 = ((p >> 28) & 3u) == M_VERB ? (uint32_t)lane : (((uint32_t)lane * w0) >> 5);
-                const uint32_t j1 = ((p >> 30) & 3u) == M_VERB ? (uint32_t)lane : (((uint32_t)lane * w1) >> 5);
-                const uint32_t *p0 = b + ((p & 63u) >> 2) + j0;
-                const uint32_t *p1 = b + (((p >> 6) & 1023u) >> 2) + j1;
-                lo0[u] = p0[0]; hi0[u] = p0[1];
-                lo1[u] = p1[0]; hi1[u] = p1[1];
-                const uint32_t hw = (uint32_t)lane >> 5;
-                sw0[u] = b[((m & 63u) >> 2) + hw];
-                sw1[u] = b[(((m >> 12) & 63u) >> 2) + hw];
-                zw0[u] = (m & (1u << 25)) ? b[(((m >> 6) & 63u) >> 2) + hw] : 0u;
-                zw1[u] = (m & (1u << 27)) ? b[(((m >> 18) & 63u) >> 2) + hw] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < G; ++u) {
-                const int i = i0 + u;
-                const uint32_t p = P[u], m = M[u], bit = (uint32_t)lane & 31u;
-                const bool n0 = (m & (1u << 24)) ? ((sw0[u] >> bit) & 1u) : ((m >> 28) & 1u);
-                const bool n1 = (m & (1u << 26)) ? ((sw1[u] >> bit) & 1u) : ((m >> 29) & 1u);
-                const bool z0 = (zw0[u] >> bit) & 1u, z1 = (zw1[u] >> bit) & 1u;
-                const int32_t a0 = __builtin_amdgcn_readlane(av0, i), a1 = __builtin_amdgcn_readlane(av1, i);
-                s.re[tix(((c0 + i) << 6) + lane)] = decode_value_d<DOM>((p >> 28) & 3u, (p >> 16) & 63u, a0, lo0[u], hi0[u], n0, z0, cp);
-                s.im[tix(((c0 + i) << 6) + lane)] = decode_value_d<DOM>((p >> 30) & 3u, (p >> 22) & 63u, a1, lo1[u], hi1[u], n1, z1, cp);
-            }
-        }
+        const uint8_t *body = body_ptr(a.pool_in, a.host_in, a.pool_cap, e & kDirOffsetMask);
+        const int32_t an0 = Lv.lz0 ? *(const int32_t *)body : 0;
+        const int32_t an1 = Lv.lz1 ? *(const int32_t *)(body + (Lv.lz0 ? 4 : 0)) : 0;
+        const uint32_t t0 = tix((uint32_t)(c << 6) + 16u * (uint32_t)q);
+        decode_quad<DOM>(eh0, an0, body, Lv.off_sm0, Lv.off_zm0, Lv.off_p0, s.re + t0, q, act, cp);
+        decode_quad<DOM>(eh1, an1, body, Lv.off_sm1, Lv.off_zm1, Lv.off_p1, s.im + t0, q, act, cp);
     } else {
         for (int i = 0; i < CPW; ++i) {
             const uint64_t g = lane_u64(my_g, i);
