@@ -749,6 +749,14 @@ struct QuadPlane {
     int32_t kp[16];     // this lane's codes after the zero substitution
 };
 
+// A VERBATIM plane keeps the lane's 16 raw values, in place of its codes.
+__device__ __forceinline__ void verbatim_quad(const float *x, QuadPlane &P)
+{
+    P.hdr = M_VERB;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) P.kp[j] = (int32_t)__float_as_uint(x[j]);
+}
+
 // Encode one plane of a chunk; x points at this lane's 16 values (LDS).
 template <int DOM>
 __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &cp, int q, QuadPlane &P)
@@ -820,7 +828,7 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     P.anchor = 0;
     P.w = 0;
     P.carry = 0;
-    if (f & 1u) { P.hdr = M_VERB; return; }
+    if (f & 1u) { verbatim_quad(x, P); return; }
     const bool allzero = log_dom ? !(f & 4u) : !(f & 2u);
     if (allzero) { P.hdr = M_ZERO; return; }
     // zeros take the code of the last non-zero value at or before them, else
@@ -869,7 +877,7 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     const uint32_t s_lz = 4u + masks + 8u * wl, s_q0 = masks + 8u * wq;
     uint32_t mode = M_LZ, best = s_lz;
     if (s_q0 < best) { mode = M_Q0; best = s_q0; }
-    if (256u < best) { P.hdr = M_VERB; return; }
+    if (256u < best) { verbatim_quad(x, P); return; }
     P.w = (mode == M_LZ) ? wl : wq;
     P.hdr = mode | (P.w << 2) | (sc << 8) | (zc << 10);
     P.anchor = P.kp[0];
@@ -944,17 +952,27 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
     }
 }
 
-// Store this lane's part of a plane's payload: packed planes as 16 w-bit
-// fields from bit 16 w q of the payload (LSB-first), VERBATIM planes as the
-// 16 raw values from word 16 q.  When w is odd the lanes q = 1, 3 start in
-// the middle of a word whose low half the previous lane fills; that word is
-// assembled from both lanes and stored once.
-__device__ __forceinline__ void store_quad_payload(const QuadPlane &P, const float *x, uint32_t *pay, int q)
+// The wave's output stream is assembled in LDS before it goes to memory:
+// stream word i lives at st0[i] for i < R, else at st1[i - R] (the wave's own
+// tile rows of the real and imaginary planes, free once its chunks are
+// encoded).
+struct Staging {
+    uint32_t *st0, *st1;
+    uint32_t R;
+    __device__ __forceinline__ uint32_t *word(uint32_t i) const { return i < R ? st0 + i : st1 + (i - R); }
+};
+
+// Stage this lane's part of a plane's payload, which starts at stream word
+// pw: packed planes as 16 w-bit fields from bit 16 w q of the payload
+// (LSB-first), VERBATIM planes as the 16 raw values from word 16 q.  When w
+// is odd the lanes q = 1, 3 start in the middle of a word whose low half the
+// previous lane fills; that word is assembled from both lanes and stored once.
+__device__ __forceinline__ void stage_quad_payload(const QuadPlane &P, const Staging &S, uint32_t pw, int q)
 {
     const uint32_t mode = P.hdr & 3u;
     if (mode == M_VERB) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) pay[16 * q + j] = __float_as_uint(x[j]);
+        for (int j = 0; j < 16; ++j) *S.word(pw + 16 * q + j) = (uint32_t)P.kp[j];
         return;
     }
     const uint32_t w = P.w;
@@ -983,7 +1001,7 @@ __device__ __forceinline__ void store_quad_payload(const QuadPlane &P, const flo
                     lead = (uint32_t)acc;
                     pending = false;
                 } else {
-                    pay[wi] = (uint32_t)acc;
+                    *S.word(pw + wi) = (uint32_t)acc;
                 }
                 ++wi;
                 acc >>= 32;
@@ -994,7 +1012,7 @@ __device__ __forceinline__ void store_quad_payload(const QuadPlane &P, const flo
     // the low half-word an even lane leaves over goes to the next lane
     const uint32_t tail = (packed && nb) ? (uint32_t)acc : 0u;
     const uint32_t from_prev = qperm<0x90>(tail);      // lane q takes lane q - 1's value
-    if (packed && off) pay[(16u * w * (uint32_t)q) >> 5] = lead | from_prev;
+    if (packed && off) *S.word(pw + ((16u * w * (uint32_t)q) >> 5)) = lead | from_prev;
 }
 
 template <int T, int NT>
@@ -1142,22 +1160,32 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     if (lane == 0 && overflow) atomicOr(&cnt[C_OVERFLOW], 1ull);
     if (lane == 0 && total && !overflow)
         atomicAdd(&cnt[wave_off < a.pool_cap ? C_DEV_BYTES : C_HOST_BYTES], (unsigned long long)total);
-    // the chunk's body offset, from its quad's lane 0
+    // the chunk's body offset in the wave's stream, from its quad's lane 0
     const uint32_t rel = qperm<QB0>(incl - size);
     const uint64_t off = wave_off + rel;
-    if (act && !overflow && (h0 | h1)) {
-        uint8_t *body = (uint8_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, off);
-        if (q == 0) {
-            if (Lv.lz0) *(int32_t *)body = P0.anchor;
-            if (Lv.lz1) *(int32_t *)(body + (Lv.lz0 ? 4 : 0)) = P1.anchor;
+    if (!overflow && total) {
+        // assemble the wave's bodies in its own LDS rows, then copy them out
+        // in full contiguous words
+        const Staging S{(uint32_t *)(s.re + tix((uint32_t)c0 << 6)), (uint32_t *)(s.im + tix((uint32_t)c0 << 6)),
+                        (uint32_t)CPW * 68u};
+        wave_sync_lds();                              // every lane has read its values
+        if (act && (h0 | h1)) {
+            if (q == 0) {
+                if (Lv.lz0) *S.word(rel >> 2) = (uint32_t)P0.anchor;
+                if (Lv.lz1) *S.word((rel >> 2) + (Lv.lz0 ? 1 : 0)) = (uint32_t)P1.anchor;
+            }
+            // each lane stages its 16 bits (bytes 2q, 2q + 1) of the mixed masks
+            const uint32_t mw = (uint32_t)q >> 1, mh = (uint32_t)q & 1u;
+            if (Lv.hs0) ((uint16_t *)S.word(((rel + Lv.off_sm0) >> 2) + mw))[mh] = (uint16_t)P0.negb;
+            if (Lv.hz0) ((uint16_t *)S.word(((rel + Lv.off_zm0) >> 2) + mw))[mh] = (uint16_t)(~P0.nzb);
+            if (Lv.hs1) ((uint16_t *)S.word(((rel + Lv.off_sm1) >> 2) + mw))[mh] = (uint16_t)P1.negb;
+            if (Lv.hz1) ((uint16_t *)S.word(((rel + Lv.off_zm1) >> 2) + mw))[mh] = (uint16_t)(~P1.nzb);
+            stage_quad_payload(P0, S, (rel + Lv.off_p0) >> 2, q);
+            stage_quad_payload(P1, S, (rel + Lv.off_p1) >> 2, q);
         }
-        // each lane stores its 16 bits of the mixed masks
-        if (Lv.hs0) *(uint16_t *)(body + Lv.off_sm0 + 2 * q) = (uint16_t)P0.negb;
-        if (Lv.hz0) *(uint16_t *)(body + Lv.off_zm0 + 2 * q) = (uint16_t)(~P0.nzb);
-        if (Lv.hs1) *(uint16_t *)(body + Lv.off_sm1 + 2 * q) = (uint16_t)P1.negb;
-        if (Lv.hz1) *(uint16_t *)(body + Lv.off_zm1 + 2 * q) = (uint16_t)(~P1.nzb);
-        store_quad_payload(P0, s.re + t0, (uint32_t *)(body + Lv.off_p0), q);
-        store_quad_payload(P1, s.im + t0, (uint32_t *)(body + Lv.off_p1), q);
+        wave_sync_lds();
+        uint32_t *dst = (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, wave_off);
+        for (uint32_t wd = (uint32_t)lane; wd < (total >> 2); wd += 64u) dst[wd] = *S.word(wd);
     }
     if (act && q == 0)
         a.dir_out[g >> 6] = (h0 | h1) == 0u ? 0ull
