@@ -575,33 +575,53 @@ __device__ __forceinline__ void apply_dense_mfma(float *sre, float *sim, const O
         for (int j = 0; j < K; ++j) o |= (uint32_t)((r >> j) & 1) << pos[j];
         return o;
     };
-    for (int cb = wave * 32; cb < G; cb += (NT / 64) * 32) {
-        uint32_t base = (uint32_t)(cb + col);
+    // NB column blocks at a time give the matrix core independent chains
+    // (one 32 x 32 block per instruction chain would wait on each result)
+    constexpr int NW = NT / 64;
+    constexpr int NB = (RB == 1 && (G / 32) % (2 * NW) == 0) ? 2 : 1;
+    for (int cb = wave * 32 * NB; cb < G; cb += NW * 32 * NB) {
+        uint32_t base[NB];
+        floatx16 acc[NB][RB];
 #pragma unroll
-        for (int j = 0; j < K; ++j) base = ((base >> sp[j]) << (sp[j] + 1)) | (base & ((1u << sp[j]) - 1u));
-        floatx16 acc[RB];
+        for (int u = 0; u < NB; ++u) {
+            base[u] = (uint32_t)(cb + 32 * u + col);
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+            for (int j = 0; j < K; ++j)
+                base[u] = ((base[u] >> sp[j]) << (sp[j] + 1)) | (base[u] & ((1u << sp[j]) - 1u));
 #pragma unroll
-            for (int v = 0; v < 16; ++v) acc[rb][v] = 0.0f;
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[u][rb][v] = 0.0f;
+        }
 #pragma unroll 4
         for (int st = 0; st < STEPS; ++st) {
             const int k = 2 * st + hi;                     // k < D exactly when st < D / 2
-            const uint32_t idx = tix(base | row_off(k & (D - 1)));
-            const float bv = (st < D / 2) ? sre[idx] : sim[idx];
+            const uint32_t ro = row_off(k & (D - 1));
+            float bv[NB];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-                acc[rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(block_elem<D>(M, rb * 32 + col, k), bv, acc[rb], 0, 0, 0);
+            for (int u = 0; u < NB; ++u) {
+                const uint32_t idx = tix(base[u] | ro);
+                bv[u] = (st < D / 2) ? sre[idx] : sim[idx];
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                const float av = block_elem<D>(M, rb * 32 + col, k);
+#pragma unroll
+                for (int u = 0; u < NB; ++u)
+                    acc[u][rb] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv[u], acc[u][rb], 0, 0, 0);
+            }
         }
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+        for (int u = 0; u < NB; ++u)
 #pragma unroll
-            for (int v = 0; v < 16; ++v) {
-                const int i = rb * 32 + 8 * (v >> 2) + 4 * hi + (v & 3);   // output row of A
-                const uint32_t idx = tix(base | row_off(i & (D - 1)));
-                if (i < D) sre[idx] = acc[rb][v];
-                else sim[idx] = acc[rb][v];
-            }
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int i = rb * 32 + 8 * (v >> 2) + 4 * hi + (v & 3);   // output row of A
+                    const uint32_t idx = tix(base[u] | row_off(i & (D - 1)));
+                    if (i < D) sre[idx] = acc[u][rb][v];
+                    else sim[idx] = acc[u][rb][v];
+                }
     }
 }
 
