@@ -35,10 +35,15 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="qft", choices=["qft", "random-mirror", "batch"],
+    ap.add_argument("--workload", default="qft", choices=["qft", "random-mirror", "batch", "qaoa-spill"],
                     help="qft: QFT on an Ry product (default, 30 qubits); random-mirror: random U3/CZ layers "
                          "(33 qubits, depth 16) followed by their inverse; batch: 512 uneven circuits of "
-                         "18-26 qubits run together (sv_batch_apply) and one after another")
+                         "18-26 qubits run together (sv_batch_apply) and one after another; qaoa-spill: "
+                         "QAOA ring p=3 (32 qubits) with the device pools capped so records spill to a "
+                         "pinned host pool, against the same run on the device only")
+    ap.add_argument("--pool-frac", type=float, default=0.25,
+                    help="qaoa-spill: device pool capacity per state copy, as a fraction of the "
+                         "uncompressed complex64 size")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--n", type=int, default=0, help="qubits (default: 30 for qft, 33 for random-mirror)")
     ap.add_argument("--flags", type=int, default=0, help="sv_config_t flags (1 no scratch, 2 no MFMA)")
@@ -188,8 +193,94 @@ def bench_batch(args):
     print(json.dumps(out))
 
 
+def qaoa_ring_closed_form(n, gammas, betas, xs):
+    """<x| prod_l RX(beta_l)^n RZZ_ring(gamma_l) H^n |0> for each x: a sum over
+    Z-basis worldlines per site, contracted around the ring as the trace of a
+    product of 2^p x 2^p transfer matrices (batched over the samples)."""
+    import numpy as np
+    p = len(gammas)
+    W = 1 << p
+    bits = [(np.arange(W) >> l) & 1 for l in range(p)]
+    ang = np.zeros((W, W))
+    for l in range(p):
+        s_w = 1 - 2 * bits[l]
+        ang += -gammas[l] / 2 * np.outer(s_w, s_w)
+    bond = np.exp(1j * ang)
+    def rx(b):
+        c, s_ = np.cos(b / 2), np.sin(b / 2)
+        return np.array([[c, -1j * s_], [-1j * s_, c]])
+    R = [rx(b) for b in betas]
+    site = np.ones((2, W), dtype=np.complex128)        # site factor for x_i = 0, 1
+    for xi in (0, 1):
+        for l in range(p):
+            dst = bits[l + 1] if l + 1 < p else np.full(W, xi)
+            site[xi] *= R[l][dst, bits[l]]
+    xs = np.asarray(xs, dtype=np.uint64)
+    T = np.broadcast_to(np.eye(W, dtype=np.complex128), (xs.size, W, W)).copy()
+    for i in range(n):
+        xi = ((xs >> np.uint64(i)) & np.uint64(1)).astype(np.int64)
+        T = T @ (site[xi][:, :, None] * bond[None, :, :])
+    return np.trace(T, axis1=1, axis2=2) / 2 ** (n / 2)
+
+
+def bench_qaoa_spill(args):
+    """Two-level memory at scale: the same QAOA run with device pools large
+    enough and with capped device pools plus a pinned host pool."""
+    import numpy as np
+    import torch
+    from paper_2410_14088_amd import bmq
+    from paper_2410_14088_amd import circuits as C
+    n = args.n or 32
+    gates, gammas, betas = C.qaoa_ring(n, 3, 1003)
+    res = {}
+    rng = np.random.default_rng(7)
+    idx = rng.integers(0, 1 << n, 512).astype(np.uint64)
+    want = qaoa_ring_closed_form(n, gammas, betas, idx)
+    for mode in ("device", "spill"):
+        pool = int(args.pool_frac * (8 << n)) & ~255 if mode == "spill" else 0
+        cfg = bmq.Config(n=n, b=n - 8, inner=2, fuse=args.fuse or 4, domain=1, eb=1e-5, pool_bytes=pool,
+                         flags=bmq.SV_FLAG_NO_SCRATCH)
+        plan = bmq.Plan(gates, cfg)
+        sv = bmq.State(cfg, "cuda:0")
+        if mode == "spill":
+            sv.attach_host_pool(2 * (8 << n))
+        for _ in range(args.warmup):
+            sv.reset()
+            sv.apply(plan)
+        torch.cuda.synchronize()
+        sv.reset()
+        t0 = time.perf_counter()
+        st = sv.apply(plan, stats=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy().astype(np.complex128)
+        f2 = abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real)
+        rec, host, _ = sv.footprint()
+        res[mode] = dict(ms=dt * 1e3, value=(2 ** n) * len(gates) / dt, fidelity_f2_sampled=f2,
+                         max_abs_err_sampled=float(np.abs(got - want).max()), record_bytes=rec, host_bytes=host,
+                         peak_host_bytes=max(s["bytes_out_host"] for s in st), device_pool_bytes=pool or None,
+                         stages=len(st))
+        sv.close()
+        del sv
+        torch.cuda.empty_cache()
+    out = {
+        "metric": METRIC, "value": res["spill"]["value"], "unit": "amplitude·gates/s", "n_gpus": 1, "steps": 1,
+        "warmup": args.warmup, "ms_per_step": res["spill"]["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"qaoa-ring-{n}q-p3-host-spill", "n_qubits": n, "gates": len(gates),
+                   "block_qubits": n - 8, "domain": "log", "eb": 1e-5, "fuse_qubits": args.fuse or 4,
+                   "flags": bmq.SV_FLAG_NO_SCRATCH, "device_pool_frac": args.pool_frac},
+        "spill": res["spill"], "device_only": res["device"],
+        "compression_ratio_vs_complex64": (8 << n) / res["spill"]["record_bytes"],
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
+    if args.workload == "qaoa-spill" and args.gpus == 1:
+        bench_qaoa_spill(args)
+        return
     if args.workload == "batch" and args.gpus == 1 and not args.copy_calibration:
         bench_batch(args)
         return
