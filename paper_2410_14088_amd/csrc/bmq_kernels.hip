@@ -160,6 +160,9 @@ __device__ __forceinline__ float log_decode(int32_t k, int s, float delta)
     p = __builtin_fmaf(p, f, 0.24022650718688965f);
     p = __builtin_fmaf(p, f, 0.6931471824645996f);
     p = __builtin_fmaf(p, f, 1.0f);
+    // within the normal exponent range 2^i is one float and one scaling
+    // rounds exactly as the two half scalings below (p 2^(i/2) is exact)
+    if (__builtin_expect(i >= -126 && i <= 127, 1)) return p * pow2i(i);
     const int ic = i < -250 ? -250 : (i > 250 ? 250 : i);
     const int i1 = ic >> 1, i2 = ic - i1;
     return (p * pow2i(i1)) * pow2i(i2);
@@ -865,7 +868,9 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     if (q >= 2 && h1) carry = l1;
     if (q >= 3 && h2) carry = l2;
     P.carry = carry;
-    uint32_t orl = 0, orq = 0;
+    // zigzag(v) grows with |v| on each side of zero, so the widest field of a
+    // mode is the zigzag of the smallest or of the largest value
+    int32_t dmin = 0, dmax = 0, kmin = INT32_MAX, kmax = INT32_MIN;
     int32_t prev = carry;
     if (nzb != 0xFFFFu) {
 #pragma unroll
@@ -873,8 +878,10 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
             const int32_t kp = ((nzb >> j) & 1u) ? P.kp[j] : prev;
             P.kp[j] = kp;
             const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
-            orl |= zigzag(d);
-            orq |= zigzag(kp);
+            dmin = min(dmin, d);
+            dmax = max(dmax, d);
+            kmin = min(kmin, kp);
+            kmax = max(kmax, kp);
             prev = kp;
         }
     } else {
@@ -882,11 +889,14 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
         for (int j = 0; j < 16; ++j) {
             const int32_t kp = P.kp[j];
             const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
-            orl |= zigzag(d);
-            orq |= zigzag(kp);
+            dmin = min(dmin, d);
+            dmax = max(dmax, d);
+            kmin = min(kmin, kp);
+            kmax = max(kmax, kp);
             prev = kp;
         }
     }
+    const uint32_t orl = zigzag(dmin) | zigzag(dmax), orq = zigzag(kmin) | zigzag(kmax);
     const uint32_t wl = bitlen(quad_or(orl)), wq = bitlen(quad_or(orq));
     uint32_t sc = 0, zc = 0;
     if (log_dom) {
