@@ -948,8 +948,9 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const uint32_t oj = o + (uint32_t)j * w;
-        const uint32_t lo = pay[oj >> 5], hi = pay[(oj >> 5) + 1];
-        const uint32_t f = (uint32_t)((((uint64_t)hi << 32) | lo) >> (oj & 31u)) & fmask;
+        uint64_t v;                                     // the two words holding the field, one load
+        __builtin_memcpy(&v, pay + (oj >> 5), 8);
+        const uint32_t f = (uint32_t)(v >> (oj & 31u)) & fmask;
         k[j] = unzigzag(f);
     }
     if (mode == M_LZ) {
@@ -1214,8 +1215,18 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
             stage_quad_payload(P1, S, (rel + Lv.off_p1) >> 2, q);
         }
         wave_sync_lds();
+        // 16 bytes per lane and step (the stream is 4-byte aligned; the
+        // staging rows are 16-byte aligned and R is a multiple of 4 words)
         uint32_t *dst = (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, wave_off);
-        for (uint32_t wd = (uint32_t)lane; wd < (total >> 2); wd += 64u) dst[wd] = *S.word(wd);
+        const uint32_t nw = total >> 2;
+        for (uint32_t w4 = 4u * (uint32_t)lane; w4 < nw; w4 += 256u) {
+            if (w4 + 4u <= nw) {
+                const uint4 v = *(const uint4 *)S.word(w4);
+                __builtin_memcpy(dst + w4, &v, 16);
+            } else {
+                for (uint32_t wd = w4; wd < nw; ++wd) dst[wd] = *S.word(wd);
+            }
+        }
     }
     if (act && q == 0)
         a.dir_out[g >> 6] = (h0 | h1) == 0u ? 0ull
