@@ -501,35 +501,55 @@ __device__ __forceinline__ void apply_dense(float *sre, float *sim, const OpDesc
 #pragma unroll
         for (int j = 0; j + 1 < K - i; ++j)
             if (sp[j] > sp[j + 1]) { const int t = sp[j]; sp[j] = sp[j + 1]; sp[j + 1] = t; }
-    for (int g = threadIdx.x; g < (TILE >> K); g += NT) {
-        uint32_t i0 = (uint32_t)g;
+    // UG groups per step: all their amplitudes are read before any is
+    // written, so the LDS reads of a step are issued together instead of one
+    // group waiting on the previous group's stores
+    constexpr int NG = TILE >> K, IT = (NG + NT - 1) / NT;
+    constexpr int UGMAX = K < 4 ? (16 >> K) : 1, UG = IT < UGMAX ? IT : UGMAX;
+    static_assert(IT % UG == 0, "whole steps");
+#pragma unroll 1
+    for (int s0 = 0; s0 < IT; s0 += UG) {
+        uint32_t i0[UG];
+        bool ok[UG];
+        float ar[UG][D], ai[UG][D];
 #pragma unroll
-        for (int j = 0; j < K; ++j) i0 = ((i0 >> sp[j]) << (sp[j] + 1)) | (i0 & ((1u << sp[j]) - 1u));
-        float ar[D], ai[D];
+        for (int u = 0; u < UG; ++u) {
+            const int g = (int)threadIdx.x + (s0 + u) * NT;
+            ok[u] = (NG % NT == 0) || g < NG;
+            uint32_t x = (uint32_t)(ok[u] ? g : 0);
 #pragma unroll
-        for (int c = 0; c < D; ++c) {
-            uint32_t o = 0;
+            for (int j = 0; j < K; ++j) x = ((x >> sp[j]) << (sp[j] + 1)) | (x & ((1u << sp[j]) - 1u));
+            i0[u] = x;
 #pragma unroll
-            for (int j = 0; j < K; ++j) o |= (uint32_t)((c >> j) & 1) << pos[j];
-            ar[c] = sre[tix(i0 + o)];
-            ai[c] = sim[tix(i0 + o)];
+            for (int c = 0; c < D; ++c) {
+                uint32_t o = 0;
+#pragma unroll
+                for (int j = 0; j < K; ++j) o |= (uint32_t)((c >> j) & 1) << pos[j];
+                ar[u][c] = sre[tix(x + o)];
+                ai[u][c] = sim[tix(x + o)];
+            }
         }
 #pragma unroll UNR
         for (int r = 0; r < D; ++r) {
-            float br = 0.0f, bi = 0.0f;
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                const float2 m = const_ld(M, r * D + c);
-                br = __builtin_fmaf(m.x, ar[c], br);
-                br = __builtin_fmaf(-m.y, ai[c], br);
-                bi = __builtin_fmaf(m.x, ai[c], bi);
-                bi = __builtin_fmaf(m.y, ar[c], bi);
-            }
             uint32_t o = 0;
 #pragma unroll
             for (int j = 0; j < K; ++j) o |= (uint32_t)((r >> j) & 1) << pos[j];
-            sre[tix(i0 + o)] = br;
-            sim[tix(i0 + o)] = bi;
+#pragma unroll
+            for (int u = 0; u < UG; ++u) {
+                float br = 0.0f, bi = 0.0f;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    const float2 m = const_ld(M, r * D + c);
+                    br = __builtin_fmaf(m.x, ar[u][c], br);
+                    br = __builtin_fmaf(-m.y, ai[u][c], br);
+                    bi = __builtin_fmaf(m.x, ai[u][c], bi);
+                    bi = __builtin_fmaf(m.y, ar[u][c], bi);
+                }
+                if (ok[u]) {
+                    sre[tix(i0[u] + o)] = br;
+                    sim[tix(i0[u] + o)] = bi;
+                }
+            }
         }
     }
 }
@@ -659,17 +679,31 @@ __device__ __forceinline__ void apply_diag(float *sre, float *sim, const OpDesc 
         }
     }
     __syncthreads();
+    // G amplitudes per step, all read (phase, real, imaginary) before any is
+    // written back, so the step's LDS reads are in flight together
+    constexpr int M = TILE / NT, G = M < 8 ? M : 8;
 #pragma unroll
-    for (int m = 0; m < TILE / NT; ++m) {
-        uint32_t idx = it;
+    for (int m0 = 0; m0 < M; m0 += G) {
+        float2 ph[G];
+        float ar[G], ai[G];
 #pragma unroll
-        for (int b = 0; b < MB; ++b)
-            if ((m >> b) & 1) idx |= W[b];
-        const int i = tid + (tid >> 4) + m * (NT + NT / 16);      // tix(tid + m NT), NT a multiple of 16
-        const float2 ph = s_tab[idx];
-        const float ar = sre[i], ai = sim[i];
-        sre[i] = __builtin_fmaf(ph.x, ar, -ph.y * ai);
-        sim[i] = __builtin_fmaf(ph.x, ai, ph.y * ar);
+        for (int u = 0; u < G; ++u) {
+            const int m = m0 + u;
+            uint32_t idx = it;
+#pragma unroll
+            for (int b = 0; b < MB; ++b)
+                if ((m >> b) & 1) idx |= W[b];
+            const int i = tid + (tid >> 4) + m * (NT + NT / 16);      // tix(tid + m NT), NT a multiple of 16
+            ph[u] = s_tab[idx];
+            ar[u] = sre[i];
+            ai[u] = sim[i];
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int i = tid + (tid >> 4) + (m0 + u) * (NT + NT / 16);
+            sre[i] = __builtin_fmaf(ph[u].x, ar[u], -ph[u].y * ai[u]);
+            sim[i] = __builtin_fmaf(ph[u].x, ai[u], ph[u].y * ar[u]);
+        }
     }
 }
 
