@@ -47,7 +47,8 @@ enum {
     SV_ERR_CAPACITY = -3,     /* a compressed pool overflowed during a stage */
     SV_ERR_HIP = -4,          /* a HIP runtime call failed */
     SV_ERR_CORRUPT = -5,      /* a stream or directory entry is malformed */
-    SV_ERR_UNSUPPORTED = -6   /* valid request the library does not implement */
+    SV_ERR_UNSUPPORTED = -6,  /* valid request the library does not implement */
+    SV_ERR_TIMEOUT = -7       /* a bounded device-side wait ran out (persistent launch) */
 };
 
 /* Codec domains (Section 4.3).  LIN: the error bound applies to each real
@@ -243,6 +244,28 @@ int sv_batch_workspace(sv_t *const *states, const sv_plan_t *const *plans, size_
                        uint64_t *bytes);
 int sv_batch_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
                    void *workspace_dev, uint64_t workspace_bytes, void *hip_stream);
+
+/* sv_persistent_apply -- the work of sv_batch_apply (every stage of
+ * plans[i] on states[i]) in ONE launch per tile size and codec domain
+ * instead of one launch per pass step.  Stages run one after another because
+ * each reads every block the previous one wrote (Section 4.2 workflow, Fig. 6);
+ * here the stage boundary is a per-circuit barrier inside the launch:
+ * workgroups take (pass, tile) items from a device queue in pass order, and
+ * a tile of pass k of a circuit starts once all tiles of that circuit's pass
+ * k - 1 are done (atomic counters), so circuits advance independently and a
+ * workgroup never waits for the launch to end.  Results are identical to
+ * sv_batch_apply and stage_apply_compressed (same pass body, same records).
+ * wait_limit_us bounds every device-side wait (0 = 10 s): a wait that runs
+ * out aborts the whole launch, which always finishes; the states of an
+ * aborted launch are poisoned (sv_reset clears that) and SV_ERR_TIMEOUT is
+ * returned.  Same arguments, checks, limits and ownership as sv_batch_apply;
+ * workspace_dev: device memory, 256-byte aligned, of sv_persistent_workspace
+ * bytes (launch arguments, queue and counters).  Synchronises. */
+int sv_persistent_workspace(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
+                            uint64_t *bytes);
+int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
+                        void *workspace_dev, uint64_t workspace_bytes, uint32_t wait_limit_us,
+                        void *hip_stream);
 
 /* sv_fidelity -- FP64 reductions on the device (Section 5.3 fidelity):
  *   fidelity    = |<ref|psi>|^2 / (|ref|^2 |psi|^2)   (the squared form;

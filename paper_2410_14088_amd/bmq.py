@@ -24,7 +24,7 @@ SV_CHUNK_SLOT_BYTES = 576
 KIND = {k: i for i, k in enumerate(
     ["H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "U3", "CX", "CZ", "CP", "RZZ"])}
 ERRORS = {-1: "SV_ERR_INVALID", -2: "SV_ERR_OOM", -3: "SV_ERR_CAPACITY", -4: "SV_ERR_HIP",
-          -5: "SV_ERR_CORRUPT", -6: "SV_ERR_UNSUPPORTED"}
+          -5: "SV_ERR_CORRUPT", -6: "SV_ERR_UNSUPPORTED", -7: "SV_ERR_TIMEOUT"}
 
 
 class BmqError(RuntimeError):
@@ -57,7 +57,7 @@ EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_destr
            "sv_debug_dump", "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
            "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
            "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune",
-           "sv_batch_workspace", "sv_batch_apply"]
+           "sv_batch_workspace", "sv_batch_apply", "sv_persistent_workspace", "sv_persistent_apply"]
 SV_FEATURES, SV_MLP_NPARAM = 32, 6597
 
 _lib = None
@@ -96,6 +96,8 @@ def lib():
         L.sv_graph_capture.argtypes = [V, V, C.c_size_t, C.c_size_t, P(V)]
         L.sv_batch_workspace.argtypes = [V, V, C.c_size_t, P(C.c_uint64)]
         L.sv_batch_apply.argtypes = [V, V, C.c_size_t, V, C.c_uint64, V]
+        L.sv_persistent_workspace.argtypes = [V, V, C.c_size_t, P(C.c_uint64)]
+        L.sv_persistent_apply.argtypes = [V, V, C.c_size_t, V, C.c_uint64, C.c_uint32, V]
         L.sv_autotune.argtypes = [V, C.c_size_t, P(sv_config_t), V, C.c_uint64, V, C.c_size_t, P(sv_config_t),
                                   P(C.c_float)]
         L.sv_graph_launch.argtypes = [V, V]
@@ -345,6 +347,23 @@ def batch_apply(states, plans):
     base = _ptr(ws)
     off = (-base) % 256
     _check(lib().sv_batch_apply(sa, pa, n, C.c_void_p(base + off), int(need.value), _stream()))
+
+
+def persistent_apply(states, plans, wait_limit_us: int = 0):
+    """Run every circuit's stages in one persistent launch per tile size
+    (sv_persistent_apply); wait_limit_us bounds each device-side wait
+    (0 = the library default)."""
+    import torch
+    n = len(states)
+    sa = (C.c_void_p * n)(*[st.h.value for st in states])
+    pa = (C.c_void_p * n)(*[pl.h.value for pl in plans])
+    need = C.c_uint64()
+    _check(lib().sv_persistent_workspace(sa, pa, n, C.byref(need)))
+    ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=states[0].arena.device)
+    base = _ptr(ws)
+    off = (-base) % 256
+    _check(lib().sv_persistent_apply(sa, pa, n, C.c_void_p(base + off), int(need.value), int(wait_limit_us),
+                                     _stream()))
 
 
 class Graph:

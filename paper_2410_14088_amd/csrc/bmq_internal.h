@@ -100,6 +100,24 @@ hipError_t launch_pass(const PassArgs &a, hipStream_t s);
 hipError_t launch_pass_batch(int t, int domain, const PassArgs *args_dev, const uint32_t *first_block_dev, int n,
                              uint32_t blocks, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+
+// Whole-circuit launch over a queue of (pass, tile) items, one workgroup per
+// item.  Pass L owns items [first_item[L], first_item[L + 1]) (its tiles in
+// order); dep[L] is the pass whose items must all be done before any item of
+// L starts (-1: none), and dep[L] < L.  sync (device, zeroed before the
+// launch): [0] next item, [1] abort flag, [2..3] unused, [4 + L] items of
+// pass L done.
+struct PersistArgs {
+    const PassArgs *args;
+    const uint32_t *first_item;
+    const int32_t *dep;
+    uint32_t *sync;
+    uint64_t limit_ticks;       // longest wait, in s_memrealtime ticks
+    uint32_t n_pass, total;
+    int32_t system_scope;       // records may live in host memory
+};
+constexpr int kSyncHead = 4;
+hipError_t launch_pass_queue(int t, int domain, const PersistArgs &pa, hipStream_t s);
 hipError_t launch_init_state(uint64_t *dir, uint64_t n_chunks, uint8_t *pool,
                              unsigned long long *counters, CodecParams cp, hipStream_t s);
 hipError_t launch_export(const uint64_t *dir, const PoolView &pv, CodecParams cp,

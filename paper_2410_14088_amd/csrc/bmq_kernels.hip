@@ -26,6 +26,8 @@
 // log2|x| = e + p.  Every float32 step is written out (no contraction, own
 // log2 and exp2), so codes and streams are reproducible bit for bit.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "bmq_internal.h"
@@ -1308,6 +1310,78 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_batch(const PassArg
     pass_body<T, NT, DOM, CArgs>(((CArgs *)args)[lo], blockIdx.x - first_block[lo]);
 }
 
+// Whole-circuit launch over a work queue: every stage of every circuit in
+// one launch.  Each workgroup takes the next (pass, tile) item from a single
+// device counter, runs it with the same pass body as the per-pass launches
+// and counts it done; a tile of a pass that depends on an earlier pass (the
+// previous pass of the same circuit) first waits until every tile of that
+// pass is done: the per-circuit stage barrier of an atomic done-counter.
+// Items are handed out in queue order, only to running workgroups, and a
+// dependency always precedes its dependants, so every item a waiting
+// workgroup depends on is already held by a running workgroup: the earliest
+// unfinished item never waits and the queue always drains, whatever number
+// of workgroups is resident.  Every wait is bounded (pa.limit_ticks of the
+// constant-rate clock); a wait that runs out raises the abort flag, after
+// which every workgroup leaves at its claim or wait, so the grid always
+// finishes.  One item per workgroup (the grid has one workgroup per item)
+// keeps the pass body free of an item loop, which would make the compiler
+// keep per-thread values live across items.
+template <int T, int NT, int DOM>
+__global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_queue(PersistArgs pa)
+{
+    __shared__ uint32_t s_item, s_go;
+    typedef const __attribute__((address_space(4))) PassArgs CArgs;
+    uint32_t *const next = pa.sync, *const abort_flag = pa.sync + 1, *const done = pa.sync + kSyncHead;
+    if (threadIdx.x == 0) {
+        uint32_t it = atomicAdd(next, 1u);
+        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = pa.total;
+        s_item = it;
+    }
+    __syncthreads();
+    const uint32_t it = s_item;
+    if (it >= pa.total) return;
+    int lo = 0, hi = (int)pa.n_pass;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (pa.first_item[mid] <= it) lo = mid;
+        else hi = mid;
+    }
+    const int d = pa.dep[lo];
+    if (d >= 0) {
+        // poll with plain coherent loads and a growing sleep (no cache
+        // maintenance per poll), then one acquire for every wave
+        if (threadIdx.x == 0) {
+            const uint32_t need = pa.first_item[d + 1] - pa.first_item[d];
+            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+            uint32_t go = 1, nap = 1;
+            while (__hip_atomic_load(done + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                    __builtin_amdgcn_s_memrealtime() - t0 > pa.limit_ticks) {
+                    __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    go = 0;
+                    break;
+                }
+                for (uint32_t z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(4);
+                nap = nap < 4u ? 2u * nap : 4u;
+            }
+            s_go = go;
+        }
+        __syncthreads();
+        if (!s_go) return;
+        if (pa.system_scope) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+        else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    pass_body<T, NT, DOM, CArgs>(((CArgs *)pa.args)[lo], it - pa.first_item[lo]);
+    // every wave's records and directory entries out before the count
+    if (pa.system_scope) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (pa.system_scope) __hip_atomic_fetch_add(done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        else __hip_atomic_fetch_add(done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
 // ------------------------------------------------------------------ utility kernels
 
 __global__ void fill_u64_kernel(uint64_t *p, uint64_t n, uint64_t v)
@@ -1560,6 +1634,21 @@ hipError_t launch_pass(const PassArgs &a, hipStream_t s)
     switch (key) {
 #define BMQ_PASS(T, NT, D) \
     case T * 2 + D: hipLaunchKernelGGL((pass_kernel<T, NT, D>), grid, dim3(NT), 0, s, a); break;
+    BMQ_PASS(10, 256, 0) BMQ_PASS(10, 256, 1) BMQ_PASS(11, 256, 0) BMQ_PASS(11, 256, 1)
+    BMQ_PASS(12, 256, 0) BMQ_PASS(12, 256, 1) BMQ_PASS(13, 512, 0) BMQ_PASS(13, 512, 1)
+#undef BMQ_PASS
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pass_queue(int t, int domain, const PersistArgs &pa, hipStream_t s)
+{
+    if (pa.total == 0) return hipSuccess;
+    const dim3 grid(pa.total);
+    switch (t * 2 + domain) {
+#define BMQ_PASS(T, NT, D) \
+    case T * 2 + D: hipLaunchKernelGGL((pass_kernel_queue<T, NT, D>), grid, dim3(NT), 0, s, pa); break;
     BMQ_PASS(10, 256, 0) BMQ_PASS(10, 256, 1) BMQ_PASS(11, 256, 0) BMQ_PASS(11, 256, 1)
     BMQ_PASS(12, 256, 0) BMQ_PASS(12, 256, 1) BMQ_PASS(13, 512, 0) BMQ_PASS(13, 512, 1)
 #undef BMQ_PASS

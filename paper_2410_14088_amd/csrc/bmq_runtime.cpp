@@ -489,7 +489,7 @@ bmq::PoolView pool_view(const sv_t *sv, int which)
 int check_state(const sv_t *sv)
 {
     if (!sv) return fail(SV_ERR_INVALID, "state is NULL");
-    if (sv->poisoned) return fail(SV_ERR_CAPACITY, "state is poisoned by an earlier overflow");
+    if (sv->poisoned) return fail(SV_ERR_CAPACITY, "state is poisoned by an earlier overflow or aborted launch");
     return SV_OK;
 }
 
@@ -1167,6 +1167,167 @@ int sv_batch_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t co
     for (const BatchGroup &g : groups)
         HIP_TRY(bmq::launch_pass_batch(g.t, g.dom, (const bmq::PassArgs *)(ws + g.args_off), (const uint32_t *)(ws + g.fb_off),
                                        (int)g.members.size(), g.blocks, stream));
+    std::vector<unsigned long long> hc;
+    int first_err = SV_OK;
+    std::string err;
+    for (size_t i = 0; i < count; ++i) {
+        int rc = read_counters(states[i], args[i].size(), hc);
+        if (rc == SV_OK) rc = collect_stages(states[i], plans[i], 0, plans[i]->stages.size(), hc, nullptr);
+        if (rc != SV_OK && first_err == SV_OK) {
+            first_err = rc;
+            err = g_err;
+        }
+    }
+    if (first_err != SV_OK) g_err = err;
+    return first_err;
+}
+
+}  // extern "C"
+
+namespace {
+
+// One persistent launch per tile size and domain: the pass list of its
+// circuits in queue order (pass k of every circuit that has one, then pass
+// k + 1, ...), each pass depending on the previous pass of its circuit.
+struct PersistClass {
+    int t, dom;
+    std::vector<size_t> members;                  // state indices
+    std::vector<std::pair<size_t, size_t>> pass;  // (state index, pass index)
+    std::vector<uint32_t> first_item;             // n_pass + 1
+    std::vector<int32_t> dep;
+    uint64_t args_off, first_off, dep_off, sync_off, sync_words;
+};
+
+int plan_persistent(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
+                    std::vector<PersistClass> &classes, uint64_t &bytes)
+{
+    std::vector<BatchGroup> groups;              // validation shared with the batched launches
+    uint64_t unused = 0;
+    if (int rc = plan_batch(states, plans, count, groups, unused)) return rc;
+    classes.clear();
+    bytes = 0;
+    for (int key = 20; key < 2 * (bmq::kMaxTile + 1); ++key) {
+        PersistClass c;
+        c.t = key / 2;
+        c.dom = key % 2;
+        size_t kmax = 0;
+        for (size_t i = 0; i < count; ++i)
+            if (plans[i]->t == c.t && states[i]->cfg.domain == c.dom) {
+                c.members.push_back(i);
+                kmax = std::max(kmax, launches_of(plans[i], 0, plans[i]->stages.size()));
+            }
+        if (c.members.empty()) continue;
+        std::vector<int32_t> last(count, -1);
+        uint64_t items = 0;
+        for (size_t k = 0; k < kmax; ++k)
+            for (size_t i : c.members) {
+                if (launches_of(plans[i], 0, plans[i]->stages.size()) <= k) continue;
+                c.first_item.push_back((uint32_t)items);
+                c.dep.push_back(last[i]);
+                last[i] = (int32_t)c.pass.size();
+                c.pass.push_back({i, k});
+                items += 1ull << (states[i]->n - c.t);
+                if (items > 0x7FFFFFFFull) return fail(SV_ERR_UNSUPPORTED, "a persistent launch exceeds 2^31 tiles");
+            }
+        if (c.pass.empty()) continue;
+        c.first_item.push_back((uint32_t)items);
+        c.args_off = bytes;
+        bytes += align256(c.pass.size() * sizeof(bmq::PassArgs));
+        c.first_off = bytes;
+        bytes += align256(c.first_item.size() * sizeof(uint32_t));
+        c.dep_off = bytes;
+        bytes += align256(c.dep.size() * sizeof(int32_t));
+        c.sync_off = bytes;
+        c.sync_words = (bmq::kSyncHead + c.pass.size() + 1) / 2;        // u64 words
+        bytes += align256(c.sync_words * 8);
+        classes.push_back(std::move(c));
+    }
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sv_persistent_workspace(sv_t *const *states, const sv_plan_t *const *plans, size_t count, uint64_t *bytes)
+{
+    if (!bytes) return fail(SV_ERR_INVALID, "bytes is NULL");
+    std::vector<PersistClass> classes;
+    return plan_persistent(states, plans, count, classes, *bytes);
+}
+
+int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t count, void *workspace_dev,
+                        uint64_t workspace_bytes, uint32_t wait_limit_us, void *hip_stream)
+{
+    std::vector<PersistClass> classes;
+    uint64_t need = 0;
+    if (int rc = plan_persistent(states, plans, count, classes, need)) return rc;
+    if (!workspace_dev || ((uintptr_t)workspace_dev & 255u) || workspace_bytes < need)
+        return fail(SV_ERR_INVALID, "workspace must be 256-byte aligned and hold %llu bytes", (unsigned long long)need);
+    hipStream_t stream = (hipStream_t)hip_stream;
+    for (size_t i = 0; i < count; ++i)
+        if (states[i]->stream != stream)
+            return fail(SV_ERR_INVALID, "state %zu was created on another stream", i);
+    int dev = 0, khz = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    if (khz <= 0) return fail(SV_ERR_UNSUPPORTED, "the device reports no constant-rate clock");
+    const uint64_t limit_us = wait_limit_us ? wait_limit_us : 10000000u;
+    for (size_t i = 0; i < count; ++i) {
+        if (int rc = resolve_graph(states[i])) return rc;
+        if (int rc = upload_plan(states[i], plans[i])) return rc;
+    }
+    std::vector<std::vector<bmq::PassArgs>> args(count);
+    for (size_t i = 0; i < count; ++i) {
+        size_t li = 0;
+        for (const StagePlan &st : plans[i]->stages)
+            for (int pi = 0; pi < (int)st.passes.size(); ++pi, ++li) {
+                bmq::PassArgs a;
+                build_pass_args(states[i], plans[i], st, pi, li, a);
+                args[i].push_back(a);
+            }
+    }
+    std::vector<uint8_t> host(need, 0);
+    for (const PersistClass &c : classes) {
+        bmq::PassArgs *ga = (bmq::PassArgs *)(host.data() + c.args_off);
+        for (size_t L = 0; L < c.pass.size(); ++L) ga[L] = args[c.pass[L].first][c.pass[L].second];
+        std::memcpy(host.data() + c.first_off, c.first_item.data(), c.first_item.size() * sizeof(uint32_t));
+        std::memcpy(host.data() + c.dep_off, c.dep.data(), c.dep.size() * sizeof(int32_t));
+    }
+    uint8_t *ws = (uint8_t *)workspace_dev;
+    HIP_TRY(hipMemcpyAsync(ws, host.data(), need, hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));          // the host image is pageable
+    for (size_t i = 0; i < count; ++i)
+        HIP_TRY(bmq::launch_fill_u64((uint64_t *)states[i]->counters, args[i].size() * kStageCounters, 0, stream));
+    for (const PersistClass &c : classes) {
+        bmq::PersistArgs pa;
+        std::memset(&pa, 0, sizeof(pa));
+        pa.args = (const bmq::PassArgs *)(ws + c.args_off);
+        pa.first_item = (const uint32_t *)(ws + c.first_off);
+        pa.dep = (const int32_t *)(ws + c.dep_off);
+        pa.sync = (uint32_t *)(ws + c.sync_off);
+        pa.limit_ticks = limit_us * (uint64_t)khz / 1000u;
+        pa.n_pass = (uint32_t)c.pass.size();
+        pa.total = c.first_item.back();
+        for (size_t i : c.members) pa.system_scope |= states[i]->host_cap ? 1 : 0;
+        HIP_TRY(bmq::launch_fill_u64((uint64_t *)pa.sync, c.sync_words, 0, stream));
+        HIP_TRY(bmq::launch_pass_queue(c.t, c.dom, pa, stream));
+    }
+    // abort flags first: an aborted class leaves its states half-written
+    std::vector<uint32_t> flags(classes.size(), 0);
+    for (size_t k = 0; k < classes.size(); ++k)
+        HIP_TRY(hipMemcpyAsync(&flags[k], ws + classes[k].sync_off + 4, 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    bool aborted = false;
+    for (size_t k = 0; k < classes.size(); ++k)
+        if (flags[k]) {
+            aborted = true;
+            for (size_t i : classes[k].members) states[i]->poisoned = true;
+        }
+    if (aborted)
+        return fail(SV_ERR_TIMEOUT, "a persistent launch waited longer than %llu us for a dependency and was "
+                                    "aborted; its states are poisoned",
+                    (unsigned long long)limit_us);
     std::vector<unsigned long long> hc;
     int first_err = SV_OK;
     std::string err;
