@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-n", type=int, default=21, help="qubits of the CPU-baseline sample")
     ap.add_argument("--stats-out", default="")
+    ap.add_argument("--persistent", action="store_true",
+                    help="also time the whole-circuit queue launch (sv_persistent_apply) and report it beside")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
@@ -166,13 +168,15 @@ def bench_batch(args):
         states.append(bmq.State(cfg, "cuda:0"))
         amp_gates += (1 << d["n"]) * len(d["gates"])
     res = {}
-    for mode in ["batched"] * args.warmup + ["batched", "sequential"]:
+    for mode in ["batched"] * args.warmup + ["batched", "sequential"] + ["persistent"] * (args.warmup + 1):
         for st in states:
             st.reset()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         if mode == "batched":
             bmq.batch_apply(states, plans)
+        elif mode == "persistent":
+            bmq.persistent_apply(states, plans)
         else:
             for st, p in zip(states, plans):
                 st.apply(p)
@@ -188,6 +192,8 @@ def bench_batch(args):
                    "eb": 1e-5, "fuse_qubits": args.fuse or 4, "flags": flags, "block_qubits": "n-8"},
         "sequential_value": amp_gates / res["sequential"], "sequential_ms": res["sequential"] * 1e3,
         "speedup_vs_sequential": res["sequential"] / res["batched"],
+        "persistent_ms": res["persistent"] * 1e3,
+        "persistent_value": amp_gates / res["persistent"],
         "compression_ratio_vs_complex64": sum(8 << d["n"] for d in mix) / fp,
     }
     print(json.dumps(out))
@@ -355,6 +361,7 @@ def main():
     ratio128 = (16 << n) / peak_bytes
 
     # result check outside the timed region
+    peak_bytes_final = sv.footprint()[0]
     _, _, norm2 = sv.fidelity(None)
     if args.workload == "qft":
         # sampled closed-form amplitudes
@@ -402,6 +409,20 @@ def main():
         "max_abs_err_sampled": maxerr,
         "norm2": norm2,
     }
+    if args.persistent:
+        # every stage in one queue launch; same records as the per-pass launches
+        for _ in range(args.warmup):
+            sv.reset()
+            bmq.persistent_apply([sv], [plan])
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            sv.reset()
+            bmq.persistent_apply([sv], [plan])
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        out["persistent_ms_per_step"] = ev0.elapsed_time(ev1) / args.steps
+        out["persistent_footprint_equal"] = sv.footprint()[0] == peak_bytes_final
     if args.stats_out:
         with open(args.stats_out, "w") as f:
             json.dump(last, f, indent=1)

@@ -110,10 +110,11 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 struct PersistArgs {
     const PassArgs *args;
     const uint32_t *first_item;
+    const uint32_t *tiles_per_item;
     const int32_t *dep;
     uint32_t *sync;
     uint64_t limit_ticks;       // longest wait, in s_memrealtime ticks
-    uint32_t n_pass, total;
+    uint32_t n_pass, total, max_grid;
     int32_t system_scope;       // records may live in host memory
 };
 constexpr int kSyncHead = 4;

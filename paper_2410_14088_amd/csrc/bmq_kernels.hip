@@ -491,7 +491,8 @@ __device__ __forceinline__ float2 const_ld(const float2 *p, int i)
 __device__ __forceinline__ uint32_t tix(uint32_t e) { return e + (e >> 4); }
 
 template <int K, int TILE, int NT>
-__device__ __forceinline__ void apply_dense(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M)
+__device__ __forceinline__ void apply_dense(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M,
+                                            int tid)
 {
     constexpr int D = 1 << K;
     constexpr int UNR = K <= 3 ? D : 1;
@@ -516,7 +517,7 @@ __device__ __forceinline__ void apply_dense(float *sre, float *sim, const OpDesc
         float ar[UG][D], ai[UG][D];
 #pragma unroll
         for (int u = 0; u < UG; ++u) {
-            const int g = (int)threadIdx.x + (s0 + u) * NT;
+            const int g = tid + (s0 + u) * NT;
             ok[u] = (NG % NT == 0) || g < NG;
             uint32_t x = (uint32_t)(ok[u] ? g : 0);
 #pragma unroll
@@ -579,11 +580,12 @@ __device__ __forceinline__ float block_elem(const float2 *__restrict__ M, int i,
 }
 
 template <int K, int TILE, int NT>
-__device__ __forceinline__ void apply_dense_mfma(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M)
+__device__ __forceinline__ void apply_dense_mfma(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ M,
+                                                 int tid)
 {
     constexpr int D = 1 << K, G = TILE >> K, RB = 2 * D / 32, STEPS = D;   // row blocks, k-steps of 2
     static_assert(G % 32 == 0, "column blocks of 32 groups");
-    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
+    const int lane = tid & 63, wave = tid >> 6;
     const int hi = lane >> 5, col = lane & 31;
     int pos[K], sp[K];
 #pragma unroll
@@ -656,14 +658,13 @@ __device__ __forceinline__ void apply_dense_mfma(float *sre, float *sim, const O
 // built from wave-uniform words, so each amplitude costs one OR and a lookup.
 template <int T, int NT>
 __device__ __forceinline__ void apply_diag(float *sre, float *sim, const OpDesc &op, const float2 *__restrict__ tab, uint64_t base,
-                           float2 *s_tab)
+                           float2 *s_tab, int tid)
 {
     constexpr int TILE = 1 << T;
     constexpr int LNT = __builtin_ctz(NT);
     constexpr int MB = T - LNT;
     const int k = op.k;
-    for (int i = threadIdx.x; i < (1 << k); i += NT) s_tab[i] = tab[i];
-    const int tid = (int)threadIdx.x;
+    for (int i = tid; i < (1 << k); i += NT) s_tab[i] = tab[i];
     uint32_t it = 0;
     uint32_t W[MB];
 #pragma unroll
@@ -1116,8 +1117,14 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     static_assert(CPW >= 1 && CPW <= 64, "chunks per wave");
     __shared__ L s;
 
-    const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
+    // the thread index through an opaque copy: when the body runs in a loop
+    // over work items, nothing derived from it can be hoisted out of the
+    // loop and kept live (and spilled) across items
+    uint32_t tid_u;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(tid_u) : "v"((uint32_t)threadIdx.x));
+    const int tid = (int)tid_u;
+    const int lane = tid & 63;
+    const int wave = tid >> 6;
     const CodecParams cp = copy_cp(a.cp);
     const uint64_t base = deposit((uint64_t)tile, a.nontile, a.n_nontile);
     const int c0 = wave * CPW;
@@ -1157,19 +1164,19 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         const OpDesc &op = a.ops[o];
         const float2 *data = a.opdata + op.data;
         if (op.type == OP_DIAG) {
-            apply_diag<T, NT>(s.re, s.im, op, data, base, s.tab);
+            apply_diag<T, NT>(s.re, s.im, op, data, base, s.tab, tid);
         } else {
             switch (op.k) {
-            case 1: apply_dense<1, L::TILE, NT>(s.re, s.im, op, data); break;
-            case 2: apply_dense<2, L::TILE, NT>(s.re, s.im, op, data); break;
-            case 3: apply_dense<3, L::TILE, NT>(s.re, s.im, op, data); break;
+            case 1: apply_dense<1, L::TILE, NT>(s.re, s.im, op, data, tid); break;
+            case 2: apply_dense<2, L::TILE, NT>(s.re, s.im, op, data, tid); break;
+            case 3: apply_dense<3, L::TILE, NT>(s.re, s.im, op, data, tid); break;
             case 4:
-                if (a.mfma) apply_dense_mfma<4, L::TILE, NT>(s.re, s.im, op, data);
-                else apply_dense<4, L::TILE, NT>(s.re, s.im, op, data);
+                if (a.mfma) apply_dense_mfma<4, L::TILE, NT>(s.re, s.im, op, data, tid);
+                else apply_dense<4, L::TILE, NT>(s.re, s.im, op, data, tid);
                 break;
             default:
-                if (a.mfma) apply_dense_mfma<5, L::TILE, NT>(s.re, s.im, op, data);
-                else apply_dense<5, L::TILE, NT>(s.re, s.im, op, data);
+                if (a.mfma) apply_dense_mfma<5, L::TILE, NT>(s.re, s.im, op, data, tid);
+                else apply_dense<5, L::TILE, NT>(s.re, s.im, op, data, tid);
                 break;
             }
         }
@@ -1188,7 +1195,7 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
 
     // ---- encode: four lanes per chunk, lane q holding values 16q..16q+15
     // (see encode_quad); one allocation per wave
-    if (threadIdx.x < 6) s.hist[threadIdx.x] = 0;
+    if (tid < 6) s.hist[tid] = 0;
     const int qc = lane >> 2, q = lane & 3;
     const bool act = qc < CPW;
     const int c = c0 + (act ? qc : 0);
@@ -1280,7 +1287,7 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         atomicAdd(&s.hist[4], zsum);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         unsigned long long *cc = a.counters + (tile & (uint32_t)(a.n_seg - 1)) * C_NUM;
         if (s.hist[4]) atomicAdd(&cc[C_ZERO_CHUNKS], (unsigned long long)s.hist[4]);
         atomicAdd(&cc[C_MODE0], (unsigned long long)s.hist[0] | ((unsigned long long)s.hist[1] << 32));
@@ -1332,53 +1339,56 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_queue(PersistArgs p
     __shared__ uint32_t s_item, s_go;
     typedef const __attribute__((address_space(4))) PassArgs CArgs;
     uint32_t *const next = pa.sync, *const abort_flag = pa.sync + 1, *const done = pa.sync + kSyncHead;
-    if (threadIdx.x == 0) {
-        uint32_t it = atomicAdd(next, 1u);
-        if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = pa.total;
-        s_item = it;
-    }
-    __syncthreads();
-    const uint32_t it = s_item;
-    if (it >= pa.total) return;
-    int lo = 0, hi = (int)pa.n_pass;
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (pa.first_item[mid] <= it) lo = mid;
-        else hi = mid;
-    }
-    const int d = pa.dep[lo];
-    if (d >= 0) {
-        // poll with plain coherent loads and a growing sleep (no cache
-        // maintenance per poll), then one acquire for every wave
+    int acquired = -1;
+    for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t need = pa.first_item[d + 1] - pa.first_item[d];
-            const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-            uint32_t go = 1, nap = 1;
-            while (__hip_atomic_load(done + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-                if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
-                    __builtin_amdgcn_s_memrealtime() - t0 > pa.limit_ticks) {
-                    __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    go = 0;
-                    break;
-                }
-                for (uint32_t z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(4);
-                nap = nap < 4u ? 2u * nap : 4u;
-            }
-            s_go = go;
+            uint32_t it = atomicAdd(next, 1u);
+            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = pa.total;
+            s_item = it;
         }
         __syncthreads();
-        if (!s_go) return;
-        if (pa.system_scope) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
-        else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    }
-    pass_body<T, NT, DOM, CArgs>(((CArgs *)pa.args)[lo], it - pa.first_item[lo]);
-    // every wave's records and directory entries out before the count
-    if (pa.system_scope) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-    else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (pa.system_scope) __hip_atomic_fetch_add(done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        else __hip_atomic_fetch_add(done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t it = s_item;
+        if (it >= pa.total) return;
+        int lo = 0, hi = (int)pa.n_pass;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pa.first_item[mid] <= it) lo = mid;
+            else hi = mid;
+        }
+        const int d = pa.dep[lo];
+        if (d >= 0 && d != acquired) {
+            if (threadIdx.x == 0) {
+                const uint32_t need = pa.first_item[d + 1] - pa.first_item[d];
+                const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+                uint32_t go = 1, nap = 1;
+                while (__hip_atomic_load(done + d, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+                    if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ||
+                        __builtin_amdgcn_s_memrealtime() - t0 > pa.limit_ticks) {
+                        __hip_atomic_store(abort_flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        go = 0;
+                        break;
+                    }
+                    for (uint32_t z = 0; z < nap; ++z) __builtin_amdgcn_s_sleep(4);
+                    nap = nap < 4u ? 2u * nap : 4u;
+                }
+                s_go = go;
+            }
+            __syncthreads();
+            if (!s_go) return;
+            if (pa.system_scope) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");
+            else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            acquired = d;
+        }
+        const uint32_t tpi = pa.tiles_per_item[lo];
+        const uint32_t tile0 = (it - pa.first_item[lo]) * tpi;
+        for (uint32_t u = 0; u < tpi; ++u) pass_body<T, NT, DOM, CArgs>(((CArgs *)pa.args)[lo], tile0 + u);
+        if (pa.system_scope) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+        else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            if (pa.system_scope) __hip_atomic_fetch_add(done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+            else __hip_atomic_fetch_add(done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
     }
 }
 
@@ -1645,7 +1655,7 @@ hipError_t launch_pass(const PassArgs &a, hipStream_t s)
 hipError_t launch_pass_queue(int t, int domain, const PersistArgs &pa, hipStream_t s)
 {
     if (pa.total == 0) return hipSuccess;
-    const dim3 grid(pa.total);
+    const dim3 grid(std::min(pa.total, pa.max_grid));
     switch (t * 2 + domain) {
 #define BMQ_PASS(T, NT, D) \
     case T * 2 + D: hipLaunchKernelGGL((pass_kernel_queue<T, NT, D>), grid, dim3(NT), 0, s, pa); break;

@@ -1194,12 +1194,13 @@ struct PersistClass {
     std::vector<size_t> members;                  // state indices
     std::vector<std::pair<size_t, size_t>> pass;  // (state index, pass index)
     std::vector<uint32_t> first_item;             // n_pass + 1
+    std::vector<uint32_t> tpi;
     std::vector<int32_t> dep;
-    uint64_t args_off, first_off, dep_off, sync_off, sync_words;
+    uint64_t args_off, first_off, tpi_off, dep_off, sync_off, sync_words;
 };
 
 int plan_persistent(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
-                    std::vector<PersistClass> &classes, uint64_t &bytes)
+                    std::vector<PersistClass> &classes, uint64_t &bytes, int cus)
 {
     std::vector<BatchGroup> groups;              // validation shared with the batched launches
     uint64_t unused = 0;
@@ -1217,16 +1218,33 @@ int plan_persistent(sv_t *const *states, const sv_plan_t *const *plans, size_t c
                 kmax = std::max(kmax, launches_of(plans[i], 0, plans[i]->stages.size()));
             }
         if (c.members.empty()) continue;
+        // An item is a run of consecutive tiles of one pass, so that the two
+        // device-wide atomics and the cache write-back of finishing an item
+        // are paid once per run: as long as every pass step still has about
+        // eight items per resident workgroup (resident: four per compute
+        // unit), up to 32 tiles per item.
+        uint64_t widest = 0;
+        for (size_t k = 0; k < kmax; ++k) {
+            uint64_t w = 0;
+            for (size_t i : c.members)
+                if (launches_of(plans[i], 0, plans[i]->stages.size()) > k) w += 1ull << (states[i]->n - c.t);
+            widest = std::max(widest, w);
+        }
+        uint64_t per_max = 1;
+        while (per_max < 32 && widest / (2 * per_max) >= 8ull * 4ull * cus) per_max *= 2;
         std::vector<int32_t> last(count, -1);
         uint64_t items = 0;
         for (size_t k = 0; k < kmax; ++k)
             for (size_t i : c.members) {
                 if (launches_of(plans[i], 0, plans[i]->stages.size()) <= k) continue;
+                const uint64_t tiles = 1ull << (states[i]->n - c.t);
+                const uint64_t per = std::min(per_max, tiles);
                 c.first_item.push_back((uint32_t)items);
+                c.tpi.push_back((uint32_t)per);
                 c.dep.push_back(last[i]);
                 last[i] = (int32_t)c.pass.size();
                 c.pass.push_back({i, k});
-                items += 1ull << (states[i]->n - c.t);
+                items += tiles / per;
                 if (items > 0x7FFFFFFFull) return fail(SV_ERR_UNSUPPORTED, "a persistent launch exceeds 2^31 tiles");
             }
         if (c.pass.empty()) continue;
@@ -1235,6 +1253,8 @@ int plan_persistent(sv_t *const *states, const sv_plan_t *const *plans, size_t c
         bytes += align256(c.pass.size() * sizeof(bmq::PassArgs));
         c.first_off = bytes;
         bytes += align256(c.first_item.size() * sizeof(uint32_t));
+        c.tpi_off = bytes;
+        bytes += align256(c.tpi.size() * sizeof(uint32_t));
         c.dep_off = bytes;
         bytes += align256(c.dep.size() * sizeof(int32_t));
         c.sync_off = bytes;
@@ -1253,24 +1273,25 @@ int sv_persistent_workspace(sv_t *const *states, const sv_plan_t *const *plans, 
 {
     if (!bytes) return fail(SV_ERR_INVALID, "bytes is NULL");
     std::vector<PersistClass> classes;
-    return plan_persistent(states, plans, count, classes, *bytes);
+    return plan_persistent(states, plans, count, classes, *bytes, 256);   // sizes do not depend on the CU count
 }
 
 int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t count, void *workspace_dev,
                         uint64_t workspace_bytes, uint32_t wait_limit_us, void *hip_stream)
 {
+    int dev = 0, khz = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     std::vector<PersistClass> classes;
     uint64_t need = 0;
-    if (int rc = plan_persistent(states, plans, count, classes, need)) return rc;
+    if (int rc = plan_persistent(states, plans, count, classes, need, std::max(cus, 1))) return rc;
     if (!workspace_dev || ((uintptr_t)workspace_dev & 255u) || workspace_bytes < need)
         return fail(SV_ERR_INVALID, "workspace must be 256-byte aligned and hold %llu bytes", (unsigned long long)need);
     hipStream_t stream = (hipStream_t)hip_stream;
     for (size_t i = 0; i < count; ++i)
         if (states[i]->stream != stream)
             return fail(SV_ERR_INVALID, "state %zu was created on another stream", i);
-    int dev = 0, khz = 0;
-    HIP_TRY(hipGetDevice(&dev));
-    HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     if (khz <= 0) return fail(SV_ERR_UNSUPPORTED, "the device reports no constant-rate clock");
     const uint64_t limit_us = wait_limit_us ? wait_limit_us : 10000000u;
     for (size_t i = 0; i < count; ++i) {
@@ -1293,6 +1314,7 @@ int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size
         for (size_t L = 0; L < c.pass.size(); ++L) ga[L] = args[c.pass[L].first][c.pass[L].second];
         std::memcpy(host.data() + c.first_off, c.first_item.data(), c.first_item.size() * sizeof(uint32_t));
         std::memcpy(host.data() + c.dep_off, c.dep.data(), c.dep.size() * sizeof(int32_t));
+        std::memcpy(host.data() + c.tpi_off, c.tpi.data(), c.tpi.size() * sizeof(uint32_t));
     }
     uint8_t *ws = (uint8_t *)workspace_dev;
     HIP_TRY(hipMemcpyAsync(ws, host.data(), need, hipMemcpyHostToDevice, stream));
@@ -1304,6 +1326,8 @@ int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size
         std::memset(&pa, 0, sizeof(pa));
         pa.args = (const bmq::PassArgs *)(ws + c.args_off);
         pa.first_item = (const uint32_t *)(ws + c.first_off);
+        pa.tiles_per_item = (const uint32_t *)(ws + c.tpi_off);
+        pa.max_grid = (uint32_t)std::max(cus, 1) * 4u;       // resident workgroups
         pa.dep = (const int32_t *)(ws + c.dep_off);
         pa.sync = (uint32_t *)(ws + c.sync_off);
         pa.limit_ticks = limit_us * (uint64_t)khz / 1000u;
