@@ -250,10 +250,11 @@ int sv_batch_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t co
  * instead of one launch per pass step.  Stages run one after another because
  * each reads every block the previous one wrote (Section 4.2 workflow, Fig. 6);
  * here the stage boundary is a per-circuit barrier inside the launch:
- * workgroups take (pass, tile) items from a device queue in pass order, and
- * a tile of pass k of a circuit starts once all tiles of that circuit's pass
- * k - 1 are done (atomic counters), so circuits advance independently and a
- * workgroup never waits for the launch to end.  Results are identical to
+ * workgroups take items (runs of consecutive tiles of one pass) from a
+ * device queue in pass order, and an item of pass k of a circuit starts once
+ * every item of that circuit's pass k - 1 is done (atomic counters), so
+ * circuits advance independently and a workgroup never waits for the launch
+ * to end.  Results are identical to
  * sv_batch_apply and stage_apply_compressed (same pass body, same records).
  * wait_limit_us bounds every device-side wait (0 = 10 s): a wait that runs
  * out aborts the whole launch, which always finishes; the states of an
