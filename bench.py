@@ -27,6 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9     # CUs x SIMDs x lanes x clock: one wave64 VALU op per SIMD per 4 cycles
 METRIC = "compressed-SV amplitude·gates/s, GB/s vs HBM peak at fidelity≥0.99; compression ratio"
 
 
@@ -111,6 +112,31 @@ def counter_traffic(n: int, tile: int, fuse: int, flags: int = 0, workload: str 
     if not m_sha or not m_val or m_sha.group(1) != sha:
         return None
     return int(m_val.group(1))
+
+
+def valu_profile(n: int, tile: int, fuse: int, flags: int = 0, workload: str = "qft"):
+    """Issued VALU lane-operations per second of the pass kernel and their
+    fraction of the plain-VALU ceiling, from the committed SQ-counter profile
+    of the default workload (None when the workload differs or the kernel
+    source changed since the counters were taken)."""
+    import hashlib
+    import re
+    if (n, tile or 12, fuse, flags, workload) != (30, 12, 4, 0, "qft"):
+        return None
+    prof = os.path.join(ROOT, "profiles", "pass_kernel_qft30_sq_counters.md")
+    src = os.path.join(ROOT, "paper_2410_14088_amd", "csrc", "bmq_kernels.hip")
+    try:
+        text = open(prof).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    m_sha = re.search(r"^kernel_sha256: ([0-9a-f]{64})$", text, re.M)
+    m_ops = re.search(r"^valu_lane_ops_per_s: ([0-9.e+]+)$", text, re.M)
+    if not m_sha or not m_ops or m_sha.group(1) != sha:
+        return None
+    ops = float(m_ops.group(1))
+    return {"bound": "alu", "achieved": ops, "peak": VALU_PEAK_LANE_OPS, "unit": "lane-op/s",
+            "frac": ops / VALU_PEAK_LANE_OPS, "source": "issued VALU instructions (SQ counters), not algorithmic"}
 
 
 def cpu_baseline(n: int):
@@ -396,6 +422,7 @@ def main():
                    "tile_qubits": args.tile or 12, "flags": args.flags},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(n, args.tile, args.fuse, args.flags, args.workload)},
+        "alu_roofline": valu_profile(n, args.tile, args.fuse, args.flags, args.workload),
         "gbps_algorithmic": achieved,
         "kernel_ms_per_step": kern_ms / args.steps,
         "pass_launch_avg_ms": kern_ms / launches,
