@@ -119,7 +119,6 @@ __device__ __forceinline__ void wave_sync_lds()
 __device__ __forceinline__ uint32_t zigzag(int32_t d) { return ((uint32_t)d << 1) ^ (uint32_t)(d >> 31); }
 __device__ __forceinline__ int32_t unzigzag(uint32_t z) { return (int32_t)((z >> 1) ^ (0u - (z & 1u))); }
 __device__ __forceinline__ uint32_t bitlen(uint32_t v) { return v ? 32u - (uint32_t)__clz((int)v) : 0u; }
-__device__ __forceinline__ float pow2i(int i) { return __uint_as_float((uint32_t)(i + 127) << 23); }
 
 // ------------------------------------------------------------------ codec arithmetic
 
@@ -162,12 +161,11 @@ __device__ __forceinline__ float log_decode(int32_t k, int s, float delta)
     p = __builtin_fmaf(p, f, 0.24022650718688965f);
     p = __builtin_fmaf(p, f, 0.6931471824645996f);
     p = __builtin_fmaf(p, f, 1.0f);
-    // within the normal exponent range 2^i is one float and one scaling
-    // rounds exactly as the two half scalings below (p 2^(i/2) is exact)
-    if (__builtin_expect(i >= -126 && i <= 127, 1)) return p * pow2i(i);
-    const int ic = i < -250 ? -250 : (i > 250 ? 250 : i);
-    const int i1 = ic >> 1, i2 = ic - i1;
-    return (p * pow2i(i1)) * pow2i(i2);
+    // p 2^i rounded once: one v_ldexp_f32.  For i in the normal range this
+    // is the exact scaling p * 2^i; beyond it the result is what the two
+    // half scalings (p 2^(i/2) exact, then one rounding) give: a subnormal
+    // rounded once, zero below, infinity above.
+    return __builtin_amdgcn_ldexpf(p, i);
 }
 
 // quantize v with step 2^-s and verify |v - k 2^-s| <= eb in float32 (one
@@ -986,7 +984,7 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
     for (int j = 0; j < 16; ++j) {
         const uint32_t oj = o + (uint32_t)j * w;
         uint64_t v;                                     // the two words holding the field, one load
-        __builtin_memcpy(&v, pay + (oj >> 5), 8);
+        __builtin_memcpy(&v, (const uint8_t *)pay + ((uint64_t)(oj >> 5) << 2), 8);
         const uint32_t f = (uint32_t)(v >> (oj & 31u)) & fmask;
         k[j] = unzigzag(f);
     }
@@ -1013,8 +1011,12 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
         if (DOM == 0) {
             v = (float)k[j] * cp.delta;
         } else {
-            const float mag = log_decode(k[j], cp.s, cp.delta);
-            v = ((zb >> j) & 1u) ? 0.0f : (((negb >> j) & 1u) ? -mag : mag);
+            // the magnitude is positive: the sign bit comes from the sign
+            // mask, and a flagged zero clears every bit (+0)
+            const uint32_t mag = __float_as_uint(log_decode(k[j], cp.s, cp.delta));
+            const uint32_t sgn = negb << (31 - j);
+            const uint32_t keep = ~(uint32_t)__builtin_amdgcn_sbfe((int)zb, j, 1);
+            v = __uint_as_float(((sgn & 0x80000000u) | mag) & keep);
         }
         dst[j] = v;
     }
