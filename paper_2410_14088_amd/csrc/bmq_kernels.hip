@@ -1026,17 +1026,33 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
 // stream word i lives at st0[i] for i < R, else at st1[i - R] (the wave's own
 // tile rows of the real and imaginary planes, free once its chunks are
 // encoded).
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
 struct Staging {
-    uint32_t *st0, *st1;
+    uint32_t a0, a1;     // LDS byte addresses of st0 and of st1 - 4 R
     uint32_t R;
-    __device__ __forceinline__ uint32_t *word(uint32_t i) const { return i < R ? st0 + i : st1 + (i - R); }
+    __device__ __forceinline__ lds_u32 *word(uint32_t i) const
+    {
+        return (lds_u32 *)(uintptr_t)(4u * i + (i < R ? a0 : a1));
+    }
 };
+__device__ __forceinline__ Staging make_staging(uint32_t *st0, uint32_t *st1, uint32_t R)
+{
+    const uint32_t a0 = (uint32_t)(uintptr_t)(lds_u32 *)st0, a1 = (uint32_t)(uintptr_t)(lds_u32 *)st1;
+    return Staging{a0, a1 - 4u * R, R};
+}
 
 // Stage this lane's part of a plane's payload, which starts at stream word
 // pw: packed planes as 16 w-bit fields from bit 16 w q of the payload
-// (LSB-first), VERBATIM planes as the 16 raw values from word 16 q.  When w
-// is odd the lanes q = 1, 3 start in the middle of a word whose low half the
-// previous lane fills; that word is assembled from both lanes and stored once.
+// (LSB-first), VERBATIM planes as the 16 raw values from word 16 q.  Field j
+// of a packed plane sits at stream bit 32 pw + 16 w q + j w and is ORed into
+// the one or two staging words it overlaps (the staging words are zero
+// beforehand), so the fields need no per-lane word assembly and a word that
+// two neighbouring lanes share needs no merging.  The second OR of a field
+// that ends inside its first word adds nothing; its word is at most the
+// stream's last word + 1, which still lies in the staging rows.
 __device__ __forceinline__ void stage_quad_payload(const QuadPlane &P, const Staging &S, uint32_t pw, int q)
 {
     const uint32_t mode = P.hdr & 3u;
@@ -1046,43 +1062,21 @@ __device__ __forceinline__ void stage_quad_payload(const QuadPlane &P, const Sta
         return;
     }
     const uint32_t w = P.w;
-    uint32_t lead = 0;
-    const bool packed = mode != M_ZERO && w != 0u;
-    uint64_t acc = 0;
-    uint32_t nb = 0, wi = 0, off = 0;
-    bool pending = false;
-    if (packed) {
-        const uint32_t start = 16u * w * (uint32_t)q;
-        wi = start >> 5;
-        off = start & 31u;
-        nb = off;
-        pending = off != 0u;
-        int32_t prev = P.carry;
+    if (mode == M_ZERO || w == 0u) return;
+    const uint32_t b0 = 32u * pw + 16u * w * (uint32_t)q;
+    int32_t prev = P.carry;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
-            const int32_t kp = P.kp[j];
-            const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
-            prev = kp;
-            const uint32_t fld = (mode == M_LZ) ? zigzag(d) : zigzag(kp);
-            acc |= (uint64_t)fld << nb;
-            nb += w;
-            if (nb >= 32u) {
-                if (pending) {
-                    lead = (uint32_t)acc;
-                    pending = false;
-                } else {
-                    *S.word(pw + wi) = (uint32_t)acc;
-                }
-                ++wi;
-                acc >>= 32;
-                nb -= 32u;
-            }
-        }
+    for (int j = 0; j < 16; ++j) {
+        const int32_t kp = P.kp[j];
+        const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
+        prev = kp;
+        const uint32_t fld = (mode == M_LZ) ? zigzag(d) : zigzag(kp);
+        const uint32_t b = b0 + (uint32_t)j * w;
+        const uint64_t t = (uint64_t)fld << (b & 31u);
+        __hip_atomic_fetch_or(S.word(b >> 5), (uint32_t)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __hip_atomic_fetch_or(S.word((b >> 5) + 1u), (uint32_t)(t >> 32), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
-    // the low half-word an even lane leaves over goes to the next lane
-    const uint32_t tail = (packed && nb) ? (uint32_t)acc : 0u;
-    const uint32_t from_prev = qperm<0x90>(tail);      // lane q takes lane q - 1's value
-    if (packed && off) *S.word(pw + ((16u * w * (uint32_t)q) >> 5)) = lead | from_prev;
 }
 
 template <int T, int NT>
@@ -1242,9 +1236,17 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     if (!overflow && total) {
         // assemble the wave's bodies in its own LDS rows, then copy them out
         // in full contiguous words
-        const Staging S{(uint32_t *)(s.re + tix((uint32_t)c0 << 6)), (uint32_t *)(s.im + tix((uint32_t)c0 << 6)),
-                        (uint32_t)CPW * 68u};
+        const Staging S = make_staging((uint32_t *)(s.re + tix((uint32_t)c0 << 6)),
+                                       (uint32_t *)(s.im + tix((uint32_t)c0 << 6)), (uint32_t)CPW * 68u);
         wave_sync_lds();                              // every lane has read its values
+        // zero the stream's staging words (the payload fields are ORed in)
+        const uint32_t nw0 = total >> 2;
+        for (uint32_t w4 = 4u * (uint32_t)lane; w4 < nw0; w4 += 256u) {
+            if (w4 + 4u <= nw0) *(lds_u32x4 *)S.word(w4) = u32x4{0u, 0u, 0u, 0u};
+            else
+                for (uint32_t wd = w4; wd < nw0; ++wd) *S.word(wd) = 0u;
+        }
+        wave_sync_lds();
         if (act && (h0 | h1)) {
             if (q == 0) {
                 if (Lv.lz0) *S.word(rel >> 2) = (uint32_t)P0.anchor;
@@ -1252,10 +1254,10 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
             }
             // each lane stages its 16 bits (bytes 2q, 2q + 1) of the mixed masks
             const uint32_t mw = (uint32_t)q >> 1, mh = (uint32_t)q & 1u;
-            if (Lv.hs0) ((uint16_t *)S.word(((rel + Lv.off_sm0) >> 2) + mw))[mh] = (uint16_t)P0.negb;
-            if (Lv.hz0) ((uint16_t *)S.word(((rel + Lv.off_zm0) >> 2) + mw))[mh] = (uint16_t)(~P0.nzb);
-            if (Lv.hs1) ((uint16_t *)S.word(((rel + Lv.off_sm1) >> 2) + mw))[mh] = (uint16_t)P1.negb;
-            if (Lv.hz1) ((uint16_t *)S.word(((rel + Lv.off_zm1) >> 2) + mw))[mh] = (uint16_t)(~P1.nzb);
+            if (Lv.hs0) ((lds_u16 *)S.word(((rel + Lv.off_sm0) >> 2) + mw))[mh] = (uint16_t)P0.negb;
+            if (Lv.hz0) ((lds_u16 *)S.word(((rel + Lv.off_zm0) >> 2) + mw))[mh] = (uint16_t)(~P0.nzb);
+            if (Lv.hs1) ((lds_u16 *)S.word(((rel + Lv.off_sm1) >> 2) + mw))[mh] = (uint16_t)P1.negb;
+            if (Lv.hz1) ((lds_u16 *)S.word(((rel + Lv.off_zm1) >> 2) + mw))[mh] = (uint16_t)(~P1.nzb);
             stage_quad_payload(P0, S, (rel + Lv.off_p0) >> 2, q);
             stage_quad_payload(P1, S, (rel + Lv.off_p1) >> 2, q);
         }
@@ -1266,7 +1268,7 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         const uint32_t nw = total >> 2;
         for (uint32_t w4 = 4u * (uint32_t)lane; w4 < nw; w4 += 256u) {
             if (w4 + 4u <= nw) {
-                const uint4 v = *(const uint4 *)S.word(w4);
+                const u32x4 v = *(const lds_u32x4 *)S.word(w4);
                 __builtin_memcpy(dst + w4, &v, 16);
             } else {
                 for (uint32_t wd = w4; wd < nw; ++wd) dst[wd] = *S.word(wd);
