@@ -1214,30 +1214,17 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     const uint32_t seg = (tile * NW + (uint32_t)wave) & (uint32_t)(a.n_seg - 1);
     unsigned long long *cnt = a.counters + seg * C_NUM;
+    // the wave's allocation: issued now, its result is needed only for the
+    // copy-out, so the record staging below runs while it is in flight
     unsigned long long got = 0;
     if (lane == 0 && total) got = atomicAdd(&cnt[C_CURSOR], (unsigned long long)total);
-    const uint64_t b = uniform_u64(got);
-    uint64_t wave_off = (uint64_t)seg * a.seg_cap + b;       // directory offset of the wave's first body
-    bool overflow = false;
-    if (total && b + total > a.seg_cap) {
-        // segment full: the wave's bodies go to the host pool, or are lost
-        unsigned long long goth = 0;
-        if (lane == 0 && a.host_cap) goth = atomicAdd(&a.counters[C_HOST_CURSOR], (unsigned long long)total);
-        const uint64_t hb = uniform_u64(goth);
-        overflow = !a.host_cap || hb + total > a.host_cap;
-        wave_off = a.pool_cap + hb;
-    }
-    if (lane == 0 && overflow) atomicOr(&cnt[C_OVERFLOW], 1ull);
-    if (lane == 0 && total && !overflow)
-        atomicAdd(&cnt[wave_off < a.pool_cap ? C_DEV_BYTES : C_HOST_BYTES], (unsigned long long)total);
     // the chunk's body offset in the wave's stream, from its quad's lane 0
     const uint32_t rel = qperm<QB0>(incl - size);
-    const uint64_t off = wave_off + rel;
-    if (!overflow && total) {
-        // assemble the wave's bodies in its own LDS rows, then copy them out
-        // in full contiguous words
-        const Staging S = make_staging((uint32_t *)(s.re + tix((uint32_t)c0 << 6)),
-                                       (uint32_t *)(s.im + tix((uint32_t)c0 << 6)), (uint32_t)CPW * 68u);
+    // assemble the wave's bodies in its own LDS rows (offsets relative to
+    // the wave's stream)
+    const Staging S = make_staging((uint32_t *)(s.re + tix((uint32_t)c0 << 6)),
+                                   (uint32_t *)(s.im + tix((uint32_t)c0 << 6)), (uint32_t)CPW * 68u);
+    if (total) {
         wave_sync_lds();                              // every lane has read its values
         // zero the stream's staging words (the payload fields are ORed in)
         const uint32_t nw0 = total >> 2;
@@ -1262,8 +1249,26 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
             stage_quad_payload(P1, S, (rel + Lv.off_p1) >> 2, q);
         }
         wave_sync_lds();
-        // 16 bytes per lane and step (the stream is 4-byte aligned; the
-        // staging rows are 16-byte aligned and R is a multiple of 4 words)
+    }
+    const uint64_t b = uniform_u64(got);
+    uint64_t wave_off = (uint64_t)seg * a.seg_cap + b;       // directory offset of the wave's first body
+    bool overflow = false;
+    if (total && b + total > a.seg_cap) {
+        // segment full: the wave's bodies go to the host pool, or are lost
+        unsigned long long goth = 0;
+        if (lane == 0 && a.host_cap) goth = atomicAdd(&a.counters[C_HOST_CURSOR], (unsigned long long)total);
+        const uint64_t hb = uniform_u64(goth);
+        overflow = !a.host_cap || hb + total > a.host_cap;
+        wave_off = a.pool_cap + hb;
+    }
+    if (lane == 0 && overflow) atomicOr(&cnt[C_OVERFLOW], 1ull);
+    if (lane == 0 && total && !overflow)
+        atomicAdd(&cnt[wave_off < a.pool_cap ? C_DEV_BYTES : C_HOST_BYTES], (unsigned long long)total);
+    const uint64_t off = wave_off + rel;
+    if (!overflow && total) {
+        // copy the staged stream out: 16 bytes per lane and step (the stream
+        // is 4-byte aligned; the staging rows are 16-byte aligned and R is a
+        // multiple of 4 words)
         uint32_t *dst = (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, wave_off);
         const uint32_t nw = total >> 2;
         for (uint32_t w4 = 4u * (uint32_t)lane; w4 < nw; w4 += 256u) {
