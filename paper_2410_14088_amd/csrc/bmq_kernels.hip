@@ -1085,7 +1085,6 @@ struct PassLds {
     float re[TILE + TILE / 16];           // tile, padded layout (tix)
     float im[TILE + TILE / 16];
     float2 tab[1 << kMaxDiagQubits];      // apply phase: diagonal table
-    uint32_t hist[6];
 };
 
 __device__ __forceinline__ CodecParams copy_cp(const CodecParams &c) { return c; }
@@ -1191,7 +1190,6 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
 
     // ---- encode: four lanes per chunk, lane q holding values 16q..16q+15
     // (see encode_quad); one allocation per wave
-    if (tid < 6) s.hist[tid] = 0;
     const int qc = lane >> 2, q = lane & 3;
     const bool act = qc < CPW;
     const int c = c0 + (act ? qc : 0);
@@ -1289,18 +1287,14 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     const uint32_t zw = (act && q == 0 && (h0 | h1) == 0u) ? 1u : 0u;
     const uint32_t hsum = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_add(hw), 63);
     const uint32_t zsum = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_add(zw), 63);
-    __syncthreads();
+    // each wave adds its counts to its own segment's counters (no barrier:
+    // the waves of a tile finish independently)
     if (lane == 0) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) atomicAdd(&s.hist[m], (hsum >> (8 * m)) & 0xFFu);
-        atomicAdd(&s.hist[4], zsum);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        unsigned long long *cc = a.counters + (tile & (uint32_t)(a.n_seg - 1)) * C_NUM;
-        if (s.hist[4]) atomicAdd(&cc[C_ZERO_CHUNKS], (unsigned long long)s.hist[4]);
-        atomicAdd(&cc[C_MODE0], (unsigned long long)s.hist[0] | ((unsigned long long)s.hist[1] << 32));
-        atomicAdd(&cc[C_MODE0 + 2], (unsigned long long)s.hist[2] | ((unsigned long long)s.hist[3] << 32));
+        if (zsum) atomicAdd(&cnt[C_ZERO_CHUNKS], (unsigned long long)zsum);
+        if (hsum & 0xFFFFu)
+            atomicAdd(&cnt[C_MODE0], (unsigned long long)(hsum & 0xFFu) | ((unsigned long long)((hsum >> 8) & 0xFFu) << 32));
+        if (hsum >> 16)
+            atomicAdd(&cnt[C_MODE0 + 2], (unsigned long long)((hsum >> 16) & 0xFFu) | ((unsigned long long)(hsum >> 24) << 32));
     }
 }
 
