@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--eb", type=float, default=0.0, help="codec error bound (default 1e-5)")
     ap.add_argument("--fuse", type=int, default=0, help="fusion width (default 4 for qft, 5 for random-mirror)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-n", type=int, default=21, help="qubits of the CPU-baseline sample")
+    ap.add_argument("--cpu-n", type=int, default=22, help="qubits of the CPU-baseline sample")
     ap.add_argument("--stats-out", default="")
     ap.add_argument("--persistent", action="store_true",
                     help="also time the whole-circuit queue launch (sv_persistent_apply) and report it beside")
