@@ -1130,6 +1130,7 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
 
     // ---- load
     if (a.in_mode == IO_COMPRESSED) {
+        __builtin_amdgcn_s_setprio(2);                  // the loads leave ahead of other waves' arithmetic
         // four lanes per chunk (see decode_quad)
         const int qc = lane >> 2, q = lane & 3;
         const bool act = qc < CPW;
@@ -1145,6 +1146,7 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         const uint32_t t0 = tix((uint32_t)(c << 6) + 16u * (uint32_t)q);
         decode_quad<DOM>(eh0, an0, body, Lv.off_sm0, Lv.off_zm0, Lv.off_p0, s.re + t0, q, act, cp);
         decode_quad<DOM>(eh1, an1, body, Lv.off_sm1, Lv.off_zm1, Lv.off_p1, s.im + t0, q, act, cp);
+        __builtin_amdgcn_s_setprio(0);
     } else {
         for (int i = 0; i < CPW; ++i) {
             const uint64_t g = lane_u64(my_g, i);
