@@ -1148,11 +1148,13 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         decode_quad<DOM>(eh1, an1, body, Lv.off_sm1, Lv.off_zm1, Lv.off_p1, s.im + t0, q, act, cp);
         __builtin_amdgcn_s_setprio(0);
     } else {
+        __builtin_amdgcn_s_setprio(2);                  // as for the decoder's loads
         for (int i = 0; i < CPW; ++i) {
             const uint64_t g = lane_u64(my_g, i);
             s.re[tix(((c0 + i) << 6) + lane)] = a.scr_re[g + lane];
             s.im[tix(((c0 + i) << 6) + lane)] = a.scr_im[g + lane];
         }
+        __builtin_amdgcn_s_setprio(0);
     }
     __syncthreads();
 
