@@ -47,10 +47,11 @@ def parse():
                          "uncompressed complex64 size")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--n", type=int, default=0, help="qubits (default: 30 for qft, 33 for random-mirror)")
-    ap.add_argument("--flags", type=int, default=0, help="sv_config_t flags (1 no scratch, 2 no MFMA)")
+    ap.add_argument("--flags", type=int, default=0,
+                    help="sv_config_t flags (1 no scratch, 2 no MFMA, 4 one stage per gate)")
     ap.add_argument("--tile", type=int, default=0)
-    ap.add_argument("--domain", choices=["log", "lin"], default="log",
-                    help="codec domain of the qft / random-mirror workloads (default log)")
+    ap.add_argument("--domain", choices=["log", "lin", "raw"], default="log",
+                    help="codec domain of the qft / random-mirror workloads (default log; raw = no compression)")
     ap.add_argument("--eb", type=float, default=0.0, help="codec error bound (default 1e-5)")
     ap.add_argument("--fuse", type=int, default=0, help="fusion width (default 4 for qft, 5 for random-mirror)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -345,7 +346,7 @@ def main():
         fuse = args.fuse or 5
         wname = f"random-{n}q-d16-mirror"
     args.fuse = fuse
-    d["domain"] = 1 if args.domain == "log" else 0
+    d["domain"] = {"lin": 0, "log": 1, "raw": 2}[args.domain]
     d["eb"] = args.eb or d["eb"]
     cfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=fuse, domain=d["domain"], eb=d["eb"], tile=args.tile,
                      flags=args.flags)

@@ -54,8 +54,12 @@ enum {
 /* Codec domains (Section 4.3).  LIN: the error bound applies to each real
  * and imaginary part directly (point-wise absolute).  LOG: Algorithm 2 --
  * sign bitmap, magnitude, log2, absolute bound eb on log2|x|, which is the
- * point-wise relative bound 2^eb - 1 of Eq. 1-2. */
-enum { SV_DOMAIN_LIN = 0, SV_DOMAIN_LOG = 1 };
+ * point-wise relative bound 2^eb - 1 of Eq. 1-2.  RAW: no compression --
+ * every chunk is stored VERBATIM (raw float32, lossless; eb is not used), the
+ * same stage loop without the codec, as in the no-compression comparison of
+ * Section 5's compression-overhead analysis.  Only the initial state keeps
+ * its all-zero chunks as ZERO directory entries. */
+enum { SV_DOMAIN_LIN = 0, SV_DOMAIN_LOG = 1, SV_DOMAIN_RAW = 2 };
 
 /* Gate kinds.  1-qubit matrices as usual; for 2-qubit gates the 4x4 matrix
  * index is 2*bit(q[0]) + bit(q[1]), the row order of Section 2.1.
@@ -82,7 +86,7 @@ typedef struct {
     int32_t block_qubits; /* b: SV block = 2^b amplitudes, 6 <= b <= n */
     int32_t inner_size;   /* Algorithm 1 inner size; threshold = max(inner, 2) */
     int32_t fuse_qubits;  /* widest dense fused gate, 1..5 */
-    int32_t domain;       /* SV_DOMAIN_LIN or SV_DOMAIN_LOG */
+    int32_t domain;       /* SV_DOMAIN_LIN, SV_DOMAIN_LOG or SV_DOMAIN_RAW */
     int32_t tile_qubits;  /* amplitudes per on-chip tile = 2^tile_qubits; 0 = default (12) */
     double eb;            /* absolute bound in the codec domain, > 0 */
     uint64_t pool_bytes;  /* device capacity of each compressed pool; 0 = worst case */
@@ -98,6 +102,20 @@ typedef struct {
 /* SV_FLAG_NO_MFMA: apply dense 4- and 5-qubit fused operations with vector
  * FMAs instead of the matrix cores (for comparison; both are float32). */
 #define SV_FLAG_NO_MFMA 2u
+/* SV_FLAG_GATE_PER_STAGE: planning only (a state accepts plans with or
+ * without it).  Every gate becomes a stage of its own, so the whole state is
+ * decompressed, updated by one gate and recompressed once per gate: the basic
+ * per-gate workflow that Section 3 contrasts with Algorithm 1, kept for the
+ * ablation of compression count against fidelity and time. */
+#define SV_FLAG_GATE_PER_STAGE 4u
+/* SV_FLAG_DIAGONAL_FREE: planning only.  Algorithm 1 counts only the global
+ * indices of non-diagonal gates.  A diagonal gate (Z, S, T, RZ, CZ, CP, RZZ)
+ * multiplies each amplitude by a phase fixed by that amplitude's own index
+ * bits, so it never pairs two SV blocks (the two-block case of Section 3's
+ * update rules does not arise) and runs inside any group: fewer stages, so
+ * fewer compressions.  The planner variant that Section 4.1's goal (as few
+ * compressions as possible) suggests; ignored with SV_FLAG_GATE_PER_STAGE. */
+#define SV_FLAG_DIAGONAL_FREE 8u
 
 /* Per-stage statistics (all counts over the whole state). */
 typedef struct {

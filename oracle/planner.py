@@ -19,18 +19,46 @@ from __future__ import annotations
 from typing import List, Sequence, Tuple
 
 
+# Gates whose matrix is diagonal in the computational basis (Section 2.1):
+# each amplitude is multiplied by a phase fixed by its own index bits.
+DIAGONAL = {"Z", "S", "T", "RZ", "CZ", "CP", "RZZ"}
+
+
 def global_qubits(qubits, b: int):
     return {q for q in qubits if q >= b}
 
 
-def partition(gates: Sequence, b: int, inner_size: int) -> List[Tuple[int, int]]:
-    """Algorithm 1.  Returns stages as half-open gate index ranges."""
+def pairing_globals(gate, b: int, diag_free: bool = False):
+    """Global indices on which a gate pairs amplitudes of different blocks.
+    With diag_free a diagonal gate pairs none: its phase for amplitude i
+    depends on i alone, so the two-block update case of Section 3 never
+    arises for it."""
+    kind, q, _ = gate
+    if diag_free and kind in DIAGONAL:
+        return set()
+    return global_qubits(q, b)
+
+
+def partition(gates: Sequence, b: int, inner_size: int, per_gate: bool = False,
+              diag_free: bool = False) -> List[Tuple[int, int]]:
+    """Algorithm 1.  Returns stages as half-open gate index ranges.
+
+    per_gate: the basic workflow that Section 3 describes before Algorithm 1
+    (the state is decompressed, updated and recompressed once per gate), i.e.
+    one stage per gate, kept for comparison.
+    diag_free: diagonal gates add no global index to a stage (see
+    pairing_globals)."""
     threshold = max(inner_size, 2)
+    if per_gate:
+        for i, (_, q, _) in enumerate(gates):
+            if len(global_qubits(q, b)) > threshold:
+                raise ValueError(f"gate {i} touches more than {threshold} global qubits")
+        return [(i, i + 1) for i in range(len(gates))]
     stages: List[Tuple[int, int]] = []
     start = 0
     cur_globals: set = set()
-    for i, (_, q, _) in enumerate(gates):
-        g = global_qubits(q, b)
+    for i, gate in enumerate(gates):
+        g = pairing_globals(gate, b, diag_free)
         if len(g) > threshold:
             raise ValueError(f"gate {i} touches {len(g)} global qubits > {threshold}")
         if len(cur_globals | g) > threshold:
@@ -44,10 +72,10 @@ def partition(gates: Sequence, b: int, inner_size: int) -> List[Tuple[int, int]]
     return stages
 
 
-def inner_indices(gates: Sequence, stage: Tuple[int, int], b: int) -> List[int]:
+def inner_indices(gates: Sequence, stage: Tuple[int, int], b: int, diag_free: bool = False) -> List[int]:
     s = set()
-    for _, q, _ in gates[stage[0]:stage[1]]:
-        s |= global_qubits(q, b)
+    for gate in gates[stage[0]:stage[1]]:
+        s |= pairing_globals(gate, b, diag_free)
     return sorted(s)
 
 

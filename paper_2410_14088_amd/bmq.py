@@ -17,9 +17,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SO = os.path.join(HERE, "_build", "libbmq.so")
 
-SV_DOMAIN_LIN, SV_DOMAIN_LOG = 0, 1
+SV_DOMAIN_LIN, SV_DOMAIN_LOG, SV_DOMAIN_RAW = 0, 1, 2
 SV_FLAG_NO_SCRATCH = 1
 SV_FLAG_NO_MFMA = 2
+SV_FLAG_GATE_PER_STAGE = 4
+SV_FLAG_DIAGONAL_FREE = 8
 SV_CHUNK_SLOT_BYTES = 576
 KIND = {k: i for i, k in enumerate(
     ["H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "U3", "CX", "CZ", "CP", "RZZ"])}

@@ -820,6 +820,15 @@ template <int DOM>
 __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &cp, int q, QuadPlane &P)
 {
     constexpr bool log_dom = DOM == 1;
+    if (DOM == 2) {                                    // no compression: every chunk raw
+        P.nzb = 0xFFFFu;
+        P.negb = 0;
+        P.anchor = 0;
+        P.w = 0;
+        P.carry = 0;
+        verbatim_quad(x, P);
+        return;
+    }
     uint32_t nzb = 0xFFFFu, negb = 0, bad = 0, anynz = 0;
     if (log_dom) {
         uint32_t efmax = 0;
@@ -1008,7 +1017,7 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         float v;
-        if (DOM == 0) {
+        if (DOM != 1) {
             v = (float)k[j] * cp.delta;
         } else {
             // the magnitude is positive: the sign bit comes from the sign
@@ -1647,12 +1656,14 @@ hipError_t launch_pass(const PassArgs &a, hipStream_t s)
     const uint64_t tiles = 1ull << (a.n - a.t);
     if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
     const dim3 grid((unsigned)tiles);
-    const int key = a.t * 2 + (a.cp.domain == 1 ? 1 : 0);
+    const int key = a.t * 3 + a.cp.domain;
     switch (key) {
 #define BMQ_PASS(T, NT, D) \
-    case T * 2 + D: hipLaunchKernelGGL((pass_kernel<T, NT, D>), grid, dim3(NT), 0, s, a); break;
-    BMQ_PASS(10, 256, 0) BMQ_PASS(10, 256, 1) BMQ_PASS(11, 256, 0) BMQ_PASS(11, 256, 1)
-    BMQ_PASS(12, 256, 0) BMQ_PASS(12, 256, 1) BMQ_PASS(13, 512, 0) BMQ_PASS(13, 512, 1)
+    case T * 3 + D: hipLaunchKernelGGL((pass_kernel<T, NT, D>), grid, dim3(NT), 0, s, a); break;
+    BMQ_PASS(10, 256, 0) BMQ_PASS(10, 256, 1) BMQ_PASS(10, 256, 2)
+    BMQ_PASS(11, 256, 0) BMQ_PASS(11, 256, 1) BMQ_PASS(11, 256, 2)
+    BMQ_PASS(12, 256, 0) BMQ_PASS(12, 256, 1) BMQ_PASS(12, 256, 2)
+    BMQ_PASS(13, 512, 0) BMQ_PASS(13, 512, 1) BMQ_PASS(13, 512, 2)
 #undef BMQ_PASS
     default: return hipErrorInvalidValue;
     }
@@ -1663,11 +1674,13 @@ hipError_t launch_pass_queue(int t, int domain, const PersistArgs &pa, hipStream
 {
     if (pa.total == 0) return hipSuccess;
     const dim3 grid(std::min(pa.total, pa.max_grid));
-    switch (t * 2 + domain) {
+    switch (t * 3 + domain) {
 #define BMQ_PASS(T, NT, D) \
-    case T * 2 + D: hipLaunchKernelGGL((pass_kernel_queue<T, NT, D>), grid, dim3(NT), 0, s, pa); break;
-    BMQ_PASS(10, 256, 0) BMQ_PASS(10, 256, 1) BMQ_PASS(11, 256, 0) BMQ_PASS(11, 256, 1)
-    BMQ_PASS(12, 256, 0) BMQ_PASS(12, 256, 1) BMQ_PASS(13, 512, 0) BMQ_PASS(13, 512, 1)
+    case T * 3 + D: hipLaunchKernelGGL((pass_kernel_queue<T, NT, D>), grid, dim3(NT), 0, s, pa); break;
+    BMQ_PASS(10, 256, 0) BMQ_PASS(10, 256, 1) BMQ_PASS(10, 256, 2)
+    BMQ_PASS(11, 256, 0) BMQ_PASS(11, 256, 1) BMQ_PASS(11, 256, 2)
+    BMQ_PASS(12, 256, 0) BMQ_PASS(12, 256, 1) BMQ_PASS(12, 256, 2)
+    BMQ_PASS(13, 512, 0) BMQ_PASS(13, 512, 1) BMQ_PASS(13, 512, 2)
 #undef BMQ_PASS
     default: return hipErrorInvalidValue;
     }
@@ -1678,14 +1691,16 @@ hipError_t launch_pass_batch(int t, int domain, const PassArgs *args_dev, const 
                              uint32_t blocks, hipStream_t s)
 {
     const dim3 grid(blocks);
-    const int key = t * 2 + (domain == 1 ? 1 : 0);
+    const int key = t * 3 + domain;
     switch (key) {
 #define BMQ_PASS(T, NT, D) \
-    case T * 2 + D: \
+    case T * 3 + D: \
         hipLaunchKernelGGL((pass_kernel_batch<T, NT, D>), grid, dim3(NT), 0, s, args_dev, first_block_dev, n); \
         break;
-    BMQ_PASS(10, 256, 0) BMQ_PASS(10, 256, 1) BMQ_PASS(11, 256, 0) BMQ_PASS(11, 256, 1)
-    BMQ_PASS(12, 256, 0) BMQ_PASS(12, 256, 1) BMQ_PASS(13, 512, 0) BMQ_PASS(13, 512, 1)
+    BMQ_PASS(10, 256, 0) BMQ_PASS(10, 256, 1) BMQ_PASS(10, 256, 2)
+    BMQ_PASS(11, 256, 0) BMQ_PASS(11, 256, 1) BMQ_PASS(11, 256, 2)
+    BMQ_PASS(12, 256, 0) BMQ_PASS(12, 256, 1) BMQ_PASS(12, 256, 2)
+    BMQ_PASS(13, 512, 0) BMQ_PASS(13, 512, 1) BMQ_PASS(13, 512, 2)
 #undef BMQ_PASS
     default: return hipErrorInvalidValue;
     }

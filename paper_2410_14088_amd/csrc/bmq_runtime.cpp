@@ -203,16 +203,16 @@ int validate_cfg(const sv_config_t *c)
         return fail(SV_ERR_INVALID, "block_qubits %d outside [6, n]", c->block_qubits);
     if (c->fuse_qubits < 1 || c->fuse_qubits > 5)
         return fail(SV_ERR_INVALID, "fuse_qubits %d outside [1, 5]", c->fuse_qubits);
-    if (c->domain != SV_DOMAIN_LIN && c->domain != SV_DOMAIN_LOG)
+    if (c->domain != SV_DOMAIN_LIN && c->domain != SV_DOMAIN_LOG && c->domain != SV_DOMAIN_RAW)
         return fail(SV_ERR_INVALID, "domain %d", c->domain);
     const int t = c->tile_qubits ? c->tile_qubits : kDefaultTile;
     if (t < 10 || t > bmq::kMaxTile || t > c->n_qubits)
         return fail(SV_ERR_INVALID, "tile_qubits %d outside [10, min(13, n)]", t);
     if (!(c->eb > 0) || !std::isfinite(c->eb) || !std::isfinite((float)c->eb) || (float)c->eb <= 0)
         return fail(SV_ERR_INVALID, "eb must be a positive finite float32");
-    if (c->flags & ~(SV_FLAG_NO_SCRATCH | SV_FLAG_NO_MFMA)) return fail(SV_ERR_INVALID, "unknown flags 0x%x", c->flags);
+    if (c->flags & ~(SV_FLAG_NO_SCRATCH | SV_FLAG_NO_MFMA | SV_FLAG_GATE_PER_STAGE | SV_FLAG_DIAGONAL_FREE)) return fail(SV_ERR_INVALID, "unknown flags 0x%x", c->flags);
     if (c->reserved) return fail(SV_ERR_INVALID, "reserved must be 0");
-    if (!step_ok(c->domain, step_shift((float)c->eb)))
+    if (c->domain != SV_DOMAIN_RAW && !step_ok(c->domain, step_shift((float)c->eb)))
         return fail(SV_ERR_INVALID, "eb %g outside the codec's range for this domain (LOG: 2^-23 <= eb < 1/2)", c->eb);
     return SV_OK;
 }
@@ -239,7 +239,7 @@ bmq::CodecParams codec_params(const sv_config_t &c)
     cp.domain = c.domain;
     cp.ebf = (float)c.eb;
     cp.s = step_shift(cp.ebf);
-    cp.code_ok = step_ok(c.domain, cp.s) ? 1 : 0;
+    cp.code_ok = c.domain != SV_DOMAIN_RAW && step_ok(c.domain, cp.s) ? 1 : 0;   // RAW: every chunk verbatim
     const int s = cp.code_ok ? cp.s : 0;
     cp.s = s;
     cp.delta = std::ldexp(1.0f, -s);
@@ -248,8 +248,12 @@ bmq::CodecParams codec_params(const sv_config_t &c)
 }
 
 // Algorithm 1: greedy in gate order, close the stage when its global indices
-// would exceed threshold = max(inner, 2).  Never emits an empty stage.
-int partition(const std::vector<GateRec> &gates, int b, int inner, std::vector<StagePlan> &out)
+// would exceed threshold = max(inner, 2).  Never emits an empty stage.  With
+// per_gate every gate closes its own stage (the per-gate workflow of Section
+// 3, for comparison); with diag_free a diagonal gate adds no global index
+// (it pairs no blocks, so it runs inside any group).
+int partition(const std::vector<GateRec> &gates, int b, int inner, bool per_gate, bool diag_free,
+              std::vector<StagePlan> &out)
 {
     const int threshold = std::max(inner, 2);
     size_t start = 0;
@@ -257,13 +261,13 @@ int partition(const std::vector<GateRec> &gates, int b, int inner, std::vector<S
     for (size_t i = 0; i < gates.size(); ++i) {
         std::vector<int> gq;
         for (int j = 0; j < gates[i].nq; ++j)
-            if (gates[i].q[j] >= b) gq.push_back(gates[i].q[j]);
+            if (gates[i].q[j] >= b && !(diag_free && gates[i].diag)) gq.push_back(gates[i].q[j]);
         if ((int)gq.size() > threshold)
             return fail(SV_ERR_INVALID, "gate %zu touches %zu global qubits > threshold %d", i, gq.size(), threshold);
         std::vector<int> uni = cur;
         for (int q : gq)
             if (std::find(uni.begin(), uni.end(), q) == uni.end()) uni.push_back(q);
-        if ((int)uni.size() > threshold) {
+        if ((int)uni.size() > threshold || per_gate) {
             if (i > start) {
                 StagePlan s;
                 s.g0 = start;
@@ -526,7 +530,8 @@ int stage_plan(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, s
         if (r.nq == 2 && r.q[0] == r.q[1]) { delete P; return fail(SV_ERR_INVALID, "gate %zu: repeated qubit", i); }
         P->gates.push_back(r);
     }
-    if (int rc = partition(P->gates, cfg->block_qubits, cfg->inner_size, P->stages)) { delete P; return rc; }
+    if (int rc = partition(P->gates, cfg->block_qubits, cfg->inner_size, (cfg->flags & SV_FLAG_GATE_PER_STAGE) != 0,
+                                 (cfg->flags & SV_FLAG_DIAGONAL_FREE) != 0, P->stages)) { delete P; return rc; }
     for (StagePlan &st : P->stages)
         if (!plan_passes(*P, st)) { delete P; return fail(SV_ERR_INVALID, "internal: dense operation outside its tile"); }
     if ((uint64_t)P->ops.size() * sizeof(OpDesc) + P->data.size() * sizeof(float2) + 256 > kOpsArenaBytes) {
@@ -802,8 +807,8 @@ int plan_batch(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
     groups.clear();
     bytes = 0;
     for (size_t k = 0; k < kmax; ++k)
-        for (int key = 20; key < 2 * (bmq::kMaxTile + 1); ++key) {
-            const int t = key / 2, dom = key % 2;
+        for (int key = 30; key < 3 * (bmq::kMaxTile + 1); ++key) {      // tile sizes 10.. x domains
+            const int t = key / 3, dom = key % 3;
             BatchGroup g{k, t, dom, {}, 0, 0, 0};
             uint64_t blocks = 0;
             for (size_t i = 0; i < count; ++i)
@@ -1207,10 +1212,10 @@ int plan_persistent(sv_t *const *states, const sv_plan_t *const *plans, size_t c
     if (int rc = plan_batch(states, plans, count, groups, unused)) return rc;
     classes.clear();
     bytes = 0;
-    for (int key = 20; key < 2 * (bmq::kMaxTile + 1); ++key) {
+    for (int key = 30; key < 3 * (bmq::kMaxTile + 1); ++key) {          // tile sizes 10.. x domains
         PersistClass c;
-        c.t = key / 2;
-        c.dom = key % 2;
+        c.t = key / 3;
+        c.dom = key % 3;
         size_t kmax = 0;
         for (size_t i = 0; i < count; ++i)
             if (plans[i]->t == c.t && states[i]->cfg.domain == c.dom) {
@@ -1574,7 +1579,7 @@ int sv_debug_dump(sv_t *sv, float *re_dev, float *im_dev)
 int codec_encode_chunks(const float *re_dev, const float *im_dev, uint64_t n_values, const sv_config_t *cfg,
                         void *slots_dev, uint32_t *sizes_dev, void *hip_stream)
 {
-    if (!cfg || !(cfg->eb > 0) || (cfg->domain != SV_DOMAIN_LIN && cfg->domain != SV_DOMAIN_LOG))
+    if (!cfg || !(cfg->eb > 0) || (cfg->domain < SV_DOMAIN_LIN || cfg->domain > SV_DOMAIN_RAW))
         return fail(SV_ERR_INVALID, "bad codec config");
     if (!n_values) return SV_OK;
     if (!re_dev || !im_dev || !slots_dev || !sizes_dev) return fail(SV_ERR_INVALID, "NULL pointer");
@@ -1586,7 +1591,7 @@ int codec_encode_chunks(const float *re_dev, const float *im_dev, uint64_t n_val
 int codec_decode_chunks(const void *slots_dev, uint64_t n_values, const sv_config_t *cfg, float *re_dev, float *im_dev,
                         void *hip_stream)
 {
-    if (!cfg || !(cfg->eb > 0) || (cfg->domain != SV_DOMAIN_LIN && cfg->domain != SV_DOMAIN_LOG))
+    if (!cfg || !(cfg->eb > 0) || (cfg->domain < SV_DOMAIN_LIN || cfg->domain > SV_DOMAIN_RAW))
         return fail(SV_ERR_INVALID, "bad codec config");
     if (!n_values) return SV_OK;
     if (!re_dev || !im_dev || !slots_dev) return fail(SV_ERR_INVALID, "NULL pointer");

@@ -54,14 +54,63 @@ def test_planner_matches_oracle_alg1(bmq, inner):
             assert st["passes"] >= 1
 
 
+@pytest.mark.parametrize("inner", [2, 4])
+def test_gate_per_stage_plan(bmq, inner):
+    # the per-gate workflow: one stage per gate, its inner indices are the
+    # gate's own global qubits, and one gate per fused operation
+    for gates, n, b in [(C.config(0)["gates"], 16, 10), (C.qaoa_ring(16, 2, 5)[0], 16, 12)]:
+        cfg = bmq.Config(n=n, b=b, inner=inner, fuse=4, domain=1, eb=1e-5, flags=bmq.SV_FLAG_GATE_PER_STAGE)
+        plan = bmq.Plan(gates, cfg)
+        want = OP.partition(gates, b, inner, per_gate=True)
+        assert want == [(i, i + 1) for i in range(len(gates))]
+        assert plan.n_stages == len(gates)
+        for s in range(0, len(gates), 7):
+            st = plan.stage(s)
+            assert st["gates"] == want[s]
+            assert st["inner"] == sorted(q for q in gates[s][1] if q >= b)
+        assert len(OP.partition(gates, b, inner)) < len(gates)     # Algorithm 1 groups gates
+
+
+@pytest.mark.parametrize("inner", [0, 2, 3])
+def test_diagonal_free_plan_matches_oracle(bmq, inner):
+    cases = [(C.config(1, n=20)["gates"], 20, 14), (C.qaoa_ring(16, 3, 2)[0], 16, 11),
+             (C.config(0)["gates"], 16, 10), (C.random_layers(18, 5, 9) + C.qft_ladder(18), 18, 12)]
+    for gates, n, b in cases:
+        cfg = bmq.Config(n=n, b=b, inner=inner, fuse=4, domain=1, eb=1e-5, flags=bmq.SV_FLAG_DIAGONAL_FREE)
+        plan = bmq.Plan(gates, cfg)
+        want = OP.partition(gates, b, inner, diag_free=True)
+        assert plan.n_stages == len(want)
+        for s, (g0, g1) in enumerate(want):
+            st = plan.stage(s)
+            assert st["gates"] == (g0, g1)
+            assert st["inner"] == OP.inner_indices(gates, (g0, g1), b, diag_free=True)
+        assert len(want) <= len(OP.partition(gates, b, inner))
+
+
+def test_diagonal_free_partition_pins():
+    # a circuit of diagonal gates only is one stage, whatever qubits it
+    # touches; a non-diagonal gate on a third global qubit still cuts
+    b = 8
+    diag = [("CP", (9, 12), (0.3,)), ("RZZ", (10, 11), (0.2,)), ("CZ", (8, 13), ()), ("T", (14,), ())]
+    assert OP.partition(diag, b, 2, diag_free=True) == [(0, 4)]
+    assert len(OP.partition(diag, b, 2)) == 4
+    mix = [("H", (9,), ()), ("CP", (9, 12), (0.3,)), ("H", (10,), ()), ("RZZ", (11, 13), (0.1,)), ("X", (11,), ())]
+    assert OP.partition(mix, b, 2, diag_free=True) == [(0, 4), (4, 5)]
+    assert OP.inner_indices(mix, (0, 4), b, diag_free=True) == [9, 10]
+    # the QFT's phase ladders are diagonal: 30 qubits on 2^22 blocks go from
+    # dozens of stages to a handful
+    d = C.config(1, n=30)
+    assert len(OP.partition(d["gates"], 22, 2, diag_free=True)) <= 8 < len(OP.partition(d["gates"], 22, 2))
+
+
 def test_config_stage_counts(bmq):
     d = C.config(0)
     assert bmq.Plan(d["gates"], bmq.Config(n=16, b=10)).n_stages == len(OP.partition(d["gates"], 10, 2))
 
 
 @pytest.mark.parametrize("bad", [dict(n=9), dict(n=41), dict(b=5), dict(b=17), dict(fuse=0),
-                                 dict(fuse=6), dict(domain=2), dict(eb=0.0), dict(eb=-1.0),
-                                 dict(tile=9), dict(tile=14), dict(eb=float("nan")), dict(flags=4),
+                                 dict(fuse=6), dict(domain=3), dict(domain=-1), dict(eb=0.0), dict(eb=-1.0),
+                                 dict(tile=9), dict(tile=14), dict(eb=float("nan")), dict(flags=16),
                                  dict(flags=0x80000000)])
 def test_invalid_configs_rejected(bmq, bad):
     kw = dict(n=16, b=10, inner=2, fuse=2, domain=0, eb=1e-6)

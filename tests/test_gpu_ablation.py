@@ -1,0 +1,222 @@
+"""The two comparison modes of the stage loop and the diagonal-free planner
+variant on the GPU.
+
+* One stage per gate (SV_FLAG_GATE_PER_STAGE): the per-gate workflow that
+  Section 3 describes before Algorithm 1.  Its stages are the gates, its
+  streams are bit-exact with the CPU codec like any other stage's, and with
+  about four times as many compressions as Algorithm 1's stages its fidelity
+  is lower (the accumulation of error that Section 3 names).
+* No compression (SV_DOMAIN_RAW): every chunk is stored verbatim, as in the
+  no-compression version of Section 5's compression-overhead analysis.  Its
+  streams hold exactly the values the stage computed (the expected stream is
+  assembled here from the format: two VERBATIM headers and the raw float32
+  values per chunk, decoded again by the oracle's independent decoder), and
+  its final state differs from the FP64 oracle only by float32 rounding.
+* Diagonal-free stages (SV_FLAG_DIAGONAL_FREE): Algorithm 1 counting only
+  the global indices of non-diagonal gates; fewer stages, same results to the
+  oracle and the same bit-exact streams.
+"""
+import struct
+
+import numpy as np
+import pytest
+
+from oracle import native as N
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2410_14088_amd import bmq  # noqa: E402
+from paper_2410_14088_amd import circuits as C  # noqa: E402
+
+DEV = "cuda:0"
+
+
+def raw_stream(re, im, eb):
+    """Block stream of a RAW block: 16-byte block header, then per chunk the
+    two VERBATIM headers (mode 3) and the 64 raw values of each plane."""
+    n = re.size
+    nch = (n + 63) // 64
+    out = [struct.pack("<BBBBIII", 0x51, 1, 2, 6, int(np.float32(eb).view(np.uint32)), n, nch)]
+    for c in range(nch):
+        r = np.zeros(64, np.float32)
+        i = np.zeros(64, np.float32)
+        r[:min(64, n - 64 * c)] = re[64 * c:64 * c + 64]
+        i[:min(64, n - 64 * c)] = im[64 * c:64 * c + 64]
+        out.append(struct.pack("<II", 3, 3) + r.tobytes() + i.tobytes())
+    return b"".join(out)
+
+
+def _run(d, domain, eb, flags):
+    cfg = bmq.Config(n=d["n"], b=d["b"], inner=2, fuse=d["fuse"], domain=domain, eb=eb, flags=flags)
+    plan = bmq.Plan(d["gates"], cfg)
+    sv = bmq.State(cfg, DEV)
+    stats = sv.apply(plan, stats=True)
+    return plan, sv, stats
+
+
+def test_gate_per_stage_more_compressions_lower_fidelity():
+    d = C.config(0)                                      # 16 qubits, LIN eb = 1e-6
+    ref = torch.from_numpy(np.ascontiguousarray(N.simulate(d["n"], d["gates"]))).to(DEV)
+    res = {}
+    for flags in (0, bmq.SV_FLAG_GATE_PER_STAGE):
+        print(f"random-16 LIN 1e-6, flags {flags}", flush=True)
+        plan, sv, stats = _run(d, 0, d["eb"], flags)
+        f2, mx, _ = sv.fidelity(ref)
+        res[flags] = (plan.n_stages, f2, mx)
+        print(f"  stages={plan.n_stages} F2={f2:.12f} max|d|={mx:.3e}", flush=True)
+    (s_alg, f_alg, m_alg), (s_pg, f_pg, m_pg) = res[0], res[bmq.SV_FLAG_GATE_PER_STAGE]
+    assert s_pg == len(d["gates"]) and s_alg < s_pg
+    assert f_pg >= 0.99
+    assert 1 - f_pg > 1 - f_alg                          # more compressions, more error
+    assert m_pg > m_alg
+
+
+@pytest.mark.parametrize("domain,eb", [(0, 1e-6), (2, 1e-5)])
+def test_gate_per_stage_and_raw_streams_bitexact(domain, eb):
+    n, b = 14, 8
+    gates = C.random_layers(n, 1, 78) + C.qft_ladder(n)[:12]
+    cfg = bmq.Config(n=n, b=b, inner=2, fuse=3, domain=domain, eb=eb, flags=bmq.SV_FLAG_GATE_PER_STAGE)
+    plan = bmq.Plan(gates, cfg)
+    assert plan.n_stages == len(gates)
+    sv = bmq.State(cfg, DEV)
+    dre = torch.empty(1 << n, dtype=torch.float32, device=DEV)
+    dim = torch.empty_like(dre)
+    sv.debug_dump(dre, dim)
+    rng = np.random.default_rng(3)
+    for s in range(0, plan.n_stages, 3):
+        print(f"domain {domain} per-gate stages {s}..{s + 2}", flush=True)
+        sv.apply(plan, s, min(3, plan.n_stages - s))
+        pre_re = dre.cpu().numpy()
+        pre_im = dim.cpu().numpy()
+        out = sv.export().cpu().numpy()
+        for blk in rng.choice(1 << (n - b), 4, replace=False):
+            lo, hi = int(blk) << b, (int(blk) + 1) << b
+            gpu = sv.block_stream(int(blk))
+            if domain == 2:
+                want = raw_stream(pre_re[lo:hi], pre_im[lo:hi], eb)
+            else:
+                want = N.encode_block(pre_re[lo:hi], pre_im[lo:hi], domain, eb)
+            assert gpu == want, f"stage {s} block {blk}: streams differ"
+            r2, i2 = N.decode_block(gpu, hi - lo)
+            assert np.array_equal(r2.view(np.uint32), out.real[lo:hi].astype(np.float32).view(np.uint32))
+            assert np.array_equal(i2.view(np.uint32), out.imag[lo:hi].astype(np.float32).view(np.uint32))
+        if domain == 2:                                  # lossless: the stage's own values
+            assert np.array_equal(out.real.astype(np.float32), pre_re)
+            assert np.array_equal(out.imag.astype(np.float32), pre_im)
+
+
+def test_raw_domain_is_float32_exact_and_above_compressed():
+    d = C.config(0)
+    ref = torch.from_numpy(np.ascontiguousarray(N.simulate(d["n"], d["gates"]))).to(DEV)
+    print("random-16 RAW", flush=True)
+    plan, sv, stats = _run(d, 2, 1e-5, 0)
+    f2, mx, n2 = sv.fidelity(ref)
+    print(f"  RAW F2={f2:.14f} max|d|={mx:.3e} norm2={n2:.12f}", flush=True)
+    assert 1 - f2 < 1e-8 and mx < 1e-5 and abs(n2 - 1) < 1e-5
+    # every chunk of every stage's output is stored raw: 64 amplitudes x 8 B
+    # of record body (the two headers live in the chunk's directory entry)
+    chunks = 1 << (d["n"] - 6)
+    for st in stats:
+        assert st["bytes_out"] == chunks * 512
+        assert st["mode_hist"][3] == 2 * chunks and sum(st["mode_hist"][:3]) == 0
+    _, sv_lin, _ = _run(d, 0, d["eb"], 0)
+    f2_lin, _, _ = sv_lin.fidelity(ref)
+    assert f2 > f2_lin
+
+
+def test_raw_domain_batch_and_persistent_launches():
+    # the batched and whole-circuit launches run RAW states too, with records
+    # identical to the per-pass launches
+    mix = [dict(gates=C.random_layers(14, 3, 900 + j), n=14, b=8, fuse=2 + j % 3, domain=2 if j % 2 == 0 else 1,
+                eb=1e-5) for j in range(4)]
+    eager, states, plans = [], [], []
+    for dd in mix:
+        plan, sv, _ = _run(dd, dd["domain"], dd["eb"], 0)
+        eager.append(sv)
+        cfg = bmq.Config(n=dd["n"], b=dd["b"], inner=2, fuse=dd["fuse"], domain=dd["domain"], eb=dd["eb"])
+        plans.append(bmq.Plan(dd["gates"], cfg))
+        states.append(bmq.State(cfg, DEV))
+    print("RAW + LOG mix, persistent launch", flush=True)
+    bmq.persistent_apply(states, plans, wait_limit_us=5_000_000)
+    for k, (a, b_) in enumerate(zip(eager, states)):
+        for blk in range(a.n_blocks):
+            assert a.block_stream(blk) == b_.block_stream(blk), (k, blk)
+    for s in states:
+        s.reset()
+    print("RAW + LOG mix, batched launch", flush=True)
+    bmq.batch_apply(states, plans)
+    for k, (a, b_) in enumerate(zip(eager, states)):
+        for blk in range(a.n_blocks):
+            assert a.block_stream(blk) == b_.block_stream(blk), (k, blk)
+
+
+# ---------------------------------------------------------------- planner variant
+# SV_FLAG_DIAGONAL_FREE: Algorithm 1 counting only the global indices of
+# non-diagonal gates.  Diagonal operations then act on outer global qubits,
+# whose bits are constant over a tile; the results must still match the
+# oracle, and the streams the CPU codec.
+
+def test_diagonal_free_qft_closed_form_fewer_stages():
+    n, b = 20, 14
+    d = C.config(1, n=n)
+    ref = torch.from_numpy(np.ascontiguousarray(N.qft_ry_state(n, d["thetas"]))).to(DEV)
+    res = {}
+    for flags in (0, bmq.SV_FLAG_DIAGONAL_FREE):
+        print(f"QFT-20 LOG 1e-5, flags {flags}", flush=True)
+        cfg = bmq.Config(n=n, b=b, inner=2, fuse=4, domain=1, eb=1e-5, flags=flags)
+        plan = bmq.Plan(d["gates"], cfg)
+        sv = bmq.State(cfg, DEV)
+        sv.apply(plan)
+        f2, mx, _ = sv.fidelity(ref)
+        res[flags] = (plan.n_stages, f2, mx)
+        print(f"  stages={plan.n_stages} F2={f2:.12f} max|d|={mx:.3e}", flush=True)
+    assert res[bmq.SV_FLAG_DIAGONAL_FREE][0] < res[0][0]
+    assert res[bmq.SV_FLAG_DIAGONAL_FREE][1] >= 0.9999 and res[0][1] >= 0.9999
+
+
+def test_diagonal_free_qaoa_and_mirror():
+    n = 18
+    gates, _, _ = C.qaoa_ring(n, 3, 1003)
+    ref = torch.from_numpy(np.ascontiguousarray(N.simulate(n, gates))).to(DEV)
+    cfg = bmq.Config(n=n, b=11, inner=2, fuse=4, domain=1, eb=1e-5, flags=bmq.SV_FLAG_DIAGONAL_FREE)
+    plan = bmq.Plan(gates, cfg)
+    sv = bmq.State(cfg, DEV)
+    print("QAOA-18 diagonal-free", flush=True)
+    sv.apply(plan)
+    f2, mx, _ = sv.fidelity(ref)
+    print(f"  stages={plan.n_stages} F2={f2:.12f} max|d|={mx:.3e}", flush=True)
+    assert f2 >= 0.9999
+    # random layers and their inverse return to |0...0>: exact F^2 from amplitude 0
+    g = C.mirror(C.random_layers(20, 6, 4242))
+    cfg = bmq.Config(n=20, b=13, inner=2, fuse=5, domain=1, eb=1e-5, flags=bmq.SV_FLAG_DIAGONAL_FREE)
+    plan = bmq.Plan(g, cfg)
+    sv = bmq.State(cfg, DEV)
+    print("mirror-20 diagonal-free", flush=True)
+    sv.apply(plan)
+    a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
+    _, _, norm2 = sv.fidelity(None)
+    assert abs(a0) ** 2 / norm2 >= 0.9999
+
+
+def test_diagonal_free_streams_bitexact():
+    n, b = 14, 8
+    gates = C.qaoa_ring(n, 2, 5)[0] + C.random_layers(n, 1, 79) + C.qft_ladder(n)[:30]
+    cfg = bmq.Config(n=n, b=b, inner=2, fuse=3, domain=1, eb=1e-5, flags=bmq.SV_FLAG_DIAGONAL_FREE)
+    plan = bmq.Plan(gates, cfg)
+    sv = bmq.State(cfg, DEV)
+    dre = torch.empty(1 << n, dtype=torch.float32, device=DEV)
+    dim = torch.empty_like(dre)
+    sv.debug_dump(dre, dim)
+    rng = np.random.default_rng(5)
+    for s in range(plan.n_stages):
+        print(f"diagonal-free stage {s} of {plan.n_stages}", flush=True)
+        sv.apply(plan, s, 1)
+        pre_re = dre.cpu().numpy()
+        pre_im = dim.cpu().numpy()
+        for blk in rng.choice(1 << (n - b), 4, replace=False):
+            lo, hi = int(blk) << b, (int(blk) + 1) << b
+            assert sv.block_stream(int(blk)) == N.encode_block(pre_re[lo:hi], pre_im[lo:hi], 1, 1e-5), (s, blk)
+    ref = torch.from_numpy(np.ascontiguousarray(N.simulate(n, gates))).to(DEV)
+    f2, _, _ = sv.fidelity(ref)
+    assert f2 >= 0.9999
