@@ -317,19 +317,19 @@ def bench_qaoa_spill(args):
 
 def main():
     args = parse()
-    if args.workload == "qaoa-spill" and args.gpus == 1:
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding of the "
+              "stage loop is a design note, not implemented", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == "qaoa-spill":
         bench_qaoa_spill(args)
         return
-    if args.workload == "batch" and args.gpus == 1 and not args.copy_calibration:
+    if args.workload == "batch" and not args.copy_calibration:
         bench_batch(args)
         return
     if args.copy_calibration:
         copy_calibration()
         return
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding of the "
-              "stage loop is a design note, not implemented", file=sys.stderr)
-        sys.exit(2)
     import numpy as np
     import torch
 

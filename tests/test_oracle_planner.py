@@ -8,7 +8,10 @@
   outer {2, 4}: 4 groups of 4 blocks);
 * the paper's central claim that groups are independent: simulating every
   group of every stage as a separate small state reproduces the full
-  simulation exactly.
+  simulation exactly;
+* the same for the diagonal-free variant: a diagonal gate on an outer index
+  acts inside each group as a phase fixed by that group's outer bits, and
+  every non-diagonal gate of a stage stays within the group's qubits.
 """
 import numpy as np
 import pytest
@@ -103,3 +106,54 @@ def test_groups_are_independent(inner):
         ref = sim.simulate(n, gates)
         got = simulate_by_groups(n, b, inner, gates)
         assert np.abs(ref - got).max() < 1e-12
+
+
+def simulate_by_groups_diag_free(n, b, inner_size, gates):
+    """Groups of the diagonal-free partition simulated one by one: diagonal
+    gates as phases read off each amplitude's full index (outer bits
+    included), every other gate on the group's relabelled qubits only (a
+    non-diagonal gate on an outer index has no relabelling and fails)."""
+    psi = np.zeros(2 ** n, dtype=complex)
+    psi[0] = 1
+    for s in P.partition(gates, b, inner_size, diag_free=True):
+        inner = P.inner_indices(gates, s, b, diag_free=True)
+        relabel = {q: q for q in range(b)}
+        relabel.update({q: b + i for i, q in enumerate(inner)})
+        for blocks in P.groups(n, b, inner):
+            idx = np.concatenate([np.arange(2 ** b) + (blk << b) for blk in blocks])
+            sub = psi[idx].copy()
+            for k, q, p in gates[s[0]:s[1]]:
+                if k in P.DIAGONAL:
+                    d = np.diag(sim.gate_matrix(k, p))
+                    sel = (idx >> q[0]) & 1 if len(q) == 1 else 2 * ((idx >> q[0]) & 1) + ((idx >> q[1]) & 1)
+                    sub = sub * d[sel]
+                else:
+                    sub = sim.simulate(b + len(inner), [(k, tuple(relabel[x] for x in q), p)], sub)
+            psi[idx] = sub
+    return psi
+
+
+@pytest.mark.parametrize("inner", [2, 3])
+def test_diagonal_free_groups_are_independent(inner):
+    n, b = 8, 4
+    for gates in (C.random_layers(n, 3, 8), C.qft_on_ry(n, 2)[0], C.qaoa_ring(n, 2, 1)[0],
+                  C.qaoa_ring(n, 1, 4)[0] + C.qft_on_ry(n, 3)[0]):
+        assert len(P.partition(gates, b, inner, diag_free=True)) <= len(P.partition(gates, b, inner))
+        ref = sim.simulate(n, gates)
+        got = simulate_by_groups_diag_free(n, b, inner, gates)
+        assert np.abs(ref - got).max() < 1e-12
+
+
+def test_diagonal_free_groups_catch_a_misread_gate():
+    # reading H as diagonal (a plausible slip) lets it onto outer indices and
+    # the group decomposition no longer reproduces the circuit
+    n, b = 8, 4
+    gates = C.qft_on_ry(n, 2)[0]
+    saved = set(P.DIAGONAL)
+    try:
+        P.DIAGONAL.add("H")
+        got = simulate_by_groups_diag_free(n, b, 2, gates)
+        assert np.abs(sim.simulate(n, gates) - got).max() > 1e-2
+    finally:
+        P.DIAGONAL.clear()
+        P.DIAGONAL.update(saved)
