@@ -310,6 +310,22 @@ int sv_amplitudes(const sv_t *sv, const uint64_t *idx_dev, uint64_t k, void *out
  * Any output pointer may be NULL. */
 int sv_footprint(const sv_t *sv, uint64_t *record_bytes, uint64_t *host_bytes, uint64_t *dir_bytes);
 
+/* sv_check -- validate the live state copy's chunk directory on the device
+ * (the stage loop itself trusts it and does not): every entry must be 0 (an
+ * all-zero chunk) or carry two well-formed plane headers for the state's
+ * codec domain (the record format of Section 4.3's codec: mode, width <= 32,
+ * sign class not 3, zero class 0 or 2, no sign or zero class in LIN, no
+ * packed plane in RAW) and the offset of a record that lies inside the pool
+ * it names (device pool, or the attached host pool's half).  *n_bad (may be
+ * NULL) receives the number of bad entries.  Returns SV_OK, or
+ * SV_ERR_CORRUPT with the state poisoned.  Synchronises.
+ * sv_directory -- a read-only diagnostic view of that directory: its device
+ * address (*dir_dev, one u64 per 64-amplitude chunk: body offset in bits
+ * 39:0, real-plane header in 51:40, imaginary-plane header in 63:52) and its
+ * number of entries.  Valid until the next call that runs a stage. */
+int sv_check(sv_t *sv, uint64_t *n_bad);
+int sv_directory(const sv_t *sv, const uint64_t **dir_dev, uint64_t *n_entries);
+
 /* sv_block_stream -- the canonical stream of SV block `block` (2^b
  * amplitudes): a 16-byte block header (u8 0x51, u8 version 1, u8 domain,
  * u8 log2 chunk = 6, u32 eb float bits, u32 n_values, u32 n_chunks) followed

@@ -55,7 +55,7 @@ class sv_stage_stats_t(C.Structure):
 
 EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_destroy",
            "sv_mem_required", "sv_create", "sv_destroy", "sv_attach_host_pool", "sv_reset", "stage_apply_compressed",
-           "sv_fidelity", "sv_export", "sv_amplitudes", "sv_footprint", "sv_block_stream",
+           "sv_fidelity", "sv_export", "sv_amplitudes", "sv_footprint", "sv_check", "sv_directory", "sv_block_stream",
            "sv_debug_dump", "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
            "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
            "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune",
@@ -90,6 +90,8 @@ def lib():
         L.sv_export.argtypes = [V, C.c_uint64, C.c_uint64, V]
         L.sv_amplitudes.argtypes = [V, V, C.c_uint64, V]
         L.sv_footprint.argtypes = [V, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
+        L.sv_check.argtypes = [V, P(C.c_uint64)]
+        L.sv_directory.argtypes = [V, P(C.c_void_p), P(C.c_uint64)]
         L.sv_block_stream.argtypes = [V, C.c_uint64, V, C.c_uint64, P(C.c_uint64)]
         L.sv_debug_dump.argtypes = [V, V, V]
         L.codec_encode_chunks.argtypes = [V, V, C.c_uint64, P(sv_config_t), V, V, V]
@@ -264,6 +266,19 @@ class State:
         r, h, d = C.c_uint64(), C.c_uint64(), C.c_uint64()
         _check(lib().sv_footprint(self.h, C.byref(r), C.byref(h), C.byref(d)))
         return r.value, h.value, d.value
+
+    def check(self) -> int:
+        """Validate the chunk directory on the device; returns the number of
+        bad entries (0), or raises BmqError (SV_ERR_CORRUPT, state poisoned)."""
+        nb = C.c_uint64()
+        _check(lib().sv_check(self.h, C.byref(nb)))
+        return nb.value
+
+    def directory(self):
+        """(device address, entries) of the live copy's chunk directory."""
+        ptr, n = C.c_void_p(), C.c_uint64()
+        _check(lib().sv_directory(self.h, C.byref(ptr), C.byref(n)))
+        return ptr.value, n.value
 
     def attach_host_pool(self, nbytes: int):
         """Second memory level: a pinned host buffer of nbytes (0 detaches)."""

@@ -100,6 +100,8 @@ hipError_t launch_pass(const PassArgs &a, hipStream_t s);
 hipError_t launch_pass_batch(int t, int domain, const PassArgs *args_dev, const uint32_t *first_block_dev, int n,
                              uint32_t blocks, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_check_dir(const uint64_t *dir, uint64_t n, uint64_t pool_cap, uint64_t host_cap, int domain,
+                            unsigned long long *bad, hipStream_t s);
 
 // Whole-circuit launch over a queue of (pass, tile) items, one workgroup per
 // item.  Pass L owns items [first_item[L], first_item[L + 1]) (its tiles in

@@ -1641,6 +1641,39 @@ __global__ void codec_decode_kernel(const uint8_t *slots, uint64_t n, CodecParam
     }
 }
 
+// ------------------------------------------------------------------ directory check
+// A directory entry is 0 (an all-zero chunk) or two well-formed plane
+// headers for the state's codec domain plus the offset of a record that lies
+// inside the pool the offset names (the device pool below cap, else the host
+// pool half).  Counts the entries that are neither.
+__device__ __forceinline__ bool header_ok(uint32_t h, int domain)
+{
+    const uint32_t mode = h & 3u, w = (h >> 2) & 63u, sc = (h >> 8) & 3u, zc = (h >> 10) & 3u;
+    if (mode == M_ZERO || mode == M_VERB) return (h >> 2) == 0u;
+    if (domain == 2) return false;                     // no packed plane without the codec
+    if (w > 32u || sc == 3u || zc == 1u || zc == 3u) return false;
+    return domain == 1 || (sc | zc) == 0u;             // LIN planes carry no sign or zero class
+}
+
+__global__ void check_dir_kernel(const uint64_t *__restrict__ dir, uint64_t n, uint64_t pool_cap, uint64_t host_cap,
+                                 int domain, unsigned long long *bad)
+{
+    unsigned long long nb = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = dir[i];
+        if (e == 0) continue;
+        const uint32_t h0 = (uint32_t)(e >> 40) & 0xFFFu, h1 = (uint32_t)(e >> 52);
+        bool ok = e != kDirInvalid && (h0 | h1) != 0u && header_ok(h0, domain) && header_ok(h1, domain);
+        if (ok) {
+            const uint64_t off = e & kDirOffsetMask, size = layout_of(h0, h1).size;
+            ok = off < pool_cap ? size <= pool_cap - off
+                                : (off - pool_cap <= host_cap && size <= host_cap - (off - pool_cap));
+        }
+        nb += ok ? 0u : 1u;
+    }
+    if (nb) atomicAdd(bad, nb);
+}
+
 // ------------------------------------------------------------------ launchers
 
 static inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap = 65536)
@@ -1704,6 +1737,14 @@ hipError_t launch_pass_batch(int t, int domain, const PassArgs *args_dev, const 
 #undef BMQ_PASS
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_check_dir(const uint64_t *dir, uint64_t n, uint64_t pool_cap, uint64_t host_cap, int domain,
+                            unsigned long long *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(check_dir_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, dir, n, pool_cap, host_cap,
+                       domain, bad);
     return hipGetLastError();
 }
 

@@ -493,7 +493,7 @@ bmq::PoolView pool_view(const sv_t *sv, int which)
 int check_state(const sv_t *sv)
 {
     if (!sv) return fail(SV_ERR_INVALID, "state is NULL");
-    if (sv->poisoned) return fail(SV_ERR_CAPACITY, "state is poisoned by an earlier overflow or aborted launch");
+    if (sv->poisoned) return fail(SV_ERR_CAPACITY, "state is poisoned by an earlier overflow, aborted launch or bad directory");
     return SV_OK;
 }
 
@@ -1431,6 +1431,35 @@ int sv_footprint(const sv_t *sv, uint64_t *record_bytes, uint64_t *host_bytes, u
     if (record_bytes) *record_bytes = sv->live_bytes;
     if (host_bytes) *host_bytes = sv->live_host;
     if (dir_bytes) *dir_bytes = (1ull << (sv->n - 6)) * 8ull;
+    return SV_OK;
+}
+
+int sv_directory(const sv_t *sv, const uint64_t **dir_dev, uint64_t *n_entries)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (int rc = resolve_graph(const_cast<sv_t *>(sv))) return rc;
+    if (dir_dev) *dir_dev = sv->dir[sv->cur];
+    if (n_entries) *n_entries = 1ull << (sv->n - 6);
+    return SV_OK;
+}
+
+int sv_check(sv_t *sv, uint64_t *n_bad)
+{
+    if (n_bad) *n_bad = 0;
+    if (int rc = check_state(sv)) return rc;
+    if (int rc = resolve_graph(sv)) return rc;
+    unsigned long long *bad = (unsigned long long *)sv->out5;
+    HIP_TRY(bmq::launch_fill_u64((uint64_t *)bad, 1, 0, sv->stream));
+    HIP_TRY(bmq::launch_check_dir(sv->dir[sv->cur], 1ull << (sv->n - 6), sv->pool_cap,
+                                  sv->host[sv->cur] ? sv->host_cap : 0, sv->cfg.domain, bad, sv->stream));
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, bad, 8, hipMemcpyDeviceToHost, sv->stream));
+    HIP_TRY(hipStreamSynchronize(sv->stream));
+    if (n_bad) *n_bad = h;
+    if (h) {
+        sv->poisoned = true;
+        return fail(SV_ERR_CORRUPT, "%llu malformed directory entries", h);
+    }
     return SV_OK;
 }
 

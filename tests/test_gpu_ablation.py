@@ -220,3 +220,34 @@ def test_diagonal_free_streams_bitexact():
     ref = torch.from_numpy(np.ascontiguousarray(N.simulate(n, gates))).to(DEV)
     f2, _, _ = sv.fidelity(ref)
     assert f2 >= 0.9999
+
+
+@pytest.mark.parametrize("flags", [bmq.SV_FLAG_GATE_PER_STAGE, bmq.SV_FLAG_DIAGONAL_FREE])
+def test_plan_flags_in_persistent_and_graph_launches(flags):
+    # the planning flags only change the stage table: the whole-circuit queue
+    # launch and a replayed graph leave the records of the per-pass launches
+    d = C.config(0)
+    n, b = d["n"], d["b"]
+    gates = d["gates"][:160]
+    cfg = bmq.Config(n=n, b=b, inner=2, fuse=3, domain=1, eb=1e-5, flags=flags)
+    plan = bmq.Plan(gates, cfg)
+    eager = bmq.State(cfg, DEV)
+    eager.apply(plan)
+    want = [eager.block_stream(k) for k in range(eager.n_blocks)]
+    print(f"flags {flags}: persistent launch of {plan.n_stages} stages", flush=True)
+    sv = bmq.State(cfg, DEV)
+    bmq.persistent_apply([sv], [bmq.Plan(gates, cfg)], wait_limit_us=5_000_000)
+    assert [sv.block_stream(k) for k in range(sv.n_blocks)] == want
+    print(f"flags {flags}: graph replays", flush=True)
+    plan2 = bmq.Plan(gates, cfg)
+    sv2 = bmq.State(cfg, DEV)
+    g = sv2.capture(plan2)
+    for r in range(2):
+        sv2.reset()
+        g.launch()
+        sv2.graph_sync()
+        assert [sv2.block_stream(k) for k in range(sv2.n_blocks)] == want, r
+        eager.reset()                       # eager work between replays
+        eager.apply(plan)
+        torch.cuda.synchronize()
+    g.close()
