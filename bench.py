@@ -58,6 +58,8 @@ def parse():
                     help="qft / random-mirror: 64 MiB device pools, so that the records live in a pinned host "
                          "pool that the kernels read and write over the host link")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="skip the diagonal-free planner variant (profiles of the headline launches only)")
     ap.add_argument("--cpu-n", type=int, default=22, help="qubits of the CPU-baseline sample")
     ap.add_argument("--stats-out", default="")
     ap.add_argument("--persistent", action="store_true",
@@ -468,7 +470,7 @@ def main():
         out["persistent_ms_per_step"] = ev0.elapsed_time(ev1) / args.steps
         out["persistent_footprint_equal"] = sv.footprint()[0] == peak_bytes_final
     if args.workload == "qft" and not args.flags & (bmq.SV_FLAG_GATE_PER_STAGE | bmq.SV_FLAG_DIAGONAL_FREE) \
-            and not args.host_resident:
+            and not args.host_resident and not args.no_variant:
         # the diagonal-free planner variant of Algorithm 1 on the same circuit
         # and state (diagonal gates add no global index to a stage), timed
         # the same way; the headline above stays on Algorithm 1 as written
