@@ -116,6 +116,16 @@ typedef struct {
  * fewer compressions.  The planner variant that Section 4.1's goal (as few
  * compressions as possible) suggests; ignored with SV_FLAG_GATE_PER_STAGE. */
 #define SV_FLAG_DIAGONAL_FREE 8u
+/* SV_FLAG_COMMUTE: planning only.  Algorithm 1 with commutation: a stage
+ * takes, in input order, every remaining gate that fits the threshold and
+ * commutes with each remaining gate it overtakes (disjoint qubits, or both
+ * diagonal: the reordered circuit has the same unitary); the gates it defers
+ * form the next stage's candidates.  Fewer stages, so fewer compressions
+ * (Section 4.1's goal).  The plan's gate order then differs from the input
+ * order: plan_stage ranges index the plan order, plan_gate_order maps it
+ * back.  Combines with SV_FLAG_DIAGONAL_FREE; ignored with
+ * SV_FLAG_GATE_PER_STAGE. */
+#define SV_FLAG_COMMUTE 16u
 
 /* Per-stage statistics (all counts over the whole state). */
 typedef struct {
@@ -160,10 +170,16 @@ int stage_plan(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg,
 /* Plan summary: stages, fused operations and tile passes (any may be NULL). */
 int plan_info(const sv_plan_t *p, size_t *n_stages, size_t *n_ops, size_t *n_passes);
 
-/* Stage s: its gate range [gate_begin, gate_end), its inner indices (up to 8
- * written to inner_out, count in n_inner) and its number of tile passes. */
+/* Stage s: its gate range [gate_begin, gate_end) in the plan's gate order,
+ * its inner indices (up to 8 written to inner_out, count in n_inner) and its
+ * number of tile passes. */
 int plan_stage(const sv_plan_t *p, size_t s, size_t *gate_begin, size_t *gate_end,
                int32_t *inner_out, int32_t *n_inner, int32_t *n_passes);
+
+/* plan_gate_order -- order_out[k] (host, n = the plan's gate count) receives
+ * the input index of the plan's k-th gate: the identity unless the plan was
+ * made with SV_FLAG_COMMUTE. */
+int plan_gate_order(const sv_plan_t *p, uint32_t *order_out, size_t n);
 
 void plan_destroy(sv_plan_t *p);
 

@@ -72,6 +72,42 @@ def partition(gates: Sequence, b: int, inner_size: int, per_gate: bool = False,
     return stages
 
 
+def commute(g, h) -> bool:
+    """Sufficient commutation test: disjoint qubits, or both gates diagonal
+    (diagonal matrices commute)."""
+    (kg, qg, _), (kh, qh, _) = g, h
+    return not set(qg) & set(qh) or (kg in DIAGONAL and kh in DIAGONAL)
+
+
+def partition_commute(gates: Sequence, b: int, inner_size: int, diag_free: bool = False) -> List[List[int]]:
+    """Algorithm 1 with commutation.  Each stage sweeps the remaining gates in
+    input order and takes a gate when the stage's global indices stay within
+    the threshold and the gate commutes with every gate this sweep has
+    deferred so far (the ones it overtakes); the deferred gates are the next
+    sweep.  Returns each stage as the list of input gate indices it applies,
+    in order."""
+    threshold = max(inner_size, 2)
+    for i, gate in enumerate(gates):
+        if len(pairing_globals(gate, b, diag_free)) > threshold:
+            raise ValueError(f"gate {i} touches more than {threshold} global qubits")
+    remaining = list(range(len(gates)))
+    stages: List[List[int]] = []
+    while remaining:
+        stage: List[int] = []
+        cur: set = set()
+        deferred: List[int] = []
+        for i in remaining:
+            g = pairing_globals(gates[i], b, diag_free)
+            if len(cur | g) <= threshold and all(commute(gates[i], gates[j]) for j in deferred):
+                stage.append(i)
+                cur |= g
+            else:
+                deferred.append(i)
+        stages.append(stage)
+        remaining = deferred
+    return stages
+
+
 def inner_indices(gates: Sequence, stage: Tuple[int, int], b: int, diag_free: bool = False) -> List[int]:
     s = set()
     for gate in gates[stage[0]:stage[1]]:

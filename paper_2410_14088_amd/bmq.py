@@ -22,6 +22,7 @@ SV_FLAG_NO_SCRATCH = 1
 SV_FLAG_NO_MFMA = 2
 SV_FLAG_GATE_PER_STAGE = 4
 SV_FLAG_DIAGONAL_FREE = 8
+SV_FLAG_COMMUTE = 16
 SV_CHUNK_SLOT_BYTES = 576
 KIND = {k: i for i, k in enumerate(
     ["H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "U3", "CX", "CZ", "CP", "RZZ"])}
@@ -53,7 +54,7 @@ class sv_stage_stats_t(C.Structure):
                 ("n_gates", C.c_uint32), ("n_inner", C.c_uint32), ("ms", C.c_float), ("pad", C.c_uint32)]
 
 
-EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_destroy",
+EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_order", "plan_destroy",
            "sv_mem_required", "sv_create", "sv_destroy", "sv_attach_host_pool", "sv_reset", "stage_apply_compressed",
            "sv_fidelity", "sv_export", "sv_amplitudes", "sv_footprint", "sv_check", "sv_directory", "sv_block_stream",
            "sv_debug_dump", "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
@@ -75,6 +76,7 @@ def lib():
         L.sv_last_error.restype = C.c_char_p
         L.stage_plan.argtypes = [V, C.c_size_t, P(sv_config_t), P(V)]
         L.plan_info.argtypes = [V, P(C.c_size_t), P(C.c_size_t), P(C.c_size_t)]
+        L.plan_gate_order.argtypes = [V, P(C.c_uint32), C.c_size_t]
         L.plan_stage.argtypes = [V, C.c_size_t, P(C.c_size_t), P(C.c_size_t), P(C.c_int32),
                                  P(C.c_int32), P(C.c_int32)]
         L.plan_destroy.argtypes = [V]
@@ -182,6 +184,17 @@ class Plan:
         ni, npass = C.c_int32(), C.c_int32()
         _check(lib().plan_stage(self.h, s, C.byref(g0), C.byref(g1), inner, C.byref(ni), C.byref(npass)))
         return dict(gates=(g0.value, g1.value), inner=list(inner[:ni.value]), passes=npass.value)
+
+    def gate_order(self):
+        """Input index of each of the plan's gates (identity unless SV_FLAG_COMMUTE)."""
+        arr = (C.c_uint32 * max(1, self.n_gates))()
+        _check(lib().plan_gate_order(self.h, arr, self.n_gates))
+        return list(arr[:self.n_gates])
+
+    def stage_gates(self, s: int):
+        """Input indices of stage s's gates, in the order they are applied."""
+        g0, g1 = self.stage(s)["gates"]
+        return self.gate_order()[g0:g1]
 
     @property
     def n_stages(self) -> int:

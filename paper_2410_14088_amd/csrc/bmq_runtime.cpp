@@ -141,7 +141,8 @@ struct StagePlan {
 struct sv_plan {
     sv_config_t cfg{};
     int t = kDefaultTile;
-    std::vector<GateRec> gates;
+    std::vector<GateRec> gates;          // in plan order (input order unless SV_FLAG_COMMUTE)
+    std::vector<uint32_t> order;         // plan position -> input gate index
     std::vector<StagePlan> stages;
     std::vector<OpDesc> ops;
     std::vector<float2> data;
@@ -210,7 +211,8 @@ int validate_cfg(const sv_config_t *c)
         return fail(SV_ERR_INVALID, "tile_qubits %d outside [10, min(13, n)]", t);
     if (!(c->eb > 0) || !std::isfinite(c->eb) || !std::isfinite((float)c->eb) || (float)c->eb <= 0)
         return fail(SV_ERR_INVALID, "eb must be a positive finite float32");
-    if (c->flags & ~(SV_FLAG_NO_SCRATCH | SV_FLAG_NO_MFMA | SV_FLAG_GATE_PER_STAGE | SV_FLAG_DIAGONAL_FREE)) return fail(SV_ERR_INVALID, "unknown flags 0x%x", c->flags);
+    if (c->flags & ~(SV_FLAG_NO_SCRATCH | SV_FLAG_NO_MFMA | SV_FLAG_GATE_PER_STAGE | SV_FLAG_DIAGONAL_FREE |
+                     SV_FLAG_COMMUTE)) return fail(SV_ERR_INVALID, "unknown flags 0x%x", c->flags);
     if (c->reserved) return fail(SV_ERR_INVALID, "reserved must be 0");
     if (c->domain != SV_DOMAIN_RAW && !step_ok(c->domain, step_shift((float)c->eb)))
         return fail(SV_ERR_INVALID, "eb %g outside the codec's range for this domain (LOG: 2^-23 <= eb < 1/2)", c->eb);
@@ -289,6 +291,73 @@ int partition(const std::vector<GateRec> &gates, int b, int inner, bool per_gate
         std::sort(s.inner.begin(), s.inner.end());
         out.push_back(s);
     }
+    return SV_OK;
+}
+
+// Algorithm 1 with commutation: each stage takes, in input order, every
+// remaining gate that fits the threshold and commutes with every remaining
+// gate it would overtake (the ones deferred before it in this sweep); the
+// deferred gates form the next sweep.  Two gates commute here when their
+// qubits are disjoint or both are diagonal, so the reordered circuit has the
+// same unitary.  Commutation is tracked per qubit: a diagonal gate is blocked
+// by a deferred non-diagonal gate on one of its qubits, any other gate by any
+// deferred gate on one of its qubits.  gates is permuted into plan order,
+// order receives plan position -> input index.
+int partition_commute(std::vector<GateRec> &gates, int b, int inner, bool diag_free, std::vector<StagePlan> &out,
+                      std::vector<uint32_t> &order)
+{
+    const int threshold = std::max(inner, 2);
+    auto globals_of = [&](const GateRec &g) {
+        std::vector<int> gq;
+        for (int j = 0; j < g.nq; ++j)
+            if (g.q[j] >= b && !(diag_free && g.diag)) gq.push_back(g.q[j]);
+        return gq;
+    };
+    for (size_t i = 0; i < gates.size(); ++i)
+        if ((int)globals_of(gates[i]).size() > threshold)
+            return fail(SV_ERR_INVALID, "gate %zu touches more than threshold %d global qubits", i, threshold);
+    std::vector<uint32_t> remaining(gates.size());
+    for (size_t i = 0; i < gates.size(); ++i) remaining[i] = (uint32_t)i;
+    std::vector<GateRec> planned;
+    order.clear();
+    std::vector<uint8_t> blocked_any(64), blocked_nondiag(64);
+    while (!remaining.empty()) {
+        std::fill(blocked_any.begin(), blocked_any.end(), 0);
+        std::fill(blocked_nondiag.begin(), blocked_nondiag.end(), 0);
+        std::vector<uint32_t> deferred;
+        std::vector<int> cur;
+        StagePlan s;
+        s.g0 = planned.size();
+        for (uint32_t i : remaining) {
+            const GateRec &g = gates[i];
+            bool ok = true;
+            for (int j = 0; j < g.nq && ok; ++j)
+                ok = g.diag ? !blocked_nondiag[g.q[j]] : !blocked_any[g.q[j]];
+            std::vector<int> uni = cur;
+            if (ok) {
+                for (int q : globals_of(g))
+                    if (std::find(uni.begin(), uni.end(), q) == uni.end()) uni.push_back(q);
+                ok = (int)uni.size() <= threshold;
+            }
+            if (ok) {
+                planned.push_back(g);
+                order.push_back(i);
+                cur = uni;
+            } else {
+                deferred.push_back(i);
+                for (int j = 0; j < g.nq; ++j) {
+                    blocked_any[g.q[j]] = 1;
+                    if (!g.diag) blocked_nondiag[g.q[j]] = 1;
+                }
+            }
+        }
+        s.g1 = planned.size();
+        s.inner = cur;
+        std::sort(s.inner.begin(), s.inner.end());
+        out.push_back(s);
+        remaining.swap(deferred);
+    }
+    gates.swap(planned);
     return SV_OK;
 }
 
@@ -530,8 +599,17 @@ int stage_plan(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, s
         if (r.nq == 2 && r.q[0] == r.q[1]) { delete P; return fail(SV_ERR_INVALID, "gate %zu: repeated qubit", i); }
         P->gates.push_back(r);
     }
-    if (int rc = partition(P->gates, cfg->block_qubits, cfg->inner_size, (cfg->flags & SV_FLAG_GATE_PER_STAGE) != 0,
-                                 (cfg->flags & SV_FLAG_DIAGONAL_FREE) != 0, P->stages)) { delete P; return rc; }
+    const bool per_gate = (cfg->flags & SV_FLAG_GATE_PER_STAGE) != 0;
+    const bool diag_free = (cfg->flags & SV_FLAG_DIAGONAL_FREE) != 0;
+    int prc;
+    if ((cfg->flags & SV_FLAG_COMMUTE) && !per_gate) {
+        prc = partition_commute(P->gates, cfg->block_qubits, cfg->inner_size, diag_free, P->stages, P->order);
+    } else {
+        prc = partition(P->gates, cfg->block_qubits, cfg->inner_size, per_gate, diag_free, P->stages);
+        P->order.resize(P->gates.size());
+        for (size_t i = 0; i < P->order.size(); ++i) P->order[i] = (uint32_t)i;
+    }
+    if (prc) { delete P; return prc; }
     for (StagePlan &st : P->stages)
         if (!plan_passes(*P, st)) { delete P; return fail(SV_ERR_INVALID, "internal: dense operation outside its tile"); }
     if ((uint64_t)P->ops.size() * sizeof(OpDesc) + P->data.size() * sizeof(float2) + 256 > kOpsArenaBytes) {
@@ -553,6 +631,15 @@ int plan_info(const sv_plan_t *p, size_t *n_stages, size_t *n_ops, size_t *n_pas
         for (const auto &s : p->stages) np += s.passes.size();
         *n_passes = np;
     }
+    return SV_OK;
+}
+
+int plan_gate_order(const sv_plan_t *p, uint32_t *order_out, size_t n)
+{
+    if (!p) return fail(SV_ERR_INVALID, "plan is NULL");
+    if (n != p->order.size()) return fail(SV_ERR_INVALID, "order array of %zu entries for %zu gates", n, p->order.size());
+    if (n && !order_out) return fail(SV_ERR_INVALID, "order_out is NULL");
+    std::copy(p->order.begin(), p->order.end(), order_out);
     return SV_OK;
 }
 

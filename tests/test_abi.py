@@ -87,6 +87,28 @@ def test_diagonal_free_plan_matches_oracle(bmq, inner):
         assert len(want) <= len(OP.partition(gates, b, inner))
 
 
+@pytest.mark.parametrize("flags", [16, 24])
+@pytest.mark.parametrize("inner", [0, 2, 3])
+def test_commute_plan_matches_oracle(bmq, inner, flags):
+    cases = [(C.config(0)["gates"], 16, 10), (C.qaoa_ring(16, 3, 2)[0], 16, 11),
+             (C.mirror(C.random_layers(18, 5, 9)), 18, 12), (C.config(1, n=20)["gates"], 20, 14)]
+    for gates, n, b in cases:
+        cfg = bmq.Config(n=n, b=b, inner=inner, fuse=4, domain=1, eb=1e-5, flags=flags)
+        plan = bmq.Plan(gates, cfg)
+        want = OP.partition_commute(gates, b, inner, diag_free=bool(flags & bmq.SV_FLAG_DIAGONAL_FREE))
+        assert plan.n_stages == len(want)
+        order = plan.gate_order()
+        assert sorted(order) == list(range(len(gates)))
+        for s, st_want in enumerate(want):
+            g0, g1 = plan.stage(s)["gates"]
+            assert order[g0:g1] == st_want
+            assert plan.stage(s)["inner"] == sorted(set().union(
+                *[OP.pairing_globals(gates[i], b, bool(flags & 8)) for i in st_want]))
+    # without the flag the plan order is the input order
+    plan = bmq.Plan(C.config(0)["gates"], bmq.Config(n=16, b=10))
+    assert plan.gate_order() == list(range(len(C.config(0)["gates"])))
+
+
 def test_diagonal_free_partition_pins():
     # a circuit of diagonal gates only is one stage, whatever qubits it
     # touches; a non-diagonal gate on a third global qubit still cuts
@@ -110,7 +132,7 @@ def test_config_stage_counts(bmq):
 
 @pytest.mark.parametrize("bad", [dict(n=9), dict(n=41), dict(b=5), dict(b=17), dict(fuse=0),
                                  dict(fuse=6), dict(domain=3), dict(domain=-1), dict(eb=0.0), dict(eb=-1.0),
-                                 dict(tile=9), dict(tile=14), dict(eb=float("nan")), dict(flags=16),
+                                 dict(tile=9), dict(tile=14), dict(eb=float("nan")), dict(flags=32),
                                  dict(flags=0x80000000)])
 def test_invalid_configs_rejected(bmq, bad):
     kw = dict(n=16, b=10, inner=2, fuse=2, domain=0, eb=1e-6)

@@ -157,3 +157,80 @@ def test_diagonal_free_groups_catch_a_misread_gate():
     finally:
         P.DIAGONAL.clear()
         P.DIAGONAL.update(saved)
+
+
+# ---------------------------------------------------------------- commutation
+def _flat(stages):
+    return [i for st in stages for i in st]
+
+
+def _commute_cases():
+    n = 8
+    yield n, C.random_layers(n, 4, 21)
+    yield n, C.qft_on_ry(n, 6)[0]
+    yield n, C.qaoa_ring(n, 2, 8)[0]
+    yield n, C.mirror(C.random_layers(n, 3, 22))
+    yield n, C.ghz(n) + C.qft_ladder(n)
+
+
+@pytest.mark.parametrize("diag_free", [False, True])
+@pytest.mark.parametrize("inner", [2, 3])
+def test_commute_partition_reorders_validly(inner, diag_free):
+    b = 4
+    for n, gates in _commute_cases():
+        stages = P.partition_commute(gates, b, inner, diag_free)
+        order = _flat(stages)
+        assert sorted(order) == list(range(len(gates))) and all(stages)
+        for st in stages:
+            glob = set()
+            for i in st:
+                glob |= P.pairing_globals(gates[i], b, diag_free)
+            assert len(glob) <= max(inner, 2)
+        assert len(stages) <= len(P.partition(gates, b, inner, diag_free=diag_free))
+        # the reordered circuit is the same unitary: same final state
+        ref = sim.simulate(n, gates)
+        assert np.abs(sim.simulate(n, [gates[i] for i in order]) - ref).max() < 1e-12
+        # and its stages are independent groups (diagonal gates on outer
+        # indices as phases when diag_free)
+        re = [gates[i] for i in order]
+        psi = np.zeros(2 ** n, dtype=complex)
+        psi[0] = 1
+        start = 0
+        for st in stages:
+            seg = re[start:start + len(st)]
+            start += len(st)
+            inner_q = sorted(set().union(*[P.pairing_globals(g, b, diag_free) for g in seg]))
+            relabel = {q: q for q in range(b)}
+            relabel.update({q: b + k for k, q in enumerate(inner_q)})
+            for blocks in P.groups(n, b, inner_q):
+                idx = np.concatenate([np.arange(2 ** b) + (blk << b) for blk in blocks])
+                sub = psi[idx].copy()
+                for k, q, p in seg:
+                    if diag_free and k in P.DIAGONAL:
+                        d = np.diag(sim.gate_matrix(k, p))
+                        sel = (idx >> q[0]) & 1 if len(q) == 1 else 2 * ((idx >> q[0]) & 1) + ((idx >> q[1]) & 1)
+                        sub = sub * d[sel]
+                    else:
+                        sub = sim.simulate(b + len(inner_q), [(k, tuple(relabel[x] for x in q), p)], sub)
+                psi[idx] = sub
+        assert np.abs(psi - ref).max() < 1e-12
+
+
+def test_commute_partition_packs_random_layers():
+    # a layer's single-qubit gates and disjoint CZs commute: far fewer stages
+    gates = C.random_layers(12, 8, 5)
+    assert len(P.partition_commute(gates, 6, 2)) * 2 < len(P.partition(gates, 6, 2))
+
+
+def test_commute_test_catches_a_wrong_rule():
+    # a commutation rule that lets gates sharing a qubit pass each other (a
+    # plausible slip) changes the circuit: the reordered state differs
+    n, b = 8, 4
+    gates = C.random_layers(n, 4, 21)
+    saved = P.commute
+    try:
+        P.commute = lambda g, h: True
+        order = _flat(P.partition_commute(gates, b, 2))
+        assert np.abs(sim.simulate(n, [gates[i] for i in order]) - sim.simulate(n, gates)).max() > 1e-3
+    finally:
+        P.commute = saved
