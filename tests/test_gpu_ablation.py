@@ -230,7 +230,8 @@ def test_diagonal_free_streams_bitexact():
                                    bmq.SV_FLAG_COMMUTE | bmq.SV_FLAG_DIAGONAL_FREE])
 def test_plan_flags_in_persistent_and_graph_launches(flags):
     # the planning flags only change the stage table: the whole-circuit queue
-    # launch and a replayed graph leave the records of the per-pass launches
+    # launch, the batched launch and a replayed graph leave the records of the
+    # per-pass launches
     d = C.config(0)
     n, b = d["n"], d["b"]
     gates = d["gates"][:160]
@@ -243,6 +244,10 @@ def test_plan_flags_in_persistent_and_graph_launches(flags):
     sv = bmq.State(cfg, DEV)
     bmq.persistent_apply([sv], [bmq.Plan(gates, cfg)], wait_limit_us=5_000_000)
     assert [sv.block_stream(k) for k in range(sv.n_blocks)] == want
+    print(f"flags {flags}: batched launch", flush=True)
+    sv3 = bmq.State(cfg, DEV)
+    bmq.batch_apply([sv3], [bmq.Plan(gates, cfg)])
+    assert [sv3.block_stream(k) for k in range(sv3.n_blocks)] == want
     print(f"flags {flags}: graph replays", flush=True)
     plan2 = bmq.Plan(gates, cfg)
     sv2 = bmq.State(cfg, DEV)
