@@ -409,45 +409,94 @@ bool plan_passes(sv_plan &P, StagePlan &st)
         for (int q : tq) pp.tileq.push_back(q);
         auto in_tile = [&](int q) { return std::find(pp.tileq.begin(), pp.tileq.end(), q) != pp.tileq.end(); };
 
-        // greedy order-preserving fusion
+        // fusion with deferred diagonals.  Diagonal gates commute with each
+        // other and with any gate on other qubits, so a diagonal gate that does
+        // not fit the dense operation being built waits in a pending set that
+        // is applied after that operation.  A later non-diagonal gate takes the
+        // pending gates that share a qubit with it (they must act before it)
+        // into its own dense operation when they fit there, else they go out
+        // first as one diagonal operation; the other pending gates keep
+        // waiting.  Every gate thus moves only past gates it commutes with,
+        // and the ladders of several controlled phases share one diagonal
+        // operation instead of one each.
         const int K = P.cfg.fuse_qubits;
         std::vector<FusedOp> fused;
-        FusedOp curop{-1, {}, {}};
-        auto flush = [&]() {
-            if (curop.type >= 0) fused.push_back(curop);
-            curop = FusedOp{-1, {}, {}};
+        FusedOp cur{-1, {}, {}};                       // dense operation being built
+        std::vector<size_t> pend;                      // deferred diagonal gates, in order
+        auto add_qubits = [&](std::vector<int> &qs, size_t g) {
+            const GateRec &r = P.gates[g];
+            for (int j = 0; j < r.nq; ++j)
+                if (std::find(qs.begin(), qs.end(), r.q[j]) == qs.end()) qs.push_back(r.q[j]);
+        };
+        auto qubits_of = [&](const std::vector<size_t> &gs) {
+            std::vector<int> qs;
+            for (size_t g : gs) add_qubits(qs, g);
+            std::sort(qs.begin(), qs.end());
+            return qs;
+        };
+        auto emit_cur = [&]() {
+            if (cur.type >= 0) fused.push_back(cur);
+            cur = FusedOp{-1, {}, {}};
+        };
+        auto emit_diag = [&](const std::vector<size_t> &gs) {
+            if (!gs.empty()) fused.push_back(FusedOp{bmq::OP_DIAG, qubits_of(gs), gs});
         };
         for (size_t g : pass_gates[pi]) {
             const GateRec &gr = P.gates[g];
-            std::vector<int> uni = curop.qubits;
-            bool subset = true;
-            for (int j = 0; j < gr.nq; ++j)
-                if (std::find(uni.begin(), uni.end(), gr.q[j]) == uni.end()) { uni.push_back(gr.q[j]); subset = false; }
-            std::sort(uni.begin(), uni.end());
             if (gr.diag) {
-                if (curop.type == bmq::OP_DENSE && subset) { curop.gates.push_back(g); continue; }
-                if (curop.type == bmq::OP_DIAG && (int)uni.size() <= kMaxDiagQubits) {
-                    curop.qubits = uni; curop.gates.push_back(g); continue;
-                }
-                flush();
-                curop.type = bmq::OP_DIAG;
-            } else {
-                bool all_in = true;
-                for (int q : curop.qubits) all_in = all_in && in_tile(q);
-                if (curop.type == bmq::OP_DENSE && (int)uni.size() <= K) {
-                    curop.qubits = uni; curop.gates.push_back(g); continue;
-                }
-                if (curop.type == bmq::OP_DIAG && all_in && (int)uni.size() <= K) {
-                    curop.type = bmq::OP_DENSE; curop.qubits = uni; curop.gates.push_back(g); continue;
-                }
-                flush();
-                curop.type = bmq::OP_DENSE;
+                bool subset = cur.type >= 0;
+                for (int j = 0; j < gr.nq && subset; ++j)
+                    subset = std::find(cur.qubits.begin(), cur.qubits.end(), gr.q[j]) != cur.qubits.end();
+                if (subset) { cur.gates.push_back(g); continue; }
+                std::vector<size_t> trial = pend;
+                trial.push_back(g);
+                if ((int)qubits_of(trial).size() <= kMaxDiagQubits) { pend.swap(trial); continue; }
+                emit_cur();
+                emit_diag(pend);
+                pend.assign(1, g);
+                continue;
             }
-            for (int j = 0; j < gr.nq; ++j) curop.qubits.push_back(gr.q[j]);
-            std::sort(curop.qubits.begin(), curop.qubits.end());
-            curop.gates.push_back(g);
+            std::vector<size_t> before, rest;
+            for (size_t d : pend) {
+                const GateRec &dr = P.gates[d];
+                bool shares = false;
+                for (int a = 0; a < dr.nq; ++a)
+                    for (int c = 0; c < gr.nq; ++c) shares = shares || dr.q[a] == gr.q[c];
+                (shares ? before : rest).push_back(d);
+            }
+            const std::vector<int> bq = qubits_of(before);
+            bool before_in_tile = true;
+            for (int q : bq) before_in_tile = before_in_tile && in_tile(q);
+            std::vector<int> need = bq;
+            add_qubits(need, g);
+            if (cur.type >= 0) {
+                std::vector<int> grown = need;
+                for (int q : cur.qubits)
+                    if (std::find(grown.begin(), grown.end(), q) == grown.end()) grown.push_back(q);
+                if (before_in_tile && (int)grown.size() <= K) {
+                    std::sort(grown.begin(), grown.end());
+                    cur.qubits = grown;
+                    cur.gates.insert(cur.gates.end(), before.begin(), before.end());
+                    cur.gates.push_back(g);
+                    pend.swap(rest);
+                    continue;
+                }
+            }
+            emit_cur();
+            std::sort(need.begin(), need.end());
+            if (before_in_tile && (int)need.size() <= K) {
+                cur = FusedOp{bmq::OP_DENSE, need, before};
+                cur.gates.push_back(g);
+            } else {
+                emit_diag(before);
+                cur = FusedOp{bmq::OP_DENSE, {}, {g}};
+                add_qubits(cur.qubits, g);
+                std::sort(cur.qubits.begin(), cur.qubits.end());
+            }
+            pend.swap(rest);
         }
-        flush();
+        emit_cur();
+        emit_diag(pend);
 
         pp.op_begin = (int)P.ops.size();
         for (const FusedOp &f : fused) {
