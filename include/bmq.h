@@ -181,6 +181,19 @@ int plan_stage(const sv_plan_t *p, size_t s, size_t *gate_begin, size_t *gate_en
  * made with SV_FLAG_COMMUTE. */
 int plan_gate_order(const sv_plan_t *p, uint32_t *order_out, size_t n);
 
+/* plan_stage_ops -- the fused operations of stage s are plan operations
+ * [op_begin, op_end), applied in that order (pass after pass).
+ * plan_op -- read-only view of plan operation i, for checking the fusion on
+ * the host: type (0 dense, 1 diagonal), k qubits written to qubits[0..k)
+ * (operation qubit j is bit j of the matrix or table index), and, when
+ * data_host is not NULL, its complex64 values (interleaved float32 pairs):
+ * dense, the 2^k x 2^k matrix row major; diagonal, the 2^k phases.
+ * cap_elems is data_host's capacity in complex64 values (SV_ERR_INVALID when
+ * too small). */
+int plan_stage_ops(const sv_plan_t *p, size_t s, size_t *op_begin, size_t *op_end);
+int plan_op(const sv_plan_t *p, size_t i, int32_t *type, int32_t *k, int32_t *qubits, void *data_host,
+            size_t cap_elems);
+
 void plan_destroy(sv_plan_t *p);
 
 /* ---------------------------------------------------------------- state

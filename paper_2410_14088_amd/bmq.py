@@ -54,7 +54,7 @@ class sv_stage_stats_t(C.Structure):
                 ("n_gates", C.c_uint32), ("n_inner", C.c_uint32), ("ms", C.c_float), ("pad", C.c_uint32)]
 
 
-EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_order", "plan_destroy",
+EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_order", "plan_stage_ops", "plan_op", "plan_destroy",
            "sv_mem_required", "sv_create", "sv_destroy", "sv_attach_host_pool", "sv_reset", "stage_apply_compressed",
            "sv_fidelity", "sv_export", "sv_amplitudes", "sv_footprint", "sv_check", "sv_directory", "sv_block_stream",
            "sv_debug_dump", "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
@@ -77,6 +77,8 @@ def lib():
         L.stage_plan.argtypes = [V, C.c_size_t, P(sv_config_t), P(V)]
         L.plan_info.argtypes = [V, P(C.c_size_t), P(C.c_size_t), P(C.c_size_t)]
         L.plan_gate_order.argtypes = [V, P(C.c_uint32), C.c_size_t]
+        L.plan_stage_ops.argtypes = [V, C.c_size_t, P(C.c_size_t), P(C.c_size_t)]
+        L.plan_op.argtypes = [V, C.c_size_t, P(C.c_int32), P(C.c_int32), P(C.c_int32), V, C.c_size_t]
         L.plan_stage.argtypes = [V, C.c_size_t, P(C.c_size_t), P(C.c_size_t), P(C.c_int32),
                                  P(C.c_int32), P(C.c_int32)]
         L.plan_destroy.argtypes = [V]
@@ -190,6 +192,24 @@ class Plan:
         arr = (C.c_uint32 * max(1, self.n_gates))()
         _check(lib().plan_gate_order(self.h, arr, self.n_gates))
         return list(arr[:self.n_gates])
+
+    def stage_ops(self, s: int):
+        """Fused operations of stage s in application order: (type, qubits,
+        values) with values a complex64 matrix (dense) or phase vector."""
+        import numpy as np
+        b, e = C.c_size_t(), C.c_size_t()
+        _check(lib().plan_stage_ops(self.h, s, C.byref(b), C.byref(e)))
+        out = []
+        for i in range(b.value, e.value):
+            t, k = C.c_int32(), C.c_int32()
+            qs = (C.c_int32 * 16)()
+            _check(lib().plan_op(self.h, i, C.byref(t), C.byref(k), qs, None, 0))
+            n = (1 << k.value) ** (2 if t.value == 0 else 1)
+            buf = np.zeros(n, dtype=np.complex64)
+            _check(lib().plan_op(self.h, i, None, None, None, C.c_void_p(buf.ctypes.data), n))
+            vals = buf.reshape(1 << k.value, 1 << k.value) if t.value == 0 else buf
+            out.append(("dense" if t.value == 0 else "diag", list(qs[:k.value]), vals))
+        return out
 
     def stage_gates(self, s: int):
         """Input indices of stage s's gates, in the order they are applied."""

@@ -683,6 +683,34 @@ int plan_info(const sv_plan_t *p, size_t *n_stages, size_t *n_ops, size_t *n_pas
     return SV_OK;
 }
 
+int plan_stage_ops(const sv_plan_t *p, size_t s, size_t *op_begin, size_t *op_end)
+{
+    if (!p) return fail(SV_ERR_INVALID, "plan is NULL");
+    if (s >= p->stages.size()) return fail(SV_ERR_INVALID, "stage %zu out of range", s);
+    const StagePlan &st = p->stages[s];
+    if (op_begin) *op_begin = st.passes.empty() ? 0 : (size_t)st.passes.front().op_begin;
+    if (op_end) *op_end = st.passes.empty() ? 0 : (size_t)st.passes.back().op_end;
+    return SV_OK;
+}
+
+int plan_op(const sv_plan_t *p, size_t i, int32_t *type, int32_t *k, int32_t *qubits, void *data_host,
+            size_t cap_elems)
+{
+    if (!p) return fail(SV_ERR_INVALID, "plan is NULL");
+    if (i >= p->ops.size()) return fail(SV_ERR_INVALID, "operation %zu out of range", i);
+    const OpDesc &d = p->ops[i];
+    const size_t D = (size_t)1 << d.k, n = d.type == bmq::OP_DENSE ? D * D : D;
+    if (type) *type = d.type;
+    if (k) *k = d.k;
+    if (qubits)
+        for (int j = 0; j < d.k; ++j) qubits[j] = d.gq[j];
+    if (data_host) {
+        if (cap_elems < n) return fail(SV_ERR_INVALID, "operation %zu has %zu complex64 values", i, n);
+        std::memcpy(data_host, p->data.data() + d.data, n * sizeof(float2));
+    }
+    return SV_OK;
+}
+
 int plan_gate_order(const sv_plan_t *p, uint32_t *order_out, size_t n)
 {
     if (!p) return fail(SV_ERR_INVALID, "plan is NULL");
