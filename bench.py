@@ -469,13 +469,17 @@ def main():
         torch.cuda.synchronize()
         out["persistent_ms_per_step"] = ev0.elapsed_time(ev1) / args.steps
         out["persistent_footprint_equal"] = sv.footprint()[0] == peak_bytes_final
-    if args.workload == "qft" and not args.flags & (bmq.SV_FLAG_GATE_PER_STAGE | bmq.SV_FLAG_DIAGONAL_FREE) \
-            and not args.host_resident and not args.no_variant:
-        # the diagonal-free planner variant of Algorithm 1 on the same circuit
-        # and state (diagonal gates add no global index to a stage), timed
-        # the same way; the headline above stays on Algorithm 1 as written
+    # a planner variant of Algorithm 1 on the same circuit and state, timed
+    # the same way; the headline above stays on Algorithm 1 as written.  The
+    # QFT gains from the diagonal-free rule (its phase ladders are diagonal),
+    # random layers from commutation (a layer's gates commute).
+    variant = {"qft": ("diagonal_free", bmq.SV_FLAG_DIAGONAL_FREE),
+               "random-mirror": ("commute", bmq.SV_FLAG_COMMUTE)}.get(args.workload)
+    plan_flags = bmq.SV_FLAG_GATE_PER_STAGE | bmq.SV_FLAG_DIAGONAL_FREE | bmq.SV_FLAG_COMMUTE
+    if variant and not args.flags & plan_flags and not args.host_resident and not args.no_variant:
+        vname, vflag = variant
         vcfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=fuse, domain=d["domain"], eb=d["eb"], tile=args.tile,
-                          flags=args.flags | bmq.SV_FLAG_DIAGONAL_FREE)
+                          flags=args.flags | vflag)
         vplan = bmq.Plan(gates, vcfg)
         vinfo = vplan.info()
         for _ in range(args.warmup):
@@ -489,15 +493,19 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         vms = ev0.elapsed_time(ev1) / args.steps
-        rng = np.random.default_rng(1)
-        idx = rng.integers(0, 1 << n, 4096).astype(np.uint64)
-        want = qft_ry_closed_form(n, d["thetas"], idx)
-        got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy().astype(np.complex128)
-        out["diagonal_free"] = {
-            "value": (2 ** n) * G / (vms * 1e-3), "ms_per_step": vms,
-            "stages": vinfo["stages"], "passes": vinfo["passes"],
-            "fidelity_f2": float(abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real)),
-            "max_abs_err_sampled": float(np.abs(got - want).max())}
+        res = {"value": (2 ** n) * G / (vms * 1e-3), "ms_per_step": vms, "stages": vinfo["stages"],
+               "passes": vinfo["passes"]}
+        if args.workload == "qft":
+            rng = np.random.default_rng(1)
+            idx = rng.integers(0, 1 << n, 4096).astype(np.uint64)
+            want = qft_ry_closed_form(n, d["thetas"], idx)
+            got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy().astype(np.complex128)
+            res["fidelity_f2"] = float(abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real))
+            res["max_abs_err_sampled"] = float(np.abs(got - want).max())
+        else:
+            a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
+            res["fidelity_f2"] = abs(a0) ** 2 / sv.fidelity(None)[2]
+        out[vname] = res
     if args.stats_out:
         with open(args.stats_out, "w") as f:
             json.dump(last, f, indent=1)
