@@ -157,3 +157,29 @@ def test_no_scratch_flag_shrinks_the_arena(bmq):
         bmq._check(bmq.lib().sv_mem_required(C_.byref(bmq.Config(n=24, b=16, flags=flags).c()), C_.byref(v)))
         need.append(v.value)
     assert need[0] - need[1] >= 2 * 4 * (1 << 24)       # two float32 scratch planes
+
+
+def test_plan_views_reject_bad_arguments(bmq):
+    import ctypes as C_
+    L = bmq.lib()
+    gates = C.config(0)["gates"]
+    plan = bmq.Plan(gates, bmq.Config(n=16, b=10, flags=bmq.SV_FLAG_COMMUTE))
+    order = (C_.c_uint32 * len(gates))()
+    assert L.plan_gate_order(plan.h, order, len(gates) - 1) == -1          # wrong length
+    assert L.plan_gate_order(None, order, len(gates)) == -1
+    assert L.plan_gate_order(plan.h, order, len(gates)) == 0
+    assert sorted(order) == list(range(len(gates)))
+    b, e = C_.c_size_t(), C_.c_size_t()
+    assert L.plan_stage_ops(plan.h, plan.n_stages, C_.byref(b), C_.byref(e)) == -1
+    assert L.plan_stage_ops(plan.h, 0, C_.byref(b), C_.byref(e)) == 0 and e.value > b.value
+    n_ops = plan.info()["ops"]
+    t, k = C_.c_int32(), C_.c_int32()
+    assert L.plan_op(plan.h, n_ops, C_.byref(t), C_.byref(k), None, None, 0) == -1
+    assert L.plan_op(plan.h, 0, C_.byref(t), C_.byref(k), None, None, 0) == 0
+    small = (C_.c_float * 2)()
+    assert k.value >= 1 and L.plan_op(plan.h, 0, None, None, None, small, 1) == -1   # capacity below 2^k values
+    # the state-level views refuse a NULL handle without touching a device
+    nb = C_.c_uint64()
+    assert L.sv_check(None, C_.byref(nb)) == -1
+    ptr, n = C_.c_void_p(), C_.c_uint64()
+    assert L.sv_directory(None, C_.byref(ptr), C_.byref(n)) == -1
