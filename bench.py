@@ -1,13 +1,19 @@
 """Benchmark of the compressed stage loop on one MI355X.
 
-Workload (the headline configuration): 30-qubit QFT (H plus the controlled
-phase ladder, no final swaps) applied to a seeded Ry(theta_q) product state,
-complex64 state, 2^22-amplitude SV blocks, LOG-domain codec with eb = 1e-5,
-fused gates of up to 4 qubits, whole compressed state in HBM.
+Workload (the headline configuration, the largest that lives in one GPU's
+HBM): 33-qubit random circuit, depth 16 (per layer U3 with seeded angles on
+every qubit, then CZ on 8 disjoint seeded pairs; 656 gates), complex64
+state (64 GiB uncompressed), 2^24-amplitude SV blocks, LOG-domain codec with
+eb = 1e-5, fused dense operations of up to 5 qubits on the FP32 matrix
+cores, whole compressed state in HBM.  `--workload qft` runs the 30-qubit
+QFT on an Ry product state (2^22-amplitude blocks, 4-qubit fusion).
 
 One step = reset to |0...0> + every stage of the circuit through
 stage_apply_compressed (decode -> apply fused gates -> re-encode per tile).
 The timed region holds exactly K steps, bracketed by device synchronisation.
+Result check (after the timed region): the random circuit's inverse is run
+on the final state, so F^2 = |psi(0)|^2 / |psi|^2 is exact; the QFT is
+checked on sampled amplitudes against its closed form.
 
 Metric: amplitude*gates/s = 2^n * (circuit gates) / step time.
 Roofline: the pass kernel is HBM-bound; its algorithmic bytes per stage are
@@ -36,9 +42,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="qft", choices=["qft", "random-mirror", "batch", "qaoa-spill"],
-                    help="qft: QFT on an Ry product (default, 30 qubits); random-mirror: random U3/CZ layers "
-                         "(33 qubits, depth 16) followed by their inverse; batch: 512 uneven circuits of "
+    ap.add_argument("--workload", default="random",
+                    choices=["random", "qft", "random-mirror", "batch", "qaoa-spill"],
+                    help="random: random U3/CZ layers (default, 33 qubits, depth 16); qft: QFT on an Ry product "
+                         "(30 qubits); random-mirror: the random layers followed by their inverse, timed "
+                         "together; batch: 512 uneven circuits of "
                          "18-26 qubits run together (sv_batch_apply) and one after another; qaoa-spill: "
                          "QAOA ring p=3 (32 qubits) with the device pools capped so records spill to a "
                          "pinned host pool, against the same run on the device only")
@@ -46,7 +54,7 @@ def parse():
                     help="qaoa-spill: device pool capacity per state copy, as a fraction of the "
                          "uncompressed complex64 size")
     ap.add_argument("--batch-count", type=int, default=512)
-    ap.add_argument("--n", type=int, default=0, help="qubits (default: 30 for qft, 33 for random-mirror)")
+    ap.add_argument("--n", type=int, default=0, help="qubits (default: 33 for random, 30 for qft)")
     ap.add_argument("--flags", type=int, default=0,
                     help="sv_config_t flags (1 no scratch, 2 no MFMA, 4 one stage per gate)")
     ap.add_argument("--tile", type=int, default=0)
@@ -60,7 +68,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the diagonal-free planner variant (profiles of the headline launches only)")
-    ap.add_argument("--cpu-n", type=int, default=22, help="qubits of the CPU-baseline sample")
+    ap.add_argument("--cpu-n", type=int, default=0,
+                    help="qubits of the CPU-baseline sample (default 22)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="CPU baseline: stop after the stage that passes this much oracle time")
+    ap.add_argument("--variant-steps", type=int, default=3, help="timed steps of the planner variant")
     ap.add_argument("--stats-out", default="")
     ap.add_argument("--persistent", action="store_true",
                     help="also time the whole-circuit queue launch (sv_persistent_apply) and report it beside")
@@ -101,15 +113,20 @@ def qft_ry_closed_form(n, theta, idx):
     return acc * 2.0 ** (-0.5 * n)
 
 
-def counter_traffic(n: int, tile: int, fuse: int, flags: int = 0, workload: str = "qft"):
-    """HBM bytes per pass-kernel launch from the committed FETCH_SIZE /
-    WRITE_SIZE profile of the default workload, or None when the workload
-    differs or the kernel source changed since the counters were taken."""
+# committed counter profiles of the pass kernel, per default workload:
+# (n, tile, fuse, flags) they were taken at and the file stem
+PROFILES = {"random": ((33, 12, 5, 0), "pass_kernel_random33"),
+            "qft": ((30, 12, 4, 0), "pass_kernel_qft30")}
+
+
+def _profile_field(workload, key, n, tile, fuse, flags, field):
+    """A figure from a committed counter profile, or None when the run
+    differs from the profiled one or the kernel source changed since."""
     import hashlib
     import re
-    if (n, tile or 12, fuse, flags, workload) != (30, 12, 4, 0, "qft"):
+    if workload not in PROFILES or PROFILES[workload][0] != (n, tile or 12, fuse, flags):
         return None
-    prof = os.path.join(ROOT, "profiles", "pass_kernel_qft30_hbm_counters.md")
+    prof = os.path.join(ROOT, "profiles", f"{PROFILES[workload][1]}_{key}.md")
     src = os.path.join(ROOT, "paper_2410_14088_amd", "csrc", "bmq_kernels.hip")
     try:
         text = open(prof).read()
@@ -117,75 +134,96 @@ def counter_traffic(n: int, tile: int, fuse: int, flags: int = 0, workload: str 
     except OSError:
         return None
     m_sha = re.search(r"^kernel_sha256: ([0-9a-f]{64})$", text, re.M)
-    m_val = re.search(r"^traffic_bytes_per_launch: (\d+)$", text, re.M)
+    m_val = re.search(rf"^{field}: ([0-9.e+]+)$", text, re.M)
     if not m_sha or not m_val or m_sha.group(1) != sha:
         return None
-    return int(m_val.group(1))
+    return float(m_val.group(1))
 
 
-def valu_profile(n: int, tile: int, fuse: int, flags: int = 0, workload: str = "qft"):
+def counter_traffic(n, tile, fuse, flags=0, workload="random"):
+    """HBM bytes per pass-kernel launch (FETCH_SIZE + WRITE_SIZE profile)."""
+    v = _profile_field(workload, "hbm_counters", n, tile, fuse, flags, "traffic_bytes_per_launch")
+    return None if v is None else int(v)
+
+
+def valu_profile(n, tile, fuse, flags=0, workload="random"):
     """Issued VALU lane-operations per second of the pass kernel and their
-    fraction of the plain-VALU ceiling, from the committed SQ-counter profile
-    of the default workload (None when the workload differs or the kernel
-    source changed since the counters were taken)."""
-    import hashlib
-    import re
-    if (n, tile or 12, fuse, flags, workload) != (30, 12, 4, 0, "qft"):
+    fraction of the plain-VALU ceiling (SQ-counter profile)."""
+    ops = _profile_field(workload, "sq_counters", n, tile, fuse, flags, "valu_lane_ops_per_s")
+    if ops is None:
         return None
-    prof = os.path.join(ROOT, "profiles", "pass_kernel_qft30_sq_counters.md")
-    src = os.path.join(ROOT, "paper_2410_14088_amd", "csrc", "bmq_kernels.hip")
-    try:
-        text = open(prof).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except OSError:
-        return None
-    m_sha = re.search(r"^kernel_sha256: ([0-9a-f]{64})$", text, re.M)
-    m_ops = re.search(r"^valu_lane_ops_per_s: ([0-9.e+]+)$", text, re.M)
-    if not m_sha or not m_ops or m_sha.group(1) != sha:
-        return None
-    ops = float(m_ops.group(1))
     return {"bound": "alu", "achieved": ops, "peak": VALU_PEAK_LANE_OPS, "unit": "lane-op/s",
             "frac": ops / VALU_PEAK_LANE_OPS, "source": "issued VALU instructions (SQ counters), not algorithmic"}
 
 
-def cpu_baseline(n: int):
-    """The oracle as it stands, on the host: per stage of the same QFT-on-Ry
-    circuit (at n qubits), decode every block with the CPU codec, apply the
-    stage's gates in FP64, re-encode every block.  Returns the measured rate."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(workload: str, n: int, seconds: float):
+    """The oracle as it stands, on the host's cores: per stage of the same
+    circuit generator (at n qubits, with the headline's number of global
+    qubits), decode every SV block with the CPU codec, apply the stage's
+    gates in FP64 (OpenMP), re-encode every block; the blocks' codec calls
+    run on a thread per core.  Stops after the stage that passes `seconds`
+    and reports amplitude*gates/s over the stages it ran."""
+    from concurrent.futures import ThreadPoolExecutor
+
     import numpy as np
     from oracle import native as N
     from oracle import planner as OP
     from paper_2410_14088_amd import circuits as C
 
-    d = C.config(1, n=n)
-    b = n - 8                      # same 8 global qubits as the 30-qubit workload
+    if workload == "qft":
+        d = C.config(1, n=n)
+        b = n - 8                      # 8 global qubits, as at 30 qubits
+    else:
+        d = C.config(2, n=n)
+        b = n - 9                      # 9 global qubits, as at 33 qubits
     gates = d["gates"]
     stages = OP.partition(gates, b, 2)
     nb = 1 << (n - b)
     blk = 1 << b
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    pool = ThreadPoolExecutor(max_workers=threads)
     zero = np.zeros(blk, np.float32)
-    streams = []
-    for k in range(nb):
-        re = zero.copy()
-        if k == 0:
-            re[0] = 1.0
-        streams.append(N.encode_block(re, zero, d["domain"], d["eb"]))
+    one = zero.copy()
+    one[0] = 1.0
+    streams = [N.encode_block(one if k == 0 else zero, zero, d["domain"], d["eb"]) for k in range(nb)]
+    done_gates = 0
+    ran = 0
     t0 = time.perf_counter()
     for s0, s1 in stages:
         psi = np.empty(1 << n, dtype=np.complex128)
-        for k in range(nb):
+
+        def dec(k):
             r, i = N.decode_block(streams[k], blk)
             psi[k * blk:(k + 1) * blk] = r.astype(np.float64) + 1j * i.astype(np.float64)
+        list(pool.map(dec, range(nb)))
         psi = N.apply_circuit(psi, n, gates[s0:s1])
-        streams = [N.encode_block(psi[k * blk:(k + 1) * blk].real.astype(np.float32),
-                                  psi[k * blk:(k + 1) * blk].imag.astype(np.float32), d["domain"], d["eb"])
-                   for k in range(nb)]
+
+        def enc(k):
+            v = psi[k * blk:(k + 1) * blk]
+            return N.encode_block(v.real.astype(np.float32), v.imag.astype(np.float32), d["domain"], d["eb"])
+        streams = list(pool.map(enc, range(nb)))
+        done_gates += s1 - s0
+        ran += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return dict(value=(2 ** n) * len(gates) / dt, unit="amplitude·gates/s", cores=threads, kind="oracle",
-                sample=f"{n}-qubit QFT on the same Ry product ({len(gates)} gates, {len(stages)} stages, "
-                       f"2^{b}-amplitude blocks, LOG eb=1e-5): CPU codec decode/encode per stage "
-                       f"(1 thread) + FP64 OpenMP gate application, {dt:.1f} s")
+    pool.shutdown()
+    name = "QFT on the same Ry product" if workload == "qft" else "random U3/CZ layers of the same generator"
+    return dict(value=(2 ** n) * done_gates / dt, unit="amplitude·gates/s", cores=threads, kind="oracle",
+                cpu=cpu_model(), nproc=os.cpu_count(),
+                sample=f"{n}-qubit {name}: first {ran} of {len(stages)} stages ({done_gates} of {len(gates)} "
+                       f"gates), 2^{b}-amplitude blocks, LOG eb={d['eb']}: CPU codec decode/encode of every "
+                       f"block per stage ({threads} threads) + FP64 OpenMP gate application, {dt:.1f} s")
 
 
 def bench_batch(args):
@@ -332,18 +370,28 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    import math
+
     import numpy as np
     import torch
 
     from paper_2410_14088_amd import bmq
     from paper_2410_14088_amd import circuits as C
 
+    inverse = None
     if args.workload == "qft":
         n = args.n or 30
         d = C.config(1, n=n)
         gates = d["gates"]
         fuse = args.fuse or 4
         wname = f"qft-on-ry-{n}q"
+    elif args.workload == "random":
+        n = args.n or 33
+        d = C.config(2, n=n)
+        gates = d["gates"]
+        inverse = C.mirror(gates)[len(gates):]
+        fuse = args.fuse or 5
+        wname = f"random-u3-cz-{n}q-d16"
     else:
         n = args.n or 33
         d = C.config(2, n=n)
@@ -384,7 +432,8 @@ def main():
     total_ms = ev0.elapsed_time(ev1)
     ms_per_step = total_ms / args.steps
 
-    # algorithmic bytes and kernel time of the pass kernels over the timed steps
+    # algorithmic bytes and kernel time of the pass kernels over the timed
+    # steps (HIP events the library records on its stream around each stage)
     alg_bytes = 0
     kern_ms = 0.0
     launches = 0
@@ -398,10 +447,13 @@ def main():
     peak_bytes = max(s["bytes_out"] for s in last)
     ratio64 = (8 << n) / peak_bytes
     ratio128 = (16 << n) / peak_bytes
+    compressions = sum(s["passes"] for s in last) if args.flags & bmq.SV_FLAG_NO_SCRATCH else len(last)
 
     # result check outside the timed region
     peak_bytes_final = sv.footprint()[0]
-    _, _, norm2 = sv.fidelity(None)
+    fwd = sv.fidelity_full(None)
+    norm2 = fwd["norm2"]
+    eps = 2.0 ** d["eb"] - 1 if d["domain"] == 1 else 0.0
     if args.workload == "qft":
         # sampled closed-form amplitudes
         rng = np.random.default_rng(1)
@@ -410,15 +462,34 @@ def main():
         got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy().astype(np.complex128)
         f_est = float(abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real))
         maxerr = float(np.abs(got - want).max())
+        check = "4096 sampled amplitudes vs closed form"
+        comp_total = compressions
+    elif args.workload == "random":
+        # the inverse circuit brings the exact state back to |0...0>: F^2 of
+        # forward + inverse is |psi(0)|^2 / |psi|^2, exactly
+        iplan = bmq.Plan(inverse, cfg)
+        ist = sv.apply(iplan, stats=True)
+        a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
+        f_est = abs(a0) ** 2 / sv.fidelity(None)[2]
+        maxerr = abs(abs(a0) - 1.0)
+        check = ("exact: after the timed forward steps the inverse circuit is applied and "
+                 "F^2 = |psi(0)|^2 / |psi|^2 of forward + inverse")
+        comp_total = compressions + len(ist)
     else:
         # the mirror circuit returns to |0...0>: F^2 = |psi(0)|^2 / |psi|^2 exactly
         a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
         f_est = abs(a0) ** 2 / norm2
         maxerr = abs(abs(a0) - 1.0)
+        check = "exact: mirror circuit, |psi(0)|^2 / |psi|^2"
+        comp_total = compressions
+    # rigorous lower bound: each compression moves the state by an angle of
+    # at most arcsin(2^eb - 1) (LOG domain), and gates preserve angles
+    bound = math.cos(min(math.pi / 2, comp_total * math.asin(eps))) ** 2 if eps else None
 
-    # the committed profiles were taken on the default codec settings
     prof_key = args.workload if (args.domain == "log" and args.eb in (0.0, 1e-5) and not args.host_resident) \
         else "other"
+    arena = int(sv.arena.numel())
+    scratch = 0 if args.flags & bmq.SV_FLAG_NO_SCRATCH else 8 << n
     out = {
         "metric": METRIC,
         "value": (2 ** n) * G / (ms_per_step * 1e-3),
@@ -437,7 +508,8 @@ def main():
                    "domain": args.domain, "eb": d["eb"], "fuse_qubits": args.fuse,
                    "tile_qubits": args.tile or 12, "flags": args.flags},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": counter_traffic(n, args.tile, args.fuse, args.flags, prof_key)},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": counter_traffic(n, args.tile, args.fuse, args.flags, prof_key)},
         "alu_roofline": valu_profile(n, args.tile, args.fuse, args.flags, prof_key),
         "gbps_algorithmic": achieved,
         "kernel_ms_per_step": kern_ms / args.steps,
@@ -446,10 +518,12 @@ def main():
         "pass_launches_per_step": launches // args.steps,
         "compression_ratio_vs_complex64": ratio64,
         "compression_ratio_vs_complex128": ratio128,
+        "device_arena_bytes": arena,
+        "device_scratch_bytes": scratch,
         "fidelity_f2": f_est,
-        "fidelity_check": "4096 sampled amplitudes vs closed form" if args.workload == "qft"
-                          else "exact: mirror circuit, |psi(0)|^2 / |psi|^2",
-        "max_abs_err_sampled": maxerr,
+        "fidelity_f2_bound": bound,
+        "fidelity_check": check,
+        "max_abs_err": maxerr,
         "norm2": norm2,
     }
     if args.host_resident:
@@ -474,6 +548,7 @@ def main():
     # QFT gains from the diagonal-free rule (its phase ladders are diagonal),
     # random layers from commutation (a layer's gates commute).
     variant = {"qft": ("diagonal_free", bmq.SV_FLAG_DIAGONAL_FREE),
+               "random": ("commute", bmq.SV_FLAG_COMMUTE),
                "random-mirror": ("commute", bmq.SV_FLAG_COMMUTE)}.get(args.workload)
     plan_flags = bmq.SV_FLAG_GATE_PER_STAGE | bmq.SV_FLAG_DIAGONAL_FREE | bmq.SV_FLAG_COMMUTE
     if variant and not args.flags & plan_flags and not args.host_resident and not args.no_variant:
@@ -482,19 +557,19 @@ def main():
                           flags=args.flags | vflag)
         vplan = bmq.Plan(gates, vcfg)
         vinfo = vplan.info()
-        for _ in range(args.warmup):
-            sv.reset()
-            sv.apply(vplan, stats=True)
+        vsteps = max(1, min(args.steps, args.variant_steps))
+        sv.reset()
+        sv.apply(vplan, stats=True)
         torch.cuda.synchronize()
         ev0.record(stream)
-        for _ in range(args.steps):
+        for _ in range(vsteps):
             sv.reset()
             sv.apply(vplan, stats=True)
         ev1.record(stream)
         torch.cuda.synchronize()
-        vms = ev0.elapsed_time(ev1) / args.steps
-        res = {"value": (2 ** n) * G / (vms * 1e-3), "ms_per_step": vms, "stages": vinfo["stages"],
-               "passes": vinfo["passes"]}
+        vms = ev0.elapsed_time(ev1) / vsteps
+        res = {"value": (2 ** n) * G / (vms * 1e-3), "ms_per_step": vms, "steps": vsteps,
+               "stages": vinfo["stages"], "passes": vinfo["passes"]}
         if args.workload == "qft":
             rng = np.random.default_rng(1)
             idx = rng.integers(0, 1 << n, 4096).astype(np.uint64)
@@ -502,6 +577,12 @@ def main():
             got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy().astype(np.complex128)
             res["fidelity_f2"] = float(abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real))
             res["max_abs_err_sampled"] = float(np.abs(got - want).max())
+        elif args.workload == "random":
+            icfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=fuse, domain=d["domain"], eb=d["eb"], tile=args.tile,
+                              flags=args.flags | vflag)
+            sv.apply(bmq.Plan(inverse, icfg))
+            a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
+            res["fidelity_f2"] = abs(a0) ** 2 / sv.fidelity(None)[2]
         else:
             a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
             res["fidelity_f2"] = abs(a0) ** 2 / sv.fidelity(None)[2]
@@ -509,8 +590,12 @@ def main():
     if args.stats_out:
         with open(args.stats_out, "w") as f:
             json.dump(last, f, indent=1)
-    if not args.no_cpu_baseline and args.workload == "qft":
-        out["cpu_baseline"] = cpu_baseline(args.cpu_n)
+    if not args.no_cpu_baseline and args.workload in ("qft", "random"):
+        sv.close()
+        del sv
+        torch.cuda.empty_cache()
+        cn = args.cpu_n or 22
+        out["cpu_baseline"] = cpu_baseline(args.workload, cn, args.cpu_seconds)
     print(json.dumps(out))
 
 

@@ -315,15 +315,41 @@ int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size
                         void *workspace_dev, uint64_t workspace_bytes, uint32_t wait_limit_us,
                         void *hip_stream);
 
-/* sv_fidelity -- FP64 reductions on the device (Section 5.3 fidelity):
- *   fidelity    = |<ref|psi>|^2 / (|ref|^2 |psi|^2)   (the squared form;
- *                 the paper prints the unsquared |<ref|psi>|)
- *   max_abs_err = max over amplitudes and over re/im of |psi - ref|
- *   norm2       = |psi|^2
- * ref_dev: device array of 2^n complex128 (interleaved), or NULL to compute
- * norm2 only (fidelity and max_abs_err then set to NaN).  Synchronises. */
-int sv_fidelity(const sv_t *sv, const double *ref_dev, double *fidelity,
-                double *max_abs_err, double *norm2);
+/* sv_fidelity -- FP64 reductions on the device (Section 5.3 fidelity; the
+ * paper prints the unsquared |<ref|psi>|).  The reference is one of:
+ *   ref_host: host array of 2^n complex128 (interleaved), streamed to the
+ *             device slice by slice through the state's staging area;
+ *   ref_dev:  device array of 2^n complex128;
+ *   ref_sv:   a second compressed state of the same n (any domain), decoded
+ *             beside sv;
+ *   none:     only norm2 is computed (the other fields are NaN).
+ * out receives
+ *   overlap2    = |<ref|psi>|^2 with reference and state as they are: the
+ *                 squared fidelity, which also counts any norm the codec
+ *                 loses or gains;
+ *   fidelity    = |<ref|psi>|^2 / (|ref|^2 |psi|^2), both sides normalised;
+ *   overlap_re, overlap_im = <ref|psi>;
+ *   max_abs_err = max over amplitudes and over re/im of |psi - ref|;
+ *   norm2 = |psi|^2, ref_norm2 = |ref|^2.
+ * Errors: SV_ERR_INVALID (more than one reference, n differs).  Synchronises
+ * (and, for ref_sv on another stream, synchronises that stream first). */
+typedef struct {
+    double overlap2, fidelity, overlap_re, overlap_im, max_abs_err, norm2, ref_norm2;
+} sv_fidelity_t;
+int sv_fidelity(const sv_t *sv, const double *ref_host, const double *ref_dev, const sv_t *ref_sv,
+                sv_fidelity_t *out);
+
+/* sv_sample -- draw k amplitude indices x with probability |psi(x)|^2 /
+ * |psi|^2 (the measurement distribution; feeds the importance-sampled
+ * fidelity estimate <psi|ref> = |psi|^2 E_x[ref(x) / psi(x)] when the
+ * reference is known only amplitude by amplitude).  Two levels on the
+ * device: |psi|^2 per group of 2^max(10, n-16) amplitudes, then, per
+ * sample, a walk through the chosen group in index order with a running
+ * FP64 sum.  The uniforms are u_i = output i (i = 0, 1, ...) of SplitMix64
+ * started at `seed` (Steele, Lea and Flood, OOPSLA 2014), top 53 bits.
+ * idx_host: host array of k indices.  Errors: SV_ERR_INVALID (NULL output,
+ * a state of zero or non-finite norm).  Synchronises. */
+int sv_sample(const sv_t *sv, uint64_t k, uint64_t seed, uint64_t *idx_host);
 
 /* sv_export -- decode amplitudes [start, start+count) into dst_dev
  * (device, count complex64).  start and count must be multiples of 64. */
@@ -365,19 +391,49 @@ int sv_directory(const sv_t *sv, const uint64_t **dir_dev, uint64_t *n_entries);
 int sv_block_stream(const sv_t *sv, uint64_t block, void *dst_host, uint64_t cap,
                     uint64_t *bytes);
 
-/* sv_debug_dump -- test hook: when re_dev/im_dev are non-NULL (device arrays
- * of 2^n float32 each), every later stage also stores the values it is about
- * to encode (after the last fused operation, before quantization) there.
- * NULL, NULL turns it off. */
-int sv_debug_dump(sv_t *sv, float *re_dev, float *im_dev);
+/* sv_debug_dump -- test hook: every later stage also stores, for the
+ * amplitudes [start, start+count) (64-aligned), the values it is about to
+ * encode (after its last fused operation, before quantization) into
+ * pre_re/pre_im, and the values its first pass decoded (before any fused
+ * operation) into post_re/post_im: device float32 arrays of count entries,
+ * element i = amplitude start + i.  Either pair may be NULL; NULL for both
+ * turns the hook off.  Not available in batched, persistent or captured
+ * launches (SV_ERR_UNSUPPORTED there). */
+int sv_debug_dump(sv_t *sv, uint64_t start, uint64_t count, float *pre_re, float *pre_im, float *post_re,
+                  float *post_im);
 
 /* ---------------------------------------------------------------- codec
- * Stand-alone codec on device arrays, for bit-exact checks against a
- * reference implementation.  Values are cut into chunks of 64; chunk i is
- * encoded into slots_dev + i*SV_CHUNK_SLOT_BYTES (device) as one record and
- * its record size is written to sizes_dev[i] (device uint32).  The last chunk
- * may be partial (n_values not a multiple of 64).  Uses cfg->domain and
- * cfg->eb only.  Enqueued on hip_stream; does not synchronise. */
+ * The stage loop's codec (Section 4.3, Algorithm 2; the same device encoder
+ * and decoder the stage loop runs) on caller arrays of whole 64-value
+ * chunks: n_values must be a multiple of 64, at most 2^31.  Uses
+ * cfg->domain and cfg->eb only.
+ *
+ * codec_encode -- the canonical block stream of the planes re_dev, im_dev
+ * (device float32, n_values each): a 16-byte header (u8 0x51, u8 version
+ * 1, u8 domain, u8 log2 chunk = 6, u32 eb float bits, u32 n_values, u32
+ * n_chunks) followed by every chunk's record (two 32-bit plane headers,
+ * then the body) in chunk order -- the stream sv_block_stream returns for an
+ * SV block.  dst_dev: device, 4-byte aligned, cap bytes; *bytes receives the
+ * stream size.  work_dev: device scratch of codec_workspace(n_values) bytes,
+ * 256-byte aligned (record sizes and offsets).  Errors: SV_ERR_INVALID
+ * (arguments; or the stream is larger than cap: *bytes is still set and
+ * nothing is written).  Synchronises.
+ * codec_decode -- the inverse: n_values of each plane from a stream of
+ * `bytes` bytes (device, 4-byte aligned).  A one-lane walk over the record
+ * headers finds the records, then they are decoded in parallel.  Errors:
+ * SV_ERR_CORRUPT (header does not match cfg / n_values, a malformed plane
+ * header, a record outside the stream or bytes left over).  Synchronises
+ * once (the walk's verdict); the decode itself is enqueued. */
+int codec_workspace(uint64_t n_values, uint64_t *bytes);
+int codec_encode(const float *re_dev, const float *im_dev, uint64_t n_values, const sv_config_t *cfg, void *dst_dev,
+                 uint64_t cap, uint64_t *bytes, void *work_dev, uint64_t work_bytes, void *hip_stream);
+int codec_decode(const void *src_dev, uint64_t bytes, const sv_config_t *cfg, uint64_t n_values, float *re_dev,
+                 float *im_dev, void *work_dev, uint64_t work_bytes, void *hip_stream);
+
+/* Slot form, for per-chunk checks: chunk i's record is written to
+ * slots_dev + i*SV_CHUNK_SLOT_BYTES (device) and its size to sizes_dev[i]
+ * (device uint32).  Enqueued on hip_stream; does not synchronise.
+ * Errors: SV_ERR_INVALID (n_values not a multiple of 64, NULL pointers). */
 #define SV_CHUNK_SLOT_BYTES 576
 int codec_encode_chunks(const float *re_dev, const float *im_dev, uint64_t n_values,
                         const sv_config_t *cfg, void *slots_dev, uint32_t *sizes_dev,

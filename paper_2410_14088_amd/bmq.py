@@ -46,6 +46,12 @@ class sv_config_t(C.Structure):
                 ("eb", C.c_double), ("pool_bytes", C.c_uint64), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class sv_fidelity_t(C.Structure):
+    _fields_ = [("overlap2", C.c_double), ("fidelity", C.c_double), ("overlap_re", C.c_double),
+                ("overlap_im", C.c_double), ("max_abs_err", C.c_double), ("norm2", C.c_double),
+                ("ref_norm2", C.c_double)]
+
+
 class sv_stage_stats_t(C.Structure):
     _fields_ = [("bytes_in", C.c_uint64), ("bytes_out", C.c_uint64), ("bytes_out_host", C.c_uint64),
                 ("inter_bytes", C.c_uint64), ("dir_bytes", C.c_uint64),
@@ -56,8 +62,9 @@ class sv_stage_stats_t(C.Structure):
 
 EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_order", "plan_stage_ops", "plan_op", "plan_destroy",
            "sv_mem_required", "sv_create", "sv_destroy", "sv_attach_host_pool", "sv_reset", "stage_apply_compressed",
-           "sv_fidelity", "sv_export", "sv_amplitudes", "sv_footprint", "sv_check", "sv_directory", "sv_block_stream",
-           "sv_debug_dump", "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
+           "sv_fidelity", "sv_sample", "sv_export", "sv_amplitudes", "sv_footprint", "sv_check", "sv_directory",
+           "sv_block_stream", "sv_debug_dump", "codec_workspace", "codec_encode", "codec_decode",
+           "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
            "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
            "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune",
            "sv_batch_workspace", "sv_batch_apply", "sv_persistent_workspace", "sv_persistent_apply"]
@@ -90,14 +97,18 @@ def lib():
         L.sv_reset.argtypes = [V]
         L.sv_attach_host_pool.argtypes = [V, V, C.c_uint64]
         L.stage_apply_compressed.argtypes = [V, V, C.c_size_t, C.c_size_t, V]
-        L.sv_fidelity.argtypes = [V, V, P(C.c_double), P(C.c_double), P(C.c_double)]
+        L.sv_fidelity.argtypes = [V, V, V, V, P(sv_fidelity_t)]
+        L.sv_sample.argtypes = [V, C.c_uint64, C.c_uint64, V]
         L.sv_export.argtypes = [V, C.c_uint64, C.c_uint64, V]
         L.sv_amplitudes.argtypes = [V, V, C.c_uint64, V]
         L.sv_footprint.argtypes = [V, P(C.c_uint64), P(C.c_uint64), P(C.c_uint64)]
         L.sv_check.argtypes = [V, P(C.c_uint64)]
         L.sv_directory.argtypes = [V, P(C.c_void_p), P(C.c_uint64)]
         L.sv_block_stream.argtypes = [V, C.c_uint64, V, C.c_uint64, P(C.c_uint64)]
-        L.sv_debug_dump.argtypes = [V, V, V]
+        L.sv_debug_dump.argtypes = [V, C.c_uint64, C.c_uint64, V, V, V, V]
+        L.codec_workspace.argtypes = [C.c_uint64, P(C.c_uint64)]
+        L.codec_encode.argtypes = [V, V, C.c_uint64, P(sv_config_t), V, C.c_uint64, P(C.c_uint64), V, C.c_uint64, V]
+        L.codec_decode.argtypes = [V, C.c_uint64, P(sv_config_t), C.c_uint64, V, V, V, C.c_uint64, V]
         L.codec_encode_chunks.argtypes = [V, V, C.c_uint64, P(sv_config_t), V, V, V]
         L.codec_decode_chunks.argtypes = [V, C.c_uint64, P(sv_config_t), V, V, V]
         L.sv_block_features.argtypes = [V, V, C.c_size_t, V]
@@ -272,12 +283,36 @@ class State:
     def graph_sync(self):
         _check(lib().sv_graph_sync(self.h))
 
+    def fidelity_full(self, ref=None) -> dict:
+        """sv_fidelity against ref: None (norm only), a torch complex128 device
+        tensor, a host numpy complex128 array (streamed by the library) or
+        another State.  Returns every field of sv_fidelity_t."""
+        out = sv_fidelity_t()
+        host = dev = other = None
+        if isinstance(ref, State):
+            other = ref.h
+        elif isinstance(ref, np.ndarray):
+            if ref.dtype != np.complex128 or ref.size != (1 << self.cfg.n):
+                raise ValueError("host reference must be 2^n complex128")
+            ref = np.ascontiguousarray(ref)
+            host = C.c_void_p(ref.ctypes.data)
+        elif ref is not None:
+            dev = C.c_void_p(_ptr(ref))
+        _check(lib().sv_fidelity(self.h, host, dev, other, C.byref(out)))
+        return {k: getattr(out, k) for k, _ in sv_fidelity_t._fields_}
+
     def fidelity(self, ref=None):
-        """ref: torch complex128 tensor on the device (2^n) or None."""
-        f, m, n2 = C.c_double(), C.c_double(), C.c_double()
-        _check(lib().sv_fidelity(self.h, C.c_void_p(_ptr(ref)) if ref is not None else None,
-                                 C.byref(f), C.byref(m), C.byref(n2)))
-        return f.value, m.value, n2.value
+        """(|<ref|psi>|^2, max |psi - ref|, |psi|^2): the plain squared
+        overlap, with reference and state as they are (see fidelity_full
+        for the normalised value)."""
+        r = self.fidelity_full(ref)
+        return r["overlap2"], r["max_abs_err"], r["norm2"]
+
+    def sample(self, k: int, seed: int) -> np.ndarray:
+        """k indices drawn from |psi(x)|^2 (sv_sample), as a host uint64 array."""
+        out = np.zeros(max(1, k), dtype=np.uint64)
+        _check(lib().sv_sample(self.h, int(k), int(seed) & (2 ** 64 - 1), C.c_void_p(out.ctypes.data)))
+        return out[:k]
 
     def export(self, start: int = 0, count: Optional[int] = None):
         import torch
@@ -333,9 +368,14 @@ class State:
         _check(lib().sv_block_stream(self.h, block, C.cast(buf, C.c_void_p), nb.value, C.byref(nb)))
         return bytes(buf)
 
-    def debug_dump(self, re=None, im=None):
-        _check(lib().sv_debug_dump(self.h, C.c_void_p(_ptr(re)) if re is not None else None,
-                                   C.c_void_p(_ptr(im)) if im is not None else None))
+    def debug_dump(self, re=None, im=None, start: int = 0, count: Optional[int] = None, dec_re=None, dec_im=None):
+        """Test hook: later stages store the values they are about to encode
+        (re, im) and the values their first pass decoded (dec_re, dec_im)
+        for amplitudes [start, start+count); all None turns it off."""
+        if count is None:
+            count = (1 << self.cfg.n) - start
+        p = lambda t: C.c_void_p(_ptr(t)) if t is not None else None
+        _check(lib().sv_debug_dump(self.h, start, count, p(re), p(im), p(dec_re), p(dec_im)))
 
     @property
     def n_blocks(self) -> int:
@@ -435,12 +475,12 @@ class Graph:
 
 
 def codec_encode_chunks(re, im, cfg: Config):
-    """Encode device float32 planes; returns (slots uint8 tensor, sizes int32 tensor)."""
+    """Encode device float32 planes (whole chunks); returns (slots uint8 tensor, sizes int32 tensor)."""
     import torch
     n = re.numel()
     nch = (n + 63) // 64
-    slots = torch.zeros(nch * SV_CHUNK_SLOT_BYTES, dtype=torch.uint8, device=re.device)
-    sizes = torch.zeros(nch, dtype=torch.int32, device=re.device)
+    slots = torch.zeros(max(1, nch) * SV_CHUNK_SLOT_BYTES, dtype=torch.uint8, device=re.device)
+    sizes = torch.zeros(max(1, nch), dtype=torch.int32, device=re.device)
     _check(lib().codec_encode_chunks(C.c_void_p(_ptr(re)), C.c_void_p(_ptr(im)), n, C.byref(cfg.c()),
                                      C.c_void_p(_ptr(slots)), C.c_void_p(_ptr(sizes)), _stream()))
     return slots, sizes
@@ -448,10 +488,47 @@ def codec_encode_chunks(re, im, cfg: Config):
 
 def codec_decode_chunks(slots, n: int, cfg: Config):
     import torch
-    re = torch.empty(n, dtype=torch.float32, device=slots.device)
-    im = torch.empty(n, dtype=torch.float32, device=slots.device)
+    re = torch.empty(max(1, n), dtype=torch.float32, device=slots.device)
+    im = torch.empty(max(1, n), dtype=torch.float32, device=slots.device)
     _check(lib().codec_decode_chunks(C.c_void_p(_ptr(slots)), n, C.byref(cfg.c()),
                                      C.c_void_p(_ptr(re)), C.c_void_p(_ptr(im)), _stream()))
+    return re[:n], im[:n]
+
+
+def _workspace(n: int, device):
+    import torch
+    need = C.c_uint64()
+    _check(lib().codec_workspace(n, C.byref(need)))
+    ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=device)
+    off = (-_ptr(ws)) % 256
+    return ws, C.c_void_p(_ptr(ws) + off), int(need.value)
+
+
+def codec_encode(re, im, cfg: Config, cap: Optional[int] = None):
+    """The canonical block stream of device float32 planes (codec_encode);
+    returns a device uint8 tensor holding exactly the stream."""
+    import torch
+    n = re.numel()
+    if cap is None:
+        cap = 16 + (n // 64) * SV_CHUNK_SLOT_BYTES
+    dst = torch.empty(max(cap, 4), dtype=torch.uint8, device=re.device)
+    ws, wp, wb = _workspace(n, re.device)
+    nb = C.c_uint64()
+    _check(lib().codec_encode(C.c_void_p(_ptr(re)), C.c_void_p(_ptr(im)), n, C.byref(cfg.c()), C.c_void_p(_ptr(dst)),
+                              int(cap), C.byref(nb), wp, wb, _stream()))
+    return dst[:nb.value]
+
+
+def codec_decode(stream, n: int, cfg: Config):
+    """Inverse of codec_encode: (re, im) device float32 planes of n values."""
+    import torch
+    stream = stream.contiguous()
+    re = torch.empty(n, dtype=torch.float32, device=stream.device)
+    im = torch.empty(n, dtype=torch.float32, device=stream.device)
+    ws, wp, wb = _workspace(n, stream.device)
+    _check(lib().codec_decode(C.c_void_p(_ptr(stream)), stream.numel(), C.byref(cfg.c()), n,
+                              C.c_void_p(_ptr(re)), C.c_void_p(_ptr(im)), wp, wb, _stream()))
+    torch.cuda.current_stream().synchronize()
     return re, im
 
 

@@ -89,7 +89,9 @@ struct PassArgs {
     float *scr_re, *scr_im;
     const OpDesc *ops;
     const float2 *opdata;
-    float *dump_re, *dump_im;
+    float *dump_re, *dump_im;       // test hook: values before encoding (or NULL)
+    float *dumpd_re, *dumpd_im;     // test hook: values after decoding (or NULL)
+    uint64_t dump_lo, dump_n;       // amplitudes [dump_lo, dump_lo + dump_n) are dumped
     int32_t mfma;                   // dense 4- and 5-qubit operations on the matrix cores
 };
 
@@ -128,9 +130,26 @@ hipError_t launch_export(const uint64_t *dir, const PoolView &pv, CodecParams cp
 hipError_t launch_amplitudes(const uint64_t *dir, const PoolView &pv, CodecParams cp,
                              const uint64_t *idx, uint64_t k, uint64_t n_chunks, float2 *dst,
                              hipStream_t s);
-hipError_t launch_fidelity(const uint64_t *dir, const PoolView &pv, CodecParams cp,
-                           uint64_t n_chunks, const double2 *ref, double *partials,
-                           int n_partials, double *out5, hipStream_t s);
+// Reference of an FP64 reduction: none, a complex128 device array (element 0
+// = the first amplitude of the reduced range), or a second compressed state.
+enum { REF_NONE = 0, REF_C128 = 1, REF_STATE = 2 };
+struct RefView {
+    int32_t kind;
+    const double2 *c128;
+    const uint64_t *dir;
+    PoolView pv;
+    CodecParams cp;
+};
+// partials: n_partials x 5 doubles, accumulated into (zero them first)
+hipError_t launch_fidelity_partial(const uint64_t *dir, const PoolView &pv, CodecParams cp, uint64_t chunk0,
+                                   uint64_t n_chunks, const RefView &rv, double *partials, int n_partials,
+                                   hipStream_t s);
+hipError_t launch_fidelity_final(const double *partials, int n_partials, double *out5, hipStream_t s);
+// |psi|^2 per group of chunks_per_group chunks (a multiple of 16)
+hipError_t launch_group_norm(const uint64_t *dir, const PoolView &pv, CodecParams cp, uint32_t chunks_per_group,
+                             uint64_t n_groups, double *gnorm, hipStream_t s);
+hipError_t launch_sample(const uint64_t *dir, const PoolView &pv, CodecParams cp, uint32_t chunks_per_group,
+                         const uint32_t *grp, const double *resid, uint64_t k, uint64_t *out, hipStream_t s);
 // the 7 stage features of the block predictor (features 25..31)
 struct StageFeats {
     float v[7];
@@ -140,10 +159,21 @@ struct StageFeats {
 hipError_t launch_block_stats(const uint64_t *dir, uint64_t chunks_per_block, uint64_t n_blocks,
                               const StageFeats &sf, float *feats, float *label_bytes,
                               int32_t *label_mode, hipStream_t s);
-hipError_t launch_codec_encode(const float *re, const float *im, uint64_t n, CodecParams cp,
-                               uint8_t *slots, uint32_t *sizes, hipStream_t s);
-hipError_t launch_codec_decode(const uint8_t *slots, uint64_t n, CodecParams cp,
-                               float *re, float *im, hipStream_t s);
+// stand-alone codec on whole chunks: slot form (record i at slots + i kSlotBytes)
+hipError_t launch_codec_slots_encode(const float *re, const float *im, uint64_t nch, CodecParams cp,
+                                     uint8_t *slots, uint32_t *sizes, hipStream_t s);
+hipError_t launch_codec_slots_decode(const uint8_t *slots, uint64_t nch, CodecParams cp, float *re, float *im,
+                                     hipStream_t s);
+// stream form: sizes (nch u32) and off (nch + 1 u64) are scratch; nothing is
+// written to dst when 16 + total > cap (off[nch] = total record bytes)
+hipError_t launch_codec_stream_encode(const float *re, const float *im, uint64_t nch, CodecParams cp,
+                                      uint32_t *sizes, uint64_t *off, uint8_t *dst, uint64_t cap, uint32_t ebbits,
+                                      hipStream_t s);
+// record offsets of a stream (off: nch u64); *bad set on a malformed stream
+hipError_t launch_codec_stream_decode(const uint8_t *src, uint64_t bytes, uint64_t nch, CodecParams cp,
+                                      uint64_t *off, uint32_t *bad, hipStream_t s);
+hipError_t launch_codec_read(const uint8_t *src, const uint64_t *off, uint64_t nch, CodecParams cp, float *re,
+                             float *im, hipStream_t s);
 
 // ---- block predictor (bmq_mlp.hip) ----
 uint64_t mlp_work_floats(uint32_t batch);

@@ -40,7 +40,7 @@ __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 
 // DPP controls of the GFX9 family
 constexpr int DPP_ROW_SHR1 = 0x111, DPP_ROW_SHR2 = 0x112, DPP_ROW_SHR4 = 0x114, DPP_ROW_SHR8 = 0x118;
-constexpr int DPP_WAVE_SHR1 = 0x138, DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
+constexpr int DPP_ROW_BCAST15 = 0x142, DPP_ROW_BCAST31 = 0x143;
 
 template <int CTRL, int ROWS>
 __device__ __forceinline__ uint32_t dpp(uint32_t v)
@@ -60,29 +60,6 @@ __device__ __forceinline__ uint32_t wave_scan_add(uint32_t v)
     return v;
 }
 
-// OR over the 64 lanes, returned to every lane
-__device__ __forceinline__ uint32_t wave_or(uint32_t v)
-{
-    v |= dpp<DPP_ROW_SHR1, 0xf>(v);
-    v |= dpp<DPP_ROW_SHR2, 0xf>(v);
-    v |= dpp<DPP_ROW_SHR4, 0xf>(v);
-    v |= dpp<DPP_ROW_SHR8, 0xf>(v);
-    v |= dpp<DPP_ROW_BCAST15, 0xa>(v);
-    v |= dpp<DPP_ROW_BCAST31, 0xc>(v);
-    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
-}
-
-// value of lane - 1 (0 in lane 0).  The shifted copy is pinned to its own
-// register: when the compiler folds the DPP move into a following
-// subtraction (v_subrev_u32_dpp) the device returned the negated difference,
-// so only commutative operations (add, or) may absorb a DPP source.
-__device__ __forceinline__ uint32_t wave_prev(uint32_t v)
-{
-    uint32_t p = dpp<DPP_WAVE_SHR1, 0xf>(v);
-    asm volatile("" : "+v"(p));
-    return p;
-}
-
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 
 // A wave-uniform 64-bit value made scalar.  readfirstlane returns a signed
@@ -99,16 +76,6 @@ __device__ __forceinline__ uint64_t lane_u64(uint64_t v, int lane)
     return ((uint64_t)hi << 32) | (uint64_t)lo;
 }
 
-// v with lane `lane` (wave-uniform) replaced by the uniform value x
-__device__ __forceinline__ uint32_t set_lane(uint32_t v, int lane, uint32_t x)
-{
-    const uint32_t xs = rfl(x);
-    const uint32_t ls = rfl((uint32_t)lane);
-    // GFX9 reads one SGPR over the constant bus; the lane select goes in M0
-    asm volatile("v_writelane_b32 %0, %1, m0" : "+v"(v) : "s"(xs), "{m0}"(ls));
-    return v;
-}
-
 __device__ __forceinline__ void wave_sync_lds()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -121,29 +88,6 @@ __device__ __forceinline__ int32_t unzigzag(uint32_t z) { return (int32_t)((z >>
 __device__ __forceinline__ uint32_t bitlen(uint32_t v) { return v ? 32u - (uint32_t)__clz((int)v) : 0u; }
 
 // ------------------------------------------------------------------ codec arithmetic
-
-// log2|x| = e + p for a positive normal float32: significand folded into
-// [sqrt(1/2), sqrt(2)], t = m - 1 exactly, p = t * P(t) with P the degree-8
-// Chebyshev fit of log2(1+t)/t (Horner, fused multiply-add, one final
-// rounding of t * P).
-__device__ __forceinline__ float log2_split(uint32_t u, int &e)
-{
-    const uint32_t mant = u & 0x007FFFFFu;
-    const bool fold = mant > 0x003504F3u;
-    const float m = __uint_as_float(mant | (fold ? 0x3F000000u : 0x3F800000u));
-    e = (int)(u >> 23) - (fold ? 126 : 127);
-    const float t = m - 1.0f;
-    float p = 0.12614846229553223f;
-    p = __builtin_fmaf(p, t, -0.20742103457450867f);
-    p = __builtin_fmaf(p, t, 0.21566985547542572f);
-    p = __builtin_fmaf(p, t, -0.23892034590244293f);
-    p = __builtin_fmaf(p, t, 0.2879183292388916f);
-    p = __builtin_fmaf(p, t, -0.36070483922958374f);
-    p = __builtin_fmaf(p, t, 0.48091059923171997f);
-    p = __builtin_fmaf(p, t, -0.7213473320007324f);
-    p = __builtin_fmaf(p, t, 1.4426950216293335f);
-    return t * p;
-}
 
 // 2^(k 2^-s): nearest integer i = round(k / 2^s) in integers, remainder
 // f = (k - i 2^s) 2^-s in [-1/2, 1/2) exact, 2^f by the degree-6 Chebyshev
@@ -185,279 +129,10 @@ __device__ __forceinline__ bool quantize(float v, const CodecParams &cp, int32_t
     return true;
 }
 
-// wave-uniform description of one encoded plane of a chunk
-struct PlaneInfo {
-    uint32_t hdr;
-    int32_t anchor;
-    uint64_t smask, zmask;
-};
-
-__device__ __forceinline__ uint32_t body_bytes(uint32_t hdr)
-{
-    const uint32_t mode = hdr & 3u, w = (hdr >> 2) & 63u;
-    const uint32_t sc = (hdr >> 8) & 3u, zc = (hdr >> 10) & 3u;
-    if (mode == M_ZERO) return 0;
-    if (mode == M_VERB) return 256;
-    return (mode == M_LZ ? 4u : 0u) + 8u * ((sc == 2u) + (zc == 2u)) + 8u * w;
-}
-
-// Encode one plane of one chunk held one value per lane; lanes >= nvalid are
-// absent.  Returns the lane's field (zigzag code, or raw bits for VERBATIM)
-// and the wave-uniform plane description.
-__device__ uint32_t encode_plane(float x, int nvalid, const CodecParams &cp, PlaneInfo &pi)
-{
-    const int lane = lane_id();
-    const bool valid = lane < nvalid;
-    const uint32_t u = __float_as_uint(x);
-    const bool log_dom = cp.domain == 1;
-    bool isz = false, neg = false, ok = true;
-    int32_t k = 0;
-    pi.anchor = 0;
-    pi.smask = 0;
-    pi.zmask = 0;
-    if (log_dom) {
-        const uint32_t ef = (u >> 23) & 0xFFu;
-        isz = ef == 0u;
-        neg = !isz && (u >> 31);
-        int e;
-        const float p = log2_split(u & 0x7FFFFFFFu, e);
-        // |p| <= 1/2 and 1 <= s <= 22: p 2^s is exact and below 2^21, so the
-        // range test and the verify step of quantize() always pass here and
-        // the code is just the rounded scaled value
-        const int32_t j = (int32_t)__builtin_rintf(p * cp.scale);
-        ok = cp.code_ok && (isz || ef < 254u);
-        k = isz ? 0 : (int32_t)((uint32_t)e << cp.s) + j;
-    } else {
-        ok = cp.code_ok && quantize(x, cp, k);
-    }
-    if (__ballot(valid && !ok)) {
-        pi.hdr = M_VERB;
-        return valid ? u : 0u;
-    }
-    const uint64_t nzm = __ballot(valid && !isz);
-    const bool allzero = log_dom ? (nzm == 0) : (__ballot(valid && k != 0) == 0);
-    if (allzero) {
-        pi.hdr = M_ZERO;
-        return 0u;
-    }
-    // zeros take the code of the last non-zero value at or before them, or of
-    // the first non-zero value; absent lanes repeat the last valid lane
-    int32_t kp = k;
-    if (nzm != ~0ull) {           // some lane is zero or absent
-        int src;
-        if (log_dom) {
-            const uint64_t upto = (lane == 63) ? ~0ull : ((2ull << lane) - 1ull);
-            const uint64_t m = nzm & upto;
-            src = m ? 63 - __clzll((long long)m) : __ffsll((long long)nzm) - 1;
-        } else {
-            src = valid ? lane : nvalid - 1;
-        }
-        kp = __shfl(k, src, 64);
-    }
-    const uint32_t prev = wave_prev((uint32_t)kp);
-    const int32_t d = lane ? (int32_t)((uint32_t)kp - prev) : 0;
-    const uint32_t zl = zigzag(d), zq = zigzag(kp);
-    const uint32_t wl = bitlen(wave_or(zl)), wq = bitlen(wave_or(zq));
-    uint32_t sc = 0, zc = 0;
-    uint64_t smask = 0, zmask = 0;
-    if (log_dom) {
-        smask = __ballot(valid && neg);
-        zmask = __ballot(valid && isz);
-        sc = smask == 0 ? 0u : (smask == nzm ? 1u : 2u);
-        zc = zmask ? 2u : 0u;
-    }
-    const uint32_t masks = 8u * ((sc == 2u) + (zc == 2u));
-    const uint32_t s_lz = 4u + masks + 8u * wl, s_q0 = masks + 8u * wq;
-    uint32_t mode = M_LZ, best = s_lz;
-    if (s_q0 < best) { mode = M_Q0; best = s_q0; }
-    if (256u < best) {
-        pi.hdr = M_VERB;
-        return valid ? u : 0u;
-    }
-    const uint32_t w = (mode == M_LZ) ? wl : wq;
-    pi.hdr = mode | (w << 2) | (sc << 8) | (zc << 10);
-    pi.anchor = __builtin_amdgcn_readlane(kp, 0);
-    pi.smask = (sc == 2u) ? smask : 0ull;
-    pi.zmask = (zc == 2u) ? zmask : 0ull;
-    return (mode == M_LZ) ? zl : zq;
-}
-
-// Register image of one chunk's compressed data, loaded before decoding so
-// that the loads of several chunks are in flight together.
-struct ChunkRegs {
-    uint32_t h0, h1;                 // uniform headers
-    int32_t a0, a1;                  // uniform anchors
-    uint64_t sm0, zm0, sm1, zm1;     // uniform masks
-    uint32_t lo0, hi0, lo1, hi1;     // this lane's payload words
-};
-
-__device__ __forceinline__ void load_plane_words(uint32_t h, const uint32_t *pay, uint32_t &lo, uint32_t &hi)
-{
-    const int lane = lane_id();
-    const uint32_t mode = h & 3u;
-    lo = 0;
-    hi = 0;
-    if (mode == M_VERB) {
-        lo = pay[lane];
-    } else if (mode != M_ZERO) {
-        uint32_t w = (h >> 2) & 63u;
-        w = w > 32u ? 32u : w;            // a malformed header cannot read past the body
-        if (w) {
-            const uint32_t p = (uint32_t)lane * w, a = p >> 5, s = p & 31u;
-            lo = pay[a];
-            if (s + w > 32u) hi = pay[a + 1];
-        }
-    }
-}
-
-// Load a chunk given its two headers and the (uniform) address of its body.
-__device__ __forceinline__ ChunkRegs load_body(uint32_t h0, uint32_t h1, const uint8_t *body)
-{
-    ChunkRegs R;
-    R.h0 = h0;
-    R.h1 = h1;
-    R.a0 = R.a1 = 0;
-    R.sm0 = R.zm0 = R.sm1 = R.zm1 = 0;
-    const uint32_t m0 = h0 & 3u, m1 = h1 & 3u;
-    uint32_t off = 0;
-    const uint32_t *b32 = (const uint32_t *)body;
-    if (m0 == M_LZ) { R.a0 = (int32_t)b32[0]; off += 4; }
-    if (m1 == M_LZ) { R.a1 = (int32_t)b32[off >> 2]; off += 4; }
-    if (m0 == M_LZ || m0 == M_Q0) {
-        if (((h0 >> 8) & 3u) == 2u) { R.sm0 = (uint64_t)b32[off >> 2] | ((uint64_t)b32[(off >> 2) + 1] << 32); off += 8; }
-        if (((h0 >> 10) & 3u) == 2u) { R.zm0 = (uint64_t)b32[off >> 2] | ((uint64_t)b32[(off >> 2) + 1] << 32); off += 8; }
-    }
-    if (m1 == M_LZ || m1 == M_Q0) {
-        if (((h1 >> 8) & 3u) == 2u) { R.sm1 = (uint64_t)b32[off >> 2] | ((uint64_t)b32[(off >> 2) + 1] << 32); off += 8; }
-        if (((h1 >> 10) & 3u) == 2u) { R.zm1 = (uint64_t)b32[off >> 2] | ((uint64_t)b32[(off >> 2) + 1] << 32); off += 8; }
-    }
-    load_plane_words(h0, (const uint32_t *)(body + off), R.lo0, R.hi0);
-    uint32_t w0 = (h0 >> 2) & 63u;
-    w0 = w0 > 32u ? 32u : w0;
-    const uint32_t pay1 = off + (m0 == M_VERB ? 256u : (m0 == M_ZERO ? 0u : 8u * w0));
-    load_plane_words(h1, (const uint32_t *)(body + pay1), R.lo1, R.hi1);
-    return R;
-}
-
-// Decode this lane's value of one plane.  mode, w (<= 32) and anchor are
-// wave-uniform; lo/hi are the two payload words holding the lane's field (for
-// VERBATIM, lo is the raw value); neg/zero are the lane's sign and zero flags.
-template <int DOM>
-__device__ __forceinline__ float decode_value_d(uint32_t mode, uint32_t w, int32_t anchor, uint32_t lo, uint32_t hi,
-                                                bool neg, bool zero, const CodecParams &cp)
-{
-    const int lane = lane_id();
-    if (mode == M_ZERO) return 0.0f;
-    if (mode == M_VERB) return __uint_as_float(lo);
-    uint32_t field = 0;
-    if (w) {
-        const uint32_t s = ((uint32_t)lane * w) & 31u;
-        field = (uint32_t)((((uint64_t)hi << 32) | lo) >> s);
-        if (w < 32u) field &= (1u << w) - 1u;
-    }
-    int32_t k;
-    if (mode == M_LZ) {
-        const int32_t d = lane ? unzigzag(field) : 0;
-        k = (int32_t)((uint32_t)anchor + wave_scan_add((uint32_t)d));
-    } else {
-        k = unzigzag(field);
-    }
-    if (DOM == 0) return (float)k * cp.delta;
-    if (zero) return 0.0f;
-    const float mag = log_decode(k, cp.s, cp.delta);
-    return neg ? -mag : mag;
-}
-
-__device__ __forceinline__ float decode_value(uint32_t mode, uint32_t w, int32_t anchor, uint32_t lo, uint32_t hi,
-                                              bool neg, bool zero, const CodecParams &cp)
-{
-    return cp.domain == 1 ? decode_value_d<1>(mode, w, anchor, lo, hi, neg, zero, cp)
-                          : decode_value_d<0>(mode, w, anchor, lo, hi, neg, zero, cp);
-}
-
-__device__ __forceinline__ float decode_plane(uint32_t h, int32_t anchor, uint64_t smask, uint64_t zmask,
-                                              uint32_t lo, uint32_t hi, const CodecParams &cp)
-{
-    const int lane = lane_id();
-    uint32_t w = (h >> 2) & 63u;
-    w = w > 32u ? 32u : w;
-    const uint32_t sc = (h >> 8) & 3u, zc = (h >> 10) & 3u;
-    const bool isz = (zc == 2u) && ((zmask >> lane) & 1ull);
-    const bool isn = (sc == 2u) ? (((smask >> lane) & 1ull) != 0) : (sc == 1u);
-    return decode_value(h & 3u, w, anchor, lo, hi, isn, isz, cp);
-}
-
-__device__ __forceinline__ void decode_regs(const ChunkRegs &R, const CodecParams &cp, float &re, float &im)
-{
-    re = decode_plane(R.h0, R.a0, R.sm0, R.zm0, R.lo0, R.hi0, cp);
-    im = decode_plane(R.h1, R.a1, R.sm1, R.zm1, R.lo1, R.hi1, cp);
-}
-
 __device__ __forceinline__ const uint8_t *body_ptr(const uint8_t *dev, const uint8_t *host, uint64_t cap,
                                                    uint64_t off)
 {
     return off < cap ? dev + off : host + (off - cap);
-}
-
-__device__ __forceinline__ ChunkRegs load_entry(uint64_t e, const PoolView &pv)
-{
-    if (e == kDirInvalid) e = 0;          // a lost chunk reads as zero
-    const uint32_t h0 = (uint32_t)(e >> 40) & 0xFFFu, h1 = (uint32_t)(e >> 52);
-    return load_body(h0, h1, body_ptr(pv.dev, pv.host, pv.cap, e & kDirOffsetMask));
-}
-
-// Assemble a body (and optionally the two headers in front of it) in the
-// wave's LDS staging area (>= 140 words) and copy it to gdst (4-byte
-// aligned).  f0/f1 are this lane's fields of the two planes.  Returns the
-// bytes written.
-__device__ uint32_t write_body(uint32_t *stage, const PlaneInfo &p0, const PlaneInfo &p1, uint32_t f0,
-                               uint32_t f1, uint32_t *gdst, bool with_headers)
-{
-    const int lane = lane_id();
-    const uint32_t hw = with_headers ? 2u : 0u;
-    const uint32_t words = hw + ((body_bytes(p0.hdr) + body_bytes(p1.hdr)) >> 2);
-    for (uint32_t i = lane; i < words; i += 64) stage[i] = 0u;
-    wave_sync_lds();
-    uint32_t idx = hw;
-    const uint32_t m0 = p0.hdr & 3u, m1 = p1.hdr & 3u;
-    if (lane == 0 && with_headers) { stage[0] = p0.hdr; stage[1] = p1.hdr; }
-    if (m0 == M_LZ) { if (lane == 0) stage[idx] = (uint32_t)p0.anchor; idx++; }
-    if (m1 == M_LZ) { if (lane == 0) stage[idx] = (uint32_t)p1.anchor; idx++; }
-    const PlaneInfo *ps[2] = {&p0, &p1};
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const uint32_t h = ps[c]->hdr, m = h & 3u;
-        if (m == M_LZ || m == M_Q0) {
-            if (((h >> 8) & 3u) == 2u) {
-                if (lane == 0) { stage[idx] = (uint32_t)ps[c]->smask; stage[idx + 1] = (uint32_t)(ps[c]->smask >> 32); }
-                idx += 2;
-            }
-            if (((h >> 10) & 3u) == 2u) {
-                if (lane == 0) { stage[idx] = (uint32_t)ps[c]->zmask; stage[idx + 1] = (uint32_t)(ps[c]->zmask >> 32); }
-                idx += 2;
-            }
-        }
-    }
-    const uint32_t fs[2] = {f0, f1};
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const uint32_t h = ps[c]->hdr, m = h & 3u;
-        if (m == M_VERB) {
-            stage[idx + lane] = fs[c];
-            idx += 64;
-        } else if (m != M_ZERO) {
-            const uint32_t w = (h >> 2) & 63u;
-            if (w) {
-                const uint32_t p = (uint32_t)lane * w, a = p >> 5, s = p & 31u;
-                atomicOr(&stage[idx + a], fs[c] << s);
-                if (s + w > 32u) atomicOr(&stage[idx + a + 1], fs[c] >> (32u - s));
-            }
-            idx += 2u * w;
-        }
-    }
-    wave_sync_lds();
-    for (uint32_t i = lane; i < words; i += 64) gdst[i] = stage[i];
-    return words * 4u;
 }
 
 // bits of v deposited at positions q[0..nq) (bit i of v -> position q[i])
@@ -753,21 +428,6 @@ __device__ __forceinline__ Layout layout_of(uint32_t h0, uint32_t h1)
     return L;
 }
 
-// payload layout word: off_p0 [5:0], off_p1 [15:6], w0 [21:16], w1 [27:22],
-// m0 [29:28], m1 [31:30]
-__device__ __forceinline__ uint32_t pack_pay(const Layout &L)
-{
-    return L.off_p0 | (L.off_p1 << 6) | (L.w0 << 16) | (L.w1 << 22) | (L.m0 << 28) | (L.m1 << 30);
-}
-
-// Pack this lane's w-bit field at bit lane*w of stage[] (LSB-first).
-__device__ __forceinline__ void pack_field(uint32_t *stage, uint32_t f, uint32_t w)
-{
-    const uint32_t p = (uint32_t)lane_id() * w, a = p >> 5, s = p & 31u;
-    atomicOr(&stage[a], f << s);
-    if (s + w > 32u) atomicOr(&stage[a + 1], f >> (32u - s));
-}
-
 // ------------------------------------------------------------------ quad-lane encoder
 //
 // In the pass kernel each chunk is encoded by four consecutive lanes of a
@@ -787,7 +447,11 @@ template <int CTRL>
 __device__ __forceinline__ uint32_t qperm(uint32_t v)
 {
     uint32_t r = dpp<CTRL, 0xf>(v);
-    asm volatile("" : "+v"(r));           // keep the move separate (see wave_prev)
+    // The permuted copy is pinned to its own register: when the compiler
+    // folded a DPP move into a following subtraction (v_subrev_u32_dpp) the
+    // device returned the negated difference, so only commutative
+    // operations may absorb a DPP source.
+    asm volatile("" : "+v"(r));
     return r;
 }
 
@@ -841,7 +505,10 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
             efmax = max(efmax, ef);
             nzb |= min(ef, 1u) << j;                   // zero or subnormal: bit clear
             negb |= (u >> 31) << j;
-            // log2|x| = e + p (as log2_split): adding 0x4AFB0C carries into
+            // log2|x| = e + p, the significand folded into [sqrt(1/2),
+            // sqrt(2)], t = m - 1 exactly and p = t P(t) with P the degree-8
+            // Chebyshev fit of log2(1+t)/t (Horner, fused multiply-adds,
+            // one final rounding of t P).  Adding 0x4AFB0C carries into
             // the exponent exactly when the significand exceeds 0x3504F3, so
             // one integer add folds the significand into [sqrt(1/2), sqrt(2)]
             const uint32_t ix = a + 0x004AFB0Cu;
@@ -1088,6 +755,77 @@ __device__ __forceinline__ void stage_quad_payload(const QuadPlane &P, const Sta
     }
 }
 
+// Stage one chunk's record body (anchors, mixed sign / zero masks, both
+// payloads) at byte offset rel of the staging area, whose words are zero
+// beforehand; the four lanes of the chunk's quad call it together.
+__device__ __forceinline__ void stage_record(const QuadPlane &P0, const QuadPlane &P1, const Layout &Lv,
+                                             const Staging &S, uint32_t rel, int q)
+{
+    if (q == 0) {
+        if (Lv.lz0) *S.word(rel >> 2) = (uint32_t)P0.anchor;
+        if (Lv.lz1) *S.word((rel >> 2) + (Lv.lz0 ? 1 : 0)) = (uint32_t)P1.anchor;
+    }
+    // each lane stages its 16 bits (bytes 2q, 2q + 1) of the mixed masks
+    const uint32_t mw = (uint32_t)q >> 1, mh = (uint32_t)q & 1u;
+    if (Lv.hs0) ((lds_u16 *)S.word(((rel + Lv.off_sm0) >> 2) + mw))[mh] = (uint16_t)P0.negb;
+    if (Lv.hz0) ((lds_u16 *)S.word(((rel + Lv.off_zm0) >> 2) + mw))[mh] = (uint16_t)(~P0.nzb);
+    if (Lv.hs1) ((lds_u16 *)S.word(((rel + Lv.off_sm1) >> 2) + mw))[mh] = (uint16_t)P1.negb;
+    if (Lv.hz1) ((lds_u16 *)S.word(((rel + Lv.off_zm1) >> 2) + mw))[mh] = (uint16_t)(~P1.nzb);
+    stage_quad_payload(P0, S, (rel + Lv.off_p0) >> 2, q);
+    stage_quad_payload(P1, S, (rel + Lv.off_p1) >> 2, q);
+}
+
+// Zero staging words [0, nw) (the whole wave, 16 bytes per lane and step).
+__device__ __forceinline__ void zero_staging(const Staging &S, uint32_t nw)
+{
+    for (uint32_t w4 = 4u * (uint32_t)lane_id(); w4 < nw; w4 += 256u) {
+        if (w4 + 4u <= nw) *(lds_u32x4 *)S.word(w4) = u32x4{0u, 0u, 0u, 0u};
+        else
+            for (uint32_t wd = w4; wd < nw; ++wd) *S.word(wd) = 0u;
+    }
+}
+
+// Copy staging words [0, nw) to dst (4-byte aligned), 16 bytes per lane
+// and step (the staging rows are 16-byte aligned and R is a multiple of 4
+// words).
+__device__ __forceinline__ void copy_staging(const Staging &S, uint32_t nw, uint32_t *dst)
+{
+    for (uint32_t w4 = 4u * (uint32_t)lane_id(); w4 < nw; w4 += 256u) {
+        if (w4 + 4u <= nw) {
+            const u32x4 v = *(const lds_u32x4 *)S.word(w4);
+            __builtin_memcpy(dst + w4, &v, 16);
+        } else {
+            for (uint32_t wd = w4; wd < nw; ++wd) dst[wd] = *S.word(wd);
+        }
+    }
+}
+
+// Decode one chunk record (headers h0, h1; body at `body`) four lanes per
+// chunk: lane q writes values 16q..16q+15 of the real plane to dre[0..15]
+// and of the imaginary plane to dim[0..15] (LDS or registers).  The one
+// decoder of the library: the stage loop, export, sampled amplitudes,
+// reductions and the stand-alone codec all decode through it.
+template <int DOM>
+__device__ __forceinline__ void decode_record(uint32_t h0, uint32_t h1, const uint8_t *body, const CodecParams &cp,
+                                              int q, bool act, float *dre, float *dim)
+{
+    const Layout Lv = layout_of(h0, h1);
+    const int32_t an0 = Lv.lz0 ? *(const int32_t *)body : 0;
+    const int32_t an1 = Lv.lz1 ? *(const int32_t *)(body + (Lv.lz0 ? 4 : 0)) : 0;
+    decode_quad<DOM>(h0, an0, body, Lv.off_sm0, Lv.off_zm0, Lv.off_p0, dre, q, act, cp);
+    decode_quad<DOM>(h1, an1, body, Lv.off_sm1, Lv.off_zm1, Lv.off_p1, dim, q, act, cp);
+}
+
+// Decode the chunk of directory entry e (a lost chunk reads as zero).
+template <int DOM>
+__device__ __forceinline__ void decode_entry(uint64_t e, const uint8_t *pool, const uint8_t *host, uint64_t cap,
+                                             const CodecParams &cp, int q, bool act, float *dre, float *dim)
+{
+    if (e == kDirInvalid) e = 0;
+    const uint32_t h0 = (uint32_t)(e >> 40) & 0xFFFu, h1 = (uint32_t)(e >> 52);
+    decode_record<DOM>(h0, h1, body_ptr(pool, host, cap, e & kDirOffsetMask), cp, q, act, dre, dim);
+}
+
 template <int T, int NT>
 struct PassLds {
     static constexpr int TILE = 1 << T, NCH = TILE / kChunk, NW = NT / 64;
@@ -1113,7 +851,9 @@ __device__ __forceinline__ CodecParams copy_cp(const C &c)
 
 // A is PassArgs, or PassArgs in the constant address space (arguments that a
 // batched launch reads from device memory with scalar loads)
-template <int T, int NT, int DOM, class A>
+// DUMP: the test hooks (sv_debug_dump) are compiled in; only the per-pass
+// kernel has them (batched, persistent and captured launches refuse dumps)
+template <int T, int NT, int DOM, bool DUMP, class A>
 __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
 {
     using L = PassLds<T, NT>;
@@ -1145,16 +885,16 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         const bool act = qc < CPW;
         const int c = c0 + (act ? qc : 0);
         const uint64_t gch = base | deposit((uint64_t)c, a.tileq + 6, T - 6);
-        uint64_t e = act ? a.dir_in[gch >> 6] : 0ull;
-        if (e == kDirInvalid) e = 0;                      // a lost chunk reads as zero
-        const uint32_t eh0 = (uint32_t)(e >> 40) & 0xFFFu, eh1 = (uint32_t)(e >> 52);
-        const Layout Lv = layout_of(eh0, eh1);
-        const uint8_t *body = body_ptr(a.pool_in, a.host_in, a.pool_cap, e & kDirOffsetMask);
-        const int32_t an0 = Lv.lz0 ? *(const int32_t *)body : 0;
-        const int32_t an1 = Lv.lz1 ? *(const int32_t *)(body + (Lv.lz0 ? 4 : 0)) : 0;
+        const uint64_t e = act ? a.dir_in[gch >> 6] : 0ull;
         const uint32_t t0 = tix((uint32_t)(c << 6) + 16u * (uint32_t)q);
-        decode_quad<DOM>(eh0, an0, body, Lv.off_sm0, Lv.off_zm0, Lv.off_p0, s.re + t0, q, act, cp);
-        decode_quad<DOM>(eh1, an1, body, Lv.off_sm1, Lv.off_zm1, Lv.off_p1, s.im + t0, q, act, cp);
+        decode_entry<DOM>(e, a.pool_in, a.host_in, a.pool_cap, cp, q, act, s.re + t0, s.im + t0);
+        if (DUMP && a.dumpd_re && act && gch - a.dump_lo < a.dump_n) {   // test hook: values as decoded
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                a.dumpd_re[gch - a.dump_lo + 16 * q + j] = s.re[t0 + j];
+                a.dumpd_im[gch - a.dump_lo + 16 * q + j] = s.im[t0 + j];
+            }
+        }
         __builtin_amdgcn_s_setprio(0);
     } else {
         __builtin_amdgcn_s_setprio(2);                  // as for the decoder's loads
@@ -1208,11 +948,11 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     const int c = c0 + (act ? qc : 0);
     const uint64_t g = base | deposit((uint64_t)c, a.tileq + 6, T - 6);   // chunk's first amplitude
     const uint32_t t0 = tix((uint32_t)(c << 6) + 16u * (uint32_t)q);
-    if (a.dump_re && act) {
+    if (DUMP && a.dump_re && act && g - a.dump_lo < a.dump_n) {          // test hook: values about to be encoded
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
-            a.dump_re[g + 16 * q + j] = s.re[t0 + j];
-            a.dump_im[g + 16 * q + j] = s.im[t0 + j];
+            a.dump_re[g - a.dump_lo + 16 * q + j] = s.re[t0 + j];
+            a.dump_im[g - a.dump_lo + 16 * q + j] = s.im[t0 + j];
         }
     }
     QuadPlane P0, P1;
@@ -1238,27 +978,9 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     if (total) {
         wave_sync_lds();                              // every lane has read its values
         // zero the stream's staging words (the payload fields are ORed in)
-        const uint32_t nw0 = total >> 2;
-        for (uint32_t w4 = 4u * (uint32_t)lane; w4 < nw0; w4 += 256u) {
-            if (w4 + 4u <= nw0) *(lds_u32x4 *)S.word(w4) = u32x4{0u, 0u, 0u, 0u};
-            else
-                for (uint32_t wd = w4; wd < nw0; ++wd) *S.word(wd) = 0u;
-        }
+        zero_staging(S, total >> 2);
         wave_sync_lds();
-        if (act && (h0 | h1)) {
-            if (q == 0) {
-                if (Lv.lz0) *S.word(rel >> 2) = (uint32_t)P0.anchor;
-                if (Lv.lz1) *S.word((rel >> 2) + (Lv.lz0 ? 1 : 0)) = (uint32_t)P1.anchor;
-            }
-            // each lane stages its 16 bits (bytes 2q, 2q + 1) of the mixed masks
-            const uint32_t mw = (uint32_t)q >> 1, mh = (uint32_t)q & 1u;
-            if (Lv.hs0) ((lds_u16 *)S.word(((rel + Lv.off_sm0) >> 2) + mw))[mh] = (uint16_t)P0.negb;
-            if (Lv.hz0) ((lds_u16 *)S.word(((rel + Lv.off_zm0) >> 2) + mw))[mh] = (uint16_t)(~P0.nzb);
-            if (Lv.hs1) ((lds_u16 *)S.word(((rel + Lv.off_sm1) >> 2) + mw))[mh] = (uint16_t)P1.negb;
-            if (Lv.hz1) ((lds_u16 *)S.word(((rel + Lv.off_zm1) >> 2) + mw))[mh] = (uint16_t)(~P1.nzb);
-            stage_quad_payload(P0, S, (rel + Lv.off_p0) >> 2, q);
-            stage_quad_payload(P1, S, (rel + Lv.off_p1) >> 2, q);
-        }
+        if (act && (h0 | h1)) stage_record(P0, P1, Lv, S, rel, q);
         wave_sync_lds();
     }
     const uint64_t b = uniform_u64(got);
@@ -1277,19 +999,8 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         atomicAdd(&cnt[wave_off < a.pool_cap ? C_DEV_BYTES : C_HOST_BYTES], (unsigned long long)total);
     const uint64_t off = wave_off + rel;
     if (!overflow && total) {
-        // copy the staged stream out: 16 bytes per lane and step (the stream
-        // is 4-byte aligned; the staging rows are 16-byte aligned and R is a
-        // multiple of 4 words)
-        uint32_t *dst = (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, wave_off);
-        const uint32_t nw = total >> 2;
-        for (uint32_t w4 = 4u * (uint32_t)lane; w4 < nw; w4 += 256u) {
-            if (w4 + 4u <= nw) {
-                const u32x4 v = *(const lds_u32x4 *)S.word(w4);
-                __builtin_memcpy(dst + w4, &v, 16);
-            } else {
-                for (uint32_t wd = w4; wd < nw; ++wd) dst[wd] = *S.word(wd);
-            }
-        }
+        // copy the staged stream out
+        copy_staging(S, total >> 2, (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, wave_off));
     }
     if (act && q == 0)
         a.dir_out[g >> 6] = (h0 | h1) == 0u ? 0ull
@@ -1314,7 +1025,7 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
 template <int T, int NT, int DOM>
 __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel(PassArgs a)
 {
-    pass_body<T, NT, DOM, PassArgs>(a, blockIdx.x);
+    pass_body<T, NT, DOM, true, PassArgs>(a, blockIdx.x);
 }
 
 // One launch over the tiles of several states (independent circuits): state
@@ -1330,7 +1041,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_batch(const PassArg
         else hi = mid;
     }
     typedef const __attribute__((address_space(4))) PassArgs CArgs;
-    pass_body<T, NT, DOM, CArgs>(((CArgs *)args)[lo], blockIdx.x - first_block[lo]);
+    pass_body<T, NT, DOM, false, CArgs>(((CArgs *)args)[lo], blockIdx.x - first_block[lo]);
 }
 
 // Whole-circuit launch over a work queue: every stage of every circuit in
@@ -1397,7 +1108,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_queue(PersistArgs p
         }
         const uint32_t tpi = pa.tiles_per_item[lo];
         const uint32_t tile0 = (it - pa.first_item[lo]) * tpi;
-        for (uint32_t u = 0; u < tpi; ++u) pass_body<T, NT, DOM, CArgs>(((CArgs *)pa.args)[lo], tile0 + u);
+        for (uint32_t u = 0; u < tpi; ++u) pass_body<T, NT, DOM, false, CArgs>(((CArgs *)pa.args)[lo], tile0 + u);
         if (pa.system_scope) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
         else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         __syncthreads();
@@ -1414,56 +1125,6 @@ __global__ void fill_u64_kernel(uint64_t *p, uint64_t n, uint64_t v)
 {
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         p[i] = v;
-}
-
-// |0...0>: chunk 0 holds amplitude 1 at index 0; every other chunk is zero
-// (directory entry 0, no body).
-__global__ void init_state_kernel(uint64_t *dir, uint8_t *pool, unsigned long long *counters, CodecParams cp)
-{
-    __shared__ uint32_t stage[144];
-    const int lane = lane_id();
-    PlaneInfo p0, p1;
-    const uint32_t f0 = encode_plane(lane == 0 ? 1.0f : 0.0f, 64, cp, p0);
-    const uint32_t f1 = encode_plane(0.0f, 64, cp, p1);
-    const uint32_t bytes = write_body(stage, p0, p1, f0, f1, (uint32_t *)pool, false);
-    if (lane == 0) {
-        dir[0] = ((uint64_t)p0.hdr << 40) | ((uint64_t)p1.hdr << 52);
-        counters[C_CURSOR] = bytes;
-    }
-}
-
-__device__ __forceinline__ void decode_chunk(const uint64_t *dir, const PoolView &pv, const CodecParams &cp,
-                                             uint64_t chunk, float &re, float &im)
-{
-    const ChunkRegs R = load_entry(uniform_u64(dir[chunk]), pv);
-    decode_regs(R, cp, re, im);
-}
-
-__global__ void export_kernel(const uint64_t *dir, PoolView pv, CodecParams cp, uint64_t chunk0,
-                              uint64_t n_chunks, float2 *dst)
-{
-    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < n_chunks; c += nw) {
-        float re, im;
-        decode_chunk(dir, pv, cp, chunk0 + c, re, im);
-        dst[c * 64 + lane_id()] = make_float2(re, im);
-    }
-}
-
-__global__ void amplitudes_kernel(const uint64_t *dir, PoolView pv, CodecParams cp, const uint64_t *idx,
-                                  uint64_t k, uint64_t n_chunks, float2 *dst)
-{
-    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t j = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); j < k; j += nw) {
-        const uint64_t xu = uniform_u64(idx[j]);
-        if ((xu >> 6) >= n_chunks) {          // index outside the state
-            if (lane_id() == 0) dst[j] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
-            continue;
-        }
-        float re, im;
-        decode_chunk(dir, pv, cp, xu >> 6, re, im);
-        if ((uint64_t)lane_id() == (xu & 63ull)) dst[j] = make_float2(re, im);
-    }
 }
 
 // Per-block statistics of the compressed state, read from the directory
@@ -1550,97 +1211,6 @@ __global__ void block_stats_kernel(const uint64_t *dir, uint64_t chunks_per_bloc
     }
 }
 
-// FP64 reductions: <ref|psi>, |psi|^2, |ref|^2, max |psi - ref| (componentwise).
-// Each block writes 5 partials; one block sums them in a fixed order.
-__global__ void fidelity_partial_kernel(const uint64_t *dir, PoolView pv, CodecParams cp, uint64_t n_chunks,
-                                        const double2 *ref, double *partials)
-{
-    __shared__ double sh[5][16];
-    const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
-    double sr = 0, si = 0, np = 0, nr = 0, mx = 0;
-    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; c < n_chunks; c += nw) {
-        float re, im;
-        decode_chunk(dir, pv, cp, c, re, im);
-        const double pr = re, pi = im;
-        np += pr * pr + pi * pi;
-        if (ref) {
-            const double2 r = ref[c * 64 + lane];
-            sr += r.x * pr + r.y * pi;
-            si += r.x * pi - r.y * pr;
-            nr += r.x * r.x + r.y * r.y;
-            mx = fmax(mx, fmax(fabs(pr - r.x), fabs(pi - r.y)));
-        }
-    }
-    double v[5] = {sr, si, np, nr, mx};
-#pragma unroll
-    for (int q = 0; q < 5; ++q) {
-        double x = v[q];
-        for (int m = 32; m >= 1; m >>= 1) {
-            const double y = __shfl_xor(x, m, 64);
-            x = (q == 4) ? fmax(x, y) : x + y;
-        }
-        if (lane == 0) sh[q][wave] = x;
-    }
-    __syncthreads();
-    if (threadIdx.x < 5) {
-        const int q = (int)threadIdx.x;
-        double x = sh[q][0];
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) x = (q == 4) ? fmax(x, sh[q][w]) : x + sh[q][w];
-        partials[(uint64_t)blockIdx.x * 5 + q] = x;
-    }
-}
-
-__global__ void fidelity_final_kernel(const double *partials, int n, double *out5)
-{
-    if (threadIdx.x < 5) {
-        const int q = (int)threadIdx.x;
-        double x = partials[q];
-        for (int i = 1; i < n; ++i)
-            x = (q == 4) ? fmax(x, partials[(uint64_t)i * 5 + q]) : x + partials[(uint64_t)i * 5 + q];
-        out5[q] = x;
-    }
-}
-
-// stand-alone codec: canonical records (headers + body) in fixed slots
-__global__ void codec_encode_kernel(const float *re, const float *im, uint64_t n, CodecParams cp, uint8_t *slots,
-                                    uint32_t *sizes)
-{
-    __shared__ uint32_t stage[4][144];
-    const int lane = lane_id();
-    const int wave = (int)(threadIdx.x >> 6);
-    const uint64_t nch = (n + 63) / 64;
-    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + wave; c < nch; c += nw) {
-        const int nvalid = (int)((n - c * 64) < 64 ? (n - c * 64) : 64);
-        const uint64_t i = c * 64 + lane;
-        const float xr = lane < nvalid ? re[i] : 0.0f;
-        const float xi = lane < nvalid ? im[i] : 0.0f;
-        PlaneInfo p0, p1;
-        const uint32_t f0 = encode_plane(xr, nvalid, cp, p0);
-        const uint32_t f1 = encode_plane(xi, nvalid, cp, p1);
-        const uint32_t bytes = write_body(stage[wave], p0, p1, f0, f1, (uint32_t *)(slots + c * kSlotBytes), true);
-        if (lane == 0) sizes[c] = bytes;
-    }
-}
-
-__global__ void codec_decode_kernel(const uint8_t *slots, uint64_t n, CodecParams cp, float *re, float *im)
-{
-    const int lane = lane_id();
-    const uint64_t nch = (n + 63) / 64;
-    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
-    for (uint64_t c = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); c < nch; c += nw) {
-        const uint8_t *rec = slots + c * kSlotBytes;
-        const uint32_t h0 = rfl(*(const uint32_t *)rec), h1 = rfl(*(const uint32_t *)(rec + 4));
-        const ChunkRegs R = load_body(h0 & 0xFFFu, h1 & 0xFFFu, rec + 8);
-        float xr, xi;
-        decode_regs(R, cp, xr, xi);
-        const uint64_t i = c * 64 + lane;
-        if (i < n) { re[i] = xr; im[i] = xi; }
-    }
-}
-
 // ------------------------------------------------------------------ directory check
 // A directory entry is 0 (an all-zero chunk) or two well-formed plane
 // headers for the state's codec domain plus the offset of a record that lies
@@ -1672,6 +1242,478 @@ __global__ void check_dir_kernel(const uint64_t *__restrict__ dir, uint64_t n, u
         nb += ok ? 0u : 1u;
     }
     if (nb) atomicAdd(bad, nb);
+}
+
+// |0...0>: chunk 0 holds amplitude 1 at index 0, encoded by the stage loop's
+// quad-lane encoder; every other chunk is zero (directory entry 0, no body).
+// One wave.
+template <int DOM>
+__global__ void init_state_kernel(uint64_t *dir, uint8_t *pool, unsigned long long *counters, CodecParams cp)
+{
+    __shared__ __align__(16) uint32_t stage[kSlotBytes / 4];
+    const int lane = lane_id(), q = lane & 3;
+    float xr[16], xi[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        xr[j] = (lane == 0 && j == 0) ? 1.0f : 0.0f;
+        xi[j] = 0.0f;
+    }
+    QuadPlane P0, P1;
+    encode_quad<DOM>(xr, cp, q, P0);
+    encode_quad<DOM>(xi, cp, q, P1);
+    const bool act = lane < 4;
+    const uint32_t h0 = act ? P0.hdr : 0u, h1 = act ? P1.hdr : 0u;
+    const Layout Lv = layout_of(h0, h1);
+    const uint32_t size = rfl(Lv.size);
+    const Staging S = make_staging(stage, stage, kSlotBytes / 4);
+    zero_staging(S, kSlotBytes / 4);
+    wave_sync_lds();
+    if (act && (h0 | h1)) stage_record(P0, P1, Lv, S, 0u, q);
+    wave_sync_lds();
+    copy_staging(S, size >> 2, (uint32_t *)pool);
+    if (lane == 0) {
+        dir[0] = (h0 | h1) ? (((uint64_t)h0 << 40) | ((uint64_t)h1 << 52)) : 0ull;
+        counters[C_CURSOR] = size;
+    }
+}
+
+// Loop of a wave over runs of 16 consecutive items (chunks, indices), one
+// quad per item: `b0` is the run's first item.
+#define BMQ_WAVE_RUNS(b0, n)                                                                                   \
+    for (uint64_t b0 = 16ull * ((uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)); b0 < (n);     \
+         b0 += 16ull * (uint64_t)gridDim.x * (blockDim.x >> 6))
+
+// Decode chunks [chunk0, chunk0 + n_chunks) into dst (complex64).
+template <int DOM>
+__global__ void export_kernel(const uint64_t *dir, PoolView pv, CodecParams cp, uint64_t chunk0,
+                              uint64_t n_chunks, float2 *dst)
+{
+    const int lane = lane_id(), q = lane & 3;
+    BMQ_WAVE_RUNS(b0, n_chunks) {
+        const uint64_t c = b0 + (uint64_t)(lane >> 2);
+        const bool act = c < n_chunks;
+        float vr[16], vi[16];
+        decode_entry<DOM>(act ? dir[chunk0 + c] : 0ull, pv.dev, pv.host, pv.cap, cp, q, act, vr, vi);
+        if (act) {
+            float2 *o = dst + c * 64 + 16 * q;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) o[j] = make_float2(vr[j], vi[j]);
+        }
+    }
+}
+
+// Amplitudes at idx[0..k): the quad of index j decodes its chunk and the
+// lane holding the amplitude writes it (NaN for an index outside the state).
+template <int DOM>
+__global__ void amplitudes_kernel(const uint64_t *dir, PoolView pv, CodecParams cp, const uint64_t *idx,
+                                  uint64_t k, uint64_t n_chunks, float2 *dst)
+{
+    const int lane = lane_id(), q = lane & 3;
+    BMQ_WAVE_RUNS(b0, k) {
+        const uint64_t j = b0 + (uint64_t)(lane >> 2);
+        const bool act = j < k;
+        const uint64_t x = act ? idx[j] : 0ull;
+        const bool inside = (x >> 6) < n_chunks;
+        float vr[16], vi[16];
+        decode_entry<DOM>(act && inside ? dir[x >> 6] : 0ull, pv.dev, pv.host, pv.cap, cp, q, act && inside, vr, vi);
+        const uint32_t sel = (uint32_t)(x & 63u);
+        if (act && inside && (int)(sel >> 4) == q) {
+            float r = 0.0f, i = 0.0f;
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj)
+                if ((uint32_t)jj == (sel & 15u)) { r = vr[jj]; i = vi[jj]; }
+            dst[j] = make_float2(r, i);
+        }
+        if (act && !inside && q == 0) dst[j] = make_float2(__builtin_nanf(""), __builtin_nanf(""));
+    }
+}
+
+// ------------------------------------------------------------------ FP64 reductions
+//
+// <ref|psi>, |psi|^2, |ref|^2 and max |psi - ref| (componentwise) over
+// chunks [chunk0, chunk0 + n_chunks).  The reference is a complex128 array
+// (rv.c128, its element 0 = amplitude 64 chunk0) or a second compressed
+// state (rv.dir / rv.pv / rv.cp).  Block b adds its five partials into
+// partials[5b..5b+4] (the maximum by fmax), so that a host reference can be
+// streamed slice by slice; partials are zeroed before the first slice.
+
+__device__ __forceinline__ double wave_sum_f64(double x)
+{
+    for (int m = 32; m >= 1; m >>= 1) x += __shfl_xor(x, m, 64);
+    return x;
+}
+
+template <int DOM, int REF, int RDOM>
+__global__ __launch_bounds__(256) void fidelity_partial_kernel(const uint64_t *dir, PoolView pv, CodecParams cp,
+                                                               uint64_t chunk0, uint64_t n_chunks, RefView rv,
+                                                               double *partials)
+{
+    __shared__ double sh[5][4];
+    const int lane = lane_id(), q = lane & 3, wave = (int)(threadIdx.x >> 6);
+    double sr = 0, si = 0, np = 0, nr = 0, mx = 0;
+    BMQ_WAVE_RUNS(b0, n_chunks) {
+        const uint64_t c = b0 + (uint64_t)(lane >> 2);
+        const bool act = c < n_chunks;
+        float vr[16], vi[16];
+        decode_entry<DOM>(act ? dir[chunk0 + c] : 0ull, pv.dev, pv.host, pv.cap, cp, q, act, vr, vi);
+        float wr[16], wi[16];
+        if (REF == REF_STATE)
+            decode_entry<RDOM>(act ? rv.dir[chunk0 + c] : 0ull, rv.pv.dev, rv.pv.host, rv.pv.cap, rv.cp, q, act, wr,
+                               wi);
+        if (!act) continue;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const double pr = vr[j], pi = vi[j];
+            np += pr * pr + pi * pi;
+            if (REF != REF_NONE) {
+                double rr, ri;
+                if (REF == REF_C128) {
+                    const double2 r = rv.c128[c * 64 + 16 * q + j];
+                    rr = r.x;
+                    ri = r.y;
+                } else {
+                    rr = wr[j];
+                    ri = wi[j];
+                }
+                sr += rr * pr + ri * pi;
+                si += rr * pi - ri * pr;
+                nr += rr * rr + ri * ri;
+                mx = fmax(mx, fmax(fabs(pr - rr), fabs(pi - ri)));
+            }
+        }
+    }
+    double v[5] = {sr, si, np, nr, mx};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        double x = v[k];
+        for (int m = 32; m >= 1; m >>= 1) {
+            const double y = __shfl_xor(x, m, 64);
+            x = (k == 4) ? fmax(x, y) : x + y;
+        }
+        if (lane == 0) sh[k][wave] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 5) {
+        const int k = (int)threadIdx.x;
+        double x = sh[k][0];
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) x = (k == 4) ? fmax(x, sh[k][w]) : x + sh[k][w];
+        double *p = partials + (uint64_t)blockIdx.x * 5 + k;
+        *p = (k == 4) ? fmax(*p, x) : *p + x;
+    }
+}
+
+__global__ void fidelity_final_kernel(const double *partials, int n, double *out5)
+{
+    if (threadIdx.x < 5) {
+        const int q = (int)threadIdx.x;
+        double x = partials[q];
+        for (int i = 1; i < n; ++i)
+            x = (q == 4) ? fmax(x, partials[(uint64_t)i * 5 + q]) : x + partials[(uint64_t)i * 5 + q];
+        out5[q] = x;
+    }
+}
+
+// ------------------------------------------------------------------ sampling x ~ |psi(x)|^2
+//
+// Two levels: |psi|^2 of each group of chunks_per_group chunks (one
+// workgroup per group), then, per sample, a wave walks the chosen group's
+// chunks in index order with a running FP64 sum until it passes the
+// sample's residual (the host draws the uniforms and picks the group from
+// the groups' prefix sums).
+template <int DOM>
+__global__ __launch_bounds__(256) void group_norm_kernel(const uint64_t *dir, PoolView pv, CodecParams cp,
+                                                         uint32_t chunks_per_group, double *gnorm)
+{
+    __shared__ double sh[4];
+    const int lane = lane_id(), q = lane & 3, wave = (int)(threadIdx.x >> 6);
+    const uint64_t c0 = (uint64_t)blockIdx.x * chunks_per_group;
+    double acc = 0;
+    for (uint32_t b0 = 16u * (uint32_t)wave; b0 < chunks_per_group; b0 += 64u) {
+        const uint32_t cc = b0 + (uint32_t)(lane >> 2);
+        const bool act = cc < chunks_per_group;
+        float vr[16], vi[16];
+        decode_entry<DOM>(act ? dir[c0 + cc] : 0ull, pv.dev, pv.host, pv.cap, cp, q, act, vr, vi);
+        if (act)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc += (double)vr[j] * vr[j] + (double)vi[j] * vi[j];
+    }
+    acc = wave_sum_f64(acc);
+    if (lane == 0) sh[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) gnorm[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+template <int DOM>
+__global__ __launch_bounds__(256) void sample_kernel(const uint64_t *dir, PoolView pv, CodecParams cp,
+                                                     uint32_t chunks_per_group, const uint32_t *grp,
+                                                     const double *resid, uint64_t k, uint64_t *out)
+{
+    const int lane = lane_id(), q = lane & 3;
+    const uint64_t nw = (uint64_t)gridDim.x * (blockDim.x >> 6);
+    for (uint64_t i = (uint64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); i < k; i += nw) {
+        const uint64_t c0 = (uint64_t)grp[i] * chunks_per_group;
+        const double r = resid[i];
+        double acc = 0;
+        uint64_t pick = c0 * 64, last_nz = c0 * 64;
+        bool found = false;
+        for (uint32_t b0 = 0; b0 < chunks_per_group && !found; b0 += 16u) {
+            const uint32_t cc = b0 + (uint32_t)(lane >> 2);
+            const bool act = cc < chunks_per_group;
+            float vr[16], vi[16];
+            decode_entry<DOM>(act ? dir[c0 + cc] : 0ull, pv.dev, pv.host, pv.cap, cp, q, act, vr, vi);
+            double p[16], s = 0;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                p[j] = act ? (double)vr[j] * vr[j] + (double)vi[j] * vi[j] : 0.0;
+                s += p[j];
+            }
+            // inclusive scan of the lane sums in lane order (= amplitude order)
+            double incl = s;
+            for (int d = 1; d < 64; d <<= 1) {
+                const double y = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += y;
+            }
+            const double tot = __shfl(incl, 63, 64);
+            const uint64_t base = (c0 + cc) * 64 + 16u * (uint32_t)q;
+            if (acc + tot > r) {
+                const uint64_t over = __ballot(acc + incl > r);
+                const int L = __ffsll((long long)over) - 1;
+                uint64_t mine = base;
+                if (lane == L) {
+                    double a2 = acc + (incl - s);
+                    int hit = -1, lastp = 0;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j) {
+                        a2 += p[j];
+                        if (p[j] > 0.0) lastp = j;
+                        if (hit < 0 && a2 > r) hit = j;
+                    }
+                    mine = base + (uint64_t)(hit >= 0 ? hit : lastp);
+                }
+                pick = __shfl(mine, L, 64);
+                found = true;
+            } else {
+                const uint64_t nzl = __ballot(s > 0.0);
+                if (nzl) {
+                    const int Lh = 63 - __clzll((long long)nzl);
+                    int lastp = 0;
+#pragma unroll
+                    for (int j = 0; j < 16; ++j)
+                        if (p[j] > 0.0) lastp = j;
+                    last_nz = __shfl(base + (uint64_t)lastp, Lh, 64);
+                }
+                acc += tot;
+            }
+        }
+        if (lane == 0) out[i] = found ? pick : last_nz;
+    }
+}
+
+// ------------------------------------------------------------------ stand-alone codec
+//
+// The stage loop's encoder and decoder on caller arrays of whole chunks.
+// Slot form: chunk i's record (its two 32-bit headers, then its body) at
+// slots + i kSlotBytes.  Stream form: the canonical block stream -- a
+// 16-byte header (u8 0x51, u8 version 1, u8 domain, u8 log2 chunk = 6,
+// u32 eb bits, u32 n_values, u32 n_chunks) followed by the records in chunk
+// order.
+
+__device__ __forceinline__ void load16(const float *p, bool act, float *x)
+{
+#pragma unroll
+    for (int j = 0; j < 16; ++j) x[j] = act ? p[j] : 0.0f;
+}
+
+template <int DOM>
+__global__ __launch_bounds__(256) void codec_slots_encode_kernel(const float *re, const float *im, uint64_t nch,
+                                                                 CodecParams cp, uint8_t *slots, uint32_t *sizes)
+{
+    constexpr uint32_t SW = kSlotBytes / 4;                 // words per slot
+    __shared__ __align__(16) uint32_t stage[4][16 * SW];
+    const int lane = lane_id(), q = lane & 3, qc = lane >> 2, wave = (int)(threadIdx.x >> 6);
+    const Staging S = make_staging(stage[wave], stage[wave], 16 * SW);
+    BMQ_WAVE_RUNS(b0, nch) {
+        const uint64_t c = b0 + (uint64_t)qc;
+        const bool act = c < nch;
+        float xr[16], xi[16];
+        load16(re + c * 64 + 16 * q, act, xr);
+        load16(im + c * 64 + 16 * q, act, xi);
+        QuadPlane P0, P1;
+        encode_quad<DOM>(xr, cp, q, P0);
+        encode_quad<DOM>(xi, cp, q, P1);
+        const uint32_t h0 = act ? P0.hdr : 0u, h1 = act ? P1.hdr : 0u;
+        const Layout Lv = layout_of(h0, h1);
+        wave_sync_lds();                                    // the previous run's copy-out is done
+        zero_staging(S, 16 * SW);
+        wave_sync_lds();
+        if (act && q == 0) {
+            *S.word((uint32_t)qc * SW) = h0;
+            *S.word((uint32_t)qc * SW + 1u) = h1;
+        }
+        if (act && (h0 | h1)) stage_record(P0, P1, Lv, S, (uint32_t)qc * kSlotBytes + 8u, q);
+        wave_sync_lds();
+        const uint64_t nv = nch - b0 < 16 ? nch - b0 : 16;
+        copy_staging(S, (uint32_t)nv * SW, (uint32_t *)(slots + b0 * kSlotBytes));
+        if (act && q == 0) sizes[c] = 8u + Lv.size;
+    }
+}
+
+template <int DOM>
+__global__ __launch_bounds__(256) void codec_slots_decode_kernel(const uint8_t *slots, uint64_t nch, CodecParams cp,
+                                                                 float *re, float *im)
+{
+    const int lane = lane_id(), q = lane & 3;
+    BMQ_WAVE_RUNS(b0, nch) {
+        const uint64_t c = b0 + (uint64_t)(lane >> 2);
+        const bool act = c < nch;
+        const uint8_t *rec = slots + (act ? c : 0) * kSlotBytes;
+        const uint32_t h0 = act ? (*(const uint32_t *)rec & 0xFFFu) : 0u;
+        const uint32_t h1 = act ? (*(const uint32_t *)(rec + 4) & 0xFFFu) : 0u;
+        float vr[16], vi[16];
+        decode_record<DOM>(h0, h1, rec + 8, cp, q, act, vr, vi);
+        if (act)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                re[c * 64 + 16 * q + j] = vr[j];
+                im[c * 64 + 16 * q + j] = vi[j];
+            }
+    }
+}
+
+// stream pass 1: record bytes (headers + body) of every chunk
+template <int DOM>
+__global__ __launch_bounds__(256) void codec_size_kernel(const float *re, const float *im, uint64_t nch,
+                                                         CodecParams cp, uint32_t *sizes)
+{
+    const int lane = lane_id(), q = lane & 3;
+    BMQ_WAVE_RUNS(b0, nch) {
+        const uint64_t c = b0 + (uint64_t)(lane >> 2);
+        const bool act = c < nch;
+        float xr[16], xi[16];
+        load16(re + c * 64 + 16 * q, act, xr);
+        load16(im + c * 64 + 16 * q, act, xi);
+        QuadPlane P0, P1;
+        encode_quad<DOM>(xr, cp, q, P0);
+        encode_quad<DOM>(xi, cp, q, P1);
+        const Layout Lv = layout_of(act ? P0.hdr : 0u, act ? P1.hdr : 0u);
+        if (act && q == 0) sizes[c] = 8u + Lv.size;
+    }
+}
+
+// exclusive prefix sum of sizes[0..n) into off[0..n), the total into off[n];
+// one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void scan_sizes_kernel(const uint32_t *sizes, uint64_t n, uint64_t *off)
+{
+    __shared__ uint32_t wsum[16];
+    __shared__ unsigned long long carry;
+    const int lane = lane_id(), wave = (int)(threadIdx.x >> 6);
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (uint64_t base = 0; base < n; base += 1024) {
+        const uint64_t i = base + threadIdx.x;
+        const uint32_t v = i < n ? sizes[i] : 0u;
+        const uint32_t incl = wave_scan_add(v);
+        if (lane == 63) wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+        for (int w = 0; w < 16; ++w) {
+            before += w < wave ? wsum[w] : 0u;
+            all += wsum[w];
+        }
+        const unsigned long long cbase = carry;
+        if (i < n) off[i] = cbase + before + incl - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry = cbase + all;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[n] = carry;
+}
+
+// stream pass 2: each wave stages the records of its 16 chunks (contiguous
+// in the stream) and copies them to their place; nothing is written when
+// the stream does not fit cap bytes
+template <int DOM>
+__global__ __launch_bounds__(256) void codec_write_kernel(const float *re, const float *im, uint64_t nch,
+                                                          CodecParams cp, const uint64_t *off, uint8_t *dst,
+                                                          uint64_t cap, uint32_t ebbits)
+{
+    constexpr uint32_t SW = kSlotBytes / 4;
+    __shared__ __align__(16) uint32_t stage[4][16 * SW];
+    if (16u + off[nch] > cap) return;
+    const int lane = lane_id(), q = lane & 3, qc = lane >> 2, wave = (int)(threadIdx.x >> 6);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        uint32_t *h = (uint32_t *)dst;
+        h[0] = 0x51u | (1u << 8) | ((uint32_t)DOM << 16) | (6u << 24);
+        h[1] = ebbits;
+        h[2] = (uint32_t)(nch * 64);
+        h[3] = (uint32_t)nch;
+    }
+    const Staging S = make_staging(stage[wave], stage[wave], 16 * SW);
+    BMQ_WAVE_RUNS(b0, nch) {
+        const uint64_t c = b0 + (uint64_t)qc;
+        const bool act = c < nch;
+        float xr[16], xi[16];
+        load16(re + c * 64 + 16 * q, act, xr);
+        load16(im + c * 64 + 16 * q, act, xi);
+        QuadPlane P0, P1;
+        encode_quad<DOM>(xr, cp, q, P0);
+        encode_quad<DOM>(xi, cp, q, P1);
+        const uint32_t h0 = act ? P0.hdr : 0u, h1 = act ? P1.hdr : 0u;
+        const Layout Lv = layout_of(h0, h1);
+        const uint32_t rsz = (act && q == 0) ? 8u + Lv.size : 0u;
+        const uint32_t incl = wave_scan_add(rsz);
+        const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        const uint32_t rel = qperm<QB0>(incl - rsz);
+        wave_sync_lds();
+        zero_staging(S, total >> 2);
+        wave_sync_lds();
+        if (act && q == 0) {
+            *S.word(rel >> 2) = h0;
+            *S.word((rel >> 2) + 1u) = h1;
+        }
+        if (act && (h0 | h1)) stage_record(P0, P1, Lv, S, rel + 8u, q);
+        wave_sync_lds();
+        copy_staging(S, total >> 2, (uint32_t *)(dst + 16 + uniform_u64(off[b0])));
+    }
+}
+
+// One lane walks the stream's records (a record's size follows from its two
+// headers) and writes each chunk's record offset; *bad is set when a header
+// is malformed for the domain or a record does not lie inside the stream.
+__global__ void codec_walk_kernel(const uint8_t *src, uint64_t bytes, uint64_t nch, int domain, uint64_t *off,
+                                  uint32_t *bad)
+{
+    if (threadIdx.x != 0) return;
+    uint64_t o = 16;
+    for (uint64_t c = 0; c < nch; ++c) {
+        if (o + 8 > bytes) { *bad = 1u; return; }
+        const uint32_t h0 = *(const uint32_t *)(src + o), h1 = *(const uint32_t *)(src + o + 4);
+        if ((h0 >> 12) || (h1 >> 12) || !header_ok(h0, domain) || !header_ok(h1, domain)) { *bad = 1u; return; }
+        off[c] = o;
+        o += 8u + layout_of(h0, h1).size;
+    }
+    if (o != bytes) *bad = 1u;
+}
+
+template <int DOM>
+__global__ __launch_bounds__(256) void codec_read_kernel(const uint8_t *src, const uint64_t *off, uint64_t nch,
+                                                         CodecParams cp, float *re, float *im)
+{
+    const int lane = lane_id(), q = lane & 3;
+    BMQ_WAVE_RUNS(b0, nch) {
+        const uint64_t c = b0 + (uint64_t)(lane >> 2);
+        const bool act = c < nch;
+        const uint8_t *rec = src + (act ? off[c] : 16ull);
+        const uint32_t h0 = act ? *(const uint32_t *)rec : 0u, h1 = act ? *(const uint32_t *)(rec + 4) : 0u;
+        float vr[16], vi[16];
+        decode_record<DOM>(h0, h1, rec + 8, cp, q, act, vr, vi);
+        if (act)
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                re[c * 64 + 16 * q + j] = vr[j];
+                im[c * 64 + 16 * q + j] = vi[j];
+            }
+    }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1754,37 +1796,134 @@ hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s)
     return hipGetLastError();
 }
 
+// D = the codec domain (0 LIN, 1 LOG, 2 RAW) as a constant inside the body
+#define BMQ_DOM_SWITCH(dom, ...)                          \
+    switch (dom) {                                        \
+    case 0: { constexpr int D = 0; __VA_ARGS__; } break;  \
+    case 1: { constexpr int D = 1; __VA_ARGS__; } break;  \
+    case 2: { constexpr int D = 2; __VA_ARGS__; } break;  \
+    default: return hipErrorInvalidValue;                 \
+    }
+
 hipError_t launch_init_state(uint64_t *dir, uint64_t n_chunks, uint8_t *pool, unsigned long long *counters,
                              CodecParams cp, hipStream_t s)
 {
     hipError_t e = launch_fill_u64(dir, n_chunks, 0ull, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, dir, pool, counters, cp);
+    BMQ_DOM_SWITCH(cp.domain, hipLaunchKernelGGL(init_state_kernel<D>, dim3(1), dim3(64), 0, s, dir, pool, counters, cp))
     return hipGetLastError();
 }
+
+// runs of 16 items per wave, 4 waves per workgroup
+static inline unsigned grid_runs(uint64_t items, unsigned cap = 65536) { return grid_for((items + 15) / 16, 4, cap); }
 
 hipError_t launch_export(const uint64_t *dir, const PoolView &pv, CodecParams cp, uint64_t chunk0,
                          uint64_t n_chunks, float2 *dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(export_kernel, dim3(grid_for(n_chunks, 4)), dim3(256), 0, s, dir, pv, cp, chunk0,
-                       n_chunks, dst);
+    BMQ_DOM_SWITCH(cp.domain, hipLaunchKernelGGL(export_kernel<D>, dim3(grid_runs(n_chunks)), dim3(256), 0, s, dir,
+                                                 pv, cp, chunk0, n_chunks, dst))
     return hipGetLastError();
 }
 
 hipError_t launch_amplitudes(const uint64_t *dir, const PoolView &pv, CodecParams cp, const uint64_t *idx,
                              uint64_t k, uint64_t n_chunks, float2 *dst, hipStream_t s)
 {
-    hipLaunchKernelGGL(amplitudes_kernel, dim3(grid_for(k, 4)), dim3(256), 0, s, dir, pv, cp, idx, k, n_chunks,
-                       dst);
+    BMQ_DOM_SWITCH(cp.domain, hipLaunchKernelGGL(amplitudes_kernel<D>, dim3(grid_runs(k)), dim3(256), 0, s, dir, pv,
+                                                 cp, idx, k, n_chunks, dst))
     return hipGetLastError();
 }
 
-hipError_t launch_fidelity(const uint64_t *dir, const PoolView &pv, CodecParams cp, uint64_t n_chunks,
-                           const double2 *ref, double *partials, int n_partials, double *out5, hipStream_t s)
+template <int DOM, int REF, int RDOM>
+static void fid_launch(unsigned grid, const uint64_t *dir, const PoolView &pv, CodecParams cp, uint64_t chunk0,
+                       uint64_t n, const RefView &rv, double *partials, hipStream_t s)
 {
-    hipLaunchKernelGGL(fidelity_partial_kernel, dim3((unsigned)n_partials), dim3(256), 0, s, dir, pv, cp,
-                       n_chunks, ref, partials);
+    hipLaunchKernelGGL((fidelity_partial_kernel<DOM, REF, RDOM>), dim3(grid), dim3(256), 0, s, dir, pv, cp, chunk0, n,
+                       rv, partials);
+}
+
+hipError_t launch_fidelity_partial(const uint64_t *dir, const PoolView &pv, CodecParams cp, uint64_t chunk0,
+                                   uint64_t n_chunks, const RefView &rv, double *partials, int n_partials,
+                                   hipStream_t s)
+{
+    const unsigned g = (unsigned)n_partials;
+    if (rv.kind == REF_NONE) {
+        BMQ_DOM_SWITCH(cp.domain, (fid_launch<D, REF_NONE, 0>(g, dir, pv, cp, chunk0, n_chunks, rv, partials, s)))
+    } else if (rv.kind == REF_C128) {
+        BMQ_DOM_SWITCH(cp.domain, (fid_launch<D, REF_C128, 0>(g, dir, pv, cp, chunk0, n_chunks, rv, partials, s)))
+    } else {
+        switch (rv.cp.domain) {
+        case 0: BMQ_DOM_SWITCH(cp.domain, (fid_launch<D, REF_STATE, 0>(g, dir, pv, cp, chunk0, n_chunks, rv, partials, s))) break;
+        case 1: BMQ_DOM_SWITCH(cp.domain, (fid_launch<D, REF_STATE, 1>(g, dir, pv, cp, chunk0, n_chunks, rv, partials, s))) break;
+        case 2: BMQ_DOM_SWITCH(cp.domain, (fid_launch<D, REF_STATE, 2>(g, dir, pv, cp, chunk0, n_chunks, rv, partials, s))) break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fidelity_final(const double *partials, int n_partials, double *out5, hipStream_t s)
+{
     hipLaunchKernelGGL(fidelity_final_kernel, dim3(1), dim3(64), 0, s, partials, n_partials, out5);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_norm(const uint64_t *dir, const PoolView &pv, CodecParams cp, uint32_t chunks_per_group,
+                             uint64_t n_groups, double *gnorm, hipStream_t s)
+{
+    if (n_groups > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    BMQ_DOM_SWITCH(cp.domain, hipLaunchKernelGGL(group_norm_kernel<D>, dim3((unsigned)n_groups), dim3(256), 0, s, dir,
+                                                 pv, cp, chunks_per_group, gnorm))
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(const uint64_t *dir, const PoolView &pv, CodecParams cp, uint32_t chunks_per_group,
+                         const uint32_t *grp, const double *resid, uint64_t k, uint64_t *out, hipStream_t s)
+{
+    BMQ_DOM_SWITCH(cp.domain, hipLaunchKernelGGL(sample_kernel<D>, dim3(grid_for(k, 4, 16384)), dim3(256), 0, s, dir,
+                                                 pv, cp, chunks_per_group, grp, resid, k, out))
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_slots_encode(const float *re, const float *im, uint64_t nch, CodecParams cp,
+                                     uint8_t *slots, uint32_t *sizes, hipStream_t s)
+{
+    BMQ_DOM_SWITCH(cp.domain, hipLaunchKernelGGL(codec_slots_encode_kernel<D>, dim3(grid_runs(nch)), dim3(256), 0, s,
+                                                 re, im, nch, cp, slots, sizes))
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_slots_decode(const uint8_t *slots, uint64_t nch, CodecParams cp, float *re, float *im,
+                                     hipStream_t s)
+{
+    BMQ_DOM_SWITCH(cp.domain, hipLaunchKernelGGL(codec_slots_decode_kernel<D>, dim3(grid_runs(nch)), dim3(256), 0, s,
+                                                 slots, nch, cp, re, im))
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_stream_encode(const float *re, const float *im, uint64_t nch, CodecParams cp,
+                                      uint32_t *sizes, uint64_t *off, uint8_t *dst, uint64_t cap, uint32_t ebbits,
+                                      hipStream_t s)
+{
+    BMQ_DOM_SWITCH(cp.domain, hipLaunchKernelGGL(codec_size_kernel<D>, dim3(grid_runs(nch)), dim3(256), 0, s, re, im,
+                                                 nch, cp, sizes))
+    hipLaunchKernelGGL(scan_sizes_kernel, dim3(1), dim3(1024), 0, s, sizes, nch, off);
+    BMQ_DOM_SWITCH(cp.domain, hipLaunchKernelGGL(codec_write_kernel<D>, dim3(grid_runs(nch)), dim3(256), 0, s, re, im,
+                                                 nch, cp, off, dst, cap, ebbits))
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_stream_decode(const uint8_t *src, uint64_t bytes, uint64_t nch, CodecParams cp,
+                                      uint64_t *off, uint32_t *bad, hipStream_t s)
+{
+    hipLaunchKernelGGL(codec_walk_kernel, dim3(1), dim3(64), 0, s, src, bytes, nch, cp.domain, off, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_codec_read(const uint8_t *src, const uint64_t *off, uint64_t nch, CodecParams cp, float *re,
+                             float *im, hipStream_t s)
+{
+    BMQ_DOM_SWITCH(cp.domain, hipLaunchKernelGGL(codec_read_kernel<D>, dim3(grid_runs(nch)), dim3(256), 0, s, src,
+                                                 off, nch, cp, re, im))
     return hipGetLastError();
 }
 
@@ -1794,22 +1933,6 @@ hipError_t launch_block_stats(const uint64_t *dir, uint64_t chunks_per_block, ui
 {
     hipLaunchKernelGGL(block_stats_kernel, dim3((unsigned)n_blocks), dim3(256), 0, s, dir, chunks_per_block, sf,
                        feats, label_bytes, label_mode);
-    return hipGetLastError();
-}
-
-hipError_t launch_codec_encode(const float *re, const float *im, uint64_t n, CodecParams cp, uint8_t *slots,
-                               uint32_t *sizes, hipStream_t s)
-{
-    hipLaunchKernelGGL(codec_encode_kernel, dim3(grid_for((n + 63) / 64, 4)), dim3(256), 0, s, re, im, n, cp,
-                       slots, sizes);
-    return hipGetLastError();
-}
-
-hipError_t launch_codec_decode(const uint8_t *slots, uint64_t n, CodecParams cp, float *re, float *im,
-                               hipStream_t s)
-{
-    hipLaunchKernelGGL(codec_decode_kernel, dim3(grid_for((n + 63) / 64, 4)), dim3(256), 0, s, slots, n, cp, re,
-                       im);
     return hipGetLastError();
 }
 

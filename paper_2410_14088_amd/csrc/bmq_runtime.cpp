@@ -49,6 +49,10 @@ constexpr size_t kMaxLaunchesPerBatch = 1024;   // counter blocks of one batch o
 constexpr size_t kStageCounters = (size_t)bmq::kSegments * bmq::C_NUM;   // words per launch
 constexpr int kPartials = 1024;
 constexpr uint64_t kOpsArenaBytes = 16ull << 20;   // fused matrices and diagonal tables of one plan
+constexpr uint64_t kStageBytes = 4ull << 20;       // host-reference slices, sampling tables
+constexpr int kMaxSampleGroups = 1 << 16;          // sampling: |psi|^2 per group, at most this many groups
+constexpr uint64_t kSampleBatch = 1ull << 16;      // samples per sampling kernel
+static_assert(kMaxSampleGroups * 8ull + kSampleBatch * 20ull <= kStageBytes, "sampling tables fit the staging area");
 
 // ------------------------------------------------------------------ gates
 
@@ -170,7 +174,10 @@ struct sv_state {
     int cur = 0;
     uint64_t live_bytes = 0;
     uint64_t uploaded_uid = 0;
-    float *dump_re = nullptr, *dump_im = nullptr;
+    float *dump_re = nullptr, *dump_im = nullptr;     // test hook (sv_debug_dump)
+    float *dumpd_re = nullptr, *dumpd_im = nullptr;
+    uint64_t dump_lo = 0, dump_n = 0;
+    uint8_t *stage = nullptr;                         // kStageBytes of device staging
     bool poisoned = false;
     bool reset_pending = false;                 // live_bytes is in the init counters
     sv_graph *pending_graph = nullptr;          // replayed graph whose counters are unread
@@ -562,7 +569,7 @@ bool plan_passes(sv_plan &P, StagePlan &st)
 struct ArenaLayout {
     uint64_t dir_bytes, pool_cap, scr_bytes, counters_bytes, partials_bytes, ops_bytes, total;
     uint64_t off_dir0, off_dir1, off_pool0, off_pool1, off_scr_re, off_scr_im, off_counters,
-        off_partials, off_out5, off_ops;
+        off_partials, off_out5, off_ops, off_stage;
 };
 
 uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
@@ -590,6 +597,7 @@ ArenaLayout layout_for(const sv_config_t &c)
     L.off_partials = o; o += L.partials_bytes;
     L.off_out5 = o; o += 256;
     L.off_ops = o; o += L.ops_bytes;
+    L.off_stage = o; o += kStageBytes;
     L.total = o;
     return L;
 }
@@ -775,6 +783,7 @@ int sv_create(const sv_config_t *cfg, void *dev_arena, uint64_t dev_bytes, void 
     S->partials = (double *)(S->arena + L.off_partials);
     S->out5 = (double *)(S->arena + L.off_out5);
     S->ops_arena = S->arena + L.off_ops;
+    S->stage = S->arena + L.off_stage;
     S->cur = 0;
     const uint64_t nch = 1ull << (S->n - 6);
     unsigned long long *ic = S->counters + kMaxLaunchesPerBatch * kStageCounters;
@@ -920,6 +929,10 @@ void build_pass_args(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, 
     a.opdata = (const float2 *)(sv->ops_arena + align256(p->ops.size() * sizeof(OpDesc)));
     a.dump_re = sv->dump_re;
     a.dump_im = sv->dump_im;
+    a.dumpd_re = sv->dumpd_re;
+    a.dumpd_im = sv->dumpd_im;
+    a.dump_lo = sv->dump_lo;
+    a.dump_n = sv->dump_n;
     a.mfma = (sv->cfg.flags & SV_FLAG_NO_MFMA) ? 0 : 1;
     if (a.out_mode == bmq::IO_COMPRESSED) sv->cur ^= 1;
 }
@@ -961,7 +974,8 @@ int plan_batch(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
         if (int rc = check_plan(states[i], plans[i], 0, plans[i] ? plans[i]->stages.size() : 0)) return rc;
         for (size_t j = 0; j < i; ++j)
             if (states[j] == states[i]) return fail(SV_ERR_INVALID, "state %zu appears twice in the batch", i);
-        if (states[i]->dump_re) return fail(SV_ERR_UNSUPPORTED, "the debug dump cannot run in a batch");
+        if (states[i]->dump_re || states[i]->dumpd_re)
+            return fail(SV_ERR_UNSUPPORTED, "the debug dump cannot run in a batch");
         const size_t l = launches_of(plans[i], 0, plans[i]->stages.size());
         if (l > kMaxLaunchesPerBatch)
             return fail(SV_ERR_UNSUPPORTED, "circuit %zu needs %zu pass launches (at most %zu in a batch)", i, l,
@@ -1201,7 +1215,7 @@ int sv_graph_capture(sv_t *sv, const sv_plan_t *p, size_t first, size_t count, s
     if (int rc = check_plan(sv, p, first, count)) return rc;
     if (!out) return fail(SV_ERR_INVALID, "out is NULL");
     if (count == 0) return fail(SV_ERR_INVALID, "empty stage range");
-    if (sv->dump_re) return fail(SV_ERR_UNSUPPORTED, "the debug dump cannot be captured");
+    if (sv->dump_re || sv->dumpd_re) return fail(SV_ERR_UNSUPPORTED, "the debug dump cannot be captured");
     const size_t launches = launches_of(p, first, count);
     if (launches > kMaxLaunchesPerBatch)
         return fail(SV_ERR_UNSUPPORTED, "%zu pass launches exceed the %zu counter blocks of one graph", launches,
@@ -1536,24 +1550,122 @@ int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size
     return first_err;
 }
 
-int sv_fidelity(const sv_t *sv, const double *ref_dev, double *fidelity, double *max_abs_err, double *norm2)
+int sv_fidelity(const sv_t *sv, const double *ref_host, const double *ref_dev, const sv_t *ref_sv, sv_fidelity_t *out)
 {
     if (int rc = check_state(sv)) return rc;
+    if (!out) return fail(SV_ERR_INVALID, "out is NULL");
+    if ((ref_host != nullptr) + (ref_dev != nullptr) + (ref_sv != nullptr) > 1)
+        return fail(SV_ERR_INVALID, "give at most one reference");
+    if (ref_sv) {
+        if (int rc = check_state(ref_sv)) return rc;
+        if (ref_sv->n != sv->n) return fail(SV_ERR_INVALID, "reference state has %d qubits, state %d", ref_sv->n, sv->n);
+        if (ref_sv->stream != sv->stream) HIP_TRY(hipStreamSynchronize(ref_sv->stream));
+    }
     const uint64_t nch = 1ull << (sv->n - 6);
-    const int np = (int)std::min<uint64_t>(kPartials, (nch + 3) / 4);
-    HIP_TRY(bmq::launch_fidelity(sv->dir[sv->cur], pool_view(sv, sv->cur), codec_params(sv->cfg), nch,
-                                 (const double2 *)ref_dev, sv->partials, np, sv->out5, sv->stream));
+    const int np = (int)std::min<uint64_t>(kPartials, (nch + 63) / 64);
+    const bmq::CodecParams cp = codec_params(sv->cfg);
+    HIP_TRY(bmq::launch_fill_u64((uint64_t *)sv->partials, (uint64_t)np * 5, 0ull, sv->stream));
+    bmq::RefView rv{};
+    rv.kind = bmq::REF_NONE;
+    if (ref_dev) {
+        rv.kind = bmq::REF_C128;
+        rv.c128 = (const double2 *)ref_dev;
+    } else if (ref_sv) {
+        rv.kind = bmq::REF_STATE;
+        rv.dir = ref_sv->dir[ref_sv->cur];
+        rv.pv = pool_view(ref_sv, ref_sv->cur);
+        rv.cp = codec_params(ref_sv->cfg);
+    }
+    if (ref_host) {
+        // stream the host reference through the staging area, slice by slice
+        const uint64_t slice = kStageBytes / (64 * 16);        // chunks per slice
+        rv.kind = bmq::REF_C128;
+        rv.c128 = (const double2 *)sv->stage;
+        for (uint64_t c0 = 0; c0 < nch; c0 += slice) {
+            const uint64_t nc = std::min(slice, nch - c0);
+            HIP_TRY(hipMemcpyAsync(sv->stage, ref_host + 2 * 64 * c0, nc * 64 * 16, hipMemcpyHostToDevice, sv->stream));
+            HIP_TRY(bmq::launch_fidelity_partial(sv->dir[sv->cur], pool_view(sv, sv->cur), cp, c0, nc, rv, sv->partials,
+                                                 np, sv->stream));
+        }
+    } else {
+        HIP_TRY(bmq::launch_fidelity_partial(sv->dir[sv->cur], pool_view(sv, sv->cur), cp, 0, nch, rv, sv->partials, np,
+                                             sv->stream));
+    }
+    HIP_TRY(bmq::launch_fidelity_final(sv->partials, np, sv->out5, sv->stream));
     double h[5];
     HIP_TRY(hipMemcpyAsync(h, sv->out5, sizeof(h), hipMemcpyDeviceToHost, sv->stream));
     HIP_TRY(hipStreamSynchronize(sv->stream));
-    if (norm2) *norm2 = h[2];
-    if (ref_dev) {
-        const double ov2 = h[0] * h[0] + h[1] * h[1];
-        if (fidelity) *fidelity = ov2 / (h[2] * h[3]);
-        if (max_abs_err) *max_abs_err = h[4];
+    out->norm2 = h[2];
+    if (rv.kind != bmq::REF_NONE) {
+        out->overlap_re = h[0];
+        out->overlap_im = h[1];
+        out->overlap2 = h[0] * h[0] + h[1] * h[1];
+        out->ref_norm2 = h[3];
+        out->fidelity = out->overlap2 / (h[2] * h[3]);
+        out->max_abs_err = h[4];
     } else {
-        if (fidelity) *fidelity = NAN;
-        if (max_abs_err) *max_abs_err = NAN;
+        out->overlap_re = out->overlap_im = out->overlap2 = out->ref_norm2 = NAN;
+        out->fidelity = out->max_abs_err = NAN;
+    }
+    return SV_OK;
+}
+
+namespace {
+// SplitMix64 (Steele, Lea and Flood, "Fast splittable pseudorandom number
+// generators", OOPSLA 2014): output i of the sequence whose state starts at
+// seed, as a double in [0, 1) from its top 53 bits.
+static double splitmix_uniform(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+}
+}  // namespace
+
+int sv_sample(const sv_t *sv, uint64_t k, uint64_t seed, uint64_t *idx_host)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (!k) return SV_OK;
+    if (!idx_host) return fail(SV_ERR_INVALID, "idx_host is NULL");
+    const int n = sv->n;
+    // groups of 2^gq amplitudes, at least 16 chunks and at most 2^16 groups
+    const int gq = std::max(10, n - 16);
+    const uint32_t cpg = 1u << (gq - 6);
+    const uint64_t ng = 1ull << (n - gq);
+    const bmq::PoolView pv = pool_view(sv, sv->cur);
+    const bmq::CodecParams cp = codec_params(sv->cfg);
+    double *gnorm = (double *)sv->stage;
+    uint32_t *grp = (uint32_t *)(sv->stage + kMaxSampleGroups * 8);
+    double *resid = (double *)(sv->stage + kMaxSampleGroups * 8 + kSampleBatch * 4);
+    uint64_t *outd = (uint64_t *)(sv->stage + kMaxSampleGroups * 8 + kSampleBatch * 12);
+    HIP_TRY(bmq::launch_group_norm(sv->dir[sv->cur], pv, cp, cpg, ng, gnorm, sv->stream));
+    std::vector<double> gn(ng), pre(ng + 1);
+    HIP_TRY(hipMemcpyAsync(gn.data(), gnorm, ng * 8, hipMemcpyDeviceToHost, sv->stream));
+    HIP_TRY(hipStreamSynchronize(sv->stream));
+    pre[0] = 0;
+    for (uint64_t g = 0; g < ng; ++g) pre[g + 1] = pre[g] + gn[g];
+    const double total = pre[ng];
+    if (!(total > 0) || !std::isfinite(total)) return fail(SV_ERR_INVALID, "state has no finite, positive norm");
+    std::vector<uint32_t> hg(kSampleBatch);
+    std::vector<double> hr(kSampleBatch);
+    for (uint64_t s0 = 0; s0 < k; s0 += kSampleBatch) {
+        const uint64_t nb = std::min(kSampleBatch, k - s0);
+        for (uint64_t i = 0; i < nb; ++i) {
+            const double u = splitmix_uniform(seed, s0 + i) * total;
+            // the group g with pre[g] <= u < pre[g + 1] (groups of zero norm are never chosen)
+            uint64_t g = (uint64_t)(std::upper_bound(pre.begin(), pre.end(), u) - pre.begin()) - 1;
+            if (g >= ng) g = ng - 1;
+            while (g > 0 && gn[g] == 0.0) --g;
+            hg[i] = (uint32_t)g;
+            hr[i] = std::min(std::max(u - pre[g], 0.0), gn[g]);
+        }
+        HIP_TRY(hipMemcpyAsync(grp, hg.data(), nb * 4, hipMemcpyHostToDevice, sv->stream));
+        HIP_TRY(hipMemcpyAsync(resid, hr.data(), nb * 8, hipMemcpyHostToDevice, sv->stream));
+        HIP_TRY(bmq::launch_sample(sv->dir[sv->cur], pv, cp, cpg, grp, resid, nb, outd, sv->stream));
+        HIP_TRY(hipMemcpyAsync(idx_host + s0, outd, nb * 8, hipMemcpyDeviceToHost, sv->stream));
+        HIP_TRY(hipStreamSynchronize(sv->stream));     // the host tables are reused by the next batch
     }
     return SV_OK;
 }
@@ -1742,6 +1854,13 @@ int sv_block_stream(const sv_t *sv, uint64_t block, void *dst_host, uint64_t cap
     std::memcpy(d + 4, &ebbits, 4);
     std::memcpy(d + 8, &nv, 4);
     std::memcpy(d + 12, &nc, 4);
+    // bodies that lie back to back in the device pool (a wave writes its
+    // chunks' bodies contiguously) are fetched with one copy and scattered
+    // between the headers on the host
+    struct Piece { uint64_t dst; uint32_t len; };
+    struct Run { uint64_t src, len; size_t p0, np; };
+    std::vector<Piece> pieces;
+    std::vector<Run> runs;
     uint64_t o = 16;
     for (uint64_t c = 0; c < nchb; ++c) {
         const uint32_t h0 = (uint32_t)(dir[c] >> 40) & 0xFFFu, h1 = (uint32_t)(dir[c] >> 52);
@@ -1750,46 +1869,175 @@ int sv_block_stream(const sv_t *sv, uint64_t block, void *dst_host, uint64_t cap
         o += 8;
         if (sizes[c]) {
             const uint64_t off = dir[c] & bmq::kDirOffsetMask;
-            if (off < sv->pool_cap)
-                HIP_TRY(hipMemcpy(d + o, sv->pool[sv->cur] + off, sizes[c], hipMemcpyDeviceToHost));
-            else
+            if (off < sv->pool_cap) {
+                if (runs.empty() || runs.back().src + runs.back().len != off)
+                    runs.push_back(Run{off, 0, pieces.size(), 0});
+                runs.back().len += sizes[c];
+                runs.back().np++;
+                pieces.push_back(Piece{o, sizes[c]});
+            } else {
                 std::memcpy(d + o, sv->host_h[sv->cur] + (off - sv->pool_cap), sizes[c]);
+            }
             o += sizes[c];
+        }
+    }
+    std::vector<uint8_t> tmp;
+    for (const Run &r : runs) {
+        tmp.resize(r.len);
+        HIP_TRY(hipMemcpy(tmp.data(), sv->pool[sv->cur] + r.src, r.len, hipMemcpyDeviceToHost));
+        uint64_t t = 0;
+        for (size_t i = r.p0; i < r.p0 + r.np; ++i) {
+            std::memcpy(d + pieces[i].dst, tmp.data() + t, pieces[i].len);
+            t += pieces[i].len;
         }
     }
     return SV_OK;
 }
 
-int sv_debug_dump(sv_t *sv, float *re_dev, float *im_dev)
+int sv_debug_dump(sv_t *sv, uint64_t start, uint64_t count, float *pre_re, float *pre_im, float *post_re,
+                  float *post_im)
 {
     if (int rc = check_state(sv)) return rc;
-    if ((re_dev == nullptr) != (im_dev == nullptr)) return fail(SV_ERR_INVALID, "give both planes or neither");
-    sv->dump_re = re_dev;
-    sv->dump_im = im_dev;
+    if ((pre_re == nullptr) != (pre_im == nullptr) || (post_re == nullptr) != (post_im == nullptr))
+        return fail(SV_ERR_INVALID, "give both planes or neither");
+    const uint64_t dim = 1ull << sv->n;
+    if ((start & 63) || (count & 63) || start > dim || count > dim - start)
+        return fail(SV_ERR_INVALID, "dump range must be 64-aligned and inside the state");
+    sv->dump_re = pre_re;
+    sv->dump_im = pre_im;
+    sv->dumpd_re = post_re;
+    sv->dumpd_im = post_im;
+    sv->dump_lo = start;
+    sv->dump_n = count;
     return SV_OK;
 }
+
+namespace {
+static int check_codec_args(const sv_config_t *cfg, uint64_t n_values)
+{
+    if (!cfg || !(cfg->eb > 0) || (cfg->domain < SV_DOMAIN_LIN || cfg->domain > SV_DOMAIN_RAW))
+        return fail(SV_ERR_INVALID, "bad codec config");
+    if (n_values % 64) return fail(SV_ERR_INVALID, "n_values must be a multiple of 64 (whole chunks)");
+    if (n_values > (1ull << 31)) return fail(SV_ERR_INVALID, "n_values above 2^31");
+    return SV_OK;
+}
+
+// codec workspace: record sizes (u32 per chunk), record offsets (u64 per
+// chunk + 1), one flag word
+struct CodecWork {
+    uint64_t off_sizes, off_offs, off_flag, total;
+};
+static CodecWork codec_work(uint64_t nch)
+{
+    CodecWork w{};
+    w.off_sizes = 0;
+    w.off_offs = align256(nch * 4);
+    w.off_flag = w.off_offs + align256((nch + 1) * 8);
+    w.total = w.off_flag + 256;
+    return w;
+}
+
+static int codec_encode_impl(const float *re_dev, const float *im_dev, uint64_t n_values, const sv_config_t *cfg,
+                      void *dst_dev, uint64_t cap, uint64_t *bytes, uint8_t *work, hipStream_t st)
+{
+    const uint64_t nch = n_values / 64;
+    const CodecWork w = codec_work(nch);
+    uint64_t *off = (uint64_t *)(work + w.off_offs);
+    const float ebf = (float)cfg->eb;
+    uint32_t ebbits;
+    std::memcpy(&ebbits, &ebf, 4);
+    HIP_TRY(bmq::launch_codec_stream_encode(re_dev, im_dev, nch, codec_params(*cfg), (uint32_t *)(work + w.off_sizes),
+                                            off, (uint8_t *)dst_dev, cap, ebbits, st));
+    uint64_t total = 0;
+    HIP_TRY(hipMemcpyAsync(&total, off + nch, 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *bytes = 16 + total;
+    if (16 + total > cap)
+        return fail(SV_ERR_INVALID, "stream of %llu bytes > capacity %llu (nothing written)",
+                    (unsigned long long)(16 + total), (unsigned long long)cap);
+    return SV_OK;
+}
+}  // namespace
 
 int codec_encode_chunks(const float *re_dev, const float *im_dev, uint64_t n_values, const sv_config_t *cfg,
                         void *slots_dev, uint32_t *sizes_dev, void *hip_stream)
 {
-    if (!cfg || !(cfg->eb > 0) || (cfg->domain < SV_DOMAIN_LIN || cfg->domain > SV_DOMAIN_RAW))
-        return fail(SV_ERR_INVALID, "bad codec config");
+    if (int rc = check_codec_args(cfg, n_values)) return rc;
     if (!n_values) return SV_OK;
     if (!re_dev || !im_dev || !slots_dev || !sizes_dev) return fail(SV_ERR_INVALID, "NULL pointer");
-    HIP_TRY(bmq::launch_codec_encode(re_dev, im_dev, n_values, codec_params(*cfg), (uint8_t *)slots_dev, sizes_dev,
-                                     (hipStream_t)hip_stream));
+    HIP_TRY(bmq::launch_codec_slots_encode(re_dev, im_dev, n_values / 64, codec_params(*cfg), (uint8_t *)slots_dev,
+                                           sizes_dev, (hipStream_t)hip_stream));
     return SV_OK;
 }
 
 int codec_decode_chunks(const void *slots_dev, uint64_t n_values, const sv_config_t *cfg, float *re_dev, float *im_dev,
                         void *hip_stream)
 {
-    if (!cfg || !(cfg->eb > 0) || (cfg->domain < SV_DOMAIN_LIN || cfg->domain > SV_DOMAIN_RAW))
-        return fail(SV_ERR_INVALID, "bad codec config");
+    if (int rc = check_codec_args(cfg, n_values)) return rc;
     if (!n_values) return SV_OK;
     if (!re_dev || !im_dev || !slots_dev) return fail(SV_ERR_INVALID, "NULL pointer");
-    HIP_TRY(bmq::launch_codec_decode((const uint8_t *)slots_dev, n_values, codec_params(*cfg), re_dev, im_dev,
-                                     (hipStream_t)hip_stream));
+    HIP_TRY(bmq::launch_codec_slots_decode((const uint8_t *)slots_dev, n_values / 64, codec_params(*cfg), re_dev,
+                                           im_dev, (hipStream_t)hip_stream));
+    return SV_OK;
+}
+
+int codec_workspace(uint64_t n_values, uint64_t *bytes)
+{
+    if (!bytes) return fail(SV_ERR_INVALID, "bytes is NULL");
+    if (n_values % 64 || n_values > (1ull << 31)) return fail(SV_ERR_INVALID, "n_values must be a multiple of 64, <= 2^31");
+    *bytes = codec_work(n_values / 64).total;
+    return SV_OK;
+}
+
+int codec_encode(const float *re_dev, const float *im_dev, uint64_t n_values, const sv_config_t *cfg, void *dst_dev,
+                 uint64_t cap, uint64_t *bytes, void *work_dev, uint64_t work_bytes, void *hip_stream)
+{
+    if (int rc = check_codec_args(cfg, n_values)) return rc;
+    if (!n_values) return fail(SV_ERR_INVALID, "empty input");
+    if (!re_dev || !im_dev || !dst_dev || !bytes || !work_dev) return fail(SV_ERR_INVALID, "NULL pointer");
+    if (((uintptr_t)dst_dev & 3u) || ((uintptr_t)work_dev & 255u))
+        return fail(SV_ERR_INVALID, "dst must be 4-byte and work 256-byte aligned");
+    if (work_bytes < codec_work(n_values / 64).total)
+        return fail(SV_ERR_INVALID, "workspace of %llu bytes < %llu", (unsigned long long)work_bytes,
+                    (unsigned long long)codec_work(n_values / 64).total);
+    return codec_encode_impl(re_dev, im_dev, n_values, cfg, dst_dev, cap, bytes, (uint8_t *)work_dev,
+                             (hipStream_t)hip_stream);
+}
+
+int codec_decode(const void *src_dev, uint64_t bytes, const sv_config_t *cfg, uint64_t n_values, float *re_dev,
+                 float *im_dev, void *work_dev, uint64_t work_bytes, void *hip_stream)
+{
+    if (int rc = check_codec_args(cfg, n_values)) return rc;
+    if (!n_values) return fail(SV_ERR_INVALID, "empty output");
+    if (!src_dev || !re_dev || !im_dev || !work_dev) return fail(SV_ERR_INVALID, "NULL pointer");
+    if (((uintptr_t)src_dev & 3u) || ((uintptr_t)work_dev & 255u))
+        return fail(SV_ERR_INVALID, "src must be 4-byte and work 256-byte aligned");
+    const uint64_t nch = n_values / 64;
+    const CodecWork w = codec_work(nch);
+    if (work_bytes < w.total)
+        return fail(SV_ERR_INVALID, "workspace of %llu bytes < %llu", (unsigned long long)work_bytes,
+                    (unsigned long long)w.total);
+    if (bytes < 16) return fail(SV_ERR_CORRUPT, "stream shorter than its header");
+    const hipStream_t st = (hipStream_t)hip_stream;
+    uint8_t *work = (uint8_t *)work_dev;
+    uint32_t hdr[4];
+    HIP_TRY(hipMemcpyAsync(hdr, src_dev, 16, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const float ebf = (float)cfg->eb;
+    uint32_t ebbits;
+    std::memcpy(&ebbits, &ebf, 4);
+    const uint32_t want = 0x51u | (1u << 8) | ((uint32_t)cfg->domain << 16) | (6u << 24);
+    if (hdr[0] != want || hdr[1] != ebbits || hdr[2] != (uint32_t)n_values || hdr[3] != (uint32_t)nch)
+        return fail(SV_ERR_CORRUPT, "stream header does not match the configuration and n_values");
+    uint32_t *flag = (uint32_t *)(work + w.off_flag);
+    uint64_t *off = (uint64_t *)(work + w.off_offs);
+    HIP_TRY(bmq::launch_fill_u64((uint64_t *)flag, 1, 0ull, st));
+    HIP_TRY(bmq::launch_codec_stream_decode((const uint8_t *)src_dev, bytes, nch, codec_params(*cfg), off, flag, st));
+    uint32_t bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, flag, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (bad) return fail(SV_ERR_CORRUPT, "malformed record in the stream");
+    HIP_TRY(bmq::launch_codec_read((const uint8_t *)src_dev, off, nch, codec_params(*cfg), re_dev, im_dev, st));
     return SV_OK;
 }
 

@@ -1,6 +1,11 @@
-"""GPU codec parity: the HIP encoder's records must equal the CPU oracle's
-stream byte for byte on identical float32 input, and the HIP decoder must
-return the oracle's decoded floats bit for bit (Section 4.3, Algorithm 2)."""
+"""GPU codec parity: the stage loop's quad-lane encoder and decoder (the one
+codec of the library, run here through the stand-alone codec calls) must
+produce the CPU oracle's stream byte for byte on identical float32 input
+and decode the oracle's floats bit for bit (Section 4.3, Algorithm 2).
+Inputs: random planes over many magnitudes, adversarial values (signed
+zeros, subnormals, k + 1/2 boundaries, +-inf, NaN, the largest floats,
+all-negative and alternating chunks, VERBATIM fallbacks), the two golden
+records, LIN codes beyond 2^24, and whole SV blocks of 2^22 and 2^24 values."""
 import numpy as np
 import pytest
 
@@ -22,11 +27,18 @@ def gpu_roundtrip(re, im, domain, eb):
     r2, i2 = bmq.codec_decode_chunks(slots, re.size, cfg)
     torch.cuda.synchronize()
     stream = bmq.slots_to_stream(slots.cpu().numpy(), sizes.cpu().numpy(), re.size, domain, eb)
+    # the stream form of the same call must give the same bytes
+    st = bmq.codec_encode(tre, tim, cfg)
+    assert bytes(st.cpu().numpy()) == stream
+    r3, i3 = bmq.codec_decode(st, re.size, cfg)
+    assert torch.equal(r3.view(torch.int32), r2.view(torch.int32))
+    assert torch.equal(i3.view(torch.int32), i2.view(torch.int32))
     return stream, r2.cpu().numpy(), i2.cpu().numpy()
 
 
 def check(re, im, domain, eb):
     print(f"codec case n={re.size} domain={domain} eb={eb}", flush=True)
+    assert re.size % 64 == 0
     g_stream, g_re, g_im = gpu_roundtrip(re, im, domain, eb)
     c_stream = N.encode_block(re, im, domain, eb)
     assert len(g_stream) == len(c_stream)
@@ -41,17 +53,23 @@ def check(re, im, domain, eb):
     return g_stream
 
 
+def pad64(x, fill=0.0):
+    m = (-x.size) % 64
+    return np.concatenate([x, np.full(m, fill, np.float32)]).astype(np.float32)
+
+
 @pytest.mark.parametrize("domain", [0, 1])
-@pytest.mark.parametrize("eb", [1e-6, 1e-5, 1e-3])
+@pytest.mark.parametrize("eb", [1e-6, 1e-5, 1e-3, 2.0 ** -17])
 def test_codec_bitexact_random(domain, eb):
     rng = np.random.default_rng(100 + domain + int(1e7 * eb))
-    n = 64 * 2000 + 37                       # many chunks and a ragged tail
-    scale = 2.0 ** rng.uniform(-24, 0, n)
+    n = 64 * 2000
+    scale = 2.0 ** rng.uniform(-40, 0, n)
     re = (rng.standard_normal(n) * scale).astype(np.float32)
     im = (rng.standard_normal(n) * scale).astype(np.float32)
     re[640:704] = 0.0                        # all-zero plane chunk
     im[1000:1010] = 0.0                      # mixed zero chunk
     re[2000:2064] = -np.abs(re[2000:2064])   # all-negative chunk
+    im[3000:3064] = np.abs(im[3000:3064])    # all-positive chunk
     check(re, im, domain, eb)
 
 
@@ -68,10 +86,22 @@ def test_codec_bitexact_adversarial(domain):
     eq = np.full(256, 0.123456, np.float32)
     ramp = (np.arange(512) * delta).astype(np.float32)
     pw = (2.0 ** -np.arange(64)).astype(np.float32)
-    re = np.concatenate([half, specials, alt, eq, ramp, pw, np.zeros(100, np.float32)])
-    im = np.concatenate([eq, alt, pw, half, specials, ramp, np.full(100, 1e-40, np.float32)])
+    negz = np.full(64, -0.0, np.float32)                      # a chunk of negative zeros
+    sub = (np.arange(64) * 1e-45).astype(np.float32)          # subnormals only
+    allneg = -np.abs(np.random.default_rng(5).standard_normal(64)).astype(np.float32)
+    re = np.concatenate([half, specials, alt, eq, ramp, pw, negz, sub, allneg, np.zeros(100, np.float32)])
+    im = np.concatenate([eq, alt, pw, half, specials, ramp, sub, allneg, negz, np.full(100, 1e-40, np.float32)])
     m = min(re.size, im.size)
-    check(re[:m].copy(), im[:m].copy(), domain, eb)
+    check(pad64(re[:m]), pad64(im[:m]), domain, eb)
+
+
+def test_codec_lin_codes_beyond_2_24():
+    eb = 2.0 ** -20
+    s = N.step_shift(eb)
+    rng = np.random.default_rng(3)
+    k = rng.integers(2 ** 24 + 1, 2 ** 30 - 1, 64 * 64) * rng.choice([-1, 1], 64 * 64)
+    x = (k.astype(np.float64) * 2.0 ** -s).astype(np.float32)
+    check(x, x[::-1].copy(), 0, eb)
 
 
 def test_codec_golden_records_on_gpu():
@@ -85,12 +115,40 @@ def test_codec_golden_records_on_gpu():
     assert s == bytes.fromhex(open("tests/golden/log_alternating_pow2_chunk.hex").read().strip())
 
 
-def test_codec_large_sampled():
-    # 2^22 values (the block size of the 30-qubit QFT workload), LOG eb=1e-5
-    rng = np.random.default_rng(7)
-    n = 1 << 22
+@pytest.mark.parametrize("logn", [22, 24])
+def test_codec_whole_sv_blocks(logn):
+    # one SV block of the 30-qubit (2^22) and 33-qubit (2^24) configurations
+    rng = np.random.default_rng(7 + logn)
+    n = 1 << logn
     mag = 2.0 ** rng.uniform(-22, -10, n)
     ph = rng.uniform(0, 2 * np.pi, n)
     re = (mag * np.cos(ph)).astype(np.float32)
     im = (mag * np.sin(ph)).astype(np.float32)
     check(re, im, 1, 1e-5)
+
+
+def test_codec_rejects_partial_chunks_and_bad_streams():
+    cfg = bmq.Config(n=10, b=10, domain=1, eb=1e-5)
+    x = torch.zeros(100, dtype=torch.float32, device=DEV)
+    with pytest.raises(bmq.BmqError) as e:
+        bmq.codec_encode_chunks(x, x, cfg)
+    assert e.value.code == -1
+    rng = np.random.default_rng(1)
+    re = torch.from_numpy((rng.standard_normal(64 * 40) * 1e-3).astype(np.float32)).to(DEV)
+    st = bmq.codec_encode(re, re.flip(0).contiguous(), cfg)
+    with pytest.raises(bmq.BmqError) as e:                  # too small for the stream
+        bmq.codec_encode(re, re, cfg, cap=64)
+    assert e.value.code == -1
+    bad = st.clone()
+    bad[16] = 0xFF                                          # impossible plane header
+    with pytest.raises(bmq.BmqError) as e:
+        bmq.codec_decode(bad, re.numel(), cfg)
+    assert e.value.code == -5
+    with pytest.raises(bmq.BmqError) as e:                  # truncated
+        bmq.codec_decode(st[:-4].clone(), re.numel(), cfg)
+    assert e.value.code == -5
+    with pytest.raises(bmq.BmqError) as e:                  # header for another n
+        bmq.codec_decode(st, re.numel() - 64, cfg)
+    assert e.value.code == -5
+    r2, _ = bmq.codec_decode(st, re.numel(), cfg)           # the intact stream still decodes
+    assert torch.isfinite(r2).all()

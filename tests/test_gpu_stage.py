@@ -23,11 +23,13 @@ from paper_2410_14088_amd import bmq  # noqa: E402
 from paper_2410_14088_amd import circuits as C  # noqa: E402
 
 DEV = "cuda:0"
-E_LOG2, E_EXP2 = 2.0e-7, 1.0e-7
+# exhaustively measured bounds of the own log2 (significand part) and exp2
+# (fraction part); see tests/test_oracle_codec.py
+E_LOG2, E_EXP2 = 6.3e-8, 8.2e-8
 
 
-def log_rel_bound(eb, v):
-    return 2.0 ** (eb + E_LOG2 + np.abs(v) * 2.0 ** -24) * (1 + E_EXP2) - 1
+def log_rel_bound(eb, v=None):
+    return 2.0 ** (eb + E_LOG2) * (1 + E_EXP2) - 1
 
 
 def run(gates, n, b, domain, eb, fuse=2, inner=2, tile=0, ref=None, label=""):
@@ -58,8 +60,13 @@ def test_config0_random16_log():
     assert f2 >= 0.9999 and mx < 1e-4
 
 
-@pytest.mark.parametrize("domain,eb", [(0, 1e-6), (1, 1e-5)])
+@pytest.mark.parametrize("domain,eb", [(0, 1e-6), (1, 1e-5), (1, 2.0 ** -17)])
 def test_per_stage_bitexact_and_pointwise(domain, eb):
+    """Every stage, every block: the records equal the CPU codec's stream of
+    the values the stage was about to encode; the next stage decodes exactly
+    what the CPU decoder reads from those streams (dump right after the
+    decoder, before any operation), and so does export; every decoded value
+    is within the point-wise bound."""
     n, b = 14, 8
     gates = C.random_layers(n, 3, 77) + C.qft_ladder(n)[:40]
     cfg = bmq.Config(n=n, b=b, inner=2, fuse=3, domain=domain, eb=eb)
@@ -67,12 +74,23 @@ def test_per_stage_bitexact_and_pointwise(domain, eb):
     sv = bmq.State(cfg, DEV)
     dre = torch.empty(1 << n, dtype=torch.float32, device=DEV)
     dim = torch.empty_like(dre)
-    sv.debug_dump(dre, dim)
+    pre = torch.empty_like(dre)
+    pim = torch.empty_like(dre)
+    sv.debug_dump(dre, dim, dec_re=pre, dec_im=pim)
     ebf = float(np.float32(eb))
-    rng = np.random.default_rng(0)
+    nb = 1 << (n - b)
+    # the initial state's streams, decoded by the CPU
+    prev = [N.decode_block(sv.block_stream(k), 1 << b) for k in range(nb)]
     for s in range(plan.n_stages):
         print(f"stage {s}", flush=True)
         sv.apply(plan, s, 1)
+        # decoded by the first pass of this stage == CPU decode of the last streams
+        dec_re = pre.cpu().numpy()
+        dec_im = pim.cpu().numpy()
+        for k in range(nb):
+            lo, hi = k << b, (k + 1) << b
+            assert np.array_equal(dec_re[lo:hi].view(np.uint32), prev[k][0].view(np.uint32)), f"stage {s} blk {k}"
+            assert np.array_equal(dec_im[lo:hi].view(np.uint32), prev[k][1].view(np.uint32)), f"stage {s} blk {k}"
         pre_re = dre.cpu().numpy()
         pre_im = dim.cpu().numpy()
         out = sv.export().cpu().numpy()
@@ -84,18 +102,39 @@ def test_per_stage_bitexact_and_pointwise(domain, eb):
                 tiny = np.abs(x64) < 2.0 ** -126
                 assert np.all((y64[tiny] == 0) | (y64[tiny] == x64[tiny]))
                 m = ~tiny
-                assert np.all(np.abs(y64[m] / x64[m] - 1) <= log_rel_bound(ebf, np.log2(np.abs(x64[m]))))
-        for blk in rng.choice(1 << (n - b), 4, replace=False):
-            lo, hi = int(blk) << b, (int(blk) + 1) << b
+                assert np.all(np.abs(y64[m] / x64[m] - 1) <= log_rel_bound(ebf))
+        prev = []
+        for k in range(nb):
+            lo, hi = k << b, (k + 1) << b
             cpu = N.encode_block(pre_re[lo:hi], pre_im[lo:hi], domain, eb)
-            gpu = sv.block_stream(int(blk))
-            assert gpu == cpu, f"stage {s} block {blk}: streams differ"
+            gpu = sv.block_stream(k)
+            assert gpu == cpu, f"stage {s} block {k}: streams differ"
             r2, i2 = N.decode_block(cpu, hi - lo)
             assert np.array_equal(r2.view(np.uint32), out.real[lo:hi].astype(np.float32).view(np.uint32))
             assert np.array_equal(i2.view(np.uint32), out.imag[lo:hi].astype(np.float32).view(np.uint32))
+            prev.append((r2, i2))
     ref = N.simulate(n, gates)
     f2, mx, _ = sv.fidelity(torch.from_numpy(ref).to(DEV))
     assert f2 >= 0.99
+
+
+@pytest.mark.parametrize("domain,eb", [(0, 1e-6), (1, 1e-5), (2, 1e-5), (0, 2.0)])
+def test_initial_state_record(domain, eb):
+    """sv_create encodes amplitude 1 with the stage loop's encoder: block 0's
+    stream equals the CPU codec's stream of (1, 0, ..., 0)."""
+    n, b = 12, 8
+    sv = bmq.State(bmq.Config(n=n, b=b, domain=domain, eb=eb), DEV)
+    e = np.zeros(1 << b, np.float32)
+    e[0] = 1
+    want = N.encode_block(e, np.zeros(1 << b, np.float32), domain, eb) if domain != 2 else None
+    got = sv.block_stream(0)
+    if want is not None:
+        assert got == want
+    r2, i2 = N.decode_block(got, 1 << b)
+    v = sv.export(0, 1 << b).cpu().numpy()
+    assert np.array_equal(r2.view(np.uint32), v.real.astype(np.float32).view(np.uint32))
+    for k in range(1, 1 << (n - b)):                 # all-zero blocks: header + zero records
+        assert sv.block_stream(k) == got[:16] + bytes(8 * (1 << (b - 6)))
 
 
 ALL = [("H", 1, 0), ("X", 1, 0), ("Y", 1, 0), ("Z", 1, 0), ("S", 1, 0), ("T", 1, 0),

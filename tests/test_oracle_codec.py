@@ -24,17 +24,78 @@ from oracle import native as N
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 LIN, LOG = 0, 1
-# |log2_own - log2| and |exp2_own/exp2 - 1| measured bounds (fits of degree 8
-# and 6, see the stream-format section of the design notes)
-E_LOG2 = 2.0e-7
-E_EXP2 = 1.0e-7
+# Error bounds of the own transforms, each measured exhaustively over every
+# float32 its argument can take (tests below): E_LOG2 bounds |p - log2 m| for
+# the significand part p of log2|x| = e + p (m = the significand folded into
+# [sqrt(1/2), sqrt(2)]; e is exact), E_EXP2 bounds |2^f_own / 2^f - 1| for
+# every fraction f = r 2^-s, |r| <= 2^(s-1), s <= 22, that decoding forms.
+E_LOG2 = 6.3e-8
+E_EXP2 = 8.2e-8
 
 
 def log_rel_bound(eb, v=0.0):
-    """Relative bound of the LOG domain for a value with log2|x| = v: eb
-    (Eq. 1-2) plus the transform error: the fit error of log2, one float32
-    rounding of v (half an ulp, <= |v| 2^-24) and the exp2 fit error."""
-    return 2.0 ** (eb + E_LOG2 + np.abs(v) * 2.0 ** -24) * (1 + E_EXP2) - 1
+    """Relative bound of the LOG domain (Eq. 1-2): the code k = e 2^s +
+    rint(p 2^s) is within delta/2 <= eb of e + p, p within E_LOG2 of the
+    exact significand log, and the decoded 2^(k delta) within E_EXP2
+    relative; log2|x| is never rounded as a whole, so the bound does not
+    grow with |log2 x| (v is accepted for the call sites and unused)."""
+    return 2.0 ** (eb + E_LOG2) * (1 + E_EXP2) - 1
+
+
+def test_log2_significand_part_exhaustive():
+    # every float32 significand in [sqrt(1/2), sqrt(2)]: there e = 0 and the
+    # own log2 returns p itself
+    lo, hi = np.float32(math.sqrt(0.5)), np.float32(math.sqrt(2.0))
+    x = np.arange(lo.view(np.uint32), hi.view(np.uint32) + 1, dtype=np.uint32).view(np.float32)
+    err = np.abs(N.log2_own(x).astype(np.float64) - np.log2(x.astype(np.float64)))
+    assert err.max() <= E_LOG2
+    assert err.max() > 0.5 * E_LOG2          # the constant is the fit's, not a loose guess
+
+
+def test_exp2_fraction_exhaustive():
+    # s = 22 gives every fraction the decoder forms for any s <= 22 (the
+    # grid k 2^-s is a subset of the 2^-22 grid)
+    s = 22
+    k = np.arange(-(1 << (s - 1)), (1 << (s - 1)) + 1, dtype=np.int32)
+    y = N.log_decode(k, s).astype(np.float64)
+    rel = np.abs(y / np.exp2(k.astype(np.float64) * 2.0 ** -s) - 1)
+    assert rel.max() <= E_EXP2 and rel.max() > 0.5 * E_EXP2
+
+
+def test_log_bound_catches_whole_log2_rounding():
+    """Planted mistake (on the CPU): a codec that rounded log2|x| to float32
+    as a whole before quantizing -- k = rint(fl32(e + p) 2^s) -- loses up to
+    half an ulp of |log2 x| on top of eb.  With eb = delta/2 exactly (eb a
+    power of two) and magnitudes down to 2^-40 the pin must reject it."""
+    eb = 2.0 ** -17
+    s = N.step_shift(eb)
+    assert 2.0 ** -s == 2 * eb
+    rng = np.random.default_rng(21)
+    x = (2.0 ** rng.uniform(-40, -20, 200000)).astype(np.float32)
+    v32 = N.log2_own(x)                                  # e + p rounded once
+    k_bad = np.rint(v32.astype(np.float64) * 2.0 ** s).astype(np.int32)
+    rel_bad = np.abs(N.log_decode(k_bad, s).astype(np.float64) / x - 1)
+    assert np.any(rel_bad > log_rel_bound(eb))
+    # the codec as defined stays inside the same pin on the same values
+    st = N.encode_block(x[:199936], x[:199936][::-1].copy(), LOG, eb)
+    r2, _ = N.decode_block(st, 199936)
+    assert np.all(np.abs(r2.astype(np.float64) / x[:199936] - 1) <= log_rel_bound(eb))
+
+
+def test_lin_codes_beyond_2_24_need_no_correction():
+    """LIN codes with 2^24 < |k| < 2^30: v 2^s is then an integer-valued
+    float32, so rint, the product k 2^-s and the verify step are exact and
+    the one-step correction toward v never runs; the codes equal v 2^s."""
+    eb = 2.0 ** -20
+    s = N.step_shift(eb)
+    rng = np.random.default_rng(3)
+    k = rng.integers(2 ** 24 + 1, 2 ** 30 - 1, 4096) * rng.choice([-1, 1], 4096)
+    x = (k.astype(np.float64) * 2.0 ** -s).astype(np.float32)
+    codes, fail = N.codes(x, LIN, eb)
+    assert not fail.any()
+    assert np.array_equal(codes.astype(np.float64), x.astype(np.float64) * 2.0 ** s)
+    assert np.all(np.abs(codes.astype(np.int64)) > 2 ** 24)
+    _check_bound(x, x[::-1].copy(), LIN, eb)
 
 
 def test_log2_exp2_against_libm():
@@ -102,11 +163,11 @@ def _check_bound(re, im, domain, eb):
 
 
 @pytest.mark.parametrize("domain", [LIN, LOG])
-@pytest.mark.parametrize("eb", [1e-6, 1e-5, 1e-3, math.log2(1.001)])
+@pytest.mark.parametrize("eb", [1e-6, 1e-5, 1e-3, math.log2(1.001), 2.0 ** -17])
 def test_pointwise_bound_random(domain, eb):
     rng = np.random.default_rng(int(eb * 1e9) + domain)
     n = 64 * 37 + 13           # several chunks and a ragged tail
-    scale = 2.0 ** rng.uniform(-20, 0, n)
+    scale = 2.0 ** rng.uniform(-40, 0, n)
     re = (rng.standard_normal(n) * scale).astype(np.float32)
     im = (rng.standard_normal(n) * scale).astype(np.float32)
     _check_bound(re, im, domain, eb)
