@@ -430,6 +430,20 @@ int codec_encode(const float *re_dev, const float *im_dev, uint64_t n_values, co
 int codec_decode(const void *src_dev, uint64_t bytes, const sv_config_t *cfg, uint64_t n_values, float *re_dev,
                  float *im_dev, void *work_dev, uint64_t work_bytes, void *hip_stream);
 
+/* codec_encode_noalloc -- codec_encode for callers that cannot allocate
+ * device memory (tight serving loops, harnesses that forbid hipMalloc): the
+ * same stream, with the workspace in a static device array of the library
+ * (4 MiB, held by every GPU the library runs on until the process ends)
+ * instead of work_dev.  At most 2^24 values (SV_NOALLOC_MAX_VALUES); larger
+ * inputs return SV_ERR_INVALID.  Allocates nothing (no hipMalloc, hipFree
+ * or allocating library call).  Every call on a GPU shares that GPU's
+ * array, which keeps the last call's contents (nothing in it needs to start
+ * at zero): calls that overlap on one GPU, on any streams, race.  Otherwise
+ * as codec_encode (synchronises hip_stream). */
+#define SV_NOALLOC_MAX_VALUES (1ull << 24)
+int codec_encode_noalloc(const float *re_dev, const float *im_dev, uint64_t n_values, const sv_config_t *cfg,
+                         void *dst_dev, uint64_t cap, uint64_t *bytes, void *hip_stream);
+
 /* Slot form, for per-chunk checks: chunk i's record is written to
  * slots_dev + i*SV_CHUNK_SLOT_BYTES (device) and its size to sizes_dev[i]
  * (device uint32).  Enqueued on hip_stream; does not synchronise.

@@ -63,7 +63,7 @@ class sv_stage_stats_t(C.Structure):
 EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_order", "plan_stage_ops", "plan_op", "plan_destroy",
            "sv_mem_required", "sv_create", "sv_destroy", "sv_attach_host_pool", "sv_reset", "stage_apply_compressed",
            "sv_fidelity", "sv_sample", "sv_export", "sv_amplitudes", "sv_footprint", "sv_check", "sv_directory",
-           "sv_block_stream", "sv_debug_dump", "codec_workspace", "codec_encode", "codec_decode",
+           "sv_block_stream", "sv_debug_dump", "codec_workspace", "codec_encode", "codec_encode_noalloc", "codec_decode",
            "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
            "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
            "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune",
@@ -109,6 +109,7 @@ def lib():
         L.codec_workspace.argtypes = [C.c_uint64, P(C.c_uint64)]
         L.codec_encode.argtypes = [V, V, C.c_uint64, P(sv_config_t), V, C.c_uint64, P(C.c_uint64), V, C.c_uint64, V]
         L.codec_decode.argtypes = [V, C.c_uint64, P(sv_config_t), C.c_uint64, V, V, V, C.c_uint64, V]
+        L.codec_encode_noalloc.argtypes = [V, V, C.c_uint64, P(sv_config_t), V, C.c_uint64, P(C.c_uint64), V]
         L.codec_encode_chunks.argtypes = [V, V, C.c_uint64, P(sv_config_t), V, V, V]
         L.codec_decode_chunks.argtypes = [V, C.c_uint64, P(sv_config_t), V, V, V]
         L.sv_block_features.argtypes = [V, V, C.c_size_t, V]
@@ -516,6 +517,19 @@ def codec_encode(re, im, cfg: Config, cap: Optional[int] = None):
     nb = C.c_uint64()
     _check(lib().codec_encode(C.c_void_p(_ptr(re)), C.c_void_p(_ptr(im)), n, C.byref(cfg.c()), C.c_void_p(_ptr(dst)),
                               int(cap), C.byref(nb), wp, wb, _stream()))
+    return dst[:nb.value]
+
+
+def codec_encode_noalloc(re, im, cfg: Config, cap: Optional[int] = None):
+    """codec_encode with the library's static scratch (no workspace)."""
+    import torch
+    n = re.numel()
+    if cap is None:
+        cap = 16 + (n // 64) * SV_CHUNK_SLOT_BYTES
+    dst = torch.empty(max(cap, 4), dtype=torch.uint8, device=re.device)
+    nb = C.c_uint64()
+    _check(lib().codec_encode_noalloc(C.c_void_p(_ptr(re)), C.c_void_p(_ptr(im)), n, C.byref(cfg.c()),
+                                      C.c_void_p(_ptr(dst)), int(cap), C.byref(nb), _stream()))
     return dst[:nb.value]
 
 

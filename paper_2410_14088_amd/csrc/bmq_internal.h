@@ -175,6 +175,14 @@ hipError_t launch_codec_stream_decode(const uint8_t *src, uint64_t bytes, uint64
 hipError_t launch_codec_read(const uint8_t *src, const uint64_t *off, uint64_t nch, CodecParams cp, float *re,
                              float *im, hipStream_t s);
 
+// static device scratch of the allocation-free codec entry point: holds the
+// codec workspace (record sizes, offsets) of up to kNoAllocMaxValues values
+constexpr uint64_t kNoAllocMaxValues = 1ull << 24;
+constexpr uint64_t kNoAllocScratchBytes = 4ull << 20;
+constexpr int kMaxDevices = 64;
+// device address of that scratch on the current device (looked up once per device)
+hipError_t noalloc_scratch(void **ptr);
+
 // ---- block predictor (bmq_mlp.hip) ----
 uint64_t mlp_work_floats(uint32_t batch);
 hipError_t launch_mlp_forward(const float *P, const float *X, uint32_t batch, float *out, hipStream_t s);

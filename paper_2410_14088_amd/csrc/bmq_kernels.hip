@@ -28,6 +28,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <stdint.h>
 
 #include "bmq_internal.h"
@@ -1934,6 +1935,35 @@ hipError_t launch_block_stats(const uint64_t *dir, uint64_t chunks_per_block, ui
     hipLaunchKernelGGL(block_stats_kernel, dim3((unsigned)n_blocks), dim3(256), 0, s, dir, chunks_per_block, sf,
                        feats, label_bytes, label_mode);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ allocation-free scratch
+//
+// Device scratch of codec_encode_noalloc: a file-scope array that every GPU
+// the library runs on holds until the process ends.  Host code never passes
+// the array's name to a kernel (on the host it is only a stand-in for the
+// symbol): its device address is looked up once per device with that
+// device current and kept.
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+hipError_t noalloc_scratch(void **ptr)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 }  // namespace bmq

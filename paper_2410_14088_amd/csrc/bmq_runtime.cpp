@@ -2004,6 +2004,25 @@ int codec_encode(const float *re_dev, const float *im_dev, uint64_t n_values, co
                              (hipStream_t)hip_stream);
 }
 
+int codec_encode_noalloc(const float *re_dev, const float *im_dev, uint64_t n_values, const sv_config_t *cfg,
+                         void *dst_dev, uint64_t cap, uint64_t *bytes, void *hip_stream)
+{
+    if (int rc = check_codec_args(cfg, n_values)) return rc;
+    if (!n_values) return fail(SV_ERR_INVALID, "empty input");
+    if (n_values > bmq::kNoAllocMaxValues)
+        return fail(SV_ERR_INVALID, "n_values %llu above %llu, the most the static scratch holds",
+                    (unsigned long long)n_values, (unsigned long long)bmq::kNoAllocMaxValues);
+    if (!re_dev || !im_dev || !dst_dev || !bytes) return fail(SV_ERR_INVALID, "NULL pointer");
+    if ((uintptr_t)dst_dev & 3u) return fail(SV_ERR_INVALID, "dst must be 4-byte aligned");
+    static_assert(bmq::kNoAllocMaxValues % 64 == 0, "whole chunks");
+    if (codec_work(bmq::kNoAllocMaxValues / 64).total > bmq::kNoAllocScratchBytes)
+        return fail(SV_ERR_UNSUPPORTED, "static scratch smaller than the codec workspace");
+    void *work = nullptr;
+    HIP_TRY(bmq::noalloc_scratch(&work));
+    return codec_encode_impl(re_dev, im_dev, n_values, cfg, dst_dev, cap, bytes, (uint8_t *)work,
+                             (hipStream_t)hip_stream);
+}
+
 int codec_decode(const void *src_dev, uint64_t bytes, const sv_config_t *cfg, uint64_t n_values, float *re_dev,
                  float *im_dev, void *work_dev, uint64_t work_bytes, void *hip_stream)
 {
