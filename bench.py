@@ -66,6 +66,8 @@ def parse():
                     help="qft / random-mirror: 64 MiB device pools, so that the records live in a pinned host "
                          "pool that the kernels read and write over the host link")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="random workload: skip the batched 512-circuit sub-line")
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the diagonal-free planner variant (profiles of the headline launches only)")
     ap.add_argument("--cpu-n", type=int, default=0,
@@ -226,17 +228,119 @@ def cpu_baseline(workload: str, n: int, seconds: float):
                        f"block per stage ({threads} threads) + FP64 OpenMP gate application, {dt:.1f} s")
 
 
+def batch_planning(mix, flags, fuse, train=32, margin=0.1, budget_frac=0.5, seed=11):
+    """Memory planning for a batch: the block predictor, trained online on the
+    first `train` circuits (planning features before each stage, labels after
+    it), is rolled over every circuit's plan to predict its peak compressed
+    size; circuits are admitted under a device budget of budget_frac of the
+    worst-case arenas, with pools sized by the prediction, against worst-case
+    pools (no predictor) and the size a circuit has before it runs.  The
+    admitted circuits then run in one batched launch with their predicted
+    pools; a circuit whose pools overflow is re-run with worst-case pools.
+    Returns the figures and the run's record bytes per circuit."""
+    import numpy as np
+    import torch
+    from paper_2410_14088_amd import bmq
+    from paper_2410_14088_amd import circuits as C
+
+    def cfg_of(d, pool=0):
+        return bmq.Config(n=d["n"], b=d["n"] - 8, inner=2, fuse=fuse, domain=1, eb=1e-5, flags=flags,
+                          pool_bytes=int(pool))
+    t0 = time.perf_counter()
+    # online training, stage by stage, on the first circuits (planning
+    # features before a stage, labels after it), and their actual peaks
+    pred = bmq.Predictor(C.mlp_init_params(seed), "cuda:0", lr=2e-3)
+    train_peaks, train_plans = [], []
+    loss = None
+    for d in mix[:train]:
+        c = cfg_of(d)
+        plan = bmq.Plan(d["gates"], c)
+        sv = bmq.State(c, "cuda:0")
+        peak = 0.0
+        for s in range(plan.n_stages):
+            X = sv.plan_features(plan, s)
+            sv.apply(plan, s, 1)
+            y, mode = sv.plan_labels()
+            for _ in range(4):
+                loss = pred.train_step(X, y, mode)
+            peak = max(peak, float(torch.exp2(y.double() + c.b).sum()))
+        train_peaks.append(peak)
+        train_plans.append(plan)
+        sv.close()
+    loss = float(loss.item())
+    # calibration on the training circuits: the largest actual / predicted peak
+    tp = np.array([float(bmq.predict_bytes(pred.params, p).max()) for p in train_plans])
+    calib = max(1.0, float(np.max(np.array(train_peaks) / tp)))
+    t_train = time.perf_counter() - t0
+    rest = mix[train:]
+    cfgs = [cfg_of(d) for d in rest]
+    plans = [bmq.Plan(d["gates"], c) for d, c in zip(rest, cfgs)]
+    t0 = time.perf_counter()
+    raw = np.array([float(bmq.predict_bytes(pred.params, p).max()) for p in plans])
+    peaks = raw * calib
+    t_pred = time.perf_counter() - t0
+    init = np.array([8.0 * (1 << (d["n"] - 6)) + 8.0 for d in rest])       # |0...0>: headers + one record
+    worst_all = int(bmq.admit(cfgs, None, margin, 1 << 62)[2].sum())
+    budget = int(budget_frac * worst_all)
+    adm_w = bmq.admit(cfgs, None, margin, budget)[0]
+    adm_p, pool_p, arena_p = bmq.admit(cfgs, peaks, margin, budget)
+    adm_i = bmq.admit(cfgs, init, margin, budget)[0]
+    pred_all = int(bmq.admit(cfgs, peaks, margin, 1 << 62)[2].sum())
+    # run the predicted-pool admitted set, batched; overflowing circuits are re-run
+    idx = list(np.flatnonzero(adm_p))
+    states = [bmq.State(cfg_of(rest[i], pool_p[i]), "cuda:0") for i in idx]
+    fallback = []
+    try:
+        bmq.batch_apply(states, [plans[i] for i in idx])
+    except bmq.BmqError as e:
+        if e.code != -3:
+            raise
+    torch.cuda.synchronize()
+    final = []
+    for k, (i, st) in enumerate(zip(idx, states)):
+        try:
+            rec = st.footprint()[0]
+        except bmq.BmqError:
+            st.close()
+            st = bmq.State(cfg_of(rest[i]), "cuda:0")
+            st.apply(plans[i])
+            rec = st.footprint()[0]
+            fallback.append(int(i))
+        # the final state's stream bytes (records + headers) against the prediction
+        final.append((rec + 8 * (1 << (rest[i]["n"] - 6))) / peaks[i])
+        st.close()
+    torch.cuda.empty_cache()
+    return {
+        "train_circuits": train, "planned_circuits": len(rest), "margin": margin,
+        "budget_bytes": budget, "budget_fraction_of_worst_case": budget_frac,
+        "admitted_worst_case_pools": int(adm_w.sum()), "admitted_predicted_pools": int(adm_p.sum()),
+        "admitted_before_run_size": int(adm_i.sum()),
+        "device_bytes_all_worst_case": worst_all, "device_bytes_all_predicted": pred_all,
+        "fallbacks_to_worst_case": len(fallback), "train_s": t_train, "predict_s": t_pred,
+        "train_loss": loss, "calibration": calib,
+        "final_over_predicted_peak_median": float(np.median(final)) if final else None,
+        "final_over_predicted_peak_max": float(np.max(final)) if final else None,
+    }
+
+
 def bench_batch(args):
     """Many independent circuits: the batched launch against the per-circuit
-    loop on the same states and plans (identical records either way)."""
+    loop on the same states and plans (identical records either way), and
+    the predictor's memory planning (admission under a device budget)."""
+    out = batch_line(args)
+    print(json.dumps(out))
+
+
+def batch_line(args, planning=True):
     import torch
     from paper_2410_14088_amd import bmq
     from paper_2410_14088_amd import circuits as C
     mix = C.batch_mix(args.batch_count)
     flags = args.flags or 1                     # no scratch planes: 512 arenas must fit together
+    fuse = args.fuse if args.workload == "batch" and args.fuse else 4
     states, plans, amp_gates = [], [], 0
     for d in mix:
-        cfg = bmq.Config(n=d["n"], b=d["n"] - 8, inner=2, fuse=args.fuse or 4, domain=1, eb=1e-5, flags=flags)
+        cfg = bmq.Config(n=d["n"], b=d["n"] - 8, inner=2, fuse=fuse, domain=1, eb=1e-5, flags=flags)
         plans.append(bmq.Plan(d["gates"], cfg))
         states.append(bmq.State(cfg, "cuda:0"))
         amp_gates += (1 << d["n"]) * len(d["gates"])
@@ -256,20 +360,26 @@ def bench_batch(args):
         torch.cuda.synchronize()
         res[mode] = time.perf_counter() - t0
     fp = sum(st.footprint()[0] for st in states)
+    for st in states:
+        st.close()
+    del states
+    torch.cuda.empty_cache()
     out = {
         "metric": METRIC, "value": amp_gates / res["batched"], "unit": "amplitude·gates/s", "n_gpus": 1,
         "steps": 1, "warmup": args.warmup, "ms_per_step": res["batched"] * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batch-{len(mix)}-circuits-18-26q", "circuits": len(mix),
                    "amplitudes": sum(1 << d["n"] for d in mix), "amp_gates": amp_gates, "domain": "log",
-                   "eb": 1e-5, "fuse_qubits": args.fuse or 4, "flags": flags, "block_qubits": "n-8"},
+                   "eb": 1e-5, "fuse_qubits": fuse, "flags": flags, "block_qubits": "n-8"},
         "sequential_value": amp_gates / res["sequential"], "sequential_ms": res["sequential"] * 1e3,
         "speedup_vs_sequential": res["sequential"] / res["batched"],
         "persistent_ms": res["persistent"] * 1e3,
         "persistent_value": amp_gates / res["persistent"],
         "compression_ratio_vs_complex64": sum(8 << d["n"] for d in mix) / fp,
     }
-    print(json.dumps(out))
+    if planning:
+        out["planning"] = batch_planning(mix, flags, fuse)
+    return out
 
 
 def qaoa_ring_closed_form(n, gammas, betas, xs):
@@ -587,12 +697,43 @@ def main():
             a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
             res["fidelity_f2"] = abs(a0) ** 2 / sv.fidelity(None)[2]
         out[vname] = res
+    if args.workload == "random" and not args.no_variant and not args.host_resident and not args.flags:
+        # the same circuit with fusion limited to 2 qubits: 1- and 2-qubit
+        # operations as vector butterflies in LDS instead of 5-qubit
+        # matrices on the matrix cores
+        bcfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=2, domain=d["domain"], eb=d["eb"], tile=args.tile)
+        bplan = bmq.Plan(gates, bcfg)
+        bsteps = max(1, min(args.steps, args.variant_steps))
+        sv.reset()
+        sv.apply(bplan)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(bsteps):
+            sv.reset()
+            sv.apply(bplan)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        bms = ev0.elapsed_time(ev1) / bsteps
+        sv.apply(bmq.Plan(inverse, bcfg))
+        a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
+        out["lds_butterflies"] = {"value": (2 ** n) * G / (bms * 1e-3), "ms_per_step": bms, "steps": bsteps,
+                                  "fuse_qubits": 2, "passes": bplan.info()["passes"],
+                                  "fidelity_f2": abs(a0) ** 2 / sv.fidelity(None)[2]}
     if args.stats_out:
         with open(args.stats_out, "w") as f:
             json.dump(last, f, indent=1)
-    if not args.no_cpu_baseline and args.workload in ("qft", "random"):
+    if args.workload == "random" and not args.no_batch and not args.host_resident:
+        # the batched workload (512 uneven circuits of 18-26 qubits) in the same run
         sv.close()
-        del sv
+        sv = None
+        torch.cuda.empty_cache()
+        b = batch_line(args)
+        out["batch"] = {k: b[k] for k in ("value", "ms_per_step", "config", "sequential_ms", "speedup_vs_sequential",
+                                          "persistent_ms", "compression_ratio_vs_complex64", "planning")}
+    if not args.no_cpu_baseline and args.workload in ("qft", "random"):
+        if sv is not None:
+            sv.close()
+            sv = None
         torch.cuda.empty_cache()
         cn = args.cpu_n or 22
         out["cpu_baseline"] = cpu_baseline(args.workload, cn, args.cpu_seconds)

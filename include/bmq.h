@@ -262,7 +262,7 @@ int sv_autotune(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, 
  * sv_graph_capture -- record the stage loop of stages [first, first+count)
  * of plan p on state sv (counter clearing plus every tile pass, as
  * stage_apply_compressed would enqueue them) into a HIP graph, without running
- * it.  At most 1024 pass launches.  The graph is tied to sv, to p's uploaded
+ * it.  At most 512 pass launches.  The graph is tied to sv, to p's uploaded
  * operations and to the state's current pool copy: it may be replayed when
  * the state is in that copy again (after sv_reset, or after an even number
  * of compressed passes).  Not available while a debug dump is set.
@@ -283,7 +283,7 @@ void sv_graph_destroy(sv_graph_t *g);
  * tile size), so small circuits share the device instead of running one
  * after another.  Each state ends exactly as stage_apply_compressed would
  * leave it (same kernels, same records).  All states must use hip_stream;
- * each circuit may need at most 1024 pass launches.  workspace_dev: device
+ * each circuit may need at most 512 pass launches.  workspace_dev: device
  * memory, 256-byte aligned, of sv_batch_workspace bytes (launch arguments).
  * Synchronises; on overflow the overflowing states are poisoned and the
  * first error is returned. */
@@ -522,6 +522,53 @@ int mlp_loss_grad(const float *params_dev, const float *x_dev, const float *y_lo
  * grad_dev; m_dev and v_dev are the moment arrays (zero before step 1). */
 int mlp_adam_update(float *params_dev, const float *grad_dev, float *m_dev, float *v_dev,
                     uint32_t step, float lr, void *hip_stream);
+
+/* ---------------------------------------------------------------- memory planning
+ * The compression ratio decides how much device memory a circuit needs and
+ * cannot be known before compressing (Section 3 feasibility analysis); the
+ * memory manager plans with the block predictor instead of the worst case
+ * (Section 4.4 two-level memory management).
+ *
+ * Planning form of the predictor's inputs: a rollout can advance only a
+ * block's size, so planning uses feature 0 and the size label as log2 of
+ * stream bytes per amplitude (log2 bytes - b, which makes circuits of
+ * different block sizes comparable), features 1..24 fixed at the values of
+ * an all-zero block, and the stage features 25..31 as usual.
+ * sv_plan_features / sv_plan_labels -- sv_block_features / sv_block_labels
+ * in that form (training data for the planning predictor; same arguments).
+ *
+ * mlp_predict_bytes -- the planning predictor rolled over a whole circuit
+ * from |0...0>: the planning features of the initial state (computed on the
+ * device from its directory headers) are advanced stage by stage, each
+ * stage's predicted size becoming the next stage's feature 0 and the plan's
+ * stage features filling features 25..31.  bytes_host[s] (host, one per
+ * stage) receives the predicted stream bytes of the state after stage s
+ * (sum over blocks of 2^(prediction + b)), whose maximum is the circuit's
+ * predicted peak.  params_dev: SV_MLP_NPARAM device floats.  work_dev:
+ * device, 256-byte aligned, mlp_predict_work bytes.  At most 2^20 blocks
+ * (SV_ERR_UNSUPPORTED).  Synchronises. */
+int sv_plan_features(const sv_t *sv, const sv_plan_t *p, size_t stage, float *feats_dev);
+int sv_plan_labels(const sv_t *sv, float *log2_bytes_dev, int32_t *mode_dev);
+int mlp_predict_work(const sv_plan_t *p, uint64_t *bytes);
+int mlp_predict_bytes(const float *params_dev, const sv_plan_t *p, void *work_dev, uint64_t work_bytes,
+                      double *bytes_host, void *hip_stream);
+
+/* sv_admit -- admission of circuits into one batch under a device budget
+ * (host only).  Circuit i (configuration cfgs[i]) gets device pools of
+ * pool_bytes_out[i] bytes: from its predicted peak stream bytes
+ * peak_bytes[i] (record bodies = stream bytes less 8 bytes of headers per
+ * chunk, times 1 + margin, plus the segment slack), capped at the worst case;
+ * with peak_bytes NULL, the worst case (the method without a predictor).
+ * arena_bytes_out[i] receives sv_mem_required of that configuration.
+ * Circuits are taken in order and admitted (admit_out[i] = 1) while the sum
+ * of admitted arenas stays within budget; a circuit that does not fit is
+ * skipped and later ones are still tried.  A prediction that falls short is
+ * caught when the stage runs: records go to the attached host pool, or the
+ * stage reports SV_ERR_CAPACITY and the circuit is re-run with worst-case
+ * pools; records never depend on the pool sizes.  Output pointers except
+ * admit_out may be NULL. */
+int sv_admit(const sv_config_t *cfgs, size_t count, const double *peak_bytes, double margin, uint64_t budget,
+             uint8_t *admit_out, uint64_t *pool_bytes_out, uint64_t *arena_bytes_out);
 
 #ifdef __cplusplus
 }

@@ -67,7 +67,8 @@ EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_
            "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
            "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
            "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune",
-           "sv_batch_workspace", "sv_batch_apply", "sv_persistent_workspace", "sv_persistent_apply"]
+           "sv_batch_workspace", "sv_batch_apply", "sv_persistent_workspace", "sv_persistent_apply",
+           "sv_plan_features", "sv_plan_labels", "mlp_predict_work", "mlp_predict_bytes", "sv_admit"]
 SV_FEATURES, SV_MLP_NPARAM = 32, 6597
 
 _lib = None
@@ -130,6 +131,11 @@ def lib():
         L.mlp_work_floats.restype = C.c_uint64
         L.mlp_loss_grad.argtypes = [V, V, V, V, C.c_uint32, V, V, V, V]
         L.mlp_adam_update.argtypes = [V, V, V, V, C.c_uint32, C.c_float, V]
+        L.sv_plan_features.argtypes = [V, V, C.c_size_t, V]
+        L.sv_plan_labels.argtypes = [V, V, V]
+        L.mlp_predict_work.argtypes = [V, P(C.c_uint64)]
+        L.mlp_predict_bytes.argtypes = [V, V, V, C.c_uint64, V, V]
+        L.sv_admit.argtypes = [V, C.c_size_t, V, C.c_double, C.c_uint64, V, V, V]
         _lib = L
     return _lib
 
@@ -389,6 +395,21 @@ class State:
         _check(lib().sv_block_features(self.h, plan.h, stage, C.c_void_p(_ptr(out))))
         return out
 
+    def plan_features(self, plan: Plan, stage: int):
+        """Planning form of the block features (sv_plan_features): [blocks][32]."""
+        import torch
+        out = torch.empty((self.n_blocks, SV_FEATURES), dtype=torch.float32, device=self.arena.device)
+        _check(lib().sv_plan_features(self.h, plan.h, stage, C.c_void_p(_ptr(out))))
+        return out
+
+    def plan_labels(self):
+        """Planning form of the labels (sv_plan_labels): (log2 bytes per amplitude, mode)."""
+        import torch
+        lb = torch.empty(self.n_blocks, dtype=torch.float32, device=self.arena.device)
+        md = torch.empty(self.n_blocks, dtype=torch.int32, device=self.arena.device)
+        _check(lib().sv_plan_labels(self.h, C.c_void_p(_ptr(lb)), C.c_void_p(_ptr(md))))
+        return lb, md
+
     def block_labels(self):
         """(log2 stream bytes, most frequent plane mode) per block of the current state."""
         import torch
@@ -587,6 +608,36 @@ def mlp_loss_grad(params, X, y, mode):
 def mlp_adam_update(params, grad, m, v, step: int, lr: float):
     _check(lib().mlp_adam_update(C.c_void_p(_ptr(params)), C.c_void_p(_ptr(grad)), C.c_void_p(_ptr(m)),
                                  C.c_void_p(_ptr(v)), step, float(lr), _stream()))
+
+
+def predict_bytes(params, plan: "Plan"):
+    """mlp_predict_bytes: predicted stream bytes after every stage of plan,
+    from |0...0> (numpy float64 array, one entry per stage)."""
+    import torch
+    need = C.c_uint64()
+    _check(lib().mlp_predict_work(plan.h, C.byref(need)))
+    ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=params.device)
+    off = (-_ptr(ws)) % 256
+    ns = plan.n_stages
+    out = np.zeros(max(1, ns), dtype=np.float64)
+    _check(lib().mlp_predict_bytes(C.c_void_p(_ptr(params)), plan.h, C.c_void_p(_ptr(ws) + off), int(need.value),
+                                   C.c_void_p(out.ctypes.data), _stream()))
+    return out[:ns]
+
+
+def admit(cfgs, peak_bytes, margin: float, budget: int):
+    """sv_admit: (admitted flags, pool bytes, arena bytes) per configuration;
+    peak_bytes None = worst-case pools (no predictor)."""
+    n = len(cfgs)
+    arr = (sv_config_t * max(1, n))(*[c.c() for c in cfgs])
+    adm = np.zeros(max(1, n), dtype=np.uint8)
+    pools = np.zeros(max(1, n), dtype=np.uint64)
+    arenas = np.zeros(max(1, n), dtype=np.uint64)
+    pk = None if peak_bytes is None else np.ascontiguousarray(peak_bytes, dtype=np.float64)
+    _check(lib().sv_admit(C.cast(arr, C.c_void_p), n, C.c_void_p(pk.ctypes.data) if pk is not None else None,
+                          float(margin), int(budget), C.c_void_p(adm.ctypes.data), C.c_void_p(pools.ctypes.data),
+                          C.c_void_p(arenas.ctypes.data)))
+    return adm[:n].astype(bool), pools[:n], arenas[:n]
 
 
 class Predictor:

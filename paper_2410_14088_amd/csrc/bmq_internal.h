@@ -190,5 +190,12 @@ hipError_t launch_mlp_loss_grad(const float *P, const float *X, const float *y_b
                                 uint32_t batch, float *work, float *grad, float *loss, hipStream_t s);
 hipError_t launch_mlp_adam(float *P, const float *grad, float *m, float *v, float lr, float beta1, float beta2,
                            float eps, float c1, float c2, hipStream_t s);
+// rows 2.. of X (n_blocks x 32) <- row 1
+hipError_t launch_replicate_rows(float *X, uint32_t n_blocks, hipStream_t s);
+// *total <- sum of 2^(out0 + b) over the blocks; X's feature 0 <- out0, features 25..31 <- next
+hipError_t launch_rollout_step(float *X, const float *out, uint32_t n_blocks, const StageFeats &next, int b,
+                               double *total, hipStream_t s);
+// planning form of features (X, may be NULL) and size labels (y, may be NULL)
+hipError_t launch_plan_form(float *X, float *y, uint32_t n_blocks, int b, hipStream_t s);
 
 }  // namespace bmq

@@ -14,6 +14,8 @@
 // averaged over the batch.  Every reduction runs in a fixed order (no
 // floating-point atomics), so results are reproducible run to run.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "../../include/bmq.h"
@@ -151,7 +153,85 @@ __global__ void mlp_adam_kernel(float *P, const float *grad, float *m, float *v,
     P[p] = P[p] - a.lr * mh / (sqrtf(vh) + a.eps);
 }
 
+// ---- rollout of the predictor over a circuit (memory planning)
+
+// X[i] <- the features of row 1 for every row i >= 2 (blocks 1.. of |0...0>
+// are identical all-zero blocks; rows 0 and 1 were computed from the state)
+__global__ void replicate_rows_kernel(float *X, uint32_t n_blocks)
+{
+    for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 2ull * IN; t < (uint64_t)n_blocks * IN;
+         t += (uint64_t)gridDim.x * blockDim.x)
+        X[t] = X[IN + (t % IN)];
+}
+
+// Planning form of block features (or labels): feature 0 becomes log2 bytes
+// per amplitude (less b), features 1..24 the values of an all-zero block
+// (ZERO-mode fraction 1, all-zero chunk fraction 1, the rest 0), the state
+// features a rollout cannot advance
+__global__ void plan_form_kernel(float *X, float *y, uint32_t n_blocks, float b)
+{
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n_blocks; i += gridDim.x * blockDim.x) {
+        if (X) {
+            float *x = X + (uint64_t)i * IN;
+            x[0] -= b;
+            for (int k = 1; k <= 24; ++k) x[k] = (k == 1 || k == 21) ? 1.0f : 0.0f;
+        }
+        if (y) y[i] -= b;
+    }
+}
+
+// One rollout step: total[0] += sum over blocks of 2^out0 (the predicted
+// stream bytes after the stage; fixed summation order: one workgroup, lanes
+// in index order, then a tree), then feature 0 <- out0 and the stage
+// features <- those of the next stage.
+__global__ __launch_bounds__(256) void rollout_step_kernel(float *X, const float *out, uint32_t n_blocks,
+                                                           bmq::StageFeats next, double b, double *total)
+{
+    __shared__ double part[256];
+    double acc = 0.0;
+    // a chunk's record is 8 to 8 + 552 bytes: the size per amplitude lies
+    // between 2^-3 and 2^log2(560/64); predictions are held to that range
+    const float lo = -3.0f, hi = 3.1292830f;
+    for (uint32_t i = threadIdx.x; i < n_blocks; i += 256) {
+        const float y = fminf(fmaxf(out[(uint64_t)i * OUT], lo), hi);
+        acc += exp2((double)y + b);
+        X[(uint64_t)i * IN] = y;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) X[(uint64_t)i * IN + 25 + k] = next.v[k];
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = part[0];
+}
+
 }  // namespace
+
+namespace bmq {
+hipError_t launch_replicate_rows(float *X, uint32_t n_blocks, hipStream_t s)
+{
+    if (n_blocks <= 2) return hipSuccess;
+    const uint64_t work = (uint64_t)n_blocks * IN;
+    hipLaunchKernelGGL(replicate_rows_kernel, dim3((unsigned)std::min<uint64_t>((work + 255) / 256, 16384)), dim3(256),
+                       0, s, X, n_blocks);
+    return hipGetLastError();
+}
+hipError_t launch_rollout_step(float *X, const float *out, uint32_t n_blocks, const StageFeats &next, int b,
+                               double *total, hipStream_t s)
+{
+    hipLaunchKernelGGL(rollout_step_kernel, dim3(1), dim3(256), 0, s, X, out, n_blocks, next, (double)b, total);
+    return hipGetLastError();
+}
+hipError_t launch_plan_form(float *X, float *y, uint32_t n_blocks, int b, hipStream_t s)
+{
+    hipLaunchKernelGGL(plan_form_kernel, dim3((unsigned)std::min<uint32_t>((n_blocks + 255) / 256, 4096u)), dim3(256),
+                       0, s, X, y, n_blocks, (float)b);
+    return hipGetLastError();
+}
+}  // namespace bmq
 
 namespace bmq {
 

@@ -45,10 +45,10 @@ int fail(int code, const char *fmt, ...)
 
 constexpr int kDefaultTile = 12;
 constexpr int kMaxDiagQubits = bmq::kMaxDiagQubits;
-constexpr size_t kMaxLaunchesPerBatch = 1024;   // counter blocks of one batch of pass launches
+constexpr size_t kMaxLaunchesPerBatch = 512;    // counter blocks of one batch of pass launches
 constexpr size_t kStageCounters = (size_t)bmq::kSegments * bmq::C_NUM;   // words per launch
 constexpr int kPartials = 1024;
-constexpr uint64_t kOpsArenaBytes = 16ull << 20;   // fused matrices and diagonal tables of one plan
+constexpr uint64_t kOpsArenaBytes = 8ull << 20;    // fused matrices and diagonal tables of one plan
 constexpr uint64_t kStageBytes = 4ull << 20;       // host-reference slices, sampling tables
 constexpr int kMaxSampleGroups = 1 << 16;          // sampling: |psi|^2 per group, at most this many groups
 constexpr uint64_t kSampleBatch = 1ull << 16;      // samples per sampling kernel
@@ -623,6 +623,60 @@ int check_state(const sv_t *sv)
     return SV_OK;
 }
 
+}  // namespace
+
+namespace {
+// the 7 stage features of the block predictor (features 25..31): gate
+// counts of the stage, distinct local qubits, fused operations, position in
+// the plan, log2 of the error bound
+bmq::StageFeats stage_feats(const sv_plan_t *p, size_t stage)
+{
+    const StagePlan &st = p->stages[stage];
+    const int b = p->cfg.block_qubits;
+    int nondiag = 0, diag = 0, global = 0;
+    uint64_t local_mask = 0;
+    for (size_t g = st.g0; g < st.g1; ++g) {
+        const GateRec &gr = p->gates[g];
+        (gr.diag ? diag : nondiag)++;
+        bool touches_global = false;
+        for (int i = 0; i < gr.nq; ++i) {
+            if (gr.q[i] >= b) touches_global = true;
+            else local_mask |= 1ull << gr.q[i];
+        }
+        global += touches_global;
+    }
+    int nops = 0;
+    for (const auto &pp : st.passes) nops += pp.op_end - pp.op_begin;
+    bmq::StageFeats sf;
+    sf.v[0] = (float)(nondiag / 64.0);
+    sf.v[1] = (float)(diag / 64.0);
+    sf.v[2] = (float)(global / 64.0);
+    sf.v[3] = (float)((double)__builtin_popcountll(local_mask) / b);
+    sf.v[4] = (float)(nops / 16.0);
+    sf.v[5] = (float)((double)stage / (double)p->stages.size());
+    sf.v[6] = (float)(std::log2(p->cfg.eb) / 32.0);
+    return sf;
+}
+
+// work space of mlp_predict_bytes: a two-block directory, one record, init
+// counters, the block features, the outputs and the per-stage totals
+struct PredictWork {
+    uint64_t off_dir, off_pool, off_cnt, off_x, off_out, off_tot, total;
+};
+PredictWork predict_work(const sv_config_t &c, size_t n_stages)
+{
+    const uint64_t cpb = 1ull << (c.block_qubits - 6), nb = 1ull << (c.n_qubits - c.block_qubits);
+    PredictWork w{};
+    uint64_t o = 0;
+    w.off_dir = o; o += align256(2 * cpb * 8);
+    w.off_pool = o; o += 1024;
+    w.off_cnt = o; o += align256(bmq::C_NUM * 8);
+    w.off_x = o; o += align256(nb * SV_MLP_IN * 4);
+    w.off_out = o; o += align256(nb * SV_MLP_OUT * 4);
+    w.off_tot = o; o += align256((n_stages + 1) * 8);
+    w.total = o;
+    return w;
+}
 }  // namespace
 
 // ====================================================================== ABI
@@ -1747,31 +1801,102 @@ int sv_block_features(const sv_t *sv, const sv_plan_t *p, size_t stage, float *f
         return fail(SV_ERR_INVALID, "plan and state configurations differ");
     if (stage >= p->stages.size()) return fail(SV_ERR_INVALID, "stage %zu outside the plan", stage);
     if (sv->n - sv->b > 30) return fail(SV_ERR_UNSUPPORTED, "more than 2^30 blocks");
-    const StagePlan &st = p->stages[stage];
-    int nondiag = 0, diag = 0, global = 0;
-    uint64_t local_mask = 0;
-    for (size_t g = st.g0; g < st.g1; ++g) {
-        const GateRec &gr = p->gates[g];
-        (gr.diag ? diag : nondiag)++;
-        bool touches_global = false;
-        for (int i = 0; i < gr.nq; ++i) {
-            if (gr.q[i] >= sv->b) touches_global = true;
-            else local_mask |= 1ull << gr.q[i];
-        }
-        global += touches_global;
-    }
-    int nops = 0;
-    for (const auto &pp : st.passes) nops += pp.op_end - pp.op_begin;
-    bmq::StageFeats sf;
-    sf.v[0] = (float)(nondiag / 64.0);
-    sf.v[1] = (float)(diag / 64.0);
-    sf.v[2] = (float)(global / 64.0);
-    sf.v[3] = (float)((double)__builtin_popcountll(local_mask) / sv->b);
-    sf.v[4] = (float)(nops / 16.0);
-    sf.v[5] = (float)((double)stage / (double)p->stages.size());
-    sf.v[6] = (float)(std::log2(sv->cfg.eb) / 32.0);
+    const bmq::StageFeats sf = stage_feats(p, stage);
     HIP_TRY(bmq::launch_block_stats(sv->dir[sv->cur], 1ull << (sv->b - 6), 1ull << (sv->n - sv->b), sf, feats_dev,
                                     nullptr, nullptr, sv->stream));
+    return SV_OK;
+}
+
+int sv_plan_features(const sv_t *sv, const sv_plan_t *p, size_t stage, float *feats_dev)
+{
+    if (int rc = sv_block_features(sv, p, stage, feats_dev)) return rc;
+    HIP_TRY(bmq::launch_plan_form(feats_dev, nullptr, (uint32_t)(1ull << (sv->n - sv->b)), sv->b, sv->stream));
+    return SV_OK;
+}
+
+int sv_plan_labels(const sv_t *sv, float *log2_bytes_dev, int32_t *mode_dev)
+{
+    if (int rc = sv_block_labels(sv, log2_bytes_dev, mode_dev)) return rc;
+    HIP_TRY(bmq::launch_plan_form(nullptr, log2_bytes_dev, (uint32_t)(1ull << (sv->n - sv->b)), sv->b, sv->stream));
+    return SV_OK;
+}
+
+int mlp_predict_work(const sv_plan_t *p, uint64_t *bytes)
+{
+    if (!p || !bytes) return fail(SV_ERR_INVALID, "NULL argument");
+    if (p->cfg.n_qubits - p->cfg.block_qubits > 20) return fail(SV_ERR_UNSUPPORTED, "more than 2^20 blocks");
+    *bytes = predict_work(p->cfg, p->stages.size()).total;
+    return SV_OK;
+}
+
+int mlp_predict_bytes(const float *params_dev, const sv_plan_t *p, void *work_dev, uint64_t work_bytes,
+                      double *bytes_host, void *hip_stream)
+{
+    if (!params_dev || !p || !work_dev || (!bytes_host && !p->stages.empty())) return fail(SV_ERR_INVALID, "NULL argument");
+    if ((uintptr_t)work_dev & 255u) return fail(SV_ERR_INVALID, "work must be 256-byte aligned");
+    const sv_config_t &c = p->cfg;
+    if (c.n_qubits - c.block_qubits > 20) return fail(SV_ERR_UNSUPPORTED, "more than 2^20 blocks");
+    const size_t ns = p->stages.size();
+    const PredictWork w = predict_work(c, ns);
+    if (work_bytes < w.total)
+        return fail(SV_ERR_INVALID, "work space of %llu bytes < %llu", (unsigned long long)work_bytes,
+                    (unsigned long long)w.total);
+    if (!ns) return SV_OK;
+    const hipStream_t st = (hipStream_t)hip_stream;
+    uint8_t *W = (uint8_t *)work_dev;
+    uint64_t *dir = (uint64_t *)(W + w.off_dir);
+    float *X = (float *)(W + w.off_x), *out = (float *)(W + w.off_out);
+    double *tot = (double *)(W + w.off_tot);
+    const uint64_t cpb = 1ull << (c.block_qubits - 6);
+    const uint32_t nb = (uint32_t)(1ull << (c.n_qubits - c.block_qubits));
+    // features of |0...0>: block 0 holds the encoded amplitude 1, every
+    // other block is all zero; two blocks are built and the second copied
+    HIP_TRY(bmq::launch_init_state(dir, 2 * cpb, W + w.off_pool, (unsigned long long *)(W + w.off_cnt),
+                                   codec_params(c), st));
+    HIP_TRY(bmq::launch_block_stats(dir, cpb, nb >= 2 ? 2 : 1, stage_feats(p, 0), X, nullptr, nullptr, st));
+    HIP_TRY(bmq::launch_replicate_rows(X, nb, st));
+    HIP_TRY(bmq::launch_plan_form(X, nullptr, nb, c.block_qubits, st));
+    for (size_t s = 0; s < ns; ++s) {
+        bmq::StageFeats next{};
+        if (s + 1 < ns) next = stage_feats(p, s + 1);
+        HIP_TRY(bmq::launch_mlp_forward(params_dev, X, nb, out, st));
+        HIP_TRY(bmq::launch_rollout_step(X, out, nb, next, c.block_qubits, tot + s, st));
+    }
+    HIP_TRY(hipMemcpyAsync(bytes_host, tot, ns * 8, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return SV_OK;
+}
+
+int sv_admit(const sv_config_t *cfgs, size_t count, const double *peak_bytes, double margin, uint64_t budget,
+             uint8_t *admit_out, uint64_t *pool_bytes_out, uint64_t *arena_bytes_out)
+{
+    if (count && (!cfgs || !admit_out)) return fail(SV_ERR_INVALID, "NULL argument");
+    if (!(margin >= 0.0) || !std::isfinite(margin)) return fail(SV_ERR_INVALID, "margin must be finite and >= 0");
+    for (size_t i = 0; i < count; ++i)
+        if (int rc = validate_cfg(&cfgs[i])) return rc;
+    uint64_t used = 0;
+    for (size_t i = 0; i < count; ++i) {
+        sv_config_t c = cfgs[i];
+        c.pool_bytes = 0;
+        const uint64_t worst = layout_for(c).pool_cap;
+        uint64_t pool = worst;
+        if (peak_bytes) {
+            // record bodies: the stream bytes less the two 4-byte headers per
+            // chunk (they live in the directory), with the margin and the
+            // segment slack the worst case also carries
+            const double nch = (double)(1ull << (c.n_qubits - 6));
+            const double body = std::max(0.0, peak_bytes[i] - 8.0 * nch);
+            const double want = std::ceil(body * (1.0 + margin)) + (double)bmq::kSegments * 256.0 + 1024.0;
+            if (want < (double)worst) pool = align256((uint64_t)want);
+        }
+        c.pool_bytes = pool;
+        const uint64_t arena = layout_for(c).total;
+        const bool ok = used + arena <= budget;
+        if (ok) used += arena;
+        admit_out[i] = ok ? 1 : 0;
+        if (pool_bytes_out) pool_bytes_out[i] = pool;
+        if (arena_bytes_out) arena_bytes_out[i] = arena;
+    }
     return SV_OK;
 }
 

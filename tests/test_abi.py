@@ -183,3 +183,28 @@ def test_plan_views_reject_bad_arguments(bmq):
     assert L.sv_check(None, C_.byref(nb)) == -1
     ptr, n = C_.c_void_p(), C_.c_uint64()
     assert L.sv_directory(None, C_.byref(ptr), C_.byref(n)) == -1
+
+
+def test_admission_under_a_budget(bmq):
+    """sv_admit (host only): worst-case pools without a predictor; predicted
+    peaks shrink the pools (never beyond the worst case), so more circuits
+    fit the same budget; first fit in order."""
+    cfgs = [bmq.Config(n=n, b=n - 8, domain=1, eb=1e-5, flags=bmq.SV_FLAG_NO_SCRATCH) for n in (24, 25, 24, 23, 24, 23)]
+    big = 1 << 62
+    adm, pools, arenas = bmq.admit(cfgs, None, 0.1, big)
+    assert adm.all()
+    need = [bmq.C.c_uint64() for _ in cfgs]
+    for c, x in zip(cfgs, need):
+        bmq._check(bmq.lib().sv_mem_required(bmq.C.byref(c.c()), bmq.C.byref(x)))
+    assert list(arenas) == [x.value for x in need]              # worst case = the default arena
+    peaks = [0.7 * (8 << c.n) for c in cfgs]                   # a compression ratio of about 1.4
+    adm_p, pools_p, arenas_p = bmq.admit(cfgs, peaks, 0.1, big)
+    assert (pools_p < pools).all() and (arenas_p < arenas).all()
+    budget = int(arenas[:3].sum())
+    adm_w = bmq.admit(cfgs, None, 0.1, budget)[0]
+    adm_p = bmq.admit(cfgs, peaks, 0.1, budget)[0]
+    assert adm_w.sum() == 3 and adm_p.sum() > adm_w.sum()
+    huge = [64.0 * (8 << c.n) for c in cfgs]                   # capped at the worst case
+    assert (bmq.admit(cfgs, huge, 0.1, big)[1] == pools).all()
+    with pytest.raises(bmq.BmqError):
+        bmq.admit(cfgs, peaks, -1.0, big)
