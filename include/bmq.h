@@ -311,6 +311,20 @@ int sv_batch_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t co
  * bytes (launch arguments, queue and counters).  Synchronises. */
 int sv_persistent_workspace(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
                             uint64_t *bytes);
+/* sv_graph_capture_persistent -- the whole-circuit queue launch of every
+ * stage of plan p on state sv, recorded into a HIP graph without running it:
+ * the preparation (plan upload and the workspace image: launch arguments,
+ * queue tables) happens now, once, and the graph holds only kernels (the
+ * counter and queue-word clears as fill kernels, then the queue kernel), so
+ * that one replay runs the whole circuit.  workspace_dev: as for
+ * sv_persistent_apply (sv_persistent_workspace bytes for {sv}, {p}); it must
+ * stay alive and unchanged while the graph exists.  Replay with
+ * sv_graph_launch (the state must be in the pool copy it was captured in:
+ * after sv_reset, or an even number of compressed passes later); the abort
+ * flags and the stage counters are read at the next synchronising call
+ * (SV_ERR_TIMEOUT, state poisoned, when a bounded wait ran out). */
+int sv_graph_capture_persistent(sv_t *sv, const sv_plan_t *p, void *workspace_dev, uint64_t workspace_bytes,
+                                uint32_t wait_limit_us, sv_graph_t **out);
 int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
                         void *workspace_dev, uint64_t workspace_bytes, uint32_t wait_limit_us,
                         void *hip_stream);

@@ -68,6 +68,7 @@ EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_
            "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
            "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune",
            "sv_batch_workspace", "sv_batch_apply", "sv_persistent_workspace", "sv_persistent_apply",
+           "sv_graph_capture_persistent",
            "sv_plan_features", "sv_plan_labels", "mlp_predict_work", "mlp_predict_bytes", "sv_admit"]
 SV_FEATURES, SV_MLP_NPARAM = 32, 6597
 
@@ -119,6 +120,7 @@ def lib():
         L.sv_batch_apply.argtypes = [V, V, C.c_size_t, V, C.c_uint64, V]
         L.sv_persistent_workspace.argtypes = [V, V, C.c_size_t, P(C.c_uint64)]
         L.sv_persistent_apply.argtypes = [V, V, C.c_size_t, V, C.c_uint64, C.c_uint32, V]
+        L.sv_graph_capture_persistent.argtypes = [V, V, V, C.c_uint64, C.c_uint32, P(V)]
         L.sv_autotune.argtypes = [V, C.c_size_t, P(sv_config_t), V, C.c_uint64, V, C.c_size_t, P(sv_config_t),
                                   P(C.c_float)]
         L.sv_graph_launch.argtypes = [V, V]
@@ -286,6 +288,23 @@ class State:
         h = C.c_void_p()
         _check(lib().sv_graph_capture(self.h, plan.h, first, count, C.byref(h)))
         return Graph(h, self, plan)
+
+    def capture_persistent(self, plan: Plan, wait_limit_us: int = 0) -> "Graph":
+        """Record the whole-circuit queue launch of plan as a HIP graph
+        (sv_graph_capture_persistent); the workspace lives with the graph."""
+        import torch
+        sa = (C.c_void_p * 1)(self.h.value)
+        pa = (C.c_void_p * 1)(plan.h.value)
+        need = C.c_uint64()
+        _check(lib().sv_persistent_workspace(sa, pa, 1, C.byref(need)))
+        ws = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=self.arena.device)
+        off = (-_ptr(ws)) % 256
+        h = C.c_void_p()
+        _check(lib().sv_graph_capture_persistent(self.h, plan.h, C.c_void_p(_ptr(ws) + off), int(need.value),
+                                                 int(wait_limit_us), C.byref(h)))
+        g = Graph(h, self, plan)
+        g.workspace = ws
+        return g
 
     def graph_sync(self):
         _check(lib().sv_graph_sync(self.h))

@@ -192,6 +192,12 @@ struct sv_graph {
     int cur_begin = 0, cur_end = 0;
     hipGraph_t g = nullptr;
     hipGraphExec_t x = nullptr;
+    // a captured whole-circuit queue launch: its workspace (launch arguments,
+    // queue and done-counters, caller-owned) and the abort flags in it
+    bool persistent = false;
+    uint8_t *ws = nullptr;
+    std::vector<uint64_t> flag_offs;
+    uint64_t limit_us = 0;
 };
 
 namespace {
@@ -1156,6 +1162,20 @@ int resolve_graph(sv_t *sv)
     if (!sv->pending_graph) return SV_OK;
     const sv_graph *g = sv->pending_graph;
     sv->pending_graph = nullptr;
+    if (g->persistent) {
+        // abort flags first: an aborted launch leaves the state half-written
+        std::vector<uint32_t> flags(g->flag_offs.size(), 0);
+        for (size_t k = 0; k < flags.size(); ++k)
+            HIP_TRY(hipMemcpyAsync(&flags[k], g->ws + g->flag_offs[k], 4, hipMemcpyDeviceToHost, sv->stream));
+        HIP_TRY(hipStreamSynchronize(sv->stream));
+        for (uint32_t f : flags)
+            if (f) {
+                sv->poisoned = true;
+                return fail(SV_ERR_TIMEOUT, "a replayed persistent launch waited longer than %llu us for a "
+                                            "dependency and was aborted; the state is poisoned",
+                            (unsigned long long)g->limit_us);
+            }
+    }
     std::vector<unsigned long long> hc;
     if (int rc = read_counters(sv, g->launches, hc)) return rc;
     return collect_stages(sv, g->plan, g->first, g->count, hc, nullptr);
@@ -1513,42 +1533,58 @@ int sv_persistent_workspace(sv_t *const *states, const sv_plan_t *const *plans, 
     return plan_persistent(states, plans, count, classes, *bytes, 256);   // sizes do not depend on the CU count
 }
 
-int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t count, void *workspace_dev,
-                        uint64_t workspace_bytes, uint32_t wait_limit_us, void *hip_stream)
+}  // extern "C"
+
+namespace {
+
+// The three steps of a whole-circuit queue launch.  prepare: checks, plan
+// uploads and the workspace image (launch arguments, item table,
+// dependencies), uploaded once (synchronises: the host image is pageable);
+// it advances each state's current pool copy to where the launch leaves it.
+// enqueue: the counter and queue-word clears (fill kernels) and the queue
+// kernels -- kernels only, so that it can be captured in a graph.  collect:
+// abort flags, then every stage's counters (synchronises).
+struct PersistPrep {
+    std::vector<PersistClass> classes;
+    std::vector<std::vector<bmq::PassArgs>> args;
+    std::vector<bmq::PersistArgs> pa;
+    uint64_t limit_us = 0;
+};
+
+int persist_prepare(sv_t *const *states, const sv_plan_t *const *plans, size_t count, void *workspace_dev,
+                    uint64_t workspace_bytes, uint32_t wait_limit_us, hipStream_t stream, PersistPrep &P)
 {
     int dev = 0, khz = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    std::vector<PersistClass> classes;
     uint64_t need = 0;
-    if (int rc = plan_persistent(states, plans, count, classes, need, std::max(cus, 1))) return rc;
+    if (int rc = plan_persistent(states, plans, count, P.classes, need, std::max(cus, 1))) return rc;
     if (!workspace_dev || ((uintptr_t)workspace_dev & 255u) || workspace_bytes < need)
         return fail(SV_ERR_INVALID, "workspace must be 256-byte aligned and hold %llu bytes", (unsigned long long)need);
-    hipStream_t stream = (hipStream_t)hip_stream;
     for (size_t i = 0; i < count; ++i)
         if (states[i]->stream != stream)
             return fail(SV_ERR_INVALID, "state %zu was created on another stream", i);
     if (khz <= 0) return fail(SV_ERR_UNSUPPORTED, "the device reports no constant-rate clock");
-    const uint64_t limit_us = wait_limit_us ? wait_limit_us : 10000000u;
+    P.limit_us = wait_limit_us ? wait_limit_us : 10000000u;
     for (size_t i = 0; i < count; ++i) {
         if (int rc = resolve_graph(states[i])) return rc;
         if (int rc = upload_plan(states[i], plans[i])) return rc;
     }
-    std::vector<std::vector<bmq::PassArgs>> args(count);
+    P.args.assign(count, {});
     for (size_t i = 0; i < count; ++i) {
         size_t li = 0;
         for (const StagePlan &st : plans[i]->stages)
             for (int pi = 0; pi < (int)st.passes.size(); ++pi, ++li) {
                 bmq::PassArgs a;
                 build_pass_args(states[i], plans[i], st, pi, li, a);
-                args[i].push_back(a);
+                P.args[i].push_back(a);
             }
     }
     std::vector<uint8_t> host(need, 0);
-    for (const PersistClass &c : classes) {
+    for (const PersistClass &c : P.classes) {
         bmq::PassArgs *ga = (bmq::PassArgs *)(host.data() + c.args_off);
-        for (size_t L = 0; L < c.pass.size(); ++L) ga[L] = args[c.pass[L].first][c.pass[L].second];
+        for (size_t L = 0; L < c.pass.size(); ++L) ga[L] = P.args[c.pass[L].first][c.pass[L].second];
         std::memcpy(host.data() + c.first_off, c.first_item.data(), c.first_item.size() * sizeof(uint32_t));
         std::memcpy(host.data() + c.dep_off, c.dep.data(), c.dep.size() * sizeof(int32_t));
         std::memcpy(host.data() + c.tpi_off, c.tpi.data(), c.tpi.size() * sizeof(uint32_t));
@@ -1556,9 +1592,8 @@ int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size
     uint8_t *ws = (uint8_t *)workspace_dev;
     HIP_TRY(hipMemcpyAsync(ws, host.data(), need, hipMemcpyHostToDevice, stream));
     HIP_TRY(hipStreamSynchronize(stream));          // the host image is pageable
-    for (size_t i = 0; i < count; ++i)
-        HIP_TRY(bmq::launch_fill_u64((uint64_t *)states[i]->counters, args[i].size() * kStageCounters, 0, stream));
-    for (const PersistClass &c : classes) {
+    P.pa.clear();
+    for (const PersistClass &c : P.classes) {
         bmq::PersistArgs pa;
         std::memset(&pa, 0, sizeof(pa));
         pa.args = (const bmq::PassArgs *)(ws + c.args_off);
@@ -1567,33 +1602,50 @@ int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size
         pa.max_grid = (uint32_t)std::max(cus, 1) * 4u;       // resident workgroups
         pa.dep = (const int32_t *)(ws + c.dep_off);
         pa.sync = (uint32_t *)(ws + c.sync_off);
-        pa.limit_ticks = limit_us * (uint64_t)khz / 1000u;
+        pa.limit_ticks = P.limit_us * (uint64_t)khz / 1000u;
         pa.n_pass = (uint32_t)c.pass.size();
         pa.total = c.first_item.back();
         for (size_t i : c.members) pa.system_scope |= states[i]->host_cap ? 1 : 0;
-        HIP_TRY(bmq::launch_fill_u64((uint64_t *)pa.sync, c.sync_words, 0, stream));
-        HIP_TRY(bmq::launch_pass_queue(c.t, c.dom, pa, stream));
+        P.pa.push_back(pa);
     }
+    return SV_OK;
+}
+
+hipError_t persist_enqueue(sv_t *const *states, size_t count, const PersistPrep &P, hipStream_t stream)
+{
+    hipError_t e = hipSuccess;
+    for (size_t i = 0; e == hipSuccess && i < count; ++i)
+        e = bmq::launch_fill_u64((uint64_t *)states[i]->counters, P.args[i].size() * kStageCounters, 0, stream);
+    for (size_t k = 0; e == hipSuccess && k < P.classes.size(); ++k) {
+        e = bmq::launch_fill_u64((uint64_t *)P.pa[k].sync, P.classes[k].sync_words, 0, stream);
+        if (e == hipSuccess) e = bmq::launch_pass_queue(P.classes[k].t, P.classes[k].dom, P.pa[k], stream);
+    }
+    return e;
+}
+
+int persist_collect(sv_t *const *states, const sv_plan_t *const *plans, size_t count, const PersistPrep &P,
+                    hipStream_t stream)
+{
     // abort flags first: an aborted class leaves its states half-written
-    std::vector<uint32_t> flags(classes.size(), 0);
-    for (size_t k = 0; k < classes.size(); ++k)
-        HIP_TRY(hipMemcpyAsync(&flags[k], ws + classes[k].sync_off + 4, 4, hipMemcpyDeviceToHost, stream));
+    std::vector<uint32_t> flags(P.classes.size(), 0);
+    for (size_t k = 0; k < P.classes.size(); ++k)
+        HIP_TRY(hipMemcpyAsync(&flags[k], P.pa[k].sync + 1, 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
     bool aborted = false;
-    for (size_t k = 0; k < classes.size(); ++k)
+    for (size_t k = 0; k < P.classes.size(); ++k)
         if (flags[k]) {
             aborted = true;
-            for (size_t i : classes[k].members) states[i]->poisoned = true;
+            for (size_t i : P.classes[k].members) states[i]->poisoned = true;
         }
     if (aborted)
         return fail(SV_ERR_TIMEOUT, "a persistent launch waited longer than %llu us for a dependency and was "
                                     "aborted; its states are poisoned",
-                    (unsigned long long)limit_us);
+                    (unsigned long long)P.limit_us);
     std::vector<unsigned long long> hc;
     int first_err = SV_OK;
     std::string err;
     for (size_t i = 0; i < count; ++i) {
-        int rc = read_counters(states[i], args[i].size(), hc);
+        int rc = read_counters(states[i], P.args[i].size(), hc);
         if (rc == SV_OK) rc = collect_stages(states[i], plans[i], 0, plans[i]->stages.size(), hc, nullptr);
         if (rc != SV_OK && first_err == SV_OK) {
             first_err = rc;
@@ -1602,6 +1654,74 @@ int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size
     }
     if (first_err != SV_OK) g_err = err;
     return first_err;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sv_persistent_apply(sv_t *const *states, const sv_plan_t *const *plans, size_t count, void *workspace_dev,
+                        uint64_t workspace_bytes, uint32_t wait_limit_us, void *hip_stream)
+{
+    const hipStream_t stream = (hipStream_t)hip_stream;
+    PersistPrep P;
+    if (int rc = persist_prepare(states, plans, count, workspace_dev, workspace_bytes, wait_limit_us, stream, P))
+        return rc;
+    HIP_TRY(persist_enqueue(states, count, P, stream));
+    return persist_collect(states, plans, count, P, stream);
+}
+
+int sv_graph_capture_persistent(sv_t *sv, const sv_plan_t *p, void *workspace_dev, uint64_t workspace_bytes,
+                                uint32_t wait_limit_us, sv_graph_t **out)
+{
+    if (int rc = check_state(sv)) return rc;
+    if (!p || !out) return fail(SV_ERR_INVALID, "NULL argument");
+    if (p->stages.empty()) return fail(SV_ERR_INVALID, "empty plan");
+    if (sv->dump_re || sv->dumpd_re) return fail(SV_ERR_UNSUPPORTED, "the debug dump cannot be captured");
+    sv_t *const states[1] = {sv};
+    const sv_plan_t *const plans[1] = {p};
+    const int cur_begin = sv->cur;
+    PersistPrep P;
+    if (int rc = persist_prepare(states, plans, 1, workspace_dev, workspace_bytes, wait_limit_us, sv->stream, P)) {
+        sv->cur = cur_begin;
+        return rc;
+    }
+    sv_graph *g = new (std::nothrow) sv_graph;
+    if (!g) {
+        sv->cur = cur_begin;
+        return fail(SV_ERR_OOM, "host allocation failed");
+    }
+    g->sv = sv;
+    g->plan = p;
+    g->plan_uid = p->uid;
+    g->first = 0;
+    g->count = p->stages.size();
+    g->launches = P.args[0].size();
+    g->cur_begin = cur_begin;
+    g->cur_end = sv->cur;
+    g->persistent = true;
+    g->ws = (uint8_t *)workspace_dev;
+    g->limit_us = P.limit_us;
+    for (const bmq::PersistArgs &pa : P.pa) g->flag_offs.push_back((uint64_t)((uint8_t *)(pa.sync + 1) - g->ws));
+    sv->cur = cur_begin;                          // capture runs nothing
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        e = persist_enqueue(states, 1, P, cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &graph);
+        if (e == hipSuccess) e = e2;
+        g->g = graph;
+        if (e == hipSuccess) e = hipGraphInstantiate(&g->x, g->g, nullptr, nullptr, 0);
+    }
+    if (cs) (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        sv_graph_destroy(g);
+        return fail(SV_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+    *out = g;
+    return SV_OK;
 }
 
 int sv_fidelity(const sv_t *sv, const double *ref_host, const double *ref_dev, const sv_t *ref_sv, sv_fidelity_t *out)

@@ -110,3 +110,49 @@ def test_autotune_picks_a_measured_candidate():
     ref = torch.from_numpy(np.ascontiguousarray(N.simulate(d["n"], d["gates"]))).to(DEV)
     f2, _, _ = sv.fidelity(ref)
     assert f2 >= 0.9999
+
+
+@pytest.mark.parametrize("which", ["random16", "qft20"])
+def test_persistent_launch_in_a_graph_matches_per_pass(which):
+    """The whole-circuit queue launch captured in a HIP graph
+    (sv_graph_capture_persistent): every replay, with eager work and
+    synchronisation between replays, leaves the records the per-pass launches
+    leave, bit for bit."""
+    import time
+    if which == "random16":
+        d = C.config(0)
+        gates, n, b, fuse = d["gates"], d["n"], d["b"], 2
+    else:
+        d = C.config(1, n=20)
+        gates, n, b, fuse = d["gates"], 20, 14, 4
+    cfg, plan, eager = _setup(gates, n, b, fuse=fuse)
+    eager.apply(plan)
+    want_streams = [eager.block_stream(k) for k in range(eager.n_blocks)]
+    want_fp = eager.footprint()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        eager.reset()
+        eager.apply(plan)
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / 3
+    _, plan2, sv = _setup(gates, n, b, fuse=fuse)
+    g = sv.capture_persistent(plan2)
+    other_cfg, other_plan, other = _setup(C.ghz(16), 16, 10, fuse=2)
+    t_rep = []
+    for r in range(3):
+        print(f"{which}: persistent replay {r}", flush=True)
+        sv.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g.launch()
+        sv.graph_sync()
+        t_rep.append(time.perf_counter() - t0)
+        assert sv.footprint() == want_fp
+        assert [sv.block_stream(k) for k in range(sv.n_blocks)] == want_streams
+        other.reset()                       # eager work between replays
+        other.apply(other_plan)
+        torch.cuda.synchronize()
+    print(f"{which}: per-pass launches {t_eager * 1e3:.2f} ms, persistent graph replay {min(t_rep) * 1e3:.2f} ms",
+          flush=True)
+    g.close()
