@@ -699,26 +699,23 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
     }
 }
 
-// The wave's output stream is assembled in LDS before it goes to memory:
-// stream word i lives at st0[i] for i < R, else at st1[i - R] (the wave's own
-// tile rows of the real and imaginary planes, free once its chunks are
-// encoded).
+// The wave's output stream is assembled in LDS before it goes to memory, in
+// a staging region whose words are addressed from one base (no per-word
+// choice of region).  In the pass kernel the records of the wave's first
+// half of chunks go to its tile rows of the real plane and those of the
+// second half to its rows of the imaginary plane (free once its chunks are
+// encoded); each half holds at most half the chunks' worst-case records.
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
 struct Staging {
-    uint32_t a0, a1;     // LDS byte addresses of st0 and of st1 - 4 R
-    uint32_t R;
-    __device__ __forceinline__ lds_u32 *word(uint32_t i) const
-    {
-        return (lds_u32 *)(uintptr_t)(4u * i + (i < R ? a0 : a1));
-    }
+    lds_u32 *p;          // staging word 0
+    __device__ __forceinline__ lds_u32 *word(uint32_t i) const { return p + i; }
 };
-__device__ __forceinline__ Staging make_staging(uint32_t *st0, uint32_t *st1, uint32_t R)
+__device__ __forceinline__ Staging make_staging(uint32_t *st)
 {
-    const uint32_t a0 = (uint32_t)(uintptr_t)(lds_u32 *)st0, a1 = (uint32_t)(uintptr_t)(lds_u32 *)st1;
-    return Staging{a0, a1 - 4u * R, R};
+    return Staging{(lds_u32 *)st};
 }
 
 // Stage this lane's part of a plane's payload, which starts at stream word
@@ -740,19 +737,24 @@ __device__ __forceinline__ void stage_quad_payload(const QuadPlane &P, const Sta
     }
     const uint32_t w = P.w;
     if (mode == M_ZERO || w == 0u) return;
-    const uint32_t b0 = 32u * pw + 16u * w * (uint32_t)q;
-    int32_t prev = P.carry;
+    // bit positions relative to word pw (its multiple of 32 changes no
+    // shift): field j at bit 16 w q + j w; Q0 fields are the codes
+    // themselves, i.e. residuals against a predecessor of 0
+    lds_u32 *const pl = S.p + pw;
+    const uint32_t b0 = 16u * w * (uint32_t)q;
+    const uint32_t keep = (mode == M_LZ) ? ~0u : 0u;
+    uint32_t prev = (uint32_t)P.carry & keep;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const int32_t kp = P.kp[j];
-        const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
-        prev = kp;
-        const uint32_t fld = (mode == M_LZ) ? zigzag(d) : zigzag(kp);
+        const uint32_t kp = (uint32_t)P.kp[j];
+        const int32_t d = (j == 0 && q == 0) ? (int32_t)(kp & ~keep) : (int32_t)(kp - prev);
+        prev = kp & keep;
+        const uint32_t fld = zigzag(d);
         const uint32_t b = b0 + (uint32_t)j * w;
         const uint64_t t = (uint64_t)fld << (b & 31u);
-        __hip_atomic_fetch_or(S.word(b >> 5), (uint32_t)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        __hip_atomic_fetch_or(S.word((b >> 5) + 1u), (uint32_t)(t >> 32), __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_WAVEFRONT);
+        lds_u32 *const wp = pl + (b >> 5);
+        __hip_atomic_fetch_or(wp, (uint32_t)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        __hip_atomic_fetch_or(wp + 1, (uint32_t)(t >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
 }
 
@@ -787,8 +789,7 @@ __device__ __forceinline__ void zero_staging(const Staging &S, uint32_t nw)
 }
 
 // Copy staging words [0, nw) to dst (4-byte aligned), 16 bytes per lane
-// and step (the staging rows are 16-byte aligned and R is a multiple of 4
-// words).
+// and step (the staging base is 16-byte aligned).
 __device__ __forceinline__ void copy_staging(const Staging &S, uint32_t nw, uint32_t *dst)
 {
     for (uint32_t w4 = 4u * (uint32_t)lane_id(); w4 < nw; w4 += 256u) {
@@ -828,7 +829,7 @@ __device__ __forceinline__ void decode_entry(uint64_t e, const uint8_t *pool, co
 }
 
 template <int T, int NT>
-struct PassLds {
+struct __attribute__((aligned(16))) PassLds {
     static constexpr int TILE = 1 << T, NCH = TILE / kChunk, NW = NT / 64;
     float re[TILE + TILE / 16];           // tile, padded layout (tix)
     float im[TILE + TILE / 16];
@@ -859,7 +860,7 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
 {
     using L = PassLds<T, NT>;
     constexpr int NCH = L::NCH, NW = L::NW, CPW = NCH / NW;
-    static_assert(CPW >= 1 && CPW <= 64, "chunks per wave");
+    static_assert(CPW >= 4 && CPW <= 16 && CPW % 4 == 0, "chunks per wave");
     __shared__ L s;
 
     // the thread index through an opaque copy: when the body runs in a loop
@@ -874,9 +875,6 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     const uint64_t base = deposit((uint64_t)tile, a.nontile, a.n_nontile);
     const int c0 = wave * CPW;
 
-    // global index of the chunk this lane stands for (lane < CPW)
-    uint64_t my_g = 0;
-    if (lane < CPW) my_g = base | deposit((uint64_t)(c0 + lane), a.tileq + 6, T - 6);
 
     // ---- load
     if (a.in_mode == IO_COMPRESSED) {
@@ -899,10 +897,20 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         __builtin_amdgcn_s_setprio(0);
     } else {
         __builtin_amdgcn_s_setprio(2);                  // as for the decoder's loads
-        for (int i = 0; i < CPW; ++i) {
-            const uint64_t g = lane_u64(my_g, i);
-            s.re[tix(((c0 + i) << 6) + lane)] = a.scr_re[g + lane];
-            s.im[tix(((c0 + i) << 6) + lane)] = a.scr_im[g + lane];
+        // 16 bytes per lane and plane: lane 16 r + u takes amplitudes
+        // 4u..4u+3 of chunk c0 + 4i + r (c0 is a multiple of CPW, itself a
+        // multiple of 4, so the chunk index bits of c0, 4i and r are
+        // disjoint and deposit separately)
+        const int r = lane >> 4, u = lane & 15;
+        const uint64_t gl = base | deposit((uint64_t)(c0 | r), a.tileq + 6, T - 6);
+#pragma unroll
+        for (int i = 0; i < CPW / 4; ++i) {
+            const uint64_t g = (gl | deposit((uint64_t)(4 * i), a.tileq + 6, T - 6)) + 4u * (uint32_t)u;
+            const float4 vr = *(const float4 *)(a.scr_re + g);
+            const float4 vi = *(const float4 *)(a.scr_im + g);
+            const uint32_t e = tix((uint32_t)((c0 + 4 * i + r) << 6) + 4u * (uint32_t)u);
+            s.re[e] = vr.x; s.re[e + 1] = vr.y; s.re[e + 2] = vr.z; s.re[e + 3] = vr.w;
+            s.im[e] = vi.x; s.im[e + 1] = vi.y; s.im[e + 2] = vi.z; s.im[e + 3] = vi.w;
         }
         __builtin_amdgcn_s_setprio(0);
     }
@@ -934,10 +942,15 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
 
     // ---- store
     if (a.out_mode == IO_SCRATCH) {
-        for (int i = 0; i < CPW; ++i) {
-            const uint64_t g = lane_u64(my_g, i);
-            a.scr_re[g + lane] = s.re[tix(((c0 + i) << 6) + lane)];
-            a.scr_im[g + lane] = s.im[tix(((c0 + i) << 6) + lane)];
+        // 16 bytes per lane and plane, as the scratch load above
+        const int r = lane >> 4, u = lane & 15;
+        const uint64_t gl = base | deposit((uint64_t)(c0 | r), a.tileq + 6, T - 6);
+#pragma unroll
+        for (int i = 0; i < CPW / 4; ++i) {
+            const uint64_t g = (gl | deposit((uint64_t)(4 * i), a.tileq + 6, T - 6)) + 4u * (uint32_t)u;
+            const uint32_t e = tix((uint32_t)((c0 + 4 * i + r) << 6) + 4u * (uint32_t)u);
+            *(float4 *)(a.scr_re + g) = make_float4(s.re[e], s.re[e + 1], s.re[e + 2], s.re[e + 3]);
+            *(float4 *)(a.scr_im + g) = make_float4(s.im[e], s.im[e + 1], s.im[e + 2], s.im[e + 3]);
         }
         return;
     }
@@ -972,16 +985,22 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     if (lane == 0 && total) got = atomicAdd(&cnt[C_CURSOR], (unsigned long long)total);
     // the chunk's body offset in the wave's stream, from its quad's lane 0
     const uint32_t rel = qperm<QB0>(incl - size);
-    // assemble the wave's bodies in its own LDS rows (offsets relative to
-    // the wave's stream)
-    const Staging S = make_staging((uint32_t *)(s.re + tix((uint32_t)c0 << 6)),
-                                   (uint32_t *)(s.im + tix((uint32_t)c0 << 6)), (uint32_t)CPW * 68u);
+    // assemble the wave's bodies in its own LDS rows: chunks [0, CPW/2) in
+    // its rows of the real plane, the rest in its rows of the imaginary
+    // plane (record offsets relative to the region's first record)
+    constexpr int H = CPW / 2 > 0 ? CPW / 2 : 1;
+    static_assert(H * 512 + 4 <= CPW * 68 * 4, "half of the worst-case records fit one plane's rows");
+    const uint32_t sh = (uint32_t)__builtin_amdgcn_readlane((int)incl, 4 * H - 1);   // bytes of chunks < H
+    const Staging S0 = make_staging((uint32_t *)(s.re + tix((uint32_t)c0 << 6)));
+    const Staging S1 = make_staging((uint32_t *)(s.im + tix((uint32_t)c0 << 6)));
+    const bool upper = qc >= H;
     if (total) {
         wave_sync_lds();                              // every lane has read its values
         // zero the stream's staging words (the payload fields are ORed in)
-        zero_staging(S, total >> 2);
+        zero_staging(S0, sh >> 2);
+        zero_staging(S1, (total - sh) >> 2);
         wave_sync_lds();
-        if (act && (h0 | h1)) stage_record(P0, P1, Lv, S, rel, q);
+        if (act && (h0 | h1)) stage_record(P0, P1, Lv, upper ? S1 : S0, upper ? rel - sh : rel, q);
         wave_sync_lds();
     }
     const uint64_t b = uniform_u64(got);
@@ -1001,7 +1020,9 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     const uint64_t off = wave_off + rel;
     if (!overflow && total) {
         // copy the staged stream out
-        copy_staging(S, total >> 2, (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, wave_off));
+        uint32_t *dst = (uint32_t *)body_ptr(a.pool_out, a.host_out, a.pool_cap, wave_off);
+        copy_staging(S0, sh >> 2, dst);
+        copy_staging(S1, (total - sh) >> 2, dst + (sh >> 2));
     }
     if (act && q == 0)
         a.dir_out[g >> 6] = (h0 | h1) == 0u ? 0ull
@@ -1266,7 +1287,7 @@ __global__ void init_state_kernel(uint64_t *dir, uint8_t *pool, unsigned long lo
     const uint32_t h0 = act ? P0.hdr : 0u, h1 = act ? P1.hdr : 0u;
     const Layout Lv = layout_of(h0, h1);
     const uint32_t size = rfl(Lv.size);
-    const Staging S = make_staging(stage, stage, kSlotBytes / 4);
+    const Staging S = make_staging(stage);
     zero_staging(S, kSlotBytes / 4);
     wave_sync_lds();
     if (act && (h0 | h1)) stage_record(P0, P1, Lv, S, 0u, q);
@@ -1532,7 +1553,7 @@ __global__ __launch_bounds__(256) void codec_slots_encode_kernel(const float *re
     constexpr uint32_t SW = kSlotBytes / 4;                 // words per slot
     __shared__ __align__(16) uint32_t stage[4][16 * SW];
     const int lane = lane_id(), q = lane & 3, qc = lane >> 2, wave = (int)(threadIdx.x >> 6);
-    const Staging S = make_staging(stage[wave], stage[wave], 16 * SW);
+    const Staging S = make_staging(stage[wave]);
     BMQ_WAVE_RUNS(b0, nch) {
         const uint64_t c = b0 + (uint64_t)qc;
         const bool act = c < nch;
@@ -1649,7 +1670,7 @@ __global__ __launch_bounds__(256) void codec_write_kernel(const float *re, const
         h[2] = (uint32_t)(nch * 64);
         h[3] = (uint32_t)nch;
     }
-    const Staging S = make_staging(stage[wave], stage[wave], 16 * SW);
+    const Staging S = make_staging(stage[wave]);
     BMQ_WAVE_RUNS(b0, nch) {
         const uint64_t c = b0 + (uint64_t)qc;
         const bool act = c < nch;
