@@ -68,10 +68,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="random workload: skip the batched 512-circuit sub-line")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="random workload: no tile / fusion autotuning (fusion width 5 unless --fuse)")
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the diagonal-free planner variant (profiles of the headline launches only)")
     ap.add_argument("--cpu-n", type=int, default=0,
-                    help="qubits of the CPU-baseline sample (default 22)")
+                    help="qubits of the CPU-baseline sample (default 30: the headline's generator and global-qubit count)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="CPU baseline: stop after the stage that passes this much oracle time")
     ap.add_argument("--variant-steps", type=int, default=3, help="timed steps of the planner variant")
@@ -81,6 +83,11 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration) and exit")
     return ap.parse_args()
+
+
+def progress(msg):
+    """A progress line on stderr (the result is the one JSON line on stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def copy_calibration():
@@ -174,7 +181,8 @@ def cpu_baseline(workload: str, n: int, seconds: float):
     qubits), decode every SV block with the CPU codec, apply the stage's
     gates in FP64 (OpenMP), re-encode every block; the blocks' codec calls
     run on a thread per core.  Stops after the stage that passes `seconds`
-    and reports amplitude*gates/s over the stages it ran."""
+    and reports amplitude*gates/s over the stages it ran, with the codec's
+    own rate (uncompressed float32 bytes decoded and encoded per second)."""
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
@@ -200,6 +208,7 @@ def cpu_baseline(workload: str, n: int, seconds: float):
     streams = [N.encode_block(one if k == 0 else zero, zero, d["domain"], d["eb"]) for k in range(nb)]
     done_gates = 0
     ran = 0
+    t_dec = t_app = t_enc = 0.0
     t0 = time.perf_counter()
     for s0, s1 in stages:
         psi = np.empty(1 << n, dtype=np.complex128)
@@ -207,22 +216,35 @@ def cpu_baseline(workload: str, n: int, seconds: float):
         def dec(k):
             r, i = N.decode_block(streams[k], blk)
             psi[k * blk:(k + 1) * blk] = r.astype(np.float64) + 1j * i.astype(np.float64)
+        ta = time.perf_counter()
         list(pool.map(dec, range(nb)))
+        tb = time.perf_counter()
         psi = N.apply_circuit(psi, n, gates[s0:s1])
+        tc = time.perf_counter()
 
         def enc(k):
             v = psi[k * blk:(k + 1) * blk]
             return N.encode_block(v.real.astype(np.float32), v.imag.astype(np.float32), d["domain"], d["eb"])
         streams = list(pool.map(enc, range(nb)))
+        td = time.perf_counter()
+        t_dec += tb - ta
+        t_app += tc - tb
+        t_enc += td - tc
         done_gates += s1 - s0
         ran += 1
+        del psi
+        progress(f"cpu baseline: stage {ran} of {len(stages)} done ({time.perf_counter() - t0:.1f} s)")
         if time.perf_counter() - t0 >= seconds:
             break
     dt = time.perf_counter() - t0
     pool.shutdown()
     name = "QFT on the same Ry product" if workload == "qft" else "random U3/CZ layers of the same generator"
+    fbytes = ran * (8 << n)            # float32 re + im per amplitude, per stage
     return dict(value=(2 ** n) * done_gates / dt, unit="amplitude·gates/s", cores=threads, kind="oracle",
                 cpu=cpu_model(), nproc=os.cpu_count(),
+                codec_decode_gbps=fbytes / t_dec / 1e9, codec_encode_gbps=fbytes / t_enc / 1e9,
+                fp64_apply_amp_gates_per_s=(2 ** n) * done_gates / t_app,
+                seconds={"decode": t_dec, "apply": t_app, "encode": t_enc},
                 sample=f"{n}-qubit {name}: first {ran} of {len(stages)} stages ({done_gates} of {len(gates)} "
                        f"gates), 2^{b}-amplitude blocks, LOG eb={d['eb']}: CPU codec decode/encode of every "
                        f"block per stage ({threads} threads) + FP64 OpenMP gate application, {dt:.1f} s")
@@ -268,6 +290,7 @@ def batch_planning(mix, flags, fuse, train=32, margin=0.1, budget_frac=0.5, seed
         train_plans.append(plan)
         sv.close()
     loss = float(loss.item())
+    progress(f"batch planning: predictor trained on {train} circuits")
     # calibration on the training circuits: the largest actual / predicted peak
     tp = np.array([float(bmq.predict_bytes(pred.params, p).max()) for p in train_plans])
     calib = max(1.0, float(np.max(np.array(train_peaks) / tp)))
@@ -359,6 +382,7 @@ def batch_line(args, planning=True):
                 st.apply(p)
         torch.cuda.synchronize()
         res[mode] = time.perf_counter() - t0
+        progress(f"batch {mode}: {res[mode] * 1e3:.1f} ms")
     fp = sum(st.footprint()[0] for st in states)
     for st in states:
         st.close()
@@ -380,6 +404,28 @@ def batch_line(args, planning=True):
     if planning:
         out["planning"] = batch_planning(mix, flags, fuse)
     return out
+
+
+def autotune_headline(d, gates, args, inner=(2,), fuse=(2, 3, 4, 5), tiles=(12, 13)):
+    """sv_autotune_space over tile sizes and fusion widths (or inner sizes)
+    on the circuit's first four layers; the winner is used for the full
+    circuit."""
+    import torch
+    from paper_2410_14088_amd import bmq
+    n = d["n"]
+    probe = 4 * (n + 8)                        # four layers: U3 on every qubit + 8 CZ
+    cfg = bmq.Config(n=n, b=d["b"], inner=inner[0], fuse=fuse[0], domain=1, eb=d["eb"],
+                     tile=args.tile or tiles[0], flags=args.flags)
+    t0 = time.perf_counter()
+    tl = (args.tile,) if args.tile else tiles
+    progress(f"autotune: tiles {tl} x fusion {fuse} x inner {inner} on the first {probe} gates")
+    best, table = bmq.autotune_space(gates, cfg, tiles=tl, fuse=fuse, inner=inner, probe_gates=probe)
+    torch.cuda.empty_cache()
+    progress(f"autotune: tile {best.tile}, fusion {best.fuse}, inner {best.inner} "
+             f"({time.perf_counter() - t0:.1f} s)")
+    return {"probe_gates": probe, "seconds": time.perf_counter() - t0,
+            "ms": {f"tile{t}_fuse{f}_inner{m}": v for (t, f, m), v in sorted(table.items())},
+            "chosen": {"tile_qubits": best.tile, "fuse_qubits": best.fuse, "inner_size": best.inner}}
 
 
 def qaoa_ring_closed_form(n, gammas, betas, xs):
@@ -467,6 +513,7 @@ def bench_qaoa_spill(args):
 
 def main():
     args = parse()
+    args.fuse_given = bool(args.fuse)
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding of the "
               "stage loop is a design note, not implemented", file=sys.stderr)
@@ -500,8 +547,14 @@ def main():
         d = C.config(2, n=n)
         gates = d["gates"]
         inverse = C.mirror(gates)[len(gates):]
-        fuse = args.fuse or 5
         wname = f"random-u3-cz-{n}q-d16"
+        fuse = args.fuse or 5
+        if not args.fuse and not args.no_autotune:
+            # tile size and fusion width by measurement (sv_autotune_space) on
+            # the first four layers; Algorithm 1's inner size stays 2
+            tune = autotune_headline(d, gates, args)
+            fuse = tune["chosen"]["fuse_qubits"]
+            args.tile = args.tile or tune["chosen"]["tile_qubits"]
     else:
         n = args.n or 33
         d = C.config(2, n=n)
@@ -526,9 +579,11 @@ def main():
         sv.reset()
         return sv.apply(plan, stats=stats)
 
+    progress(f"{wname}: {info['stages']} stages, {info['passes']} passes; warm-up")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    progress(f"{wname}: timing {args.steps} steps")
 
     all_stats = []
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -541,6 +596,7 @@ def main():
     torch.cuda.synchronize()
     total_ms = ev0.elapsed_time(ev1)
     ms_per_step = total_ms / args.steps
+    progress(f"{wname}: {ms_per_step:.1f} ms per step")
 
     # algorithmic bytes and kernel time of the pass kernels over the timed
     # steps (HIP events the library records on its stream around each stage)
@@ -636,6 +692,9 @@ def main():
         "max_abs_err": maxerr,
         "norm2": norm2,
     }
+    if args.workload == "random" and not args.fuse_given and not args.no_autotune:
+        out["autotune"] = tune
+        out["config"]["fuse_qubits_autotuned"] = True
     if args.host_resident:
         out["config"]["host_resident"] = True
         out["host_share_of_records"] = sum(s["bytes_out_host"] for s in last) / max(1, sum(s["bytes_out"] for s in last))
@@ -678,6 +737,7 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         vms = ev0.elapsed_time(ev1) / vsteps
+        progress(f"planner variant {vname}: {vms:.1f} ms per step")
         res = {"value": (2 ** n) * G / (vms * 1e-3), "ms_per_step": vms, "steps": vsteps,
                "stages": vinfo["stages"], "passes": vinfo["passes"]}
         if args.workload == "qft":
@@ -698,27 +758,45 @@ def main():
             res["fidelity_f2"] = abs(a0) ** 2 / sv.fidelity(None)[2]
         out[vname] = res
     if args.workload == "random" and not args.no_variant and not args.host_resident and not args.flags:
-        # the same circuit with fusion limited to 2 qubits: 1- and 2-qubit
-        # operations as vector butterflies in LDS instead of 5-qubit
-        # matrices on the matrix cores
-        bcfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=2, domain=d["domain"], eb=d["eb"], tile=args.tile)
-        bplan = bmq.Plan(gates, bcfg)
-        bsteps = max(1, min(args.steps, args.variant_steps))
-        sv.reset()
-        sv.apply(bplan)
-        torch.cuda.synchronize()
-        ev0.record(stream)
-        for _ in range(bsteps):
+        # the fusion comparison of the configuration: 5-qubit matrices on the
+        # matrix cores against 1- and 2-qubit operations as vector
+        # butterflies in LDS (whichever the headline is not)
+        def timed(vcfg, vsteps):
+            vplan = bmq.Plan(gates, vcfg)
             sv.reset()
-            sv.apply(bplan)
-        ev1.record(stream)
-        torch.cuda.synchronize()
-        bms = ev0.elapsed_time(ev1) / bsteps
-        sv.apply(bmq.Plan(inverse, bcfg))
-        a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
-        out["lds_butterflies"] = {"value": (2 ** n) * G / (bms * 1e-3), "ms_per_step": bms, "steps": bsteps,
-                                  "fuse_qubits": 2, "passes": bplan.info()["passes"],
-                                  "fidelity_f2": abs(a0) ** 2 / sv.fidelity(None)[2]}
+            sv.apply(vplan)
+            torch.cuda.synchronize()
+            ev0.record(stream)
+            for _ in range(vsteps):
+                sv.reset()
+                sv.apply(vplan)
+            ev1.record(stream)
+            torch.cuda.synchronize()
+            vms = ev0.elapsed_time(ev1) / vsteps
+            progress(f"variant fusion {vcfg.fuse}, inner {vcfg.inner}: {vms:.1f} ms per step")
+            sv.apply(bmq.Plan(inverse, vcfg))
+            a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
+            return {"value": (2 ** n) * G / (vms * 1e-3), "ms_per_step": vms, "steps": vsteps,
+                    "fuse_qubits": vcfg.fuse, "inner_size": vcfg.inner, "tile_qubits": vcfg.tile or 12,
+                    "stages": vplan.info()["stages"], "passes": vplan.info()["passes"],
+                    "fidelity_f2": abs(a0) ** 2 / sv.fidelity(None)[2]}
+        vsteps = max(1, min(args.steps, args.variant_steps))
+        for name, k in (("mfma_5q", 5), ("lds_butterflies", 2)):
+            if k != fuse:
+                out[name] = timed(bmq.Config(n=n, b=d["b"], inner=2, fuse=k, domain=d["domain"], eb=d["eb"],
+                                             tile=args.tile), vsteps)
+        if not args.no_autotune:
+            # Algorithm 1's inner size (the stage size) by measurement as well:
+            # fewer, larger stages (fewer compressions), more passes per stage
+            sv.close()
+            sv = None
+            torch.cuda.empty_cache()
+            st_tune = autotune_headline(d, gates, args, inner=(2, 3, 4, 5), fuse=(fuse,),
+                                        tiles=(args.tile or 12,))
+            sv = bmq.State(cfg, dev)
+            icfg = bmq.Config(n=n, b=d["b"], inner=st_tune["chosen"]["inner_size"], fuse=fuse, domain=d["domain"],
+                              eb=d["eb"], tile=args.tile)
+            out["autotuned_stage_size"] = dict(timed(icfg, vsteps), autotune=st_tune)
     if args.stats_out:
         with open(args.stats_out, "w") as f:
             json.dump(last, f, indent=1)
@@ -727,7 +805,9 @@ def main():
         sv.close()
         sv = None
         torch.cuda.empty_cache()
+        progress("batched workload: 512 circuits")
         b = batch_line(args)
+        progress("batched workload done")
         out["batch"] = {k: b[k] for k in ("value", "ms_per_step", "config", "sequential_ms", "speedup_vs_sequential",
                                           "persistent_ms", "compression_ratio_vs_complex64", "planning")}
     if not args.no_cpu_baseline and args.workload in ("qft", "random"):
@@ -735,7 +815,7 @@ def main():
             sv.close()
             sv = None
         torch.cuda.empty_cache()
-        cn = args.cpu_n or 22
+        cn = args.cpu_n or 30
         out["cpu_baseline"] = cpu_baseline(args.workload, cn, args.cpu_seconds)
     print(json.dumps(out))
 

@@ -258,6 +258,31 @@ int sv_autotune(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, 
                 uint64_t dev_bytes, void *hip_stream, size_t probe_stages, sv_config_t *best,
                 float *ms_all);
 
+/* sv_autotune_space -- the same measurement over a caller-chosen search
+ * space: every combination of the tile sizes, fusion widths and inner sizes
+ * (Algorithm 1's inner size, which sets how many global indices a stage may
+ * hold and so the number of stages; the parameter study of Section 5 varies
+ * it with the block size).  Each candidate is planned on the first
+ * probe_gates gates of the circuit (all if 0), run once to warm up and once
+ * timed from |0...0>; candidates whose plan is invalid (a gate wider than
+ * the inner size allows) or whose records overflow the pools are skipped.
+ * The arena must hold sv_mem_required(cfg) bytes (tile, fusion width and
+ * inner size do not change it); its contents are overwritten.  best: cfg
+ * with the winning tile_qubits, fuse_qubits and inner_size.  ms_out: NULL or
+ * n_tiles * n_fuse * n_inner floats, entry (it * n_fuse + ifu) * n_inner + ii
+ * = the time of (tiles[it], fuse[ifu], inner[ii]) in ms, NaN when not run.
+ * sv_autotune is this function over tiles 10..min(13, n), fusion widths 1..5
+ * and the configuration's inner size.  Synchronises. */
+typedef struct {
+    int32_t n_tiles, tiles[4];      /* tile_qubits candidates, 10..13 */
+    int32_t n_fuse, fuse[5];        /* fuse_qubits candidates, 1..5 */
+    int32_t n_inner, inner[6];      /* inner_size candidates, 1..8 */
+    uint64_t probe_gates;           /* prefix of the circuit that is timed (0: all of it) */
+} sv_tune_space_t;
+int sv_autotune_space(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, void *dev_arena,
+                      uint64_t dev_bytes, void *hip_stream, const sv_tune_space_t *space, sv_config_t *best,
+                      float *ms_out);
+
 /* ---------------------------------------------------------------- graphs
  * sv_graph_capture -- record the stage loop of stages [first, first+count)
  * of plan p on state sv (counter clearing plus every tile pass, as

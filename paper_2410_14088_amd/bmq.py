@@ -46,6 +46,11 @@ class sv_config_t(C.Structure):
                 ("eb", C.c_double), ("pool_bytes", C.c_uint64), ("flags", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+class sv_tune_space_t(C.Structure):
+    _fields_ = [("n_tiles", C.c_int32), ("tiles", C.c_int32 * 4), ("n_fuse", C.c_int32), ("fuse", C.c_int32 * 5),
+                ("n_inner", C.c_int32), ("inner", C.c_int32 * 6), ("probe_gates", C.c_uint64)]
+
+
 class sv_fidelity_t(C.Structure):
     _fields_ = [("overlap2", C.c_double), ("fidelity", C.c_double), ("overlap_re", C.c_double),
                 ("overlap_im", C.c_double), ("max_abs_err", C.c_double), ("norm2", C.c_double),
@@ -67,6 +72,7 @@ EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_
            "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
            "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
            "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune",
+           "sv_autotune_space",
            "sv_batch_workspace", "sv_batch_apply", "sv_persistent_workspace", "sv_persistent_apply",
            "sv_graph_capture_persistent",
            "sv_plan_features", "sv_plan_labels", "mlp_predict_work", "mlp_predict_bytes", "sv_admit"]
@@ -123,6 +129,8 @@ def lib():
         L.sv_graph_capture_persistent.argtypes = [V, V, V, C.c_uint64, C.c_uint32, P(V)]
         L.sv_autotune.argtypes = [V, C.c_size_t, P(sv_config_t), V, C.c_uint64, V, C.c_size_t, P(sv_config_t),
                                   P(C.c_float)]
+        L.sv_autotune_space.argtypes = [V, C.c_size_t, P(sv_config_t), V, C.c_uint64, V, P(sv_tune_space_t),
+                                        P(sv_config_t), P(C.c_float)]
         L.sv_graph_launch.argtypes = [V, V]
         L.sv_graph_sync.argtypes = [V]
         L.sv_graph_destroy.argtypes = [V]
@@ -461,6 +469,46 @@ def autotune(gates, cfg: Config, probe_stages: int = 0, device: str = "cuda:0"):
     _check(lib().sv_autotune(C.cast(arr, C.c_void_p), len(gates), C.byref(cfg.c()), C.c_void_p(base + off),
                              int(need.value), _stream(), probe_stages, C.byref(best), ms))
     table = {(10 + i // 5, 1 + i % 5): ms[i] for i in range(20) if ms[i] == ms[i]}
+    out = Config(n=best.n_qubits, b=best.block_qubits, inner=best.inner_size, fuse=best.fuse_qubits,
+                 domain=best.domain, eb=best.eb, tile=best.tile_qubits, pool_bytes=best.pool_bytes, flags=best.flags)
+    return out, table
+
+
+def autotune_space(gates, cfg: Config, tiles=(12,), fuse=(1, 2, 3, 4, 5), inner=None, probe_gates: int = 0,
+                   device: str = "cuda:0"):
+    """Measure every (tile, fusion width, inner size) candidate on the first
+    probe_gates gates (sv_autotune_space); returns (best Config,
+    {(tile, fuse, inner): ms})."""
+    import torch
+    inner = (cfg.inner,) if inner is None else tuple(inner)
+    sp = sv_tune_space_t()
+    sp.n_tiles, sp.n_fuse, sp.n_inner = len(tiles), len(fuse), len(inner)
+    for i, v in enumerate(tiles):
+        sp.tiles[i] = v
+    for i, v in enumerate(fuse):
+        sp.fuse[i] = v
+    for i, v in enumerate(inner):
+        sp.inner[i] = v
+    sp.probe_gates = probe_gates
+    need = C.c_uint64()
+    _check(lib().sv_mem_required(C.byref(cfg.c()), C.byref(need)))
+    arena = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=device)
+    base = _ptr(arena)
+    off = (-base) % 256
+    arr = gate_array(gates)
+    best = sv_config_t()
+    total = len(tiles) * len(fuse) * len(inner)
+    ms = (C.c_float * total)()
+    _check(lib().sv_autotune_space(C.cast(arr, C.c_void_p), len(gates), C.byref(cfg.c()), C.c_void_p(base + off),
+                                   int(need.value), _stream(), C.byref(sp), C.byref(best), ms))
+    del arena
+    table = {}
+    for it, t in enumerate(tiles):
+        for ifu, f in enumerate(fuse):
+            for ii, m in enumerate(inner):
+                v = ms[(it * len(fuse) + ifu) * len(inner) + ii]
+                if v == v:
+                    table[(t, f, m)] = v
     out = Config(n=best.n_qubits, b=best.block_qubits, inner=best.inner_size, fuse=best.fuse_qubits,
                  domain=best.domain, eb=best.eb, tile=best.tile_qubits, pool_bytes=best.pool_bytes, flags=best.flags)
     return out, table

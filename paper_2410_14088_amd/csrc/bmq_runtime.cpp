@@ -1228,59 +1228,108 @@ int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t co
     return SV_OK;
 }
 
-int sv_autotune(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, void *dev_arena,
-                uint64_t dev_bytes, void *hip_stream, size_t probe_stages, sv_config_t *best, float *ms_all)
+int sv_autotune_space(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, void *dev_arena,
+                      uint64_t dev_bytes, void *hip_stream, const sv_tune_space_t *space, sv_config_t *best,
+                      float *ms_out)
 {
     if (int rc = validate_cfg(cfg)) return rc;
     if (!best) return fail(SV_ERR_INVALID, "best is NULL");
-    if (ms_all)
-        for (int i = 0; i < 20; ++i) ms_all[i] = NAN;
+    if (!space) return fail(SV_ERR_INVALID, "space is NULL");
+    const sv_tune_space_t &S = *space;
+    if (S.n_tiles < 1 || S.n_tiles > 4 || S.n_fuse < 1 || S.n_fuse > 5 || S.n_inner < 1 || S.n_inner > 6)
+        return fail(SV_ERR_INVALID, "search space sizes (%d tiles, %d fusion widths, %d inner sizes) outside "
+                                    "[1, 4] x [1, 5] x [1, 6]", S.n_tiles, S.n_fuse, S.n_inner);
+    for (int i = 0; i < S.n_tiles; ++i)
+        if (S.tiles[i] < 10 || S.tiles[i] > bmq::kMaxTile || S.tiles[i] > cfg->n_qubits)
+            return fail(SV_ERR_INVALID, "tile candidate %d outside [10, min(13, n)]", S.tiles[i]);
+    for (int i = 0; i < S.n_fuse; ++i)
+        if (S.fuse[i] < 1 || S.fuse[i] > 5) return fail(SV_ERR_INVALID, "fusion candidate %d outside [1, 5]", S.fuse[i]);
+    for (int i = 0; i < S.n_inner; ++i)
+        if (S.inner[i] < 1 || S.inner[i] > 8) return fail(SV_ERR_INVALID, "inner-size candidate %d outside [1, 8]", S.inner[i]);
+    const size_t ng = S.probe_gates && S.probe_gates < n_gates ? (size_t)S.probe_gates : n_gates;
+    const int total = S.n_tiles * S.n_fuse * S.n_inner;
+    if (ms_out)
+        for (int i = 0; i < total; ++i) ms_out[i] = NAN;
     float best_ms = INFINITY;
     sv_config_t winner = *cfg;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     int rc = SV_OK;
-    for (int t = 10; t <= bmq::kMaxTile && rc == SV_OK; ++t) {
-        if (t > cfg->n_qubits) break;
-        for (int k = 1; k <= 5 && rc == SV_OK; ++k) {
-            sv_config_t c = *cfg;
-            c.tile_qubits = t;
-            c.fuse_qubits = k;
-            sv_plan_t *p = nullptr;
-            sv_t *sv = nullptr;
-            rc = stage_plan(gates, n_gates, &c, &p);
-            if (rc == SV_OK) rc = sv_create(&c, dev_arena, dev_bytes, hip_stream, &sv);
-            const size_t ns = p ? p->stages.size() : 0;
-            const size_t cnt = probe_stages && probe_stages < ns ? probe_stages : ns;
-            float ms = 0.0f;
-            // one warm-up run (first launches load code), then the timed run
-            for (int rep = 0; rc == SV_OK && rep < 2; ++rep) {
-                rc = sv_reset(sv);
-                if (rc == SV_OK && hipEventRecord(e0, sv->stream) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
-                if (rc == SV_OK) rc = stage_apply_compressed(sv, p, 0, cnt, nullptr);
-                if (rc == SV_OK && hipEventRecord(e1, sv->stream) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
-                if (rc == SV_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
-                if (rc == SV_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
-            }
-            if (sv) sv_destroy(sv);
-            if (p) plan_destroy(p);
-            if (rc == SV_ERR_CAPACITY) rc = SV_OK;     // this candidate does not fit the pools: skip it
-            else if (rc == SV_OK) {
-                if (ms_all) ms_all[(t - 10) * 5 + (k - 1)] = ms;
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    winner = c;
+    for (int it = 0; it < S.n_tiles && rc == SV_OK; ++it)
+        for (int ifu = 0; ifu < S.n_fuse && rc == SV_OK; ++ifu)
+            for (int ii = 0; ii < S.n_inner && rc == SV_OK; ++ii) {
+                sv_config_t c = *cfg;
+                c.tile_qubits = S.tiles[it];
+                c.fuse_qubits = S.fuse[ifu];
+                c.inner_size = S.inner[ii];
+                sv_plan_t *p = nullptr;
+                sv_t *sv = nullptr;
+                rc = stage_plan(gates, ng, &c, &p);
+                if (rc == SV_ERR_INVALID) {          // a gate this inner size cannot hold: not a candidate
+                    rc = SV_OK;
+                    continue;
+                }
+                if (rc == SV_OK) rc = sv_create(&c, dev_arena, dev_bytes, hip_stream, &sv);
+                float ms = 0.0f;
+                // one warm-up run (first launches load code), then the timed run
+                for (int rep = 0; rc == SV_OK && rep < 2; ++rep) {
+                    rc = sv_reset(sv);
+                    if (rc == SV_OK && hipEventRecord(e0, sv->stream) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
+                    if (rc == SV_OK) rc = stage_apply_compressed(sv, p, 0, p->stages.size(), nullptr);
+                    if (rc == SV_OK && hipEventRecord(e1, sv->stream) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
+                    if (rc == SV_OK && hipEventSynchronize(e1) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
+                    if (rc == SV_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(SV_ERR_HIP, "event");
+                }
+                if (sv) sv_destroy(sv);
+                if (p) plan_destroy(p);
+                if (rc == SV_ERR_CAPACITY) rc = SV_OK;     // this candidate does not fit the pools: skip it
+                else if (rc == SV_OK) {
+                    if (ms_out) ms_out[(it * S.n_fuse + ifu) * S.n_inner + ii] = ms;
+                    if (ms < best_ms) {
+                        best_ms = ms;
+                        winner = c;
+                    }
                 }
             }
-        }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != SV_OK) return rc;
     if (!(best_ms < INFINITY)) return fail(SV_ERR_CAPACITY, "no candidate fits the pools");
     *best = winner;
     return SV_OK;
+}
+
+int sv_autotune(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, void *dev_arena,
+                uint64_t dev_bytes, void *hip_stream, size_t probe_stages, sv_config_t *best, float *ms_all)
+{
+    if (int rc = validate_cfg(cfg)) return rc;
+    // the probe is a prefix of the circuit: the gates of its first probe_stages stages
+    size_t probe_gates = 0;
+    if (probe_stages) {
+        sv_plan_t *p = nullptr;
+        if (int rc = stage_plan(gates, n_gates, cfg, &p)) return rc;
+        if (probe_stages < p->stages.size() && !(cfg->flags & SV_FLAG_COMMUTE))
+            probe_gates = p->stages[probe_stages - 1].g1;
+        plan_destroy(p);
+    }
+    sv_tune_space_t S{};
+    S.n_tiles = 0;
+    for (int t = 10; t <= bmq::kMaxTile && t <= cfg->n_qubits; ++t) S.tiles[S.n_tiles++] = t;
+    S.n_fuse = 5;
+    for (int k = 1; k <= 5; ++k) S.fuse[k - 1] = k;
+    S.n_inner = 1;
+    S.inner[0] = cfg->inner_size;
+    S.probe_gates = probe_gates;
+    float ms[20];
+    const int rc = sv_autotune_space(gates, n_gates, cfg, dev_arena, dev_bytes, hip_stream, &S, best, ms);
+    if (ms_all) {
+        for (int i = 0; i < 20; ++i) ms_all[i] = NAN;
+        if (rc == SV_OK)
+            for (int it = 0; it < S.n_tiles; ++it)
+                for (int k = 0; k < 5; ++k) ms_all[(S.tiles[it] - 10) * 5 + k] = ms[it * 5 + k];
+    }
+    return rc;
 }
 
 int sv_graph_capture(sv_t *sv, const sv_plan_t *p, size_t first, size_t count, sv_graph_t **out)

@@ -112,6 +112,32 @@ def test_autotune_picks_a_measured_candidate():
     assert f2 >= 0.9999
 
 
+def test_autotune_space_over_inner_sizes():
+    """sv_autotune_space: every (tile, fusion, inner) candidate is timed on
+    the circuit prefix; the winner is the fastest, and inner size 1 (the
+    threshold of Algorithm 1 is max(inner, 2)) plans the same stages as 2."""
+    d = C.config(0)
+    n, b = d["n"], d["b"]
+    cfg = bmq.Config(n=n, b=b, inner=2, fuse=2, domain=1, eb=1e-5)
+    best, table = bmq.autotune_space(d["gates"], cfg, tiles=(10, 12), fuse=(2, 3), inner=(1, 2, 4), probe_gates=96)
+    print({k: round(v, 3) for k, v in table.items()}, "->", best.tile, best.fuse, best.inner, flush=True)
+    assert len(table) == 2 * 2 * 3
+    assert table[(best.tile, best.fuse, best.inner)] == min(table.values())
+    # more inner indices per stage: fewer stages on the full circuit
+    stages = [bmq.Plan(d["gates"], bmq.Config(n=n, b=b, inner=m, fuse=2, domain=1, eb=1e-5)).n_stages
+              for m in (2, 3, 4)]
+    assert stages[0] > stages[1] > stages[2]
+    # the winner runs the whole circuit within the fidelity bound
+    plan = bmq.Plan(d["gates"], best)
+    sv = bmq.State(best, DEV)
+    sv.apply(plan)
+    ref = torch.from_numpy(np.ascontiguousarray(N.simulate(n, d["gates"]))).to(DEV)
+    f2, _, _ = sv.fidelity(ref)
+    assert f2 >= 0.9999
+    with pytest.raises(bmq.BmqError):
+        bmq.autotune_space(d["gates"], cfg, tiles=(9,), fuse=(2,), inner=(2,))
+
+
 @pytest.mark.parametrize("which", ["random16", "qft20"])
 def test_persistent_launch_in_a_graph_matches_per_pass(which):
     """The whole-circuit queue launch captured in a HIP graph
