@@ -1067,21 +1067,25 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_batch(const PassArg
 }
 
 // Whole-circuit launch over a work queue: every stage of every circuit in
-// one launch.  Each workgroup takes the next (pass, tile) item from a single
-// device counter, runs it with the same pass body as the per-pass launches
-// and counts it done; a tile of a pass that depends on an earlier pass (the
-// previous pass of the same circuit) first waits until every tile of that
-// pass is done: the per-circuit stage barrier of an atomic done-counter.
+// one launch.  Each workgroup takes the next (pass, tile-run) item from a
+// single device counter, runs it with the same pass body as the per-pass
+// launches, and counts its finished items of a pass into that pass's
+// done-counter when it moves on to an item of another pass (or runs out of
+// items): one release and one atomic per workgroup and pass, not per item.
+// An item of a pass that depends on an earlier pass (the previous pass of
+// the same circuit) first waits until every item of that pass is counted:
+// the per-circuit stage barrier of an atomic done-counter.
 // Items are handed out in queue order, only to running workgroups, and a
-// dependency always precedes its dependants, so every item a waiting
-// workgroup depends on is already held by a running workgroup: the earliest
-// unfinished item never waits and the queue always drains, whatever number
-// of workgroups is resident.  Every wait is bounded (pa.limit_ticks of the
-// constant-rate clock); a wait that runs out raises the abort flag, after
-// which every workgroup leaves at its claim or wait, so the grid always
-// finishes.  One item per workgroup (the grid has one workgroup per item)
-// keeps the pass body free of an item loop, which would make the compiler
-// keep per-thread values live across items.
+// dependency always precedes its dependants.  A workgroup publishes its
+// finished items before it waits on anything and never waits on a pass it
+// holds uncounted items of, and the claim it takes while running an item
+// is always later in the queue than that item; so every item a waiting
+// workgroup depends on is finished or held by a workgroup that is running
+// or about to run it, the earliest unfinished item never waits, and the
+// queue always drains whatever number of workgroups is resident.  Every
+// wait is bounded (pa.limit_ticks of the constant-rate clock); a wait that
+// runs out raises the abort flag, after which every workgroup leaves at its
+// next claim or wait, so the grid always finishes.
 template <int T, int NT, int DOM>
 __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_queue(PersistArgs pa)
 {
@@ -1089,21 +1093,39 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_queue(PersistArgs p
     typedef const __attribute__((address_space(4))) PassArgs CArgs;
     uint32_t *const next = pa.sync, *const abort_flag = pa.sync + 1, *const done = pa.sync + kSyncHead;
     int acquired = -1;
+    int pend_pass = -1;             // pass of the finished, not yet counted items (same in every thread)
+    uint32_t pend_n = 0;
+    uint32_t claim = 0;             // thread 0: the next item, claimed while the current one runs
+    if (threadIdx.x == 0) claim = atomicAdd(next, 1u);
     for (;;) {
-        if (threadIdx.x == 0) {
-            uint32_t it = atomicAdd(next, 1u);
-            if (__hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) it = pa.total;
-            s_item = it;
-        }
+        if (threadIdx.x == 0)
+            s_item = __hip_atomic_load(abort_flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? pa.total : claim;
         __syncthreads();
         const uint32_t it = s_item;
-        if (it >= pa.total) return;
-        int lo = 0, hi = (int)pa.n_pass;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (pa.first_item[mid] <= it) lo = mid;
-            else hi = mid;
+        __syncthreads();                                // s_item is rewritten only after every thread read it
+        int lo = 0;
+        if (it < pa.total) {
+            int hi = (int)pa.n_pass;
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pa.first_item[mid] <= it) lo = mid;
+                else hi = mid;
+            }
         }
+        if (pend_n && (it >= pa.total || lo != pend_pass)) {
+            // publish: every wave's records and directory entries of the
+            // counted items are visible device-wide (or system-wide) first
+            if (pa.system_scope) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
+            else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                if (pa.system_scope)
+                    __hip_atomic_fetch_add(done + pend_pass, pend_n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                else __hip_atomic_fetch_add(done + pend_pass, pend_n, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            pend_n = 0;
+        }
+        if (it >= pa.total) return;
         const int d = pa.dep[lo];
         if (d >= 0 && d != acquired) {
             if (threadIdx.x == 0) {
@@ -1128,16 +1150,12 @@ __global__ __launch_bounds__(NT, 1024 / NT) void pass_kernel_queue(PersistArgs p
             else __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             acquired = d;
         }
+        if (threadIdx.x == 0) claim = atomicAdd(next, 1u);
         const uint32_t tpi = pa.tiles_per_item[lo];
         const uint32_t tile0 = (it - pa.first_item[lo]) * tpi;
         for (uint32_t u = 0; u < tpi; ++u) pass_body<T, NT, DOM, false, CArgs>(((CArgs *)pa.args)[lo], tile0 + u);
-        if (pa.system_scope) __builtin_amdgcn_fence(__ATOMIC_RELEASE, "");
-        else __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            if (pa.system_scope) __hip_atomic_fetch_add(done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-            else __hip_atomic_fetch_add(done + lo, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        pend_pass = lo;
+        ++pend_n;
     }
 }
 

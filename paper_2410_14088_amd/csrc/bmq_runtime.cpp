@@ -1524,11 +1524,11 @@ int plan_persistent(sv_t *const *states, const sv_plan_t *const *plans, size_t c
                 kmax = std::max(kmax, launches_of(plans[i], 0, plans[i]->stages.size()));
             }
         if (c.members.empty()) continue;
-        // An item is a run of consecutive tiles of one pass, so that the two
-        // device-wide atomics and the cache write-back of finishing an item
-        // are paid once per run: as long as every pass step still has about
-        // eight items per resident workgroup (resident: four per compute
-        // unit), up to 32 tiles per item.
+        // An item is a run of consecutive tiles of one pass, so that the
+        // device-wide claim of an item is paid once per run: as long as
+        // every pass step still has about eight items per resident
+        // workgroup (resident: four per compute unit), up to 32 tiles per
+        // item.  Finished items are counted once per workgroup and pass.
         uint64_t widest = 0;
         for (size_t k = 0; k < kmax; ++k) {
             uint64_t w = 0;
