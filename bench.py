@@ -55,8 +55,9 @@ def parse():
                          "uncompressed complex64 size")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--n", type=int, default=0, help="qubits (default: 33 for random, 30 for qft)")
-    ap.add_argument("--flags", type=int, default=0,
-                    help="sv_config_t flags (1 no scratch, 2 no MFMA, 4 one stage per gate)")
+    ap.add_argument("--flags", type=int, default=None,
+                    help="sv_config_t flags (1 no scratch, 2 no MFMA, 4 one stage per gate, 8 diagonal-free, "
+                         "16 commutation-aware, 32 group-sized scratch; default 32, batch workload 1)")
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--domain", choices=["log", "lin", "raw"], default="log",
                     help="codec domain of the qft / random-mirror workloads (default log; raw = no compression)")
@@ -359,7 +360,7 @@ def batch_line(args, planning=True):
     from paper_2410_14088_amd import bmq
     from paper_2410_14088_amd import circuits as C
     mix = C.batch_mix(args.batch_count)
-    flags = args.flags or 1                     # no scratch planes: 512 arenas must fit together
+    flags = args.flags if args.flags_given and args.flags else 1   # no scratch planes: 512 arenas fit together
     fuse = args.fuse if args.workload == "batch" and args.fuse else 4
     states, plans, amp_gates = [], [], 0
     for d in mix:
@@ -514,6 +515,10 @@ def bench_qaoa_spill(args):
 def main():
     args = parse()
     args.fuse_given = bool(args.fuse)
+    args.flags_given = args.flags is not None
+    if args.flags is None:
+        # scratch planes sized for one SV group (multi-pass stages run group by group)
+        args.flags = 0 if args.workload == "batch" else 32
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding of the "
               "stage loop is a design note, not implemented", file=sys.stderr)
@@ -655,7 +660,8 @@ def main():
     prof_key = args.workload if (args.domain == "log" and args.eb in (0.0, 1e-5) and not args.host_resident) \
         else "other"
     arena = int(sv.arena.numel())
-    scratch = 0 if args.flags & bmq.SV_FLAG_NO_SCRATCH else 8 << n
+    scratch = 0 if args.flags & bmq.SV_FLAG_NO_SCRATCH else 8 << (
+        min(n, max(d["b"] + 2, args.tile or 12)) if args.flags & bmq.SV_FLAG_GROUP_SCRATCH else n)
     out = {
         "metric": METRIC,
         "value": (2 ** n) * G / (ms_per_step * 1e-3),
@@ -757,7 +763,8 @@ def main():
             a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
             res["fidelity_f2"] = abs(a0) ** 2 / sv.fidelity(None)[2]
         out[vname] = res
-    if args.workload == "random" and not args.no_variant and not args.host_resident and not args.flags:
+    if args.workload == "random" and not args.no_variant and not args.host_resident and \
+            not args.flags & ~bmq.SV_FLAG_GROUP_SCRATCH:
         # the fusion comparison of the configuration: 5-qubit matrices on the
         # matrix cores against 1- and 2-qubit operations as vector
         # butterflies in LDS (whichever the headline is not)
@@ -793,9 +800,9 @@ def main():
             torch.cuda.empty_cache()
             st_tune = autotune_headline(d, gates, args, inner=(2, 3, 4, 5), fuse=(fuse,),
                                         tiles=(args.tile or 12,))
-            sv = bmq.State(cfg, dev)
             icfg = bmq.Config(n=n, b=d["b"], inner=st_tune["chosen"]["inner_size"], fuse=fuse, domain=d["domain"],
-                              eb=d["eb"], tile=args.tile)
+                              eb=d["eb"], tile=args.tile, flags=args.flags)
+            sv = bmq.State(icfg, dev)
             out["autotuned_stage_size"] = dict(timed(icfg, vsteps), autotune=st_tune)
     if args.stats_out:
         with open(args.stats_out, "w") as f:

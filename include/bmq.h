@@ -126,6 +126,17 @@ typedef struct {
  * back.  Combines with SV_FLAG_DIAGONAL_FREE; ignored with
  * SV_FLAG_GATE_PER_STAGE. */
 #define SV_FLAG_COMMUTE 16u
+/* SV_FLAG_GROUP_SCRATCH: the scratch planes hold one SV group instead of the
+ * whole state.  A stage that needs several tile passes then runs all of its
+ * passes group by group (Section 4.2: the groups of a stage are independent),
+ * so the planes shrink from 2^n to 2^max(b + max(inner, 2), tile) amplitudes
+ * each (e.g. 512 MiB instead of 64 GiB per plane pair at n = 33, b = 24).
+ * Same records as full scratch planes.  A plan whose multi-pass stage spans
+ * more qubits than that (a larger inner size or tile) is refused with
+ * SV_ERR_INVALID; batched and whole-circuit queue launches refuse such
+ * states when a stage has several passes (SV_ERR_UNSUPPORTED).  Ignored with
+ * SV_FLAG_NO_SCRATCH. */
+#define SV_FLAG_GROUP_SCRATCH 32u
 
 /* Per-stage statistics (all counts over the whole state). */
 typedef struct {

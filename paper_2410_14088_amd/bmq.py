@@ -8,6 +8,7 @@ missing, :func:`lib` raises -- there is no fallback path.
 from __future__ import annotations
 
 import ctypes as C
+import dataclasses
 import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
@@ -23,6 +24,7 @@ SV_FLAG_NO_MFMA = 2
 SV_FLAG_GATE_PER_STAGE = 4
 SV_FLAG_DIAGONAL_FREE = 8
 SV_FLAG_COMMUTE = 16
+SV_FLAG_GROUP_SCRATCH = 32
 SV_CHUNK_SLOT_BYTES = 576
 KIND = {k: i for i, k in enumerate(
     ["H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "U3", "CX", "CZ", "CP", "RZZ"])}
@@ -490,8 +492,11 @@ def autotune_space(gates, cfg: Config, tiles=(12,), fuse=(1, 2, 3, 4, 5), inner=
     for i, v in enumerate(inner):
         sp.inner[i] = v
     sp.probe_gates = probe_gates
-    need = C.c_uint64()
-    _check(lib().sv_mem_required(C.byref(cfg.c()), C.byref(need)))
+    need = C.c_uint64(0)
+    for m in inner:                         # group-sized scratch grows with the inner size
+        nm = C.c_uint64()
+        _check(lib().sv_mem_required(C.byref(dataclasses.replace(cfg, inner=m).c()), C.byref(nm)))
+        need = nm if nm.value > need.value else need
     arena = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=device)
     base = _ptr(arena)
     off = (-base) % 256

@@ -70,8 +70,14 @@ struct PoolView {
 struct PassArgs {
     int32_t n, t;
     int32_t tileq[16];        // tile position -> global qubit (positions 0..5 are qubits 0..5)
-    int32_t nontile[48];      // non-tile qubits, ascending; tile id bit i -> qubit nontile[i]
+    int32_t nontile[48];      // non-tile qubits of the launch, ascending; tile id bit i -> qubit nontile[i]
     int32_t n_nontile;
+    uint64_t fixed;           // bits of the amplitude index fixed for the whole launch (a group's outer bits)
+    // scratch-plane positions of the same qubits: the scratch holds one group
+    // of a multi-pass stage, with the group's qubits packed in ascending order
+    // (identical to tileq / nontile when it holds the whole state)
+    int32_t stileq[16];
+    int32_t snontile[48];
     int32_t op_begin, op_end;
     int32_t in_mode, out_mode;
     CodecParams cp;
@@ -85,6 +91,7 @@ struct PassArgs {
     uint64_t host_cap;              // host pool bytes per state copy (0: no host level)
     uint64_t seg_cap;               // bytes per output pool segment
     int32_t n_seg;                  // segments in use (power of two <= kSegments)
+    uint32_t seg_base;              // wave index of the launch's first wave (a group's launches continue the count)
     unsigned long long *counters;   // this stage's block of kSegments x C_NUM
     float *scr_re, *scr_im;
     const OpDesc *ops;

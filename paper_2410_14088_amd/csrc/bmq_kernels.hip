@@ -872,7 +872,7 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const CodecParams cp = copy_cp(a.cp);
-    const uint64_t base = deposit((uint64_t)tile, a.nontile, a.n_nontile);
+    const uint64_t base = deposit((uint64_t)tile, a.nontile, a.n_nontile) | a.fixed;
     const int c0 = wave * CPW;
 
 
@@ -902,10 +902,11 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         // multiple of 4, so the chunk index bits of c0, 4i and r are
         // disjoint and deposit separately)
         const int r = lane >> 4, u = lane & 15;
-        const uint64_t gl = base | deposit((uint64_t)(c0 | r), a.tileq + 6, T - 6);
+        const uint64_t gl = deposit((uint64_t)tile, a.snontile, a.n_nontile) |
+                            deposit((uint64_t)(c0 | r), a.stileq + 6, T - 6);
 #pragma unroll
         for (int i = 0; i < CPW / 4; ++i) {
-            const uint64_t g = (gl | deposit((uint64_t)(4 * i), a.tileq + 6, T - 6)) + 4u * (uint32_t)u;
+            const uint64_t g = (gl | deposit((uint64_t)(4 * i), a.stileq + 6, T - 6)) + 4u * (uint32_t)u;
             const float4 vr = *(const float4 *)(a.scr_re + g);
             const float4 vi = *(const float4 *)(a.scr_im + g);
             const uint32_t e = tix((uint32_t)((c0 + 4 * i + r) << 6) + 4u * (uint32_t)u);
@@ -944,10 +945,11 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     if (a.out_mode == IO_SCRATCH) {
         // 16 bytes per lane and plane, as the scratch load above
         const int r = lane >> 4, u = lane & 15;
-        const uint64_t gl = base | deposit((uint64_t)(c0 | r), a.tileq + 6, T - 6);
+        const uint64_t gl = deposit((uint64_t)tile, a.snontile, a.n_nontile) |
+                            deposit((uint64_t)(c0 | r), a.stileq + 6, T - 6);
 #pragma unroll
         for (int i = 0; i < CPW / 4; ++i) {
-            const uint64_t g = (gl | deposit((uint64_t)(4 * i), a.tileq + 6, T - 6)) + 4u * (uint32_t)u;
+            const uint64_t g = (gl | deposit((uint64_t)(4 * i), a.stileq + 6, T - 6)) + 4u * (uint32_t)u;
             const uint32_t e = tix((uint32_t)((c0 + 4 * i + r) << 6) + 4u * (uint32_t)u);
             *(float4 *)(a.scr_re + g) = make_float4(s.re[e], s.re[e + 1], s.re[e + 2], s.re[e + 3]);
             *(float4 *)(a.scr_im + g) = make_float4(s.im[e], s.im[e + 1], s.im[e + 2], s.im[e + 3]);
@@ -977,7 +979,7 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     const uint32_t size = (q == 0) ? Lv.size : 0u;
     const uint32_t incl = wave_scan_add(size);
     const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-    const uint32_t seg = (tile * NW + (uint32_t)wave) & (uint32_t)(a.n_seg - 1);
+    const uint32_t seg = (a.seg_base + tile * NW + (uint32_t)wave) & (uint32_t)(a.n_seg - 1);
     unsigned long long *cnt = a.counters + seg * C_NUM;
     // the wave's allocation: issued now, its result is needed only for the
     // copy-out, so the record staging below runs while it is in flight
@@ -1768,7 +1770,7 @@ static inline unsigned grid_for(uint64_t work, unsigned per_block, unsigned cap 
 
 hipError_t launch_pass(const PassArgs &a, hipStream_t s)
 {
-    const uint64_t tiles = 1ull << (a.n - a.t);
+    const uint64_t tiles = 1ull << a.n_nontile;
     if (tiles > 0x7FFFFFFFull) return hipErrorInvalidValue;
     const dim3 grid((unsigned)tiles);
     const int key = a.t * 3 + a.cp.domain;

@@ -163,6 +163,8 @@ struct sv_state {
     uint8_t *pool[2] = {nullptr, nullptr};
     uint64_t pool_cap = 0;
     float *scr_re = nullptr, *scr_im = nullptr;   // NULL with SV_FLAG_NO_SCRATCH
+    uint64_t scr_elems = 0;                       // amplitudes per scratch plane
+    bool group_scratch = false;                   // planes hold one group (SV_FLAG_GROUP_SCRATCH)
     uint8_t *host[2] = {nullptr, nullptr};        // host pool halves (second memory level), device view
     uint8_t *host_h[2] = {nullptr, nullptr};      // the same halves, host view
     uint64_t host_cap = 0;                        // usable bytes per half
@@ -225,7 +227,7 @@ int validate_cfg(const sv_config_t *c)
     if (!(c->eb > 0) || !std::isfinite(c->eb) || !std::isfinite((float)c->eb) || (float)c->eb <= 0)
         return fail(SV_ERR_INVALID, "eb must be a positive finite float32");
     if (c->flags & ~(SV_FLAG_NO_SCRATCH | SV_FLAG_NO_MFMA | SV_FLAG_GATE_PER_STAGE | SV_FLAG_DIAGONAL_FREE |
-                     SV_FLAG_COMMUTE)) return fail(SV_ERR_INVALID, "unknown flags 0x%x", c->flags);
+                     SV_FLAG_COMMUTE | SV_FLAG_GROUP_SCRATCH)) return fail(SV_ERR_INVALID, "unknown flags 0x%x", c->flags);
     if (c->reserved) return fail(SV_ERR_INVALID, "reserved must be 0");
     if (c->domain != SV_DOMAIN_RAW && !step_ok(c->domain, step_shift((float)c->eb)))
         return fail(SV_ERR_INVALID, "eb %g outside the codec's range for this domain (LOG: 2^-23 <= eb < 1/2)", c->eb);
@@ -572,8 +574,18 @@ bool plan_passes(sv_plan &P, StagePlan &st)
     return true;
 }
 
+// log2 of the amplitudes one scratch plane holds: the whole state, or with
+// SV_FLAG_GROUP_SCRATCH one SV group of the largest multi-pass stage the
+// configuration plans (block qubits + threshold, at least a tile)
+int scratch_qubits(const sv_config_t &c)
+{
+    if (!(c.flags & SV_FLAG_GROUP_SCRATCH)) return c.n_qubits;
+    const int t = c.tile_qubits ? c.tile_qubits : kDefaultTile;
+    return std::min(c.n_qubits, std::max(c.block_qubits + std::max(c.inner_size, 2), t));
+}
+
 struct ArenaLayout {
-    uint64_t dir_bytes, pool_cap, scr_bytes, counters_bytes, partials_bytes, ops_bytes, total;
+    uint64_t dir_bytes, pool_cap, scr_elems, scr_bytes, counters_bytes, partials_bytes, ops_bytes, total;
     uint64_t off_dir0, off_dir1, off_pool0, off_pool1, off_scr_re, off_scr_im, off_counters,
         off_partials, off_out5, off_ops, off_stage;
 };
@@ -588,7 +600,8 @@ ArenaLayout layout_for(const sv_config_t &c)
     const uint64_t worst = nch * bmq::kMaxBodyBytes + bmq::kSegments * 256ull;
     L.pool_cap = c.pool_bytes ? c.pool_bytes : worst;
     const uint64_t pool_alloc = align256(L.pool_cap + 1024);    // decoders read a little past a body
-    L.scr_bytes = (c.flags & SV_FLAG_NO_SCRATCH) ? 0 : align256((1ull << c.n_qubits) * 4ull);
+    L.scr_elems = (c.flags & SV_FLAG_NO_SCRATCH) ? 0 : 1ull << scratch_qubits(c);
+    L.scr_bytes = align256(L.scr_elems * 4ull);
     L.counters_bytes = align256((kMaxLaunchesPerBatch + 1) * kStageCounters * 8ull);
     L.partials_bytes = align256(kPartials * 5 * 8ull);
     L.ops_bytes = kOpsArenaBytes;
@@ -835,9 +848,11 @@ int sv_create(const sv_config_t *cfg, void *dev_arena, uint64_t dev_bytes, void 
     S->pool[0] = S->arena + L.off_pool0;
     S->pool[1] = S->arena + L.off_pool1;
     S->pool_cap = L.pool_cap;
-    if (L.scr_bytes) {
+    if (L.scr_elems) {
         S->scr_re = (float *)(S->arena + L.off_scr_re);
         S->scr_im = (float *)(S->arena + L.off_scr_im);
+        S->scr_elems = L.scr_elems;
+        S->group_scratch = L.scr_elems < (1ull << S->n);
     }
     S->counters = (unsigned long long *)(S->arena + L.off_counters);
     S->partials = (double *)(S->arena + L.off_partials);
@@ -945,9 +960,34 @@ int upload_plan(sv_t *sv, const sv_plan_t *p)
     return SV_OK;
 }
 
+// One SV group of a multi-pass stage run with group-sized scratch planes:
+// the group's qubits (ascending: the block qubits, the stage's inner
+// indices and any other qubit a pass's tile holds), the other (outer) qubits,
+// and the group's index, whose bits are deposited at the outer qubits.
+struct GroupRun {
+    std::vector<int> qubits, outer;
+    uint64_t g = 0;
+};
+
+// The group qubits of stage st (see GroupRun).
+void group_qubits(const sv_t *sv, const StagePlan &st, GroupRun &gr)
+{
+    std::vector<bool> in(sv->n, false);
+    for (int q = 0; q < sv->b; ++q) in[q] = true;
+    for (int q : st.inner) in[q] = true;
+    for (const PassPlan &pp : st.passes)
+        for (int q : pp.tileq) in[q] = true;
+    gr.qubits.clear();
+    gr.outer.clear();
+    for (int q = 0; q < sv->n; ++q) (in[q] ? gr.qubits : gr.outer).push_back(q);
+}
+
 // Arguments of pass pi of stage st with counter block li; flips the state's
-// current copy when the pass writes compressed output.
-void build_pass_args(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, size_t li, bmq::PassArgs &a)
+// current copy when the pass writes compressed output.  With a group, the
+// launch covers that group's tiles only and addresses the group-sized
+// scratch planes by the group qubits' packed positions.
+void build_pass_args(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, size_t li, bmq::PassArgs &a,
+                     const GroupRun *grp = nullptr)
 {
     const int n = sv->n;
     const bool scratch = sv->scr_re != nullptr;
@@ -960,10 +1000,28 @@ void build_pass_args(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, 
     std::memset(&a, 0, sizeof(a));
     a.n = n;
     a.t = p->t;
-    for (int j = 0; j < p->t; ++j) a.tileq[j] = pp.tileq[j];
+    for (int j = 0; j < p->t; ++j) a.tileq[j] = a.stileq[j] = pp.tileq[j];
     int nn = 0;
-    for (int q = 0; q < n; ++q)
-        if (std::find(pp.tileq.begin(), pp.tileq.end(), q) == pp.tileq.end()) a.nontile[nn++] = q;
+    if (!grp) {
+        for (int q = 0; q < n; ++q)
+            if (std::find(pp.tileq.begin(), pp.tileq.end(), q) == pp.tileq.end()) {
+                a.snontile[nn] = q;
+                a.nontile[nn++] = q;
+            }
+    } else {
+        // scratch position of a group qubit: its rank among the group qubits
+        auto rank = [&](int q) { return (int)(std::find(grp->qubits.begin(), grp->qubits.end(), q) - grp->qubits.begin()); };
+        for (int j = 0; j < p->t; ++j) a.stileq[j] = rank(pp.tileq[j]);
+        for (int q : grp->qubits)
+            if (std::find(pp.tileq.begin(), pp.tileq.end(), q) == pp.tileq.end()) {
+                a.snontile[nn] = rank(q);
+                a.nontile[nn++] = q;
+            }
+        for (size_t k = 0; k < grp->outer.size(); ++k)
+            a.fixed |= ((grp->g >> k) & 1ull) << grp->outer[k];
+        // the group's waves continue the segment rotation of the earlier groups
+        a.seg_base = (uint32_t)((grp->g << nn) * (p->t == 13 ? 8u : 4u));
+    }
     a.n_nontile = nn;
     a.op_begin = pp.op_begin;
     a.op_end = pp.op_end;
@@ -1006,6 +1064,49 @@ int enqueue_pass(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, size
     return SV_OK;
 }
 
+// Enqueue every launch of stage st on stream s, pass pi with counter block
+// li0 + pi.  A multi-pass stage on group-sized scratch planes runs all its
+// passes for one group, then the next group (groups are independent within a
+// stage); the launches of a pass share its counter block, so its segments'
+// cursors and statistics continue from group to group.
+int enqueue_stage(sv_t *sv, const sv_plan_t *p, const StagePlan &st, size_t li0, hipStream_t s)
+{
+    const int np = (int)st.passes.size();
+    if (!(sv->group_scratch && sv->scr_re && np > 1)) {
+        for (int pi = 0; pi < np; ++pi)
+            if (int rc = enqueue_pass(sv, p, st, pi, li0 + pi, s)) return rc;
+        return SV_OK;
+    }
+    GroupRun gr;
+    group_qubits(sv, st, gr);
+    if (gr.qubits.size() >= 64 || (1ull << gr.qubits.size()) > sv->scr_elems)
+        return fail(SV_ERR_INVALID, "a multi-pass stage spans %zu qubits; the state's group scratch holds %llu "
+                                    "amplitudes (create the state with this inner size and tile)",
+                    gr.qubits.size(), (unsigned long long)sv->scr_elems);
+    const int cur0 = sv->cur;
+    for (gr.g = 0; gr.g < (1ull << gr.outer.size()); ++gr.g)
+        for (int pi = 0; pi < np; ++pi) {
+            sv->cur = cur0;
+            bmq::PassArgs a;
+            build_pass_args(sv, p, st, pi, li0 + pi, a, &gr);
+            HIP_TRY(bmq::launch_pass(a, s));
+        }
+    sv->cur = cur0 ^ 1;
+    return SV_OK;
+}
+
+// Whether the states' plans can run in one batched or queue launch: with
+// group-sized scratch planes, a multi-pass stage runs group by group.
+int check_full_scratch(const sv_t *sv, const sv_plan_t *p, size_t i)
+{
+    if (!sv->group_scratch || !sv->scr_re) return SV_OK;
+    for (const StagePlan &st : p->stages)
+        if (st.passes.size() > 1)
+            return fail(SV_ERR_UNSUPPORTED, "state %zu has group-sized scratch planes and a multi-pass stage: run it "
+                                            "with stage_apply_compressed", i);
+    return SV_OK;
+}
+
 // Launches and counter blocks of the stage run [first, first + batch).
 size_t launches_of(const sv_plan_t *p, size_t first, size_t batch)
 {
@@ -1032,6 +1133,7 @@ int plan_batch(sv_t *const *states, const sv_plan_t *const *plans, size_t count,
     for (size_t i = 0; i < count; ++i) {
         if (int rc = check_state(states[i])) return rc;
         if (int rc = check_plan(states[i], plans[i], 0, plans[i] ? plans[i]->stages.size() : 0)) return rc;
+        if (int rc = check_full_scratch(states[i], plans[i], i)) return rc;
         for (size_t j = 0; j < i; ++j)
             if (states[j] == states[i]) return fail(SV_ERR_INVALID, "state %zu appears twice in the batch", i);
         if (states[i]->dump_re || states[i]->dumpd_re)
@@ -1214,8 +1316,8 @@ int stage_apply_compressed(sv_t *sv, const sv_plan_t *p, size_t first, size_t co
         for (size_t i = 0; i < batch; ++i) {
             const StagePlan &st = p->stages[first + done + i];
             if (stats) HIP_TRY(hipEventRecord(sv->events[2 * i], sv->stream));
-            for (int pi = 0; pi < (int)st.passes.size(); ++pi, ++li)
-                if (int rc = enqueue_pass(sv, p, st, pi, li, sv->stream)) return rc;
+            if (int rc = enqueue_stage(sv, p, st, li, sv->stream)) return rc;
+            li += st.passes.size();
             if (stats) HIP_TRY(hipEventRecord(sv->events[2 * i + 1], sv->stream));
         }
         if (int rc = read_counters(sv, launches, hc)) return rc;
@@ -1365,8 +1467,8 @@ int sv_graph_capture(sv_t *sv, const sv_plan_t *p, size_t first, size_t count, s
         size_t li = 0;
         for (size_t i = 0; e == hipSuccess && rc == SV_OK && i < count; ++i) {
             const StagePlan &st = p->stages[first + i];
-            for (int pi = 0; rc == SV_OK && pi < (int)st.passes.size(); ++pi, ++li)
-                rc = enqueue_pass(sv, p, st, pi, li, cs);
+            rc = enqueue_stage(sv, p, st, li, cs);
+            li += st.passes.size();
         }
         hipGraph_t graph = nullptr;
         const hipError_t e2 = hipStreamEndCapture(cs, &graph);

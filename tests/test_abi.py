@@ -132,7 +132,7 @@ def test_config_stage_counts(bmq):
 
 @pytest.mark.parametrize("bad", [dict(n=9), dict(n=41), dict(b=5), dict(b=17), dict(fuse=0),
                                  dict(fuse=6), dict(domain=3), dict(domain=-1), dict(eb=0.0), dict(eb=-1.0),
-                                 dict(tile=9), dict(tile=14), dict(eb=float("nan")), dict(flags=32),
+                                 dict(tile=9), dict(tile=14), dict(eb=float("nan")), dict(flags=64),
                                  dict(flags=0x80000000)])
 def test_invalid_configs_rejected(bmq, bad):
     kw = dict(n=16, b=10, inner=2, fuse=2, domain=0, eb=1e-6)

@@ -109,3 +109,51 @@ def test_mfma_and_vector_dense_paths_agree(fuse):
         assert f2 >= 0.9999 and mx < 1e-4
         out.append(sv.export())
     assert float((out[0] - out[1]).abs().max()) < 1e-5
+
+
+@pytest.mark.parametrize("which", ["qft20", "random16-t10"])
+def test_group_scratch_matches_full_scratch(which):
+    """SV_FLAG_GROUP_SCRATCH: multi-pass stages run group by group on
+    scratch planes sized for one SV group; every record equals the run with
+    whole-state scratch planes, the arena shrinks, and a captured graph of the
+    group launches replays to the same records."""
+    if which == "qft20":
+        n, b, tile, fuse = 20, 12, 12, 4
+        gates = C.qft_on_ry(n, 7)[0]
+    else:
+        d = C.config(0)
+        n, b, tile, fuse, gates = d["n"], d["b"], 10, 2, d["gates"]
+    full, plan, st_full = _run(gates, n, b, fuse=fuse, tile=tile)
+    grp, gplan, st_grp = _run(gates, n, b, fuse=fuse, tile=tile, flags=bmq.SV_FLAG_GROUP_SCRATCH)
+    multi = [s["passes"] for s in st_grp if s["passes"] > 1]
+    print(f"{which}: {len(st_grp)} stages, {len(multi)} multi-pass; arenas {full.arena.numel()} vs "
+          f"{grp.arena.numel()} bytes", flush=True)
+    assert multi, "the test needs multi-pass stages"
+    assert grp.arena.numel() < full.arena.numel()
+    assert [s["bytes_out"] for s in st_grp] == [s["bytes_out"] for s in st_full]
+    for k in range(grp.n_blocks):
+        assert grp.block_stream(k) == full.block_stream(k), k
+    # the same stage loop captured in a graph (group launches included)
+    grp.reset()
+    g = grp.capture(gplan)
+    for rep in range(3):
+        grp.reset()
+        g.launch()
+        grp.graph_sync()
+        torch.cuda.synchronize()
+        for k in range(grp.n_blocks):
+            assert grp.block_stream(k) == full.block_stream(k), (rep, k)
+    g.close()
+    # batched and queue launches need whole-state scratch for multi-pass stages
+    grp.reset()
+    with pytest.raises(bmq.BmqError) as e:
+        bmq.batch_apply([grp], [gplan])
+    assert e.value.code == -6
+    # a plan whose stages span more qubits than the group scratch holds
+    wide = bmq.Plan(gates, bmq.Config(n=n, b=b, inner=5, fuse=fuse, domain=1, eb=1e-5, tile=tile,
+                                      flags=bmq.SV_FLAG_GROUP_SCRATCH))
+    if any(wide.stage(s)["passes"] > 1 and len(wide.stage(s)["inner"]) > 2 for s in range(wide.n_stages)):
+        grp.reset()
+        with pytest.raises(bmq.BmqError) as e:
+            grp.apply(wide)
+        assert e.value.code == -1
