@@ -312,6 +312,56 @@ int sv_graph_launch(sv_t *sv, sv_graph_t *g);
 int sv_graph_sync(sv_t *sv);
 void sv_graph_destroy(sv_graph_t *g);
 
+/* ---------------------------------------------------------------- host-resident pipeline
+ * The paper's deployment (Section 4.2, Fig. 6): the compressed state lives in
+ * pinned host memory and every stage moves each SV group through the GPU --
+ * copy its blocks in, decompress / apply / recompress, copy them back -- with
+ * the groups spread over S streams so that one group's copies overlap
+ * another's kernels (the stream-count study of Section 5 varies S).
+ *
+ * Host store: one image per SV block, [the block's 2^(b-6) directory entries,
+ * body offsets relative to the image's body area] [record bodies in chunk
+ * order] (the record format of the codec), in the caller's pinned buffer.  A
+ * block's new image overwrites its old one when it fits, else it takes a new
+ * slot with a quarter of headroom (bump allocation; sv_pipe_reset starts
+ * over), so the store stays near the live compressed bytes.  Device: per
+ * stream, staging for one group (input and output directories and pools,
+ * group-sized scratch planes, packing buffers) plus the plan's operations.
+ * Records are bit-identical to stage_apply_compressed on a device state.
+ *
+ * sv_pipe_required -- device workspace bytes for cfg and `streams` (1..8),
+ *   and the smallest host store (the initial state; a run needs about
+ *   1.25 x the largest compressed state plus 8 bytes per 64 amplitudes).
+ * sv_pipe_create -- bind the device workspace (256-byte aligned, caller-owned)
+ *   and the pinned host store (hipHostMalloc or torch pin_memory, 256-byte
+ *   aligned; the library never registers or frees it), create the streams
+ *   (default priority), and set |0...0>.  SV_DOMAIN_RAW is refused.  Groups
+ *   span block_qubits + max(inner_size, 2) qubits (at least a tile).
+ * sv_pipe_reset -- back to |0...0>; the host store is reused from its start.
+ * sv_pipe_apply -- stages [first, first + count) of p; waits for earlier work
+ *   on hip_stream first and returns when every image is back in the host
+ *   store.  stats (nullable, count entries): ms = wall time of the stage,
+ *   bytes_in / bytes_out = bytes copied in / out, passes, gates, ops.
+ *   SV_ERR_CAPACITY (poisoned) when the host store is full; SV_ERR_INVALID
+ *   when a stage spans more qubits than the staging holds; SV_ERR_UNSUPPORTED
+ *   for multi-pass stages with SV_FLAG_NO_SCRATCH.
+ * sv_pipe_load -- copy the host-resident state into a device state of the same
+ *   n, b, domain and eb (its directory and current pool copy), e.g. to read or
+ *   check it with sv_fidelity / sv_block_stream.  Synchronises.
+ * sv_pipe_footprint -- record bytes, image bytes (records + directories),
+ *   host store bytes in use, and bytes copied in / out since the last reset.
+ * sv_pipe_destroy -- synchronise, destroy the streams, free the handle. */
+typedef struct sv_pipe sv_pipe_t;
+int sv_pipe_required(const sv_config_t *cfg, int32_t streams, uint64_t *dev_bytes, uint64_t *host_min_bytes);
+int sv_pipe_create(const sv_config_t *cfg, int32_t streams, void *dev_ws, uint64_t dev_bytes, void *host_pinned,
+                   uint64_t host_bytes, void *hip_stream, sv_pipe_t **out);
+int sv_pipe_reset(sv_pipe_t *pp);
+int sv_pipe_apply(sv_pipe_t *pp, const sv_plan_t *p, size_t first, size_t count, sv_stage_stats_t *stats);
+int sv_pipe_load(sv_pipe_t *pp, sv_t *sv);
+int sv_pipe_footprint(const sv_pipe_t *pp, uint64_t *record_bytes, uint64_t *image_bytes, uint64_t *host_used,
+                      uint64_t *h2d_bytes, uint64_t *d2h_bytes);
+void sv_pipe_destroy(sv_pipe_t *pp);
+
 /* ---------------------------------------------------------------- batches
  * sv_batch_apply -- run every stage of plans[i] on states[i] for count
  * independent circuits together: launch k executes the k-th tile pass of

@@ -74,7 +74,8 @@ EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_
            "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
            "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
            "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune",
-           "sv_autotune_space",
+           "sv_autotune_space", "sv_pipe_required", "sv_pipe_create", "sv_pipe_reset", "sv_pipe_apply",
+           "sv_pipe_load", "sv_pipe_footprint", "sv_pipe_destroy",
            "sv_batch_workspace", "sv_batch_apply", "sv_persistent_workspace", "sv_persistent_apply",
            "sv_graph_capture_persistent",
            "sv_plan_features", "sv_plan_labels", "mlp_predict_work", "mlp_predict_bytes", "sv_admit"]
@@ -133,6 +134,14 @@ def lib():
                                   P(C.c_float)]
         L.sv_autotune_space.argtypes = [V, C.c_size_t, P(sv_config_t), V, C.c_uint64, V, P(sv_tune_space_t),
                                         P(sv_config_t), P(C.c_float)]
+        L.sv_pipe_required.argtypes = [P(sv_config_t), C.c_int32, P(C.c_uint64), P(C.c_uint64)]
+        L.sv_pipe_create.argtypes = [P(sv_config_t), C.c_int32, V, C.c_uint64, V, C.c_uint64, V, P(V)]
+        L.sv_pipe_reset.argtypes = [V]
+        L.sv_pipe_apply.argtypes = [V, V, C.c_size_t, C.c_size_t, V]
+        L.sv_pipe_load.argtypes = [V, V]
+        L.sv_pipe_footprint.argtypes = [V] + [P(C.c_uint64)] * 5
+        L.sv_pipe_destroy.argtypes = [V]
+        L.sv_pipe_destroy.restype = None
         L.sv_graph_launch.argtypes = [V, V]
         L.sv_graph_sync.argtypes = [V]
         L.sv_graph_destroy.argtypes = [V]
@@ -474,6 +483,63 @@ def autotune(gates, cfg: Config, probe_stages: int = 0, device: str = "cuda:0"):
     out = Config(n=best.n_qubits, b=best.block_qubits, inner=best.inner_size, fuse=best.fuse_qubits,
                  domain=best.domain, eb=best.eb, tile=best.tile_qubits, pool_bytes=best.pool_bytes, flags=best.flags)
     return out, table
+
+
+def _stats_list(st, count):
+    return [dict(bytes_in=s.bytes_in, bytes_out=s.bytes_out, bytes_out_host=s.bytes_out_host,
+                 inter_bytes=s.inter_bytes, dir_bytes=s.dir_bytes, scratch_bytes=s.scratch_bytes,
+                 zero_chunks_out=s.zero_chunks_out, mode_hist=list(s.mode_hist), passes=s.passes, n_ops=s.n_ops,
+                 n_gates=s.n_gates, n_inner=s.n_inner, ms=s.ms) for s in st[:count]]
+
+
+class Pipe:
+    """Host-resident compressed state (sv_pipe_*): block images in a pinned
+    host store, each stage's SV groups moved through the device on `streams`
+    streams (copy in, decompress / apply / recompress, copy out)."""
+
+    def __init__(self, cfg: Config, streams: int = 2, host_bytes: Optional[int] = None, device: str = "cuda:0"):
+        import torch
+        self.cfg, self.streams = cfg, streams
+        dev, hmin = C.c_uint64(), C.c_uint64()
+        _check(lib().sv_pipe_required(C.byref(cfg.c()), streams, C.byref(dev), C.byref(hmin)))
+        self.ws = torch.empty(int(dev.value) + 256, dtype=torch.uint8, device=device)
+        if host_bytes is None:
+            host_bytes = int(1.4 * (8 << cfg.n)) + int(hmin.value)
+        self.host = torch.empty(int(host_bytes) + 256, dtype=torch.uint8, pin_memory=True)
+        wo = (-_ptr(self.ws)) % 256
+        ho = (-self.host.data_ptr()) % 256
+        self.h = C.c_void_p()
+        _check(lib().sv_pipe_create(C.byref(cfg.c()), streams, C.c_void_p(_ptr(self.ws) + wo), int(dev.value),
+                                    C.c_void_p(self.host.data_ptr() + ho), int(host_bytes), _stream(),
+                                    C.byref(self.h)))
+
+    def apply(self, plan: Plan, first: int = 0, count: Optional[int] = None, stats: bool = False):
+        if count is None:
+            count = plan.n_stages - first
+        st = (sv_stage_stats_t * max(1, count))() if stats else None
+        _check(lib().sv_pipe_apply(self.h, plan.h, first, count, C.cast(st, C.c_void_p) if stats else None))
+        return _stats_list(st, count) if stats else None
+
+    def reset(self):
+        _check(lib().sv_pipe_reset(self.h))
+
+    def load(self, state: "State"):
+        """Copy the host-resident state into a device State of the same configuration."""
+        _check(lib().sv_pipe_load(self.h, state.h))
+
+    def footprint(self) -> dict:
+        v = [C.c_uint64() for _ in range(5)]
+        _check(lib().sv_pipe_footprint(self.h, *[C.byref(x) for x in v]))
+        return dict(record_bytes=v[0].value, image_bytes=v[1].value, host_used=v[2].value, h2d_bytes=v[3].value,
+                    d2h_bytes=v[4].value)
+
+    def close(self):
+        if getattr(self, "h", None) and self.h.value and _lib is not None:
+            _lib.sv_pipe_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        self.close()
 
 
 def autotune_space(gates, cfg: Config, tiles=(12,), fuse=(1, 2, 3, 4, 5), inner=None, probe_gates: int = 0,

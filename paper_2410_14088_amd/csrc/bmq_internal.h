@@ -78,6 +78,9 @@ struct PassArgs {
     // (identical to tileq / nontile when it holds the whole state)
     int32_t stileq[16];
     int32_t snontile[48];
+    // the directories are indexed by the packed (scratch) positions as well:
+    // a group staged on its own, with a directory of the group's chunks only
+    int32_t dir_packed;
     int32_t op_begin, op_end;
     int32_t in_mode, out_mode;
     CodecParams cp;
@@ -181,6 +184,32 @@ hipError_t launch_codec_stream_decode(const uint8_t *src, uint64_t bytes, uint64
                                       uint64_t *off, uint32_t *bad, hipStream_t s);
 hipError_t launch_codec_read(const uint8_t *src, const uint64_t *off, uint64_t nch, CodecParams cp, float *re,
                              float *im, hipStream_t s);
+
+// ---- host-resident pipeline: staging of one SV group on the device ----
+// Add the body offset of each staged block to its chunks' directory entries
+// (entries of all-zero chunks stay 0): entry i belongs to block
+// i / chunks_per_block, whose bodies start at body_off[block] of the staging
+// pool.
+hipError_t launch_rebase_dir(uint64_t *dir, uint64_t n_entries, uint32_t chunks_per_block, const uint64_t *body_off,
+                             hipStream_t s);
+// Pack a staged group's output (directory dir in packed chunk order, bodies
+// in pool) into one image per SV block: [the block's directory, offsets
+// relative to the image's body area] [its bodies in chunk order].  Three
+// steps over segments of seg = min(1024, chunks_per_block) chunks:
+//   sizes:   rel[i] = body offset of chunk i within its segment, segsum[k] =
+//            body bytes of segment k;
+//   offsets: segsum scanned in place to each segment's offset within its
+//            block; img_off[j] = offset of block j's image (j <= n_blocks, the
+//            last entry the total; images are 16-byte aligned) and
+//            img_off[n_blocks + 1 + j] = block j's body bytes;
+//   write:   every image's directory and bodies into img.
+hipError_t launch_pack_sizes(const uint64_t *dir, uint64_t n_chunks, uint32_t seg, uint32_t *rel, uint64_t *segsum,
+                             hipStream_t s);
+hipError_t launch_pack_offsets(uint64_t *segsum, uint32_t chunks_per_block, uint32_t seg, uint32_t n_blocks,
+                               uint64_t *img_off, hipStream_t s);
+hipError_t launch_pack_write(const uint64_t *dir, const uint8_t *pool, uint32_t chunks_per_block, uint32_t seg,
+                             uint64_t n_chunks, const uint32_t *rel, const uint64_t *segsum, const uint64_t *img_off,
+                             uint8_t *img, hipStream_t s);
 
 // static device scratch of the allocation-free codec entry point: holds the
 // codec workspace (record sizes, offsets) of up to kNoAllocMaxValues values

@@ -884,7 +884,9 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         const bool act = qc < CPW;
         const int c = c0 + (act ? qc : 0);
         const uint64_t gch = base | deposit((uint64_t)c, a.tileq + 6, T - 6);
-        const uint64_t e = act ? a.dir_in[gch >> 6] : 0ull;
+        const uint64_t dch = a.dir_packed ? (deposit((uint64_t)tile, a.snontile, a.n_nontile) |
+                                             deposit((uint64_t)c, a.stileq + 6, T - 6)) : gch;
+        const uint64_t e = act ? a.dir_in[dch >> 6] : 0ull;
         const uint32_t t0 = tix((uint32_t)(c << 6) + 16u * (uint32_t)q);
         decode_entry<DOM>(e, a.pool_in, a.host_in, a.pool_cap, cp, q, act, s.re + t0, s.im + t0);
         if (DUMP && a.dumpd_re && act && gch - a.dump_lo < a.dump_n) {   // test hook: values as decoded
@@ -963,6 +965,8 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     const bool act = qc < CPW;
     const int c = c0 + (act ? qc : 0);
     const uint64_t g = base | deposit((uint64_t)c, a.tileq + 6, T - 6);   // chunk's first amplitude
+    const uint64_t dch = a.dir_packed ? (deposit((uint64_t)tile, a.snontile, a.n_nontile) |
+                                         deposit((uint64_t)c, a.stileq + 6, T - 6)) : g;   // its directory index
     const uint32_t t0 = tix((uint32_t)(c << 6) + 16u * (uint32_t)q);
     if (DUMP && a.dump_re && act && g - a.dump_lo < a.dump_n) {          // test hook: values about to be encoded
 #pragma unroll
@@ -1027,7 +1031,7 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
         copy_staging(S1, (total - sh) >> 2, dst + (sh >> 2));
     }
     if (act && q == 0)
-        a.dir_out[g >> 6] = (h0 | h1) == 0u ? 0ull
+        a.dir_out[dch >> 6] = (h0 | h1) == 0u ? 0ull
                            : (overflow ? kDirInvalid : (off | ((uint64_t)h0 << 40) | ((uint64_t)h1 << 52)));
 
     // mode histogram: 8-bit counts per mode packed in one word, summed over the wave
@@ -1835,6 +1839,128 @@ hipError_t launch_check_dir(const uint64_t *dir, uint64_t n, uint64_t pool_cap, 
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s)
 {
     hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(n, 256, 16384)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ group staging (host-resident pipeline)
+
+__global__ void rebase_dir_kernel(uint64_t *dir, uint64_t n, uint32_t cpb, const uint64_t *body_off)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t e = dir[i];
+        if (e) dir[i] = e + body_off[i / cpb];
+    }
+}
+
+// body bytes of a chunk from its directory entry
+__device__ __forceinline__ uint32_t entry_body_bytes(uint64_t e)
+{
+    if (e == 0) return 0;
+    return layout_of((uint32_t)(e >> 40) & 0xFFFu, (uint32_t)(e >> 52)).size;
+}
+
+// one workgroup (256 threads) per segment of seg <= 1024 chunks; thread t
+// takes chunks 4t..4t+3 of the segment
+__global__ __launch_bounds__(256) void pack_sizes_kernel(const uint64_t *dir, uint64_t n, uint32_t seg, uint32_t *rel,
+                                                         uint64_t *segsum)
+{
+    __shared__ uint32_t s_wave[4];
+    const uint64_t c0 = (uint64_t)blockIdx.x * seg;
+    const uint32_t t = threadIdx.x, lane = t & 63u, wave = t >> 6;
+    uint32_t sz[4], tot = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t i = 4u * t + (uint32_t)k;
+        sz[k] = (i < seg && c0 + i < n) ? entry_body_bytes(dir[c0 + i]) : 0u;
+        tot += sz[k];
+    }
+    const uint32_t incl = wave_scan_add(tot);
+    if (lane == 63) s_wave[wave] = incl;
+    __syncthreads();
+    uint32_t off = incl - tot;
+    for (uint32_t w = 0; w < wave; ++w) off += s_wave[w];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t i = 4u * t + (uint32_t)k;
+        if (i < seg && c0 + i < n) rel[c0 + i] = off;
+        off += sz[k];
+    }
+    if (t == 255) segsum[blockIdx.x] = off;
+}
+
+// one thread: the segments of each block scanned in place, then the images
+__global__ void pack_offsets_kernel(uint64_t *segsum, uint32_t cpb, uint32_t seg, uint32_t n_blocks, uint64_t *img_off)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    const uint32_t spb = cpb / seg;
+    uint64_t img = 0;
+    for (uint32_t j = 0; j < n_blocks; ++j) {
+        uint64_t acc = 0;
+        for (uint32_t k = 0; k < spb; ++k) {
+            const uint64_t v = segsum[(uint64_t)j * spb + k];
+            segsum[(uint64_t)j * spb + k] = acc;
+            acc += v;
+        }
+        img_off[j] = img;
+        img_off[n_blocks + 1 + j] = acc;
+        img += (8ull * cpb + acc + 15ull) & ~15ull;
+    }
+    img_off[n_blocks] = img;
+}
+
+// four lanes per chunk: lane 0 writes the image's directory entry, the quad
+// copies the body word by word
+__global__ __launch_bounds__(256) void pack_write_kernel(const uint64_t *dir, const uint8_t *pool, uint32_t cpb,
+                                                         uint32_t seg, uint64_t n, const uint32_t *rel,
+                                                         const uint64_t *segsum, const uint64_t *img_off, uint8_t *img)
+{
+    const uint64_t c = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 2;
+    const uint32_t q = threadIdx.x & 3u;
+    if (c >= n) return;
+    const uint64_t e = dir[c];
+    const uint64_t j = c / cpb, cl = c % cpb;
+    const uint64_t r = segsum[c / seg] + rel[c];                 // body offset within the block's body area
+    uint8_t *const im = img + img_off[j];
+    if (q == 0) ((uint64_t *)im)[cl] = e ? ((e & ~kDirOffsetMask) | r) : 0ull;
+    const uint32_t nb = entry_body_bytes(e);
+    const uint32_t *src = (const uint32_t *)(pool + (e & kDirOffsetMask));
+    uint32_t *dst = (uint32_t *)(im + 8ull * cpb + r);
+    for (uint32_t w = q; w < nb / 4u; w += 4u) dst[w] = src[w];
+}
+
+hipError_t launch_rebase_dir(uint64_t *dir, uint64_t n_entries, uint32_t chunks_per_block, const uint64_t *body_off,
+                             hipStream_t s)
+{
+    if (n_entries == 0) return hipSuccess;
+    hipLaunchKernelGGL(rebase_dir_kernel, dim3(grid_for(n_entries, 256, 16384)), dim3(256), 0, s, dir, n_entries,
+                       chunks_per_block, body_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_sizes(const uint64_t *dir, uint64_t n_chunks, uint32_t seg, uint32_t *rel, uint64_t *segsum,
+                             hipStream_t s)
+{
+    if (seg == 0 || seg > 1024 || n_chunks % seg) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pack_sizes_kernel, dim3((unsigned)(n_chunks / seg)), dim3(256), 0, s, dir, n_chunks, seg, rel,
+                       segsum);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_offsets(uint64_t *segsum, uint32_t chunks_per_block, uint32_t seg, uint32_t n_blocks,
+                               uint64_t *img_off, hipStream_t s)
+{
+    if (seg == 0 || chunks_per_block % seg) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pack_offsets_kernel, dim3(1), dim3(64), 0, s, segsum, chunks_per_block, seg, n_blocks, img_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_write(const uint64_t *dir, const uint8_t *pool, uint32_t chunks_per_block, uint32_t seg,
+                             uint64_t n_chunks, const uint32_t *rel, const uint64_t *segsum, const uint64_t *img_off,
+                             uint8_t *img, hipStream_t s)
+{
+    if (n_chunks == 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_write_kernel, dim3((unsigned)((4 * n_chunks + 255) / 256)), dim3(256), 0, s, dir, pool,
+                       chunks_per_block, seg, n_chunks, rel, segsum, img_off, img);
     return hipGetLastError();
 }
 

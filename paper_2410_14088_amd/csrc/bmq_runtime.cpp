@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <cmath>
 #include <complex>
 #include <cstdarg>
@@ -969,17 +970,49 @@ struct GroupRun {
     uint64_t g = 0;
 };
 
-// The group qubits of stage st (see GroupRun).
-void group_qubits(const sv_t *sv, const StagePlan &st, GroupRun &gr)
+// The group qubits of stage st (see GroupRun) of an n-qubit state with b
+// block qubits.
+void group_qubits(int n, int b, const StagePlan &st, GroupRun &gr)
 {
-    std::vector<bool> in(sv->n, false);
-    for (int q = 0; q < sv->b; ++q) in[q] = true;
+    std::vector<bool> in(n, false);
+    for (int q = 0; q < b; ++q) in[q] = true;
     for (int q : st.inner) in[q] = true;
     for (const PassPlan &pp : st.passes)
         for (int q : pp.tileq) in[q] = true;
     gr.qubits.clear();
     gr.outer.clear();
-    for (int q = 0; q < sv->n; ++q) (in[q] ? gr.qubits : gr.outer).push_back(q);
+    for (int q = 0; q < n; ++q) (in[q] ? gr.qubits : gr.outer).push_back(q);
+}
+
+// Tile geometry of pass pp in a: tile and non-tile qubits (of the whole
+// state, or of group grp with its outer bits fixed), their packed positions
+// in the group (scratch and packed directories), and the segment rotation
+// of the group's waves.
+void fill_geometry(bmq::PassArgs &a, int n, int t, const PassPlan &pp, const GroupRun *grp)
+{
+    for (int j = 0; j < t; ++j) a.tileq[j] = a.stileq[j] = pp.tileq[j];
+    int nn = 0;
+    if (!grp) {
+        for (int q = 0; q < n; ++q)
+            if (std::find(pp.tileq.begin(), pp.tileq.end(), q) == pp.tileq.end()) {
+                a.snontile[nn] = q;
+                a.nontile[nn++] = q;
+            }
+    } else {
+        // packed position of a group qubit: its rank among the group qubits
+        auto rank = [&](int q) { return (int)(std::find(grp->qubits.begin(), grp->qubits.end(), q) - grp->qubits.begin()); };
+        for (int j = 0; j < t; ++j) a.stileq[j] = rank(pp.tileq[j]);
+        for (int q : grp->qubits)
+            if (std::find(pp.tileq.begin(), pp.tileq.end(), q) == pp.tileq.end()) {
+                a.snontile[nn] = rank(q);
+                a.nontile[nn++] = q;
+            }
+        for (size_t k = 0; k < grp->outer.size(); ++k)
+            a.fixed |= ((grp->g >> k) & 1ull) << grp->outer[k];
+        // the group's waves continue the segment rotation of the earlier groups
+        a.seg_base = (uint32_t)((grp->g << nn) * (t == 13 ? 8u : 4u));
+    }
+    a.n_nontile = nn;
 }
 
 // Arguments of pass pi of stage st with counter block li; flips the state's
@@ -1000,29 +1033,7 @@ void build_pass_args(sv_t *sv, const sv_plan_t *p, const StagePlan &st, int pi, 
     std::memset(&a, 0, sizeof(a));
     a.n = n;
     a.t = p->t;
-    for (int j = 0; j < p->t; ++j) a.tileq[j] = a.stileq[j] = pp.tileq[j];
-    int nn = 0;
-    if (!grp) {
-        for (int q = 0; q < n; ++q)
-            if (std::find(pp.tileq.begin(), pp.tileq.end(), q) == pp.tileq.end()) {
-                a.snontile[nn] = q;
-                a.nontile[nn++] = q;
-            }
-    } else {
-        // scratch position of a group qubit: its rank among the group qubits
-        auto rank = [&](int q) { return (int)(std::find(grp->qubits.begin(), grp->qubits.end(), q) - grp->qubits.begin()); };
-        for (int j = 0; j < p->t; ++j) a.stileq[j] = rank(pp.tileq[j]);
-        for (int q : grp->qubits)
-            if (std::find(pp.tileq.begin(), pp.tileq.end(), q) == pp.tileq.end()) {
-                a.snontile[nn] = rank(q);
-                a.nontile[nn++] = q;
-            }
-        for (size_t k = 0; k < grp->outer.size(); ++k)
-            a.fixed |= ((grp->g >> k) & 1ull) << grp->outer[k];
-        // the group's waves continue the segment rotation of the earlier groups
-        a.seg_base = (uint32_t)((grp->g << nn) * (p->t == 13 ? 8u : 4u));
-    }
-    a.n_nontile = nn;
+    fill_geometry(a, n, p->t, pp, grp);
     a.op_begin = pp.op_begin;
     a.op_end = pp.op_end;
     // with scratch planes, passes between the first and the last stay
@@ -1078,7 +1089,7 @@ int enqueue_stage(sv_t *sv, const sv_plan_t *p, const StagePlan &st, size_t li0,
         return SV_OK;
     }
     GroupRun gr;
-    group_qubits(sv, st, gr);
+    group_qubits(sv->n, sv->b, st, gr);
     if (gr.qubits.size() >= 64 || (1ull << gr.qubits.size()) > sv->scr_elems)
         return fail(SV_ERR_INVALID, "a multi-pass stage spans %zu qubits; the state's group scratch holds %llu "
                                     "amplitudes (create the state with this inner size and tile)",
@@ -2454,6 +2465,477 @@ int codec_decode(const void *src_dev, uint64_t bytes, const sv_config_t *cfg, ui
     if (bad) return fail(SV_ERR_CORRUPT, "malformed record in the stream");
     HIP_TRY(bmq::launch_codec_read((const uint8_t *)src_dev, off, nch, codec_params(*cfg), re_dev, im_dev, st));
     return SV_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== host-resident pipeline
+//
+// The compressed state lives in the caller's pinned host memory as one image
+// per SV block ([the block's chunk directory, body offsets relative to the
+// image's body area] [bodies in chunk order]).  Every stage moves each SV
+// group through the device on one of S streams (Section 4.2, Fig. 6): the
+// group's block images are copied in (H2D), their directories rebased into
+// one staging pool, the stage's tile passes run on the group alone (its
+// outer bits fixed, directory and scratch in the group's packed order), the
+// output is packed into new block images and copied back (D2H).  Groups of a
+// stage are independent, so while one stream computes, the others copy.
+
+namespace {
+
+struct PipeStream {
+    hipStream_t s = nullptr;
+    hipEvent_t packed = nullptr;
+    uint64_t *dir[2] = {nullptr, nullptr};   // staging directories (packed order); [0] receives the input
+    uint8_t *pool[2] = {nullptr, nullptr};   // staging record pools
+    uint64_t *body_off = nullptr;            // per block of the group: its bodies' offset in pool[0]
+    float *scr_re = nullptr, *scr_im = nullptr;
+    unsigned long long *counters = nullptr;  // kMaxPipePasses counter blocks
+    uint32_t *rel = nullptr;
+    uint64_t *segsum = nullptr, *img_off = nullptr;
+    uint8_t *img = nullptr;
+    uint64_t *h_off = nullptr, *h_img = nullptr;   // pinned host: body offsets (in), image offsets (out)
+    bool pending = false;
+    std::vector<uint64_t> pend_blocks;
+};
+
+constexpr int kMaxPipeStreams = 8;
+constexpr size_t kMaxPipePasses = 64;
+
+struct PipeLayout {
+    int gq = 0;                     // log2 amplitudes of the largest group
+    uint64_t gch = 0, gblocks = 0;  // its chunks and blocks
+    uint64_t pool_cap = 0, seg = 0;
+    uint64_t per_stream = 0, total = 0;
+    uint64_t off_dir[2], off_pool[2], off_body, off_scr_re, off_scr_im, off_counters, off_rel, off_segsum, off_img_off,
+        off_img;
+    uint64_t off_ops, off_load_off;
+    uint64_t host_small = 0;        // pinned bytes of the per-stream arrays
+};
+
+PipeLayout pipe_layout(const sv_config_t &c, int S)
+{
+    PipeLayout L;
+    const int n = c.n_qubits, b = c.block_qubits;
+    const int t = c.tile_qubits ? c.tile_qubits : kDefaultTile;
+    L.gq = std::min(n, std::max(b + std::max(c.inner_size, 2), t));
+    L.gch = 1ull << (L.gq - 6);
+    L.gblocks = 1ull << (L.gq - b);
+    L.pool_cap = L.gch * bmq::kMaxBodyBytes + bmq::kSegments * 256ull;
+    L.seg = std::min<uint64_t>(1024, 1ull << (b - 6));
+    uint64_t o = 0;
+    L.off_dir[0] = o; o += align256(L.gch * 8);
+    L.off_dir[1] = o; o += align256(L.gch * 8);
+    L.off_pool[0] = o; o += align256(L.pool_cap + 1024);
+    L.off_pool[1] = o; o += align256(L.pool_cap + 1024);
+    L.off_body = o; o += align256(L.gblocks * 8);
+    const uint64_t scr = (c.flags & SV_FLAG_NO_SCRATCH) ? 0 : align256((1ull << L.gq) * 4);
+    L.off_scr_re = o; o += scr;
+    L.off_scr_im = o; o += scr;
+    L.off_counters = o; o += align256(kMaxPipePasses * kStageCounters * 8);
+    L.off_rel = o; o += align256(L.gch * 4);
+    L.off_segsum = o; o += align256(L.gch / L.seg * 8 + 8);
+    L.off_img_off = o; o += align256((2 * L.gblocks + 1) * 8);
+    L.off_img = o; o += align256(L.gch * (8 + bmq::kMaxBodyBytes) + 16 * L.gblocks);
+    L.per_stream = o;
+    L.off_ops = (uint64_t)S * L.per_stream;
+    L.off_load_off = L.off_ops + kOpsArenaBytes;
+    L.total = L.off_load_off + align256((1ull << (n - b)) * 8);
+    L.host_small = align256((uint64_t)S * 3 * (L.gblocks + 1) * 8);
+    return L;
+}
+
+}  // namespace
+
+struct sv_pipe {
+    sv_config_t cfg{};
+    int n = 0, b = 0, S = 0;
+    hipStream_t user = nullptr;
+    uint8_t *ws = nullptr;
+    PipeLayout L;
+    uint8_t *host = nullptr;
+    uint64_t host_bytes = 0, host_used = 0;
+    struct Slot {
+        uint64_t off = 0, cap = 0, size = 0;    // image: host offset, room, bytes (16-byte multiple)
+        uint64_t body = 0;                      // its record bodies' bytes
+    };
+    std::vector<Slot> slots;          // block images in the host buffer
+    std::vector<PipeStream> st;
+    uint8_t *ops = nullptr;
+    uint64_t uploaded_uid = 0;
+    uint64_t h2d = 0, d2h = 0;        // bytes moved since the last reset
+    bool poisoned = false;
+};
+
+namespace {
+
+// Reserve host room for block k's next image of `size` bytes: in place when
+// it fits (the old image is dead once the group's copy-in has run, which
+// precedes its copy-out on the same stream), else a new slot with a quarter
+// of headroom.
+int pipe_slot(sv_pipe *pp, uint64_t k, uint64_t size, uint64_t body)
+{
+    sv_pipe::Slot &sl = pp->slots[k];
+    if (size > sl.cap) {
+        const uint64_t cap = align256(size + size / 4);
+        if (pp->host_used + cap > pp->host_bytes) {
+            pp->poisoned = true;
+            return fail(SV_ERR_CAPACITY, "host store full: block %llu needs %llu bytes, %llu of %llu in use",
+                        (unsigned long long)k, (unsigned long long)cap, (unsigned long long)pp->host_used,
+                        (unsigned long long)pp->host_bytes);
+        }
+        sl.off = pp->host_used;
+        sl.cap = cap;
+        pp->host_used += cap;
+    }
+    sl.size = size;
+    sl.body = body;
+    return SV_OK;
+}
+
+// The group on stream ps has been packed: read its image offsets, place the
+// images in the host store and copy them out (asynchronously).
+int pipe_finish(sv_pipe *pp, PipeStream &ps)
+{
+    if (!ps.pending) return SV_OK;
+    ps.pending = false;
+    HIP_TRY(hipEventSynchronize(ps.packed));
+    for (size_t j = 0; j < ps.pend_blocks.size(); ++j) {
+        const uint64_t size = ps.h_img[j + 1] - ps.h_img[j];
+        const uint64_t k = ps.pend_blocks[j];
+        if (int rc = pipe_slot(pp, k, size, ps.h_img[ps.pend_blocks.size() + 1 + j])) return rc;
+        HIP_TRY(hipMemcpyAsync(pp->host + pp->slots[k].off, ps.img + ps.h_img[j], size, hipMemcpyDeviceToHost, ps.s));
+        pp->d2h += 8 * (1ull << (pp->b - 6)) + pp->slots[k].body;
+    }
+    return SV_OK;
+}
+
+// Pack the n_blk blocks of the staged output (dir, pool) on ps into images,
+// their offsets copied to the pinned h_img; blocks receives their ids.
+int pipe_pack(sv_pipe *pp, PipeStream &ps, const uint64_t *dir, const uint8_t *pool, uint64_t n_blk,
+              std::vector<uint64_t> &&blocks)
+{
+    const uint32_t cpb = 1u << (pp->b - 6);
+    const uint64_t nch = n_blk * cpb;
+    const uint32_t seg = (uint32_t)pp->L.seg;
+    HIP_TRY(bmq::launch_pack_sizes(dir, nch, seg, ps.rel, ps.segsum, ps.s));
+    HIP_TRY(bmq::launch_pack_offsets(ps.segsum, cpb, seg, (uint32_t)n_blk, ps.img_off, ps.s));
+    HIP_TRY(bmq::launch_pack_write(dir, pool, cpb, seg, nch, ps.rel, ps.segsum, ps.img_off, ps.img, ps.s));
+    HIP_TRY(hipMemcpyAsync(ps.h_img, ps.img_off, (2 * n_blk + 1) * 8, hipMemcpyDeviceToHost, ps.s));
+    HIP_TRY(hipEventRecord(ps.packed, ps.s));
+    ps.pending = true;
+    ps.pend_blocks = std::move(blocks);
+    return SV_OK;
+}
+
+int pipe_check(const sv_pipe *pp)
+{
+    if (!pp) return fail(SV_ERR_INVALID, "pipeline is NULL");
+    if (pp->poisoned) return fail(SV_ERR_CAPACITY, "pipeline is poisoned by an earlier overflow");
+    return SV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sv_pipe_required(const sv_config_t *cfg, int32_t streams, uint64_t *dev_bytes, uint64_t *host_min_bytes)
+{
+    if (int rc = validate_cfg(cfg)) return rc;
+    if (streams < 1 || streams > kMaxPipeStreams) return fail(SV_ERR_INVALID, "streams %d outside [1, 8]", streams);
+    const PipeLayout L = pipe_layout(*cfg, streams);
+    if (dev_bytes) *dev_bytes = L.total;
+    const uint64_t nblk = 1ull << (cfg->n_qubits - cfg->block_qubits);
+    const uint64_t cpb = 1ull << (cfg->block_qubits - 6);
+    if (host_min_bytes) *host_min_bytes = L.host_small + nblk * align256((8 * cpb + 16) * 5 / 4) + 4096;
+    return SV_OK;
+}
+
+int sv_pipe_reset(sv_pipe_t *pp);
+
+int sv_pipe_create(const sv_config_t *cfg, int32_t streams, void *dev_ws, uint64_t dev_bytes, void *host_pinned,
+                   uint64_t host_bytes, void *hip_stream, sv_pipe_t **out)
+{
+    if (int rc = validate_cfg(cfg)) return rc;
+    if (!out) return fail(SV_ERR_INVALID, "out is NULL");
+    if (streams < 1 || streams > kMaxPipeStreams) return fail(SV_ERR_INVALID, "streams %d outside [1, 8]", streams);
+    if (cfg->domain == SV_DOMAIN_RAW) return fail(SV_ERR_UNSUPPORTED, "the pipeline stores compressed images only");
+    const PipeLayout L = pipe_layout(*cfg, streams);
+    if (!dev_ws || ((uintptr_t)dev_ws & 255u) || dev_bytes < L.total)
+        return fail(SV_ERR_INVALID, "device workspace must be 256-byte aligned and hold %llu bytes",
+                    (unsigned long long)L.total);
+    if (!host_pinned || ((uintptr_t)host_pinned & 255u) || host_bytes < L.host_small)
+        return fail(SV_ERR_INVALID, "host store must be 256-byte aligned pinned memory of at least %llu bytes",
+                    (unsigned long long)L.host_small);
+    sv_pipe *pp = new (std::nothrow) sv_pipe;
+    if (!pp) return fail(SV_ERR_OOM, "host allocation failed");
+    pp->cfg = *cfg;
+    pp->n = cfg->n_qubits;
+    pp->b = cfg->block_qubits;
+    pp->S = streams;
+    pp->user = (hipStream_t)hip_stream;
+    pp->ws = (uint8_t *)dev_ws;
+    pp->L = L;
+    pp->host = (uint8_t *)host_pinned + L.host_small;
+    pp->host_bytes = host_bytes - L.host_small;
+    pp->ops = pp->ws + L.off_ops;
+    pp->st.resize(streams);
+    const bool scratch = !(cfg->flags & SV_FLAG_NO_SCRATCH);
+    for (int i = 0; i < streams; ++i) {
+        PipeStream &ps = pp->st[i];
+        uint8_t *w = pp->ws + (uint64_t)i * L.per_stream;
+        ps.dir[0] = (uint64_t *)(w + L.off_dir[0]);
+        ps.dir[1] = (uint64_t *)(w + L.off_dir[1]);
+        ps.pool[0] = w + L.off_pool[0];
+        ps.pool[1] = w + L.off_pool[1];
+        ps.body_off = (uint64_t *)(w + L.off_body);
+        if (scratch) {
+            ps.scr_re = (float *)(w + L.off_scr_re);
+            ps.scr_im = (float *)(w + L.off_scr_im);
+        }
+        ps.counters = (unsigned long long *)(w + L.off_counters);
+        ps.rel = (uint32_t *)(w + L.off_rel);
+        ps.segsum = (uint64_t *)(w + L.off_segsum);
+        ps.img_off = (uint64_t *)(w + L.off_img_off);
+        ps.img = w + L.off_img;
+        ps.h_off = (uint64_t *)host_pinned + (uint64_t)i * 3 * (L.gblocks + 1);
+        ps.h_img = ps.h_off + (L.gblocks + 1);
+        hipError_t e = hipStreamCreateWithFlags(&ps.s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ps.packed, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            sv_pipe_destroy(pp);
+            return fail(SV_ERR_HIP, "pipeline streams: %s", hipGetErrorString(e));
+        }
+    }
+    if (int rc = sv_pipe_reset(pp)) {
+        sv_pipe_destroy(pp);
+        return rc;
+    }
+    *out = pp;
+    return SV_OK;
+}
+
+// |0...0> (Section 4.2): block 0's image holds the encoded first chunk, every
+// other block's image is an all-zero directory.
+int sv_pipe_reset(sv_pipe_t *pp)
+{
+    if (!pp) return fail(SV_ERR_INVALID, "pipeline is NULL");
+    for (PipeStream &ps : pp->st) {
+        HIP_TRY(hipStreamSynchronize(ps.s));
+        ps.pending = false;
+    }
+    pp->poisoned = false;
+    pp->host_used = 0;
+    pp->h2d = pp->d2h = 0;
+    const uint64_t nblk = 1ull << (pp->n - pp->b);
+    const uint64_t cpb = 1ull << (pp->b - 6);
+    pp->slots.assign(nblk, sv_pipe::Slot{});
+    // block 0 through the device (the encoder's record of amplitude 1)
+    PipeStream &ps = pp->st[0];
+    HIP_TRY(bmq::launch_fill_u64((uint64_t *)ps.counters, kStageCounters, 0, ps.s));
+    HIP_TRY(bmq::launch_init_state(ps.dir[0], cpb, ps.pool[0], ps.counters, codec_params(pp->cfg), ps.s));
+    if (int rc = pipe_pack(pp, ps, ps.dir[0], ps.pool[0], 1, std::vector<uint64_t>{0})) return rc;
+    if (int rc = pipe_finish(pp, ps)) return rc;
+    for (uint64_t k = 1; k < nblk; ++k) {
+        if (int rc = pipe_slot(pp, k, 8 * cpb, 0)) return rc;
+        std::memset(pp->host + pp->slots[k].off, 0, 8 * cpb);
+    }
+    HIP_TRY(hipStreamSynchronize(ps.s));
+    pp->d2h = 0;
+    return SV_OK;
+}
+
+int sv_pipe_apply(sv_pipe_t *pp, const sv_plan_t *p, size_t first, size_t count, sv_stage_stats_t *stats)
+{
+    if (int rc = pipe_check(pp)) return rc;
+    if (!p) return fail(SV_ERR_INVALID, "plan is NULL");
+    if (p->cfg.n_qubits != pp->n || p->cfg.block_qubits != pp->b || p->cfg.domain != pp->cfg.domain ||
+        p->cfg.eb != pp->cfg.eb)
+        return fail(SV_ERR_INVALID, "plan and pipeline configurations differ");
+    if (first > p->stages.size() || count > p->stages.size() - first)
+        return fail(SV_ERR_INVALID, "stage range outside the plan");
+    if (pp->cfg.flags & SV_FLAG_NO_SCRATCH)
+        for (size_t i = 0; i < count; ++i)
+            if (p->stages[first + i].passes.size() > 1)
+                return fail(SV_ERR_UNSUPPORTED, "the pipeline runs multi-pass stages through its scratch planes");
+    // the plan's operations, once per plan
+    if (pp->uploaded_uid != p->uid) {
+        const uint64_t ob = p->ops.size() * sizeof(OpDesc);
+        if (align256(ob) + p->data.size() * sizeof(float2) > kOpsArenaBytes)
+            return fail(SV_ERR_UNSUPPORTED, "plan's fused operations exceed the operation arena");
+        if (ob) HIP_TRY(hipMemcpyAsync(pp->ops, p->ops.data(), ob, hipMemcpyHostToDevice, pp->user));
+        if (!p->data.empty())
+            HIP_TRY(hipMemcpyAsync(pp->ops + align256(ob), p->data.data(), p->data.size() * sizeof(float2),
+                                   hipMemcpyHostToDevice, pp->user));
+        HIP_TRY(hipStreamSynchronize(pp->user));
+        pp->uploaded_uid = p->uid;
+    }
+    HIP_TRY(hipStreamSynchronize(pp->user));       // earlier work of the caller's stream
+    const int n = pp->n, b = pp->b;
+    const uint64_t cpb = 1ull << (b - 6);
+    const bmq::CodecParams cp = codec_params(pp->cfg);
+    const bool scratch = !(pp->cfg.flags & SV_FLAG_NO_SCRATCH);
+    for (size_t si = 0; si < count; ++si) {
+        const StagePlan &st = p->stages[first + si];
+        const auto t0 = std::chrono::steady_clock::now();
+        const uint64_t h2d0 = pp->h2d, d2h0 = pp->d2h;
+        const int np = (int)st.passes.size();
+        if ((size_t)np > kMaxPipePasses) return fail(SV_ERR_UNSUPPORTED, "stage with %d passes", np);
+        GroupRun gr;
+        group_qubits(n, b, st, gr);
+        if ((int)gr.qubits.size() > pp->L.gq)
+            return fail(SV_ERR_INVALID, "stage %zu spans %zu qubits; the pipeline stages groups of %d (create it "
+                                        "with this inner size and tile)", first + si, gr.qubits.size(), pp->L.gq);
+        const int gq = (int)gr.qubits.size();
+        const uint64_t nblk = 1ull << (gq - b), nch = 1ull << (gq - 6);
+        const uint64_t ngroups = 1ull << gr.outer.size();
+        const uint64_t waves = (1ull << (gq - p->t)) * (p->t == 13 ? 8u : 4u);
+        const int n_seg = (int)std::min<uint64_t>((uint64_t)bmq::kSegments, waves);
+        for (gr.g = 0; gr.g < ngroups; ++gr.g) {
+            PipeStream &ps = pp->st[gr.g % pp->S];
+            if (int rc = pipe_finish(pp, ps)) return rc;
+            // the group's blocks in packed order: block j holds the group
+            // qubits above the block bits set to j
+            uint64_t fixed = 0;
+            for (size_t k = 0; k < gr.outer.size(); ++k) fixed |= ((gr.g >> k) & 1ull) << gr.outer[k];
+            std::vector<uint64_t> blocks(nblk);
+            uint64_t boff = 0;
+            for (uint64_t j = 0; j < nblk; ++j) {
+                uint64_t idx = fixed;
+                for (int k = 0; k < gq - b; ++k) idx |= ((j >> k) & 1ull) << gr.qubits[b + k];
+                const uint64_t blk = idx >> b;
+                blocks[j] = blk;
+                const sv_pipe::Slot &sl = pp->slots[blk];
+                const uint64_t body = sl.body;
+                HIP_TRY(hipMemcpyAsync(ps.dir[0] + j * cpb, pp->host + sl.off, 8 * cpb, hipMemcpyHostToDevice, ps.s));
+                if (body)
+                    HIP_TRY(hipMemcpyAsync(ps.pool[0] + boff, pp->host + sl.off + 8 * cpb, body,
+                                           hipMemcpyHostToDevice, ps.s));
+                ps.h_off[j] = boff;
+                boff += (body + 15) & ~15ull;
+                pp->h2d += 8 * cpb + body;
+            }
+            HIP_TRY(hipMemcpyAsync(ps.body_off, ps.h_off, nblk * 8, hipMemcpyHostToDevice, ps.s));
+            HIP_TRY(bmq::launch_rebase_dir(ps.dir[0], nch, (uint32_t)cpb, ps.body_off, ps.s));
+            HIP_TRY(bmq::launch_fill_u64((uint64_t *)ps.counters, (uint64_t)np * kStageCounters, 0, ps.s));
+            int cur = 0;
+            for (int pi = 0; pi < np; ++pi) {
+                const PassPlan &pl = st.passes[pi];
+                bmq::PassArgs a;
+                std::memset(&a, 0, sizeof(a));
+                a.n = n;
+                a.t = p->t;
+                fill_geometry(a, n, p->t, pl, &gr);
+                a.dir_packed = 1;
+                a.op_begin = pl.op_begin;
+                a.op_end = pl.op_end;
+                a.in_mode = (!scratch || pi == 0) ? bmq::IO_COMPRESSED : bmq::IO_SCRATCH;
+                a.out_mode = (!scratch || pi == np - 1) ? bmq::IO_COMPRESSED : bmq::IO_SCRATCH;
+                a.cp = cp;
+                a.dir_in = ps.dir[cur];
+                a.pool_in = ps.pool[cur];
+                a.dir_out = ps.dir[cur ^ 1];
+                a.pool_out = ps.pool[cur ^ 1];
+                a.pool_cap = pp->L.pool_cap;
+                a.n_seg = n_seg;
+                a.seg_cap = (pp->L.pool_cap / (uint64_t)n_seg) & ~3ull;
+                a.seg_base = 0;
+                a.counters = ps.counters + (size_t)pi * kStageCounters;
+                a.scr_re = ps.scr_re;
+                a.scr_im = ps.scr_im;
+                a.ops = (const OpDesc *)pp->ops;
+                a.opdata = (const float2 *)(pp->ops + align256(p->ops.size() * sizeof(OpDesc)));
+                a.mfma = (pp->cfg.flags & SV_FLAG_NO_MFMA) ? 0 : 1;
+                HIP_TRY(bmq::launch_pass(a, ps.s));
+                if (a.out_mode == bmq::IO_COMPRESSED) cur ^= 1;
+            }
+            if (int rc = pipe_pack(pp, ps, ps.dir[cur], ps.pool[cur], nblk, std::move(blocks))) return rc;
+        }
+        // stage barrier: every group's images are in the host store
+        for (PipeStream &ps : pp->st)
+            if (int rc = pipe_finish(pp, ps)) return rc;
+        for (PipeStream &ps : pp->st) HIP_TRY(hipStreamSynchronize(ps.s));
+        if (stats) {
+            sv_stage_stats_t &s = stats[si];
+            std::memset(&s, 0, sizeof(s));
+            s.ms = (float)std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            s.bytes_in = pp->h2d - h2d0;
+            s.bytes_out = pp->d2h - d2h0;
+            s.bytes_out_host = s.bytes_out;
+            s.passes = (uint32_t)np;
+            s.n_gates = (uint32_t)(st.g1 - st.g0);
+            s.n_inner = (uint32_t)st.inner.size();
+            uint32_t nops = 0;
+            for (const auto &pl : st.passes) nops += (uint32_t)(pl.op_end - pl.op_begin);
+            s.n_ops = nops;
+        }
+    }
+    return SV_OK;
+}
+
+// Copy the host-resident state into a device state of the same
+// configuration (its current copy; bodies packed block after block).
+int sv_pipe_load(sv_pipe_t *pp, sv_t *sv)
+{
+    if (int rc = pipe_check(pp)) return rc;
+    if (int rc = check_state(sv)) return rc;
+    if (sv->n != pp->n || sv->b != pp->b || sv->cfg.domain != pp->cfg.domain || sv->cfg.eb != pp->cfg.eb)
+        return fail(SV_ERR_INVALID, "state and pipeline configurations differ");
+    if (int rc = resolve_graph(sv)) return rc;
+    const uint64_t nblk = 1ull << (pp->n - pp->b), cpb = 1ull << (pp->b - 6);
+    uint64_t total = 0;
+    for (const auto &sl : pp->slots) total += sl.body;
+    if (total > sv->pool_cap) return fail(SV_ERR_CAPACITY, "state's device pool holds %llu bytes, the records %llu",
+                                          (unsigned long long)sv->pool_cap, (unsigned long long)total);
+    std::vector<uint64_t> off(nblk);
+    uint64_t o = 0;
+    for (uint64_t k = 0; k < nblk; ++k) {
+        const auto &sl = pp->slots[k];
+        HIP_TRY(hipMemcpyAsync(sv->dir[sv->cur] + k * cpb, pp->host + sl.off, 8 * cpb, hipMemcpyHostToDevice,
+                               sv->stream));
+        if (sl.body)
+            HIP_TRY(hipMemcpyAsync(sv->pool[sv->cur] + o, pp->host + sl.off + 8 * cpb, sl.body,
+                                   hipMemcpyHostToDevice, sv->stream));
+        off[k] = o;
+        o += sl.body;
+    }
+    uint64_t *doff = (uint64_t *)(pp->ws + pp->L.off_load_off);
+    HIP_TRY(hipMemcpyAsync(doff, off.data(), nblk * 8, hipMemcpyHostToDevice, sv->stream));
+    HIP_TRY(bmq::launch_rebase_dir(sv->dir[sv->cur], nblk * cpb, (uint32_t)cpb, doff, sv->stream));
+    HIP_TRY(hipStreamSynchronize(sv->stream));
+    sv->live_bytes = total;
+    sv->live_host = 0;
+    sv->reset_pending = false;
+    return SV_OK;
+}
+
+int sv_pipe_footprint(const sv_pipe_t *pp, uint64_t *record_bytes, uint64_t *image_bytes, uint64_t *host_used,
+                      uint64_t *h2d_bytes, uint64_t *d2h_bytes)
+{
+    if (!pp) return fail(SV_ERR_INVALID, "pipeline is NULL");
+    const uint64_t cpb = 1ull << (pp->b - 6);
+    uint64_t rec = 0, img = 0;
+    for (const auto &sl : pp->slots) {
+        rec += sl.body;
+        img += 8 * cpb + sl.body;
+    }
+    if (record_bytes) *record_bytes = rec;
+    if (image_bytes) *image_bytes = img;
+    if (host_used) *host_used = pp->host_used;
+    if (h2d_bytes) *h2d_bytes = pp->h2d;
+    if (d2h_bytes) *d2h_bytes = pp->d2h;
+    return SV_OK;
+}
+
+void sv_pipe_destroy(sv_pipe_t *pp)
+{
+    if (!pp) return;
+    for (PipeStream &ps : pp->st) {
+        if (ps.s) (void)hipStreamSynchronize(ps.s);
+        if (ps.packed) (void)hipEventDestroy(ps.packed);
+        if (ps.s) (void)hipStreamDestroy(ps.s);
+    }
+    delete pp;
 }
 
 }  // extern "C"
