@@ -43,13 +43,15 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="random",
-                    choices=["random", "qft", "random-mirror", "batch", "qaoa-spill"],
+                    choices=["random", "qft", "random-mirror", "batch", "qaoa-spill", "pipeline"],
                     help="random: random U3/CZ layers (default, 33 qubits, depth 16); qft: QFT on an Ry product "
                          "(30 qubits); random-mirror: the random layers followed by their inverse, timed "
                          "together; batch: 512 uneven circuits of "
                          "18-26 qubits run together (sv_batch_apply) and one after another; qaoa-spill: "
                          "QAOA ring p=3 (32 qubits) with the device pools capped so records spill to a "
-                         "pinned host pool, against the same run on the device only")
+                         "pinned host pool, against the same run on the device only; pipeline: the 30-qubit QFT "
+                         "with the compressed state in pinned host memory, each stage's groups copied through the "
+                         "GPU on S = 1, 2, 4, 8 streams (sv_pipe_*), against the device-resident run")
     ap.add_argument("--pool-frac", type=float, default=0.25,
                     help="qaoa-spill: device pool capacity per state copy, as a fraction of the "
                          "uncompressed complex64 size")
@@ -125,7 +127,7 @@ def qft_ry_closed_form(n, theta, idx):
 
 # committed counter profiles of the pass kernel, per default workload:
 # (n, tile, fuse, flags) they were taken at and the file stem
-PROFILES = {"random": ((33, 12, 5, 0), "pass_kernel_random33"),
+PROFILES = {"random": ((33, 12, 3, 32), "pass_kernel_random33"),
             "qft": ((30, 12, 4, 0), "pass_kernel_qft30")}
 
 
@@ -422,6 +424,14 @@ def autotune_headline(d, gates, args, inner=(2,), fuse=(2, 3, 4, 5), tiles=(12, 
     progress(f"autotune: tiles {tl} x fusion {fuse} x inner {inner} on the first {probe} gates")
     best, table = bmq.autotune_space(gates, cfg, tiles=tl, fuse=fuse, inner=inner, probe_gates=probe)
     torch.cuda.empty_cache()
+    # candidates within 1 % of the fastest are a tie (run-to-run spread):
+    # take the widest fusion, then the smallest tile, among them
+    fastest = min(table.values())
+    tied = [k for k, v in table.items() if v <= 1.01 * fastest]
+    t_, f_, m_ = sorted(tied, key=lambda k: (-k[2], -k[1], k[0]))[0] if len(inner) > 1 else \
+        sorted(tied, key=lambda k: (-k[1], k[0]))[0]
+    best = bmq.Config(n=best.n, b=best.b, inner=m_, fuse=f_, domain=best.domain, eb=best.eb, tile=t_,
+                      pool_bytes=best.pool_bytes, flags=best.flags)
     progress(f"autotune: tile {best.tile}, fusion {best.fuse}, inner {best.inner} "
              f"({time.perf_counter() - t0:.1f} s)")
     return {"probe_gates": probe, "seconds": time.perf_counter() - t0,
@@ -512,6 +522,80 @@ def bench_qaoa_spill(args):
     print(json.dumps(out))
 
 
+def bench_pipeline(args):
+    """Host-resident state through the pipeline: one run per stream count,
+    timed from |0...0> over every stage (host clock, each stage ends when
+    its images are back in the host store), against the device-resident
+    stage loop on the same plan; records compared after each run."""
+    import numpy as np
+    import torch
+    from paper_2410_14088_amd import bmq
+    from paper_2410_14088_amd import circuits as C
+    n = args.n or 30
+    d = C.config(1, n=n)
+    gates = d["gates"]
+    fuse = args.fuse or 4
+    cfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=fuse, domain=1, eb=d["eb"], flags=bmq.SV_FLAG_GROUP_SCRATCH)
+    plan = bmq.Plan(gates, cfg)
+    G = len(gates)
+    sv = bmq.State(cfg, "cuda:0")
+    for _ in range(max(1, args.warmup)):
+        sv.reset()
+        sv.apply(plan)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sv.reset()
+        sv.apply(plan)
+    torch.cuda.synchronize()
+    dev_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    progress(f"pipeline: device-resident {dev_ms:.1f} ms per run")
+    ref_blocks = [sv.block_stream(k) for k in range(0, sv.n_blocks, max(1, sv.n_blocks // 16))]
+    rng = np.random.default_rng(1)
+    idx = rng.integers(0, 1 << n, 4096).astype(np.uint64)
+    want = qft_ry_closed_form(n, d["thetas"], idx)
+    runs = {}
+    for S in (1, 2, 4, 8):
+        pipe = bmq.Pipe(cfg, streams=S)
+        pipe.apply(plan)                                   # warm-up
+        best = None
+        for _ in range(args.steps):
+            pipe.reset()
+            t0 = time.perf_counter()
+            st = pipe.apply(plan, stats=True)
+            dt = time.perf_counter() - t0
+            best = dt if best is None or dt < best else best
+        fp = pipe.footprint()
+        sv.reset()
+        pipe.load(sv)
+        same = all(sv.block_stream(k) == ref_blocks[i]
+                   for i, k in enumerate(range(0, sv.n_blocks, max(1, sv.n_blocks // 16))))
+        got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy().astype(np.complex128)
+        f2 = float(abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real))
+        moved = fp["h2d_bytes"] + fp["d2h_bytes"]
+        runs[str(S)] = {"ms_per_step": best * 1e3, "value": (2 ** n) * G / best, "h2d_bytes": fp["h2d_bytes"],
+                        "d2h_bytes": fp["d2h_bytes"], "host_link_gbps": moved / best / 1e9,
+                        "host_store_bytes": fp["host_used"], "record_bytes": fp["record_bytes"],
+                        "records_equal_device_run": same, "fidelity_f2_sampled": f2,
+                        "slowest_stage_ms": max(s["ms"] for s in st)}
+        progress(f"pipeline: {S} streams {best * 1e3:.1f} ms per run, {moved / best / 1e9:.1f} GB/s over the host link")
+        pipe.close()
+        del pipe
+        torch.cuda.empty_cache()
+    best_s = min(runs, key=lambda k: runs[k]["ms_per_step"])
+    out = {
+        "metric": METRIC, "value": runs[best_s]["value"], "unit": "amplitude·gates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": runs[best_s]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"qft-on-ry-{n}q-host-resident-pipeline", "n_qubits": n, "block_qubits": d["b"],
+                   "gates": G, "stages": plan.n_stages, "domain": "log", "eb": d["eb"], "fuse_qubits": fuse,
+                   "streams": int(best_s)},
+        "streams": runs, "device_resident_ms": dev_ms,
+        "note": "host-link-inclusive rates: the state lives in pinned host memory between stages",
+    }
+    print(json.dumps(out))
+
+
 def main():
     args = parse()
     args.fuse_given = bool(args.fuse)
@@ -525,6 +609,9 @@ def main():
         sys.exit(2)
     if args.workload == "qaoa-spill":
         bench_qaoa_spill(args)
+        return
+    if args.workload == "pipeline":
+        bench_pipeline(args)
         return
     if args.workload == "batch" and not args.copy_calibration:
         bench_batch(args)
@@ -612,7 +699,7 @@ def main():
         for s in st:
             alg_bytes += s["bytes_in"] + s["bytes_out"] + s["dir_bytes"]
             kern_ms += s["ms"]
-            launches += s["passes"]
+            launches += s["launches"]
     achieved = alg_bytes / (kern_ms * 1e-3) / 1e9
     last = all_stats[-1]
     peak_bytes = max(s["bytes_out"] for s in last)

@@ -153,7 +153,7 @@ typedef struct {
     uint32_t n_gates;         /* circuit gates in the stage */
     uint32_t n_inner;         /* inner (global) indices of the stage */
     float ms;                 /* device time of the stage's kernels (HIP events) */
-    uint32_t pad;
+    uint32_t launches;        /* pass-kernel launches: passes, or passes x groups with group-sized scratch */
 } sv_stage_stats_t;
 
 typedef struct sv_plan sv_plan_t;

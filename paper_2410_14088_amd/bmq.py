@@ -64,7 +64,7 @@ class sv_stage_stats_t(C.Structure):
                 ("inter_bytes", C.c_uint64), ("dir_bytes", C.c_uint64),
                 ("scratch_bytes", C.c_uint64), ("zero_chunks_out", C.c_uint64),
                 ("mode_hist", C.c_uint64 * 4), ("passes", C.c_uint32), ("n_ops", C.c_uint32),
-                ("n_gates", C.c_uint32), ("n_inner", C.c_uint32), ("ms", C.c_float), ("pad", C.c_uint32)]
+                ("n_gates", C.c_uint32), ("n_inner", C.c_uint32), ("ms", C.c_float), ("launches", C.c_uint32)]
 
 
 EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_order", "plan_stage_ops", "plan_op", "plan_destroy",
@@ -294,7 +294,7 @@ class State:
                             inter_bytes=s.inter_bytes, dir_bytes=s.dir_bytes,
                             scratch_bytes=s.scratch_bytes, zero_chunks_out=s.zero_chunks_out,
                             mode_hist=list(s.mode_hist), passes=s.passes, n_ops=s.n_ops,
-                            n_gates=s.n_gates, n_inner=s.n_inner, ms=s.ms))
+                            n_gates=s.n_gates, n_inner=s.n_inner, ms=s.ms, launches=s.launches))
         return out
 
     def reset(self):
@@ -489,7 +489,7 @@ def _stats_list(st, count):
     return [dict(bytes_in=s.bytes_in, bytes_out=s.bytes_out, bytes_out_host=s.bytes_out_host,
                  inter_bytes=s.inter_bytes, dir_bytes=s.dir_bytes, scratch_bytes=s.scratch_bytes,
                  zero_chunks_out=s.zero_chunks_out, mode_hist=list(s.mode_hist), passes=s.passes, n_ops=s.n_ops,
-                 n_gates=s.n_gates, n_inner=s.n_inner, ms=s.ms) for s in st[:count]]
+                 n_gates=s.n_gates, n_inner=s.n_inner, ms=s.ms, launches=s.launches) for s in st[:count]]
 
 
 class Pipe:

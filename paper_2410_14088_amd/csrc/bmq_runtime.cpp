@@ -1237,6 +1237,12 @@ int collect_stages(sv_t *sv, const sv_plan_t *p, size_t first, size_t batch,
             s.zero_chunks_out = zero;
             s.mode_hist[0] = mh[0]; s.mode_hist[1] = mh[1]; s.mode_hist[2] = mh[2]; s.mode_hist[3] = mh[3];
             s.passes = (uint32_t)np;
+            s.launches = (uint32_t)np;
+            if (sv->group_scratch && scratch && np > 1) {
+                GroupRun gr;
+                group_qubits(sv->n, sv->b, st, gr);
+                s.launches = (uint32_t)(np << gr.outer.size());
+            }
             uint32_t nops = 0;
             for (const auto &pp : st.passes) nops += (uint32_t)(pp.op_end - pp.op_begin);
             s.n_ops = nops;
@@ -2863,6 +2869,7 @@ int sv_pipe_apply(sv_pipe_t *pp, const sv_plan_t *p, size_t first, size_t count,
             s.bytes_out = pp->d2h - d2h0;
             s.bytes_out_host = s.bytes_out;
             s.passes = (uint32_t)np;
+            s.launches = (uint32_t)(np << gr.outer.size());
             s.n_gates = (uint32_t)(st.g1 - st.g0);
             s.n_inner = (uint32_t)st.inner.size();
             uint32_t nops = 0;
