@@ -850,6 +850,47 @@ def main():
             a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
             res["fidelity_f2"] = abs(a0) ** 2 / sv.fidelity(None)[2]
         out[vname] = res
+    if args.workload in ("qft", "random") and not args.no_variant and not args.host_resident and \
+            not args.flags & ~bmq.SV_FLAG_GROUP_SCRATCH:
+        # qubit remapping (SV_FLAG_REMAP): swaps keep the soonest-used qubits
+        # in the blocks; the state ends with its qubits at the plan's layout
+        rcfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=fuse, domain=d["domain"], eb=d["eb"], tile=args.tile,
+                          flags=args.flags | bmq.SV_FLAG_REMAP)
+        rplan = bmq.Plan(gates, rcfg)
+        rsteps = max(1, min(args.steps, args.variant_steps))
+        sv.reset()
+        sv.apply(rplan)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(rsteps):
+            sv.reset()
+            sv.apply(rplan)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        rms = ev0.elapsed_time(ev1) / rsteps
+        progress(f"planner variant remap: {rms:.1f} ms per step")
+        res = {"value": (2 ** n) * G / (rms * 1e-3), "ms_per_step": rms, "steps": rsteps,
+               "stages": rplan.n_stages, "passes": rplan.info()["passes"],
+               "swaps": sum(1 for i in rplan.gate_order() if i == 0xFFFFFFFF) // 3}
+        if args.workload == "qft":
+            lay = rplan.layout()
+            rng = np.random.default_rng(1)
+            idx = rng.integers(0, 1 << n, 4096).astype(np.uint64)
+            pidx = np.zeros_like(idx)
+            for L, pos in enumerate(lay):
+                pidx |= ((idx >> np.uint64(L)) & np.uint64(1)) << np.uint64(pos)
+            want = qft_ry_closed_form(n, d["thetas"], idx)
+            got = sv.amplitudes(torch.from_numpy(pidx.astype(np.int64))).cpu().numpy().astype(np.complex128)
+            res["fidelity_f2"] = float(abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real))
+        else:
+            # forward + inverse planned together returns to |0...0> whatever the layout
+            mplan = bmq.Plan(C.mirror(gates), rcfg)
+            sv.reset()
+            sv.apply(mplan)
+            a0 = complex(sv.amplitudes(torch.zeros(1, dtype=torch.int64)).cpu().numpy()[0])
+            res["fidelity_f2"] = abs(a0) ** 2 / sv.fidelity(None)[2]
+            res["fidelity_check"] = "forward + inverse planned together with remapping, |psi(0)|^2 / |psi|^2"
+        out["remap"] = res
     if args.workload == "random" and not args.no_variant and not args.host_resident and \
             not args.flags & ~bmq.SV_FLAG_GROUP_SCRATCH:
         # the fusion comparison of the configuration: 5-qubit matrices on the

@@ -137,6 +137,22 @@ typedef struct {
  * states when a stage has several passes (SV_ERR_UNSUPPORTED).  Ignored with
  * SV_FLAG_NO_SCRATCH. */
 #define SV_FLAG_GROUP_SCRATCH 32u
+/* SV_FLAG_REMAP: planning only.  Algorithm 1 with qubit remapping (Section
+ * 4.1's goal of fewer stages, so fewer compressions): logical qubits move
+ * between bit positions of the amplitude index.  Where the next gate would
+ * exceed the threshold, before the stage is closed, each inner (global)
+ * position of the stage, ascending, whose logical qubit is used again is
+ * swapped with the local position whose logical qubit is next used last
+ * (ties: the lowest position), if that use comes strictly later; the swap is
+ * appended to the stage as CX(l, g) CX(g, l) CX(l, g) (both positions are
+ * already in the stage).  Later gates act on their qubits' new positions.
+ * The plan's gates are then the physical circuit (plan_gate; plan_gate_order
+ * gives 0xFFFFFFFF for the swap gates) and the state ends with logical qubit
+ * L at position plan_layout[L]: amplitude x of the circuit's state is
+ * amplitude pi(x) of the simulated state, pi moving bit L to bit
+ * plan_layout[L] (pi(0) = 0).  Combines with SV_FLAG_DIAGONAL_FREE, not with
+ * SV_FLAG_GATE_PER_STAGE or SV_FLAG_COMMUTE (SV_ERR_INVALID). */
+#define SV_FLAG_REMAP 64u
 
 /* Per-stage statistics (all counts over the whole state). */
 typedef struct {
@@ -184,12 +200,21 @@ int plan_info(const sv_plan_t *p, size_t *n_stages, size_t *n_ops, size_t *n_pas
 /* Stage s: its gate range [gate_begin, gate_end) in the plan's gate order,
  * its inner indices (up to 8 written to inner_out, count in n_inner) and its
  * number of tile passes. */
+/* plan_layout -- phys_of_logical[L] (host, n = n_qubits entries) receives the
+ * bit position of logical qubit L after the plan (identity unless
+ * SV_FLAG_REMAP).  plan_gate -- the plan's k-th gate as applied (kind, the
+ * bit positions it acts on -- qubits[1] = -1 for one-qubit gates -- and its
+ * three parameters); any output may be NULL. */
+int plan_layout(const sv_plan_t *p, int32_t *phys_of_logical, size_t n);
+int plan_gate(const sv_plan_t *p, size_t k, int32_t *kind, int32_t *qubits, double *params);
+
 int plan_stage(const sv_plan_t *p, size_t s, size_t *gate_begin, size_t *gate_end,
                int32_t *inner_out, int32_t *n_inner, int32_t *n_passes);
 
-/* plan_gate_order -- order_out[k] (host, n = the plan's gate count) receives
- * the input index of the plan's k-th gate: the identity unless the plan was
- * made with SV_FLAG_COMMUTE. */
+/* plan_gate_order -- order_out[k] (host, n = the plan's gate count, i.e. the
+ * last stage's gate_end) receives the input index of the plan's k-th gate:
+ * the identity unless the plan was made with SV_FLAG_COMMUTE or
+ * SV_FLAG_REMAP (0xFFFFFFFF for a remapping swap gate). */
 int plan_gate_order(const sv_plan_t *p, uint32_t *order_out, size_t n);
 
 /* plan_stage_ops -- the fused operations of stage s are plan operations

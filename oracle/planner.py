@@ -108,6 +108,87 @@ def partition_commute(gates: Sequence, b: int, inner_size: int, diag_free: bool 
     return stages
 
 
+NEVER = 1 << 62
+
+
+def partition_remap(gates: Sequence, n: int, b: int, inner_size: int, diag_free: bool = False):
+    """Algorithm 1 with qubit remapping (Section 4.1: fewer stages, so fewer
+    compressions).  Logical qubit L sits at physical bit position phys[L] of
+    the amplitude index (identity at the start); a gate acts on the
+    positions of its qubits, and Algorithm 1 counts the global positions
+    (>= b).  When the next gate would exceed the threshold, before the stage
+    is closed, every inner (global) position pg of the stage, in ascending
+    order, whose logical qubit L is used again is offered a swap: the local
+    position l whose logical qubit is next used last (ties: the lowest l) is
+    taken if that use comes strictly later than L's next use, and the stage
+    ends with SWAP(l, pg) written as CX(l, pg) CX(pg, l) CX(l, pg).  Both
+    positions are already in the stage (pg inner, l local), so the swap
+    adds no global index, and L stays local while it is used (Belady's rule:
+    keep the qubits needed soonest in the block).  The gate that closed the
+    stage and all later ones are mapped through the new positions.
+
+    Returns (stages as half-open ranges of the output gate list, the output
+    gates on physical positions, the input index of each output gate (-1 for
+    the swap gates), phys: logical qubit -> physical position at the end).
+    The output circuit applied to |0...0> gives psi_out(pi(x)) = psi(x), pi
+    moving bit L of x to bit phys[L]."""
+    threshold = max(inner_size, 2)
+    log_at = list(range(n))              # physical position -> logical qubit
+    phys = list(range(n))                # logical qubit -> physical position
+    uses = [[] for _ in range(n)]
+    for i, (_, q, _) in enumerate(gates):
+        for x in q:
+            uses[x].append(i)
+
+    def next_use(L, i):
+        for u in uses[L]:
+            if u >= i:
+                return u
+        return NEVER
+
+    out, src, stages = [], [], []
+    start, cur = 0, set()
+    for i, (kind, q, prm) in enumerate(gates):
+        gq = pairing_globals((kind, tuple(phys[x] for x in q), prm), b, diag_free)
+        if len(gq) > threshold:
+            raise ValueError(f"gate {i} touches {len(gq)} global qubits > {threshold}")
+        if len(cur | gq) > threshold and len(out) > start:
+            for pg in sorted(cur):
+                nu = next_use(log_at[pg], i)
+                if nu == NEVER:
+                    continue
+                best, best_nu = None, nu
+                for l in range(b):
+                    v = next_use(log_at[l], i)
+                    if v > best_nu:
+                        best, best_nu = l, v
+                if best is None:
+                    continue
+                for a, c in ((best, pg), (pg, best), (best, pg)):
+                    out.append(("CX", (a, c), ()))
+                    src.append(-1)
+                la, lg = log_at[best], log_at[pg]
+                log_at[best], log_at[pg] = lg, la
+                phys[lg], phys[la] = best, pg
+            stages.append((start, len(out)))
+            start, cur = len(out), set()
+            gq = pairing_globals((kind, tuple(phys[x] for x in q), prm), b, diag_free)
+        cur |= gq
+        out.append((kind, tuple(phys[x] for x in q), prm))
+        src.append(i)
+    if len(out) > start:
+        stages.append((start, len(out)))
+    return stages, out, src, phys
+
+
+def permute_index(x, phys):
+    """pi(x): bit L of x moved to bit phys[L]."""
+    y = 0
+    for L, p in enumerate(phys):
+        y |= ((x >> L) & 1) << p
+    return y
+
+
 def inner_indices(gates: Sequence, stage: Tuple[int, int], b: int, diag_free: bool = False) -> List[int]:
     s = set()
     for gate in gates[stage[0]:stage[1]]:

@@ -25,6 +25,7 @@ SV_FLAG_GATE_PER_STAGE = 4
 SV_FLAG_DIAGONAL_FREE = 8
 SV_FLAG_COMMUTE = 16
 SV_FLAG_GROUP_SCRATCH = 32
+SV_FLAG_REMAP = 64
 SV_CHUNK_SLOT_BYTES = 576
 KIND = {k: i for i, k in enumerate(
     ["H", "X", "Y", "Z", "S", "T", "RX", "RY", "RZ", "U3", "CX", "CZ", "CP", "RZZ"])}
@@ -74,7 +75,7 @@ EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_
            "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
            "sv_block_labels", "mlp_forward", "mlp_work_floats", "mlp_loss_grad", "mlp_adam_update",
            "sv_graph_capture", "sv_graph_launch", "sv_graph_sync", "sv_graph_destroy", "sv_autotune",
-           "sv_autotune_space", "sv_pipe_required", "sv_pipe_create", "sv_pipe_reset", "sv_pipe_apply",
+           "sv_autotune_space", "plan_layout", "plan_gate", "sv_pipe_required", "sv_pipe_create", "sv_pipe_reset", "sv_pipe_apply",
            "sv_pipe_load", "sv_pipe_footprint", "sv_pipe_destroy",
            "sv_batch_workspace", "sv_batch_apply", "sv_persistent_workspace", "sv_persistent_apply",
            "sv_graph_capture_persistent",
@@ -134,6 +135,8 @@ def lib():
                                   P(C.c_float)]
         L.sv_autotune_space.argtypes = [V, C.c_size_t, P(sv_config_t), V, C.c_uint64, V, P(sv_tune_space_t),
                                         P(sv_config_t), P(C.c_float)]
+        L.plan_layout.argtypes = [V, P(C.c_int32), C.c_size_t]
+        L.plan_gate.argtypes = [V, C.c_size_t, P(C.c_int32), P(C.c_int32), P(C.c_double)]
         L.sv_pipe_required.argtypes = [P(sv_config_t), C.c_int32, P(C.c_uint64), P(C.c_uint64)]
         L.sv_pipe_create.argtypes = [P(sv_config_t), C.c_int32, V, C.c_uint64, V, C.c_uint64, V, P(V)]
         L.sv_pipe_reset.argtypes = [V]
@@ -208,11 +211,30 @@ class Plan:
 
     def __init__(self, gates: Sequence, cfg: Config):
         self.cfg = cfg
-        self.n_gates = len(gates)
         arr = gate_array(gates)
         h = C.c_void_p()
         _check(lib().stage_plan(C.cast(arr, C.c_void_p), len(gates), C.byref(cfg.c()), C.byref(h)))
         self.h = h
+        ns = self.info()["stages"]
+        # gates as applied (more than the input with SV_FLAG_REMAP's swaps)
+        self.n_gates = self.stage(ns - 1)["gates"][1] if ns else 0
+
+    def layout(self):
+        """Bit position of each logical qubit after the plan (identity unless SV_FLAG_REMAP)."""
+        arr = (C.c_int32 * self.cfg.n)()
+        _check(lib().plan_layout(self.h, arr, self.cfg.n))
+        return list(arr)
+
+    def gates(self):
+        """The plan's gates as applied: (kind, positions, params), in plan order."""
+        names = {v: k for k, v in KIND.items()}
+        out = []
+        for k in range(self.n_gates):
+            kind, q, prm = C.c_int32(), (C.c_int32 * 2)(), (C.c_double * 3)()
+            _check(lib().plan_gate(self.h, k, C.byref(kind), q, prm))
+            qs = (q[0],) if q[1] < 0 else (q[0], q[1])
+            out.append((names[kind.value], qs, tuple(prm)))
+        return out
 
     def info(self):
         a, b, c = C.c_size_t(), C.c_size_t(), C.c_size_t()
@@ -227,7 +249,8 @@ class Plan:
         return dict(gates=(g0.value, g1.value), inner=list(inner[:ni.value]), passes=npass.value)
 
     def gate_order(self):
-        """Input index of each of the plan's gates (identity unless SV_FLAG_COMMUTE)."""
+        """Input index of each of the plan's gates (identity unless SV_FLAG_COMMUTE or
+        SV_FLAG_REMAP; 0xFFFFFFFF for a remapping swap gate)."""
         arr = (C.c_uint32 * max(1, self.n_gates))()
         _check(lib().plan_gate_order(self.h, arr, self.n_gates))
         return list(arr[:self.n_gates])

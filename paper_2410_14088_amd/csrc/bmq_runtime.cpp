@@ -147,7 +147,8 @@ struct sv_plan {
     sv_config_t cfg{};
     int t = kDefaultTile;
     std::vector<GateRec> gates;          // in plan order (input order unless SV_FLAG_COMMUTE)
-    std::vector<uint32_t> order;         // plan position -> input gate index
+    std::vector<uint32_t> order;         // plan position -> input gate index (kNoInput: a remapping swap)
+    std::vector<int32_t> layout;         // logical qubit -> bit position at the end (identity unless SV_FLAG_REMAP)
     std::vector<StagePlan> stages;
     std::vector<OpDesc> ops;
     std::vector<float2> data;
@@ -228,7 +229,8 @@ int validate_cfg(const sv_config_t *c)
     if (!(c->eb > 0) || !std::isfinite(c->eb) || !std::isfinite((float)c->eb) || (float)c->eb <= 0)
         return fail(SV_ERR_INVALID, "eb must be a positive finite float32");
     if (c->flags & ~(SV_FLAG_NO_SCRATCH | SV_FLAG_NO_MFMA | SV_FLAG_GATE_PER_STAGE | SV_FLAG_DIAGONAL_FREE |
-                     SV_FLAG_COMMUTE | SV_FLAG_GROUP_SCRATCH)) return fail(SV_ERR_INVALID, "unknown flags 0x%x", c->flags);
+                     SV_FLAG_COMMUTE | SV_FLAG_GROUP_SCRATCH | SV_FLAG_REMAP))
+        return fail(SV_ERR_INVALID, "unknown flags 0x%x", c->flags);
     if (c->reserved) return fail(SV_ERR_INVALID, "reserved must be 0");
     if (c->domain != SV_DOMAIN_RAW && !step_ok(c->domain, step_shift((float)c->eb)))
         return fail(SV_ERR_INVALID, "eb %g outside the codec's range for this domain (LOG: 2^-23 <= eb < 1/2)", c->eb);
@@ -374,6 +376,110 @@ int partition_commute(std::vector<GateRec> &gates, int b, int inner, bool diag_f
         remaining.swap(deferred);
     }
     gates.swap(planned);
+    return SV_OK;
+}
+
+constexpr uint32_t kNoInput = 0xFFFFFFFFu;
+
+// Algorithm 1 with qubit remapping.  Logical qubit L sits at bit position
+// phys[L] (identity at the start); a gate acts on its qubits' positions and
+// Algorithm 1 counts the global positions (>= b).  When the next gate would
+// exceed the threshold, before the stage is closed, each inner position pg
+// of the stage, ascending, whose logical qubit is used again is offered a
+// swap: the local position whose logical qubit is next used last (ties: the
+// lowest) is taken when that use comes strictly later, and the stage ends
+// with SWAP(l, pg) = CX(l, pg) CX(pg, l) CX(l, pg) -- both positions are in
+// the stage already, so no global index is added.  Later gates map through
+// the new positions.  gates becomes the physical circuit; order receives its
+// input indices (kNoInput for swap gates), layout the final positions.
+int partition_remap(std::vector<GateRec> &gates, int n, int b, int inner, bool diag_free, std::vector<StagePlan> &out,
+                    std::vector<uint32_t> &order, std::vector<int32_t> &layout)
+{
+    const int threshold = std::max(inner, 2);
+    const uint64_t never = 1ull << 62;
+    std::vector<int> log_at(n), phys(n);
+    for (int q = 0; q < n; ++q) log_at[q] = phys[q] = q;
+    std::vector<std::vector<uint32_t>> uses(n);
+    for (size_t i = 0; i < gates.size(); ++i)
+        for (int j = 0; j < gates[i].nq; ++j) uses[gates[i].q[j]].push_back((uint32_t)i);
+    std::vector<size_t> ptr(n, 0);
+    auto next_use = [&](int L, size_t i) -> uint64_t {
+        while (ptr[L] < uses[L].size() && uses[L][ptr[L]] < i) ++ptr[L];
+        return ptr[L] < uses[L].size() ? uses[L][ptr[L]] : never;
+    };
+    auto globals_of = [&](const GateRec &g) {
+        std::vector<int> gq;
+        for (int j = 0; j < g.nq; ++j)
+            if (phys[g.q[j]] >= b && !(diag_free && g.diag)) gq.push_back(phys[g.q[j]]);
+        return gq;
+    };
+    std::vector<GateRec> res;
+    order.clear();
+    size_t start = 0;
+    std::vector<int> cur;
+    auto close = [&](size_t end) {
+        StagePlan s;
+        s.g0 = start;
+        s.g1 = end;
+        s.inner = cur;
+        std::sort(s.inner.begin(), s.inner.end());
+        out.push_back(s);
+        start = end;
+        cur.clear();
+    };
+    for (size_t i = 0; i < gates.size(); ++i) {
+        std::vector<int> gq = globals_of(gates[i]);
+        if ((int)gq.size() > threshold)
+            return fail(SV_ERR_INVALID, "gate %zu touches %zu global qubits > threshold %d", i, gq.size(), threshold);
+        std::vector<int> uni = cur;
+        for (int q : gq)
+            if (std::find(uni.begin(), uni.end(), q) == uni.end()) uni.push_back(q);
+        if ((int)uni.size() > threshold && res.size() > start) {
+            std::vector<int> inner_now = cur;
+            std::sort(inner_now.begin(), inner_now.end());
+            for (int pg : inner_now) {
+                uint64_t best_nu = next_use(log_at[pg], i);
+                if (best_nu == never) continue;
+                int best = -1;
+                for (int l = 0; l < b; ++l) {
+                    const uint64_t v = next_use(log_at[l], i);
+                    if (v > best_nu) {
+                        best = l;
+                        best_nu = v;
+                    }
+                }
+                if (best < 0) continue;
+                const int pairs[3][2] = {{best, pg}, {pg, best}, {best, pg}};
+                for (const auto &pr : pairs) {
+                    GateRec cx;
+                    cx.kind = SV_GATE_CX;
+                    cx.nq = 2;
+                    cx.q[0] = pr[0];
+                    cx.q[1] = pr[1];
+                    cx.p[0] = cx.p[1] = cx.p[2] = 0.0;
+                    cx.diag = false;
+                    res.push_back(cx);
+                    order.push_back(kNoInput);
+                }
+                const int la = log_at[best], lg = log_at[pg];
+                log_at[best] = lg;
+                log_at[pg] = la;
+                phys[lg] = best;
+                phys[la] = pg;
+            }
+            close(res.size());
+            gq = globals_of(gates[i]);
+            uni = gq;
+        }
+        cur = uni;
+        GateRec r = gates[i];
+        for (int j = 0; j < r.nq; ++j) r.q[j] = phys[gates[i].q[j]];
+        res.push_back(r);
+        order.push_back((uint32_t)i);
+    }
+    if (res.size() > start) close(res.size());
+    gates.swap(res);
+    layout.assign(phys.begin(), phys.end());
     return SV_OK;
 }
 
@@ -733,7 +839,15 @@ int stage_plan(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, s
     const bool per_gate = (cfg->flags & SV_FLAG_GATE_PER_STAGE) != 0;
     const bool diag_free = (cfg->flags & SV_FLAG_DIAGONAL_FREE) != 0;
     int prc;
-    if ((cfg->flags & SV_FLAG_COMMUTE) && !per_gate) {
+    const bool remap = (cfg->flags & SV_FLAG_REMAP) != 0;
+    if (remap && (per_gate || (cfg->flags & SV_FLAG_COMMUTE))) {
+        delete P;
+        return fail(SV_ERR_INVALID, "SV_FLAG_REMAP combines with neither SV_FLAG_GATE_PER_STAGE nor SV_FLAG_COMMUTE");
+    }
+    if (remap) {
+        prc = partition_remap(P->gates, n, cfg->block_qubits, cfg->inner_size, diag_free, P->stages, P->order,
+                              P->layout);
+    } else if ((cfg->flags & SV_FLAG_COMMUTE) && !per_gate) {
         prc = partition_commute(P->gates, cfg->block_qubits, cfg->inner_size, diag_free, P->stages, P->order);
     } else {
         prc = partition(P->gates, cfg->block_qubits, cfg->inner_size, per_gate, diag_free, P->stages);
@@ -741,6 +855,8 @@ int stage_plan(const sv_gate_t *gates, size_t n_gates, const sv_config_t *cfg, s
         for (size_t i = 0; i < P->order.size(); ++i) P->order[i] = (uint32_t)i;
     }
     if (prc) { delete P; return prc; }
+    if (P->layout.empty())
+        for (int q = 0; q < n; ++q) P->layout.push_back(q);
     for (StagePlan &st : P->stages)
         if (!plan_passes(*P, st)) { delete P; return fail(SV_ERR_INVALID, "internal: dense operation outside its tile"); }
     if ((uint64_t)P->ops.size() * sizeof(OpDesc) + P->data.size() * sizeof(float2) + 256 > kOpsArenaBytes) {
@@ -799,6 +915,29 @@ int plan_gate_order(const sv_plan_t *p, uint32_t *order_out, size_t n)
     if (n != p->order.size()) return fail(SV_ERR_INVALID, "order array of %zu entries for %zu gates", n, p->order.size());
     if (n && !order_out) return fail(SV_ERR_INVALID, "order_out is NULL");
     std::copy(p->order.begin(), p->order.end(), order_out);
+    return SV_OK;
+}
+
+int plan_layout(const sv_plan_t *p, int32_t *phys_of_logical, size_t n)
+{
+    if (!p || !phys_of_logical) return fail(SV_ERR_INVALID, "plan or output is NULL");
+    if (n != p->layout.size()) return fail(SV_ERR_INVALID, "layout array of %zu entries for %zu qubits", n, p->layout.size());
+    std::copy(p->layout.begin(), p->layout.end(), phys_of_logical);
+    return SV_OK;
+}
+
+int plan_gate(const sv_plan_t *p, size_t k, int32_t *kind, int32_t *qubits, double *params)
+{
+    if (!p) return fail(SV_ERR_INVALID, "plan is NULL");
+    if (k >= p->gates.size()) return fail(SV_ERR_INVALID, "gate %zu outside the plan's %zu gates", k, p->gates.size());
+    const GateRec &g = p->gates[k];
+    if (kind) *kind = g.kind;
+    if (qubits) {
+        qubits[0] = g.q[0];
+        qubits[1] = g.nq == 2 ? g.q[1] : -1;
+    }
+    if (params)
+        for (int j = 0; j < 3; ++j) params[j] = g.p[j];
     return SV_OK;
 }
 

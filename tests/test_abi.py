@@ -5,6 +5,7 @@ planning makes no HIP calls."""
 import os
 import re
 
+import numpy as np
 import pytest
 
 from oracle import planner as OP
@@ -109,6 +110,34 @@ def test_commute_plan_matches_oracle(bmq, inner, flags):
     assert plan.gate_order() == list(range(len(C.config(0)["gates"])))
 
 
+@pytest.mark.parametrize("flags", [64, 72])
+@pytest.mark.parametrize("inner", [2, 3])
+def test_remap_plan_matches_oracle(bmq, inner, flags):
+    """SV_FLAG_REMAP: the host planner's stages, physical gates, input
+    indices and final layout equal the oracle planner's partition_remap."""
+    cases = [(C.config(0)["gates"], 16, 10), (C.qaoa_ring(16, 3, 2)[0], 16, 11),
+             (C.config(1, n=20)["gates"], 20, 12), (C.random_layers(18, 6, 9), 18, 12)]
+    for gates, n, b in cases:
+        cfg = bmq.Config(n=n, b=b, inner=inner, fuse=4, domain=1, eb=1e-5, flags=flags)
+        plan = bmq.Plan(gates, cfg)
+        stages, out, src, phys = OP.partition_remap(gates, n, b, inner, diag_free=bool(flags & 8))
+        assert plan.n_stages == len(stages)
+        assert [plan.stage(s)["gates"] for s in range(plan.n_stages)] == stages
+        got = plan.gates()
+        assert [(k, q) for k, q, _ in got] == [(k, tuple(q)) for k, q, _ in out]
+        assert all(np.allclose(a[2][:len(b_[2])], b_[2]) for a, b_ in zip(got, out))
+        assert plan.gate_order() == [i if i >= 0 else 0xFFFFFFFF for i in src]
+        assert plan.layout() == phys
+        assert [plan.stage(s)["inner"] for s in range(plan.n_stages)] == \
+            [OP.inner_indices(out, st, b, bool(flags & 8)) for st in stages]
+    # fewer stages than Algorithm 1 on the QFT
+    g = C.config(1, n=20)["gates"]
+    assert bmq.Plan(g, bmq.Config(n=20, b=12, flags=64)).n_stages < bmq.Plan(g, bmq.Config(n=20, b=12)).n_stages
+    for bad in (64 | 16, 64 | 4):
+        with pytest.raises(bmq.BmqError):
+            bmq.Plan(g, bmq.Config(n=20, b=12, flags=bad))
+
+
 def test_diagonal_free_partition_pins():
     # a circuit of diagonal gates only is one stage, whatever qubits it
     # touches; a non-diagonal gate on a third global qubit still cuts
@@ -132,7 +161,7 @@ def test_config_stage_counts(bmq):
 
 @pytest.mark.parametrize("bad", [dict(n=9), dict(n=41), dict(b=5), dict(b=17), dict(fuse=0),
                                  dict(fuse=6), dict(domain=3), dict(domain=-1), dict(eb=0.0), dict(eb=-1.0),
-                                 dict(tile=9), dict(tile=14), dict(eb=float("nan")), dict(flags=64),
+                                 dict(tile=9), dict(tile=14), dict(eb=float("nan")), dict(flags=128),
                                  dict(flags=0x80000000)])
 def test_invalid_configs_rejected(bmq, bad):
     kw = dict(n=16, b=10, inner=2, fuse=2, domain=0, eb=1e-6)

@@ -48,7 +48,7 @@ def circuits_for(n):
     yield "mirror", C.mirror(C.random_layers(n, 2, 32))
 
 
-@pytest.mark.parametrize("flags", [0, 8, 16, 24])
+@pytest.mark.parametrize("flags", [0, 8, 16, 24, 64])
 @pytest.mark.parametrize("fuse,tile", [(1, 10), (2, 10), (4, 10), (5, 11), (4, 12)])
 def test_fused_operations_equal_the_gates(bmq, flags, fuse, tile):
     n, b = 12, 7
@@ -57,14 +57,17 @@ def test_fused_operations_equal_the_gates(bmq, flags, fuse, tile):
         cfg = bmq.Config(n=n, b=b, inner=2, fuse=fuse, domain=1, eb=1e-5, tile=tile, flags=flags)
         plan = bmq.Plan(gates, cfg)
         order = plan.gate_order()
+        # with remapping the stages apply the physical circuit (relabelled
+        # gates and swaps, checked against the oracle planner in test_abi)
+        applied = plan.gates() if flags & bmq.SV_FLAG_REMAP else [gates[i] for i in order]
         for s in range(plan.n_stages):
             g0, g1 = plan.stage(s)["gates"]
             psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
-            ref = sim.simulate(n, [gates[i] for i in order[g0:g1]], psi)
+            ref = sim.simulate(n, applied[g0:g1], psi)
             got = psi.copy()
             for kind, qs, vals in plan.stage_ops(s):
                 if kind == "dense":
-                    assert len(qs) <= fuse
+                    assert len(qs) <= max(fuse, 2)      # a 2-qubit gate is one operation at any width
                 got = apply_op(got, n, kind, qs, vals)
             scale = np.abs(ref).max()
             err = np.abs(got - ref).max() / scale

@@ -234,3 +234,90 @@ def test_commute_test_catches_a_wrong_rule():
         assert np.abs(sim.simulate(n, [gates[i] for i in order]) - sim.simulate(n, gates)).max() > 1e-3
     finally:
         P.commute = saved
+
+
+# ---- qubit remapping (Algorithm 1 with swaps of inner and local positions)
+
+def _unpermute(psi_out, n, phys):
+    """psi(x) = psi_out(pi(x)), pi moving bit L of x to bit phys[L]."""
+    x = np.arange(2 ** n, dtype=np.int64)
+    y = np.zeros_like(x)
+    for L, p in enumerate(phys):
+        y |= ((x >> L) & 1) << p
+    return psi_out[y]
+
+
+def _remap_cases():
+    yield C.random_layers(10, 6, 3), 10, 4
+    yield C.qft_on_ry(10, 4)[0], 10, 4
+    yield C.qaoa_ring(10, 2, 5)[0], 10, 4
+    yield C.random_layers(9, 4, 11), 9, 3
+
+
+@pytest.mark.parametrize("inner", [2, 3])
+def test_remap_rewrite_is_exact(inner):
+    """The physical circuit (relabelled gates plus the inserted swaps) applied
+    to |0...0> equals the input circuit's state with its qubits moved to
+    their final positions, to rounding (FP64 oracle simulator)."""
+    for gates, n, b in _remap_cases():
+        stages, out, src, phys = P.partition_remap(gates, n, b, inner)
+        ref = sim.simulate(n, gates)
+        got = _unpermute(sim.simulate(n, out), n, phys)
+        assert np.abs(ref - got).max() < 1e-12
+        # every input gate appears once, in order; swaps are CX triples
+        assert [i for i in src if i >= 0] == list(range(len(gates)))
+        sw = [g for g, i in zip(out, src) if i < 0]
+        assert len(sw) % 3 == 0 and all(g[0] == "CX" for g in sw)
+        assert sorted(phys) == list(range(n))
+
+
+@pytest.mark.parametrize("inner", [2, 3])
+def test_remap_stages_are_algorithm1_stages(inner):
+    """Each stage of the physical circuit holds at most the threshold of
+    global positions, is a valid Algorithm 1 stage (its groups are
+    independent: simulating every group alone reproduces the state), and a
+    stage is only closed where the next gate would overflow it."""
+    T = max(inner, 2)
+    for gates, n, b in _remap_cases():
+        stages, out, src, phys = P.partition_remap(gates, n, b, inner)
+        assert stages[0][0] == 0 and stages[-1][1] == len(out)
+        assert all(s[0] < s[1] for s in stages)
+        assert all(a[1] == c[0] for a, c in zip(stages, stages[1:]))
+        for s in stages:
+            assert len(P.inner_indices(out, s, b)) <= T
+        for s, t in zip(stages, stages[1:]):
+            # the gate that opened the next stage (after the swaps) overflows this one
+            nxt = out[t[0]]
+            assert len(set(P.inner_indices(out, s, b)) | P.global_qubits(nxt[1], b)) > T
+        psi = np.zeros(2 ** n, dtype=complex)
+        psi[0] = 1
+        for s in stages:
+            inner_q = P.inner_indices(out, s, b)
+            relabel = {q: q for q in range(b)}
+            relabel.update({q: b + i for i, q in enumerate(inner_q)})
+            sub = [(k, tuple(relabel[x] for x in q), p) for k, q, p in out[s[0]:s[1]]]
+            for blocks in P.groups(n, b, inner_q):
+                idx = np.concatenate([np.arange(2 ** b) + (blk << b) for blk in blocks])
+                psi[idx] = sim.simulate(b + len(inner_q), sub, psi[idx])
+        assert np.abs(psi - sim.simulate(n, out)).max() < 1e-12
+
+
+def test_remap_cuts_stages():
+    """Fewer stages than Algorithm 1 on the QFT, the random layers and the
+    QAOA ring at the configurations' shapes (counts of the planner only)."""
+    for gates, n, b in ((C.qft_on_ry(20, 7)[0], 20, 12), (C.random_layers(18, 8, 2), 18, 10),
+                        (C.qaoa_ring(18, 3, 4)[0], 18, 10)):
+        base = len(P.partition(gates, b, 2))
+        st = P.partition_remap(gates, n, b, 2)[0]
+        assert len(st) < base, (len(st), base)
+
+
+def test_remap_check_catches_dropped_swaps():
+    """The exactness pin fails for a rewrite that relabels the gates but
+    leaves the swaps out (a plausible mistake)."""
+    gates, n, b = C.qft_on_ry(10, 4)[0], 10, 4
+    stages, out, src, phys = P.partition_remap(gates, n, b, 2)
+    assert any(i < 0 for i in src)
+    broken = [g for g, i in zip(out, src) if i >= 0]
+    got = _unpermute(sim.simulate(n, broken), n, phys)
+    assert np.abs(sim.simulate(n, gates) - got).max() > 1e-3
