@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="random workload: skip the batched 512-circuit sub-line")
+    ap.add_argument("--no-predictor-pools", action="store_true",
+                    help="random workload: worst-case device pools instead of pools sized by the predictor")
     ap.add_argument("--no-autotune", action="store_true",
                     help="random workload: no tile / fusion autotuning (fusion width 5 unless --fuse)")
     ap.add_argument("--no-variant", action="store_true",
@@ -409,6 +411,54 @@ def batch_line(args, planning=True):
     return out
 
 
+def headline_pools(plan, n, b, fuse, tile, flags, eb, margin=0.1, seed=11):
+    """Memory planning for the headline (Section 4.4 with the learned
+    predictor): the block predictor is trained online on three smaller
+    circuits of the same generator and global-qubit count (planning features
+    before each stage, labels after it), calibrated by their largest actual /
+    predicted peak, and rolled over the headline's plan; the predicted peak
+    sizes the device pools (sv_admit, 10 % margin) instead of the worst case."""
+    import torch
+    from paper_2410_14088_amd import bmq
+    from paper_2410_14088_amd import circuits as C
+    t0 = time.perf_counter()
+    c = n - b
+    pred = bmq.Predictor(C.mlp_init_params(seed), "cuda:0", lr=2e-3)
+    trained = []
+    for tn, sd in ((21, 101), (22, 102), (23, 103)):
+        cfg = bmq.Config(n=tn, b=tn - c, inner=2, fuse=fuse, domain=1, eb=eb, tile=tile, flags=flags)
+        tplan = bmq.Plan(C.random_layers(tn, 16, sd), cfg)
+        sv = bmq.State(cfg, "cuda:0")
+        peak = 0.0
+        for st in range(tplan.n_stages):
+            X = sv.plan_features(tplan, st)
+            sv.apply(tplan, st, 1)
+            y, mode = sv.plan_labels()
+            for _ in range(4):
+                pred.train_step(X, y, mode)
+            peak = max(peak, float(torch.exp2(y.double() + cfg.b).sum()))
+        sv.close()
+        trained.append((peak, tplan))
+    # calibration: the largest actual / predicted peak of the training circuits
+    ratios = [pk / float(bmq.predict_bytes(pred.params, pl).max()) for pk, pl in trained]
+    calib = max(ratios)
+    raw = float(bmq.predict_bytes(pred.params, plan).max())
+    hcfg = bmq.Config(n=n, b=b, inner=2, fuse=fuse, domain=1, eb=eb, tile=tile, flags=flags)
+    _, pools, arenas = bmq.admit([hcfg], [raw * calib], margin, 1 << 62)
+    _, wpools, warenas = bmq.admit([hcfg], None, margin, 1 << 62)
+    torch.cuda.empty_cache()
+    out = {"trained_on": "random U3/CZ layers, depth 16, 21-23 qubits, 9 global qubits (seeds 101-103)",
+           "calibration": calib, "training_actual_over_predicted": ratios,
+           "predicted_peak_stream_bytes": raw * calib, "margin": margin,
+           "pool_bytes": int(pools[0]), "arena_bytes": int(arenas[0]),
+           "worst_case_pool_bytes": int(wpools[0]), "worst_case_arena_bytes": int(warenas[0]),
+           "host_pool_bytes": 8 << 30,
+           "seconds": time.perf_counter() - t0}
+    progress(f"memory planning: predicted peak {raw * calib / 1e9:.1f} GB, pools {int(pools[0]) / 1e9:.1f} GB "
+             f"(worst case {int(wpools[0]) / 1e9:.1f} GB)")
+    return out
+
+
 def autotune_headline(d, gates, args, inner=(2,), fuse=(2, 3, 4, 5), tiles=(12, 13)):
     """sv_autotune_space over tile sizes and fusion widths (or inner sizes)
     on the circuit's first four layers; the winner is used for the full
@@ -662,7 +712,17 @@ def main():
     info = plan.info()
     G = len(gates)
     dev = "cuda:0"
+    planning = None
+    if args.workload == "random" and not args.no_predictor_pools and not args.host_resident:
+        # device pools sized by the learned predictor's rollout of this plan
+        planning = headline_pools(plan, n, d["b"], fuse, args.tile or 12, args.flags, d["eb"])
+        cfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=fuse, domain=d["domain"], eb=d["eb"], tile=args.tile,
+                         flags=args.flags, pool_bytes=planning["pool_bytes"])
     sv = bmq.State(cfg, dev)
+    if planning:
+        # second memory level: records beyond the predicted device pools
+        # spill to a pinned host pool instead of failing
+        sv.attach_host_pool(planning["host_pool_bytes"])
     if args.host_resident:
         sv.attach_host_pool(2 * (8 << n))          # two state copies of up to complex64 size
     stream = torch.cuda.current_stream()
@@ -672,9 +732,36 @@ def main():
         return sv.apply(plan, stats=stats)
 
     progress(f"{wname}: {info['stages']} stages, {info['passes']} passes; warm-up")
-    for _ in range(args.warmup):
-        step()
+    for _ in range(max(1, args.warmup) if planning else args.warmup):
+        try:
+            step()
+        except bmq.BmqError as e:
+            if not planning or e.code != -3:
+                raise
+            # the prediction fell short: worst-case pools (records are the same)
+            progress("memory planning: predicted pools overflowed, worst-case pools")
+            planning["fallback"] = True
+            sv.close()
+            torch.cuda.empty_cache()
+            cfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=fuse, domain=d["domain"], eb=d["eb"], tile=args.tile,
+                             flags=args.flags)
+            sv = bmq.State(cfg, dev)
+            step()
     torch.cuda.synchronize()
+    if planning:
+        planning["warmup_host_spill_bytes"] = int(max(s["bytes_out_host"] for s in step()))
+        if planning["warmup_host_spill_bytes"]:
+            # the prediction fell short and records spilled to the host level:
+            # time the headline with worst-case device pools (same records)
+            progress("memory planning: records spilled to the host pool, worst-case pools for the timing")
+            planning["fallback"] = True
+            sv.close()
+            torch.cuda.empty_cache()
+            cfg = bmq.Config(n=n, b=d["b"], inner=2, fuse=fuse, domain=d["domain"], eb=d["eb"], tile=args.tile,
+                             flags=args.flags)
+            sv = bmq.State(cfg, dev)
+            step()
+        torch.cuda.synchronize()
     progress(f"{wname}: timing {args.steps} steps")
 
     all_stats = []
@@ -785,6 +872,12 @@ def main():
         "max_abs_err": maxerr,
         "norm2": norm2,
     }
+    if planning:
+        planning.setdefault("fallback", False)
+        planning["actual_peak_record_bytes"] = int(peak_bytes)
+        planning["timed_host_spill_bytes"] = int(sum(s["bytes_out_host"] for st in all_stats for s in st))
+        out["device_arena_bytes"] = int(sv.arena.numel())
+        out["memory_planning"] = planning
     if args.workload == "random" and not args.fuse_given and not args.no_autotune:
         out["autotune"] = tune
         out["config"]["fuse_qubits_autotuned"] = True
