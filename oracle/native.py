@@ -15,27 +15,33 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 BUILD = os.path.join(HERE, "_build")
-SO = os.path.join(BUILD, "liboracle.so")
+DEFAULT_SO = os.path.join(BUILD, "liboracle.so")
+SO = os.environ.get("ORACLE_SO") or DEFAULT_SO      # ORACLE_SO: another build (the sanitized one)
 SOURCES = ["codec_ref.c", "sim_ref.c"]
 
 _lib = None
 
 
-def build() -> str:
+def build(sanitize: bool = False) -> str:
+    """Build liboracle.so; with sanitize, liboracle_sanitized.so with
+    AddressSanitizer and UndefinedBehaviorSanitizer (load it with
+    ORACLE_SO=<path> and gcc's libasan / libubsan preloaded)."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = [os.path.join(HERE, s) for s in SOURCES]
-    tmp = SO + ".tmp"
+    out = os.path.join(BUILD, "liboracle_sanitized.so") if sanitize else DEFAULT_SO
+    tmp = out + ".tmp"
+    extra = ["-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined"] if sanitize else []
     cmd = ["gcc", "-O2", "-std=gnu11", "-fPIC", "-shared", "-fopenmp",
-           "-ffp-contract=off", "-fno-fast-math", "-o", tmp] + srcs + ["-lm"]
+           "-ffp-contract=off", "-fno-fast-math"] + extra + ["-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, SO)
-    return SO
+    os.replace(tmp, out)
+    return out
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(SO):
+        if not os.path.exists(SO) and SO == DEFAULT_SO:
             build()
         L = C.CDLL(SO)
         P = C.c_void_p

@@ -16,7 +16,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SO = os.path.join(HERE, "_build", "libbmq.so")
+# BMQ_SO selects another build of the same library (the sanitized one)
+SO = os.environ.get("BMQ_SO") or os.path.join(HERE, "_build", "libbmq.so")
 
 SV_DOMAIN_LIN, SV_DOMAIN_LOG, SV_DOMAIN_RAW = 0, 1, 2
 SV_FLAG_NO_SCRATCH = 1

@@ -35,7 +35,16 @@ def _run(cmd):
     return r
 
 
-def build(verbose: bool = False) -> str:
+# host-code sanitizers (AddressSanitizer + UndefinedBehaviorSanitizer) for the
+# runtime; device code is never built with them
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
+SO_SANITIZED = os.path.join(BUILD, "libbmq_sanitized.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Build _build/libbmq.so; with sanitize, _build/libbmq_sanitized.so whose
+    host runtime is instrumented (load it with BMQ_SO=<path> and the clang
+    ASan runtime preloaded, e.g. for the CPU test suite)."""
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     k_obj = os.path.join(BUILD, "bmq_kernels.o")
@@ -44,16 +53,18 @@ def build(verbose: bool = False) -> str:
     m_obj = os.path.join(BUILD, "bmq_mlp.o")
     _run([HIPCC] + COMMON + DEVICE + ["-c", os.path.join(CSRC, "bmq_mlp.hip"), "-o", m_obj])
     objs.append(m_obj)
-    r_obj = os.path.join(BUILD, "bmq_runtime.o")
-    _run([HIPCC] + COMMON + ["-Wall", "-c", os.path.join(CSRC, "bmq_runtime.cpp"), "-o", r_obj])
+    r_obj = os.path.join(BUILD, "bmq_runtime_sanitized.o" if sanitize else "bmq_runtime.o")
+    extra = SANITIZE + ["-g", "-fno-omit-frame-pointer"] if sanitize else []
+    _run([HIPCC] + COMMON + extra + ["-Wall", "-c", os.path.join(CSRC, "bmq_runtime.cpp"), "-o", r_obj])
     objs.append(r_obj)
-    tmp = SO + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
-    os.replace(tmp, SO)
+    out = SO_SANITIZED if sanitize else SO
+    tmp = out + ".tmp"
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC"] + (SANITIZE if sanitize else []) + ["-o", tmp] + objs)
+    os.replace(tmp, out)
     if verbose:
-        print("built", SO)
-    return SO
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv)
