@@ -90,15 +90,19 @@ __device__ __forceinline__ uint32_t bitlen(uint32_t v) { return v ? 32u - (uint3
 
 // ------------------------------------------------------------------ codec arithmetic
 
-// 2^(k 2^-s): nearest integer i = round(k / 2^s) in integers, remainder
-// f = (k - i 2^s) 2^-s in [-1/2, 1/2) exact, 2^f by the degree-6 Chebyshev
-// fit, 2^i applied as two exact power-of-two scalings.
-__device__ __forceinline__ float log_decode(int32_t k, int s, float delta)
+// 2^(k 2^-s) from kh = k + 2^(s-1): nearest integer i = round(k / 2^s) =
+// kh >> s in integers, remainder f = (k - i 2^s) 2^-s in [-1/2, 1/2),
+// computed as (kh mod 2^s) 2^-s - 1/2 (both steps exact: a power-of-two
+// scaling of an integer below 2^22, then a difference of two multiples of
+// 2^-s below 1 in magnitude), 2^f by the degree-6 Chebyshev fit, 2^i
+// applied as two exact power-of-two scalings.  The caller adds 2^(s-1) to
+// the code (folded into the Lorenzo start for LZ planes).
+__device__ __forceinline__ float log_decode_h(int32_t kh, int s, float delta)
 {
     // |k| < 2^30 and 1 <= s <= 22, so k + 2^(s-1) cannot overflow 32 bits
-    const int32_t i = (k + (1 << (s - 1))) >> s;
-    const int32_t r = k - (int32_t)((uint32_t)i << s);
-    const float f = (float)r * delta;
+    const int32_t i = kh >> s;
+    const uint32_t m = (uint32_t)kh & ((1u << s) - 1u);
+    const float f = __builtin_fmaf((float)m, delta, -0.5f);
     float p = 0.00015469732170458883f;
     p = __builtin_fmaf(p, f, 0.0013400432653725147f);
     p = __builtin_fmaf(p, f, 0.00961802527308464f);
@@ -469,7 +473,10 @@ struct QuadPlane {
     uint32_t nzb, negb; // this lane's 16 non-zero / negative bits
     uint32_t w;         // field width
     int32_t carry;      // code preceding this lane's first value
-    int32_t kp[16];     // this lane's codes after the zero substitution
+    int32_t kfirst;     // this lane's first code after the zero substitution
+    int32_t kp[16];     // after encode_quad: the zigzagged Lorenzo residuals of this lane's codes
+                        // (after the zero substitution; residual 0 for the chunk's first value),
+                        // or the 16 raw values of a VERBATIM plane
 };
 
 // A VERBATIM plane keeps the lane's 16 raw values, in place of its codes.
@@ -491,6 +498,7 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
         P.anchor = 0;
         P.w = 0;
         P.carry = 0;
+        P.kfirst = 0;
         verbatim_quad(x, P);
         return;
     }
@@ -563,6 +571,7 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     P.anchor = 0;
     P.w = 0;
     P.carry = 0;
+    P.kfirst = 0;
     if (f & 1u) { verbatim_quad(x, P); return; }
     const bool allzero = log_dom ? !(f & 4u) : !(f & 2u);
     if (allzero) { P.hdr = M_ZERO; return; }
@@ -582,16 +591,21 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     P.carry = carry;
     // zigzag(v) grows with |v| on each side of zero, so the widest field of a
     // mode is the zigzag of the smallest or of the largest value
-    int32_t dmin = 0, dmax = 0, kmin = INT32_MAX, kmax = INT32_MIN;
+    // from here on the lane keeps its Lorenzo residuals, zigzagged (the LZ
+    // fields), in place of its codes; its first code (after the zero
+    // substitution) rebuilds the codes if the chunk takes Q0.  The widest
+    // field of a mode has the highest bit of the OR of its fields.
+    int32_t kmin = INT32_MAX, kmax = INT32_MIN;
+    uint32_t orl = 0;
     int32_t prev = carry;
     if (nzb != 0xFFFFu) {
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int32_t kp = ((nzb >> j) & 1u) ? P.kp[j] : prev;
-            P.kp[j] = kp;
+            if (j == 0) P.kfirst = kp;
             const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
-            dmin = min(dmin, d);
-            dmax = max(dmax, d);
+            P.kp[j] = (int32_t)zigzag(d);
+            orl |= (uint32_t)P.kp[j];
             kmin = min(kmin, kp);
             kmax = max(kmax, kp);
             prev = kp;
@@ -600,15 +614,16 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
             const int32_t kp = P.kp[j];
+            if (j == 0) P.kfirst = kp;
             const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
-            dmin = min(dmin, d);
-            dmax = max(dmax, d);
+            P.kp[j] = (int32_t)zigzag(d);
+            orl |= (uint32_t)P.kp[j];
             kmin = min(kmin, kp);
             kmax = max(kmax, kp);
             prev = kp;
         }
     }
-    const uint32_t orl = zigzag(dmin) | zigzag(dmax), orq = zigzag(kmin) | zigzag(kmax);
+    const uint32_t orq = zigzag(kmin) | zigzag(kmax);
     const uint32_t wl = bitlen(quad_or(orl)), wq = bitlen(quad_or(orq));
     uint32_t sc = 0, zc = 0;
     if (log_dom) {
@@ -622,7 +637,7 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     if (256u < best) { verbatim_quad(x, P); return; }
     P.w = (mode == M_LZ) ? wl : wq;
     P.hdr = mode | (P.w << 2) | (sc << 8) | (zc << 10);
-    P.anchor = P.kp[0];
+    P.anchor = P.kfirst;
 }
 
 // Decode one plane of a chunk, four lanes per chunk: lane q produces values
@@ -674,12 +689,16 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
             k[j] = (int32_t)acc;
         }
         const uint32_t t0 = qperm<QB0>(acc), t1 = qperm<QB1>(acc), t2 = qperm<QB2>(acc);
-        uint32_t start = (uint32_t)anchor;
+        // LOG: the 2^(s-1) that log_decode_h expects rides on the start
+        uint32_t start = (uint32_t)anchor + (DOM == 1 ? 1u << (cp.s - 1) : 0u);
         if (q >= 1) start += t0;
         if (q >= 2) start += t1;
         if (q >= 3) start += t2;
 #pragma unroll
         for (int j = 0; j < 16; ++j) k[j] = (int32_t)(start + (uint32_t)k[j]);
+    } else if (DOM == 1) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) k[j] = (int32_t)((uint32_t)k[j] + (1u << (cp.s - 1)));
     }
     if (!act) return;
 #pragma unroll
@@ -690,7 +709,7 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
         } else {
             // the magnitude is positive: the sign bit comes from the sign
             // mask, and a flagged zero clears every bit (+0)
-            const uint32_t mag = __float_as_uint(log_decode(k[j], cp.s, cp.delta));
+            const uint32_t mag = __float_as_uint(log_decode_h(k[j], cp.s, cp.delta));
             const uint32_t sgn = negb << (31 - j);
             const uint32_t keep = ~(uint32_t)__builtin_amdgcn_sbfe((int)zb, j, 1);
             v = __uint_as_float(((sgn & 0x80000000u) | mag) & keep);
@@ -742,16 +761,23 @@ __device__ __forceinline__ void stage_quad_payload(const QuadPlane &P, const Sta
     // themselves, i.e. residuals against a predecessor of 0
     lds_u32 *const pl = S.p + pw;
     const uint32_t b0 = 16u * w * (uint32_t)q;
-    const uint32_t keep = (mode == M_LZ) ? ~0u : 0u;
-    uint32_t prev = (uint32_t)P.carry & keep;
+    uint32_t fld[16];
+    if (mode == M_Q0) {
+        // Q0 fields are the codes themselves: rebuilt from the residuals
+        uint32_t k = (uint32_t)P.kfirst;
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            if (j) k += (uint32_t)unzigzag((uint32_t)P.kp[j]);
+            fld[j] = zigzag((int32_t)k);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) fld[j] = (uint32_t)P.kp[j];
+    }
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const uint32_t kp = (uint32_t)P.kp[j];
-        const int32_t d = (j == 0 && q == 0) ? (int32_t)(kp & ~keep) : (int32_t)(kp - prev);
-        prev = kp & keep;
-        const uint32_t fld = zigzag(d);
         const uint32_t b = b0 + (uint32_t)j * w;
-        const uint64_t t = (uint64_t)fld << (b & 31u);
+        const uint64_t t = (uint64_t)fld[j] << (b & 31u);
         lds_u32 *const wp = pl + (b >> 5);
         __hip_atomic_fetch_or(wp, (uint32_t)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         __hip_atomic_fetch_or(wp + 1, (uint32_t)(t >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
