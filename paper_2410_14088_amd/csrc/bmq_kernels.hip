@@ -472,7 +472,6 @@ struct QuadPlane {
     int32_t anchor;     // LZ anchor (lane 0)
     uint32_t nzb, negb; // this lane's 16 non-zero / negative bits
     uint32_t w;         // field width
-    int32_t carry;      // code preceding this lane's first value
     int32_t kfirst;     // this lane's first code after the zero substitution
     int32_t kp[16];     // after encode_quad: the zigzagged Lorenzo residuals of this lane's codes
                         // (after the zero substitution; residual 0 for the chunk's first value),
@@ -497,23 +496,37 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
         P.negb = 0;
         P.anchor = 0;
         P.w = 0;
-        P.carry = 0;
         P.kfirst = 0;
         verbatim_quad(x, P);
         return;
     }
     uint32_t nzb = 0xFFFFu, negb = 0, bad = 0, anynz = 0;
+    // LOG codes are kept with a constant offset kbias (mod 2^32, below): the
+    // Lorenzo residuals do not see it, and the few steps that need a code
+    // itself (the chunk's first code, the extremes for Q0) remove it once
+    uint32_t kbias = 0;
     if (log_dom) {
-        uint32_t efmax = 0;
+        // rint(x 2^s) for |x 2^s| < 2^22 by one rounding addition: x + 1.5
+        // 2^(23-s) falls in [2^(23-s), 2^(24-s)), where floats are 2^-s
+        // apart, so the sum is x rounded to a multiple of 2^-s (ties to
+        // even, as 1.5 2^23 is even) and its bits are ((150 - s) << 23) +
+        // 2^22 + rint(x 2^s).  The integer work is uniform (scalar).
+        const uint32_t mbits = ((uint32_t)(150 - cp.s) << 23) | 0x00400000u;
+        const float magic = __uint_as_float(mbits);
+        kbias = (127u << cp.s) + mbits;
+        uint32_t amax = 0;
         nzb = 0;
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
+        for (int j = 15; j >= 0; --j) {
             const uint32_t u = __float_as_uint(x[j]);
             const uint32_t a = u & 0x7FFFFFFFu;
-            const uint32_t ef = a >> 23;
-            efmax = max(efmax, ef);
-            nzb |= min(ef, 1u) << j;                   // zero or subnormal: bit clear
-            negb |= (u >> 31) << j;
+            amax = max(amax, a);
+            // bits j of the masks, shifted in from the top value down:
+            // alignbit(m, v, 31) = (m << 1) | (v >> 31); a + 0x7F800000
+            // has its top bit set exactly when the exponent field is not
+            // zero (zero and subnormals: bit clear)
+            nzb = __builtin_amdgcn_alignbit(nzb, a + 0x7F800000u, 31);
+            negb = __builtin_amdgcn_alignbit(negb, u, 31);
             // log2|x| = e + p, the significand folded into [sqrt(1/2),
             // sqrt(2)], t = m - 1 exactly and p = t P(t) with P the degree-8
             // Chebyshev fit of log2(1+t)/t (Horner, fused multiply-adds,
@@ -521,7 +534,6 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
             // the exponent exactly when the significand exceeds 0x3504F3, so
             // one integer add folds the significand into [sqrt(1/2), sqrt(2)]
             const uint32_t ix = a + 0x004AFB0Cu;
-            const int32_t e = (int32_t)(ix >> 23) - 127;
             const float t = __uint_as_float((ix & 0x007FFFFFu) + 0x3F3504F4u) - 1.0f;
             float pp = 0.12614846229553223f;
             pp = __builtin_fmaf(pp, t, -0.20742103457450867f);
@@ -532,11 +544,13 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
             pp = __builtin_fmaf(pp, t, 0.48091059923171997f);
             pp = __builtin_fmaf(pp, t, -0.7213473320007324f);
             pp = __builtin_fmaf(pp, t, 1.4426950216293335f);
-            const int32_t jj = (int32_t)__builtin_rintf((t * pp) * cp.scale);
-            P.kp[j] = (int32_t)((uint32_t)e << cp.s) + jj;   // zeros are substituted below
+            // |t P| <= 1/2, so |t P 2^s| <= 2^21 for s <= 22
+            const uint32_t jb = __float_as_uint((t * pp) + magic);
+            // code (e << s) + rint(t P 2^s) with e = (ix >> 23) - 127, plus kbias
+            P.kp[j] = (int32_t)(((ix >> 23) << cp.s) + jb);   // zeros are substituted below
         }
         negb &= nzb;                                   // zeros count as non-negative
-        bad = efmax >= 254u || !cp.code_ok;
+        bad = amax >= 0x7F000000u || !cp.code_ok;      // exponent field 254 or 255
     } else {
 #pragma unroll
         for (int j = 0; j < 16; ++j) {
@@ -570,7 +584,6 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     P.negb = negb;
     P.anchor = 0;
     P.w = 0;
-    P.carry = 0;
     P.kfirst = 0;
     if (f & 1u) { verbatim_quad(x, P); return; }
     const bool allzero = log_dom ? !(f & 4u) : !(f & 2u);
@@ -588,14 +601,17 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     if (q >= 1 && h0) carry = l0;
     if (q >= 2 && h1) carry = l1;
     if (q >= 3 && h2) carry = l2;
-    P.carry = carry;
     // zigzag(v) grows with |v| on each side of zero, so the widest field of a
     // mode is the zigzag of the smallest or of the largest value
     // from here on the lane keeps its Lorenzo residuals, zigzagged (the LZ
     // fields), in place of its codes; its first code (after the zero
     // substitution) rebuilds the codes if the chunk takes Q0.  The widest
     // field of a mode has the highest bit of the OR of its fields.
-    int32_t kmin = INT32_MAX, kmax = INT32_MIN;
+    // LOG codes carry kbias and lie in [0, 2^32) as unsigned values in the
+    // order of the codes (the offset moves them away from both ends), LIN
+    // codes are plain signed values: the extremes are taken in the matching
+    // order and the offset removed from them once
+    uint32_t kmin = log_dom ? 0xFFFFFFFFu : (uint32_t)INT32_MAX, kmax = log_dom ? 0u : (uint32_t)INT32_MIN;
     uint32_t orl = 0;
     int32_t prev = carry;
     if (nzb != 0xFFFFu) {
@@ -606,8 +622,13 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
             const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
             P.kp[j] = (int32_t)zigzag(d);
             orl |= (uint32_t)P.kp[j];
-            kmin = min(kmin, kp);
-            kmax = max(kmax, kp);
+            if (log_dom) {
+                kmin = min(kmin, (uint32_t)kp);
+                kmax = max(kmax, (uint32_t)kp);
+            } else {
+                kmin = (uint32_t)min((int32_t)kmin, kp);
+                kmax = (uint32_t)max((int32_t)kmax, kp);
+            }
             prev = kp;
         }
     } else {
@@ -618,12 +639,18 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
             const int32_t d = (j == 0 && q == 0) ? 0 : (int32_t)((uint32_t)kp - (uint32_t)prev);
             P.kp[j] = (int32_t)zigzag(d);
             orl |= (uint32_t)P.kp[j];
-            kmin = min(kmin, kp);
-            kmax = max(kmax, kp);
+            if (log_dom) {
+                kmin = min(kmin, (uint32_t)kp);
+                kmax = max(kmax, (uint32_t)kp);
+            } else {
+                kmin = (uint32_t)min((int32_t)kmin, kp);
+                kmax = (uint32_t)max((int32_t)kmax, kp);
+            }
             prev = kp;
         }
     }
-    const uint32_t orq = zigzag(kmin) | zigzag(kmax);
+    P.kfirst = (int32_t)((uint32_t)P.kfirst - kbias);
+    const uint32_t orq = zigzag((int32_t)(kmin - kbias)) | zigzag((int32_t)(kmax - kbias));
     const uint32_t wl = bitlen(quad_or(orl)), wq = bitlen(quad_or(orq));
     uint32_t sc = 0, zc = 0;
     if (log_dom) {
@@ -701,20 +728,28 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
         for (int j = 0; j < 16; ++j) k[j] = (int32_t)((uint32_t)k[j] + (1u << (cp.s - 1)));
     }
     if (!act) return;
+    if (DOM != 1) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) dst[j] = (float)k[j] * cp.delta;
+        return;
+    }
+    // the magnitude is positive: the sign bit comes from the sign mask, and
+    // a flagged zero clears every bit (+0).  Waves whose planes flag no zero
+    // (a wave-uniform test) skip the zero step.
+    if (__builtin_amdgcn_ballot_w64(zb != 0u) == 0u) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const uint32_t mag = __float_as_uint(log_decode_h(k[j], cp.s, cp.delta));
+            dst[j] = __uint_as_float(((negb << (31 - j)) & 0x80000000u) | mag);
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        float v;
-        if (DOM != 1) {
-            v = (float)k[j] * cp.delta;
-        } else {
-            // the magnitude is positive: the sign bit comes from the sign
-            // mask, and a flagged zero clears every bit (+0)
-            const uint32_t mag = __float_as_uint(log_decode_h(k[j], cp.s, cp.delta));
-            const uint32_t sgn = negb << (31 - j);
-            const uint32_t keep = ~(uint32_t)__builtin_amdgcn_sbfe((int)zb, j, 1);
-            v = __uint_as_float(((sgn & 0x80000000u) | mag) & keep);
-        }
-        dst[j] = v;
+        const uint32_t mag = __float_as_uint(log_decode_h(k[j], cp.s, cp.delta));
+        const uint32_t sgn = negb << (31 - j);
+        const uint32_t keep = ~(uint32_t)__builtin_amdgcn_sbfe((int)zb, j, 1);
+        dst[j] = __uint_as_float(((sgn & 0x80000000u) | mag) & keep);
     }
 }
 
