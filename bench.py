@@ -33,7 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9     # CUs x SIMDs x lanes x clock: one wave64 VALU op per SIMD per 4 cycles
+VALU_PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9     # CUs x SIMDs x 32-bit lanes per clock x clock: FP32 vector 157.3 TFLOP/s / 2
 METRIC = "compressed-SV amplitude·gates/s, GB/s vs HBM peak at fidelity≥0.99; compression ratio"
 
 
@@ -162,7 +162,7 @@ def counter_traffic(n, tile, fuse, flags=0, workload="random"):
 
 def valu_profile(n, tile, fuse, flags=0, workload="random"):
     """Issued VALU lane-operations per second of the pass kernel and their
-    fraction of the plain-VALU ceiling (SQ-counter profile)."""
+    fraction of the 32-bit VALU ceiling (SQ-counter profile)."""
     ops = _profile_field(workload, "sq_counters", n, tile, fuse, flags, "valu_lane_ops_per_s")
     if ops is None:
         return None
