@@ -544,7 +544,9 @@ int sv_debug_dump(sv_t *sv, uint64_t start, uint64_t count, float *pre_re, float
  * (arguments; or the stream is larger than cap: *bytes is still set and
  * nothing is written).  Synchronises.
  * codec_decode -- the inverse: n_values of each plane from a stream of
- * `bytes` bytes (device, 4-byte aligned).  A one-lane walk over the record
+ * `bytes` bytes (device, 4-byte aligned; the decoder reads packed fields as
+ * 8-byte words, so up to 4 bytes past the stream's end must be readable:
+ * allocate at least bytes + 4).  A one-lane walk over the record
  * headers finds the records, then they are decoded in parallel.  Errors:
  * SV_ERR_CORRUPT (header does not match cfg / n_values, a malformed plane
  * header, a record outside the stream or bytes left over).  Synchronises
