@@ -80,7 +80,8 @@ def test_graph_speed_small_circuit():
     _, plan, sv = _setup(d["gates"], n, b, fuse=2)
     g = sv.capture(plan)
     import time
-    for mode in ("eager", "graph", "eager", "graph"):
+    best = {}
+    for mode in ("eager", "graph") * 3:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(5):
@@ -92,7 +93,12 @@ def test_graph_speed_small_circuit():
                 sv.apply(plan)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / 5
+        best[mode] = min(best.get(mode, dt), dt)
         print(f"{mode}: {dt * 1e3:.2f} ms per run of {plan.n_stages} stages", flush=True)
+    # replaying the captured launches must not lose to issuing them one by one
+    # (measured 1.95 against 2.10 ms; best of three rounds each, 10 % for
+    # timing noise)
+    assert best["graph"] <= 1.10 * best["eager"], best
 
 
 def test_autotune_picks_a_measured_candidate():
