@@ -55,6 +55,12 @@ def parse():
     ap.add_argument("--pool-frac", type=float, default=0.25,
                     help="qaoa-spill: device pool capacity per state copy, as a fraction of the "
                          "uncompressed complex64 size")
+    ap.add_argument("--device-pool-gb", type=float, default=0.0,
+                    help="qaoa-spill: device pool capacity per state copy in GB (instead of --pool-frac); "
+                         "with it the device-only run is skipped (for states whose records exceed the HBM)")
+    ap.add_argument("--host-pool-gb", type=float, default=0.0,
+                    help="qaoa-spill: pinned host pool in GB, both state copies together (default: twice "
+                         "the uncompressed complex64 size)")
     ap.add_argument("--batch-count", type=int, default=512)
     ap.add_argument("--n", type=int, default=0, help="qubits (default: 33 for random, 30 for qft)")
     ap.add_argument("--flags", type=int, default=None,
@@ -532,23 +538,47 @@ def bench_qaoa_spill(args):
     rng = np.random.default_rng(7)
     idx = rng.integers(0, 1 << n, 512).astype(np.uint64)
     want = qaoa_ring_closed_form(n, gammas, betas, idx)
-    for mode in ("device", "spill"):
-        pool = int(args.pool_frac * (8 << n)) & ~255 if mode == "spill" else 0
+    large = args.device_pool_gb > 0
+    # scratch-free at the default size; group-sized scratch planes when the
+    # device pools are given explicitly (the state is then beyond the HBM)
+    flags = bmq.SV_FLAG_GROUP_SCRATCH if large else bmq.SV_FLAG_NO_SCRATCH
+    for mode in (("spill",) if large else ("device", "spill")):
+        if mode == "device":
+            pool = 0
+        elif large:
+            pool = int(args.device_pool_gb * 1e9) & ~255
+        else:
+            pool = int(args.pool_frac * (8 << n)) & ~255
         cfg = bmq.Config(n=n, b=n - 8, inner=2, fuse=args.fuse or 4, domain=1, eb=1e-5, pool_bytes=pool,
-                         flags=bmq.SV_FLAG_NO_SCRATCH)
+                         flags=flags)
         plan = bmq.Plan(gates, cfg)
+        progress(f"qaoa {n} qubits, {mode}: {len(gates)} gates, {plan.n_stages} stages, device pool "
+                 f"{pool / 1e9:.1f} GB per copy")
         sv = bmq.State(cfg, "cuda:0")
         if mode == "spill":
-            sv.attach_host_pool(2 * (8 << n))
+            hb = int(args.host_pool_gb * 1e9) & ~255 if args.host_pool_gb > 0 else 2 * (8 << n)
+            sv.attach_host_pool(hb, exact=large)
+            progress(f"host pool {hb / 1e9:.1f} GB attached")
         for _ in range(args.warmup):
             sv.reset()
             sv.apply(plan)
         torch.cuda.synchronize()
         sv.reset()
         t0 = time.perf_counter()
-        st = sv.apply(plan, stats=True)
+        if large:
+            # stage by stage, with a progress line each (a stage moves a
+            # large share of the records over the host link)
+            st = []
+            for s in range(plan.n_stages):
+                st += sv.apply(plan, first=s, count=1, stats=True)
+                progress(f"stage {s + 1}/{plan.n_stages}: records {st[-1]['bytes_out'] / 1e9:.1f} GB, "
+                         f"{st[-1]['bytes_out_host'] / 1e9:.1f} GB of them on the host, "
+                         f"{time.perf_counter() - t0:.1f} s")
+        else:
+            st = sv.apply(plan, stats=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        progress(f"{mode}: {dt:.1f} s")
         got = sv.amplitudes(torch.from_numpy(idx.astype(np.int64))).cpu().numpy().astype(np.complex128)
         f2 = abs(np.vdot(want, got)) ** 2 / (np.vdot(want, want).real * np.vdot(got, got).real)
         rec, host, _ = sv.footprint()
@@ -565,8 +595,9 @@ def bench_qaoa_spill(args):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"qaoa-ring-{n}q-p3-host-spill", "n_qubits": n, "gates": len(gates),
                    "block_qubits": n - 8, "domain": "log", "eb": 1e-5, "fuse_qubits": args.fuse or 4,
-                   "flags": bmq.SV_FLAG_NO_SCRATCH, "device_pool_frac": args.pool_frac},
-        "spill": res["spill"], "device_only": res["device"],
+                   "flags": flags, "device_pool_frac": None if large else args.pool_frac,
+                   "device_pool_bytes": res["spill"]["device_pool_bytes"]},
+        "spill": res["spill"], "device_only": res.get("device"),
         "compression_ratio_vs_complex64": (8 << n) / res["spill"]["record_bytes"],
     }
     print(json.dumps(out))

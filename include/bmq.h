@@ -263,6 +263,17 @@ void sv_destroy(sv_t *sv);
  * state still has records in the attached host pool). */
 int sv_attach_host_pool(sv_t *sv, void *host_pinned, uint64_t host_bytes);
 
+/* sv_host_alloc -- page-locked, device-addressable host memory of exactly
+ * `bytes` (hipHostMalloc), for sv_attach_host_pool and the pipeline's host
+ * store: a host pool sized to a memory budget must not be rounded up (a
+ * caching pinned allocator that rounds to a power of two nearly doubles a
+ * 150 GB request).  *ptr receives the host address; the caller frees it
+ * with sv_host_free once no state uses it.  Errors: SV_ERR_INVALID (bytes
+ * is 0 or ptr NULL), SV_ERR_HIP (the allocation failed; *ptr is NULL).
+ * sv_host_free(NULL) does nothing. */
+int sv_host_alloc(uint64_t bytes, void **ptr);
+int sv_host_free(void *ptr);
+
 /* sv_reset -- set an existing state back to |0...0> (as sv_create does),
  * enqueued on its stream without synchronising. */
 int sv_reset(sv_t *sv);

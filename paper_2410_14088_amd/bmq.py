@@ -70,7 +70,7 @@ class sv_stage_stats_t(C.Structure):
 
 
 EXPORTS = ["sv_last_error", "stage_plan", "plan_info", "plan_stage", "plan_gate_order", "plan_stage_ops", "plan_op", "plan_destroy",
-           "sv_mem_required", "sv_create", "sv_destroy", "sv_attach_host_pool", "sv_reset", "stage_apply_compressed",
+           "sv_mem_required", "sv_create", "sv_destroy", "sv_attach_host_pool", "sv_host_alloc", "sv_host_free", "sv_reset", "stage_apply_compressed",
            "sv_fidelity", "sv_sample", "sv_export", "sv_amplitudes", "sv_footprint", "sv_check", "sv_directory",
            "sv_block_stream", "sv_debug_dump", "codec_workspace", "codec_encode", "codec_encode_noalloc", "codec_decode",
            "codec_encode_chunks", "codec_decode_chunks", "sv_block_features",
@@ -109,6 +109,8 @@ def lib():
         L.sv_destroy.restype = None
         L.sv_reset.argtypes = [V]
         L.sv_attach_host_pool.argtypes = [V, V, C.c_uint64]
+        L.sv_host_alloc.argtypes = [C.c_uint64, P(V)]
+        L.sv_host_free.argtypes = [V]
         L.stage_apply_compressed.argtypes = [V, V, C.c_size_t, C.c_size_t, V]
         L.sv_fidelity.argtypes = [V, V, V, V, P(sv_fidelity_t)]
         L.sv_sample.argtypes = [V, C.c_uint64, C.c_uint64, V]
@@ -205,6 +207,28 @@ def _ptr(t) -> int:
 def _stream():
     import torch
     return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class HostBuffer:
+    """Page-locked host memory of exactly nbytes (sv_host_alloc), freed by
+    close() or when the object goes away; the user keeps it alive while a
+    state or pipeline uses it."""
+
+    def __init__(self, nbytes: int):
+        p = C.c_void_p()
+        _check(lib().sv_host_alloc(int(nbytes), C.byref(p)))
+        self.ptr, self.nbytes = p.value, int(nbytes)
+
+    def data_ptr(self) -> int:
+        return self.ptr
+
+    def close(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.sv_host_free(C.c_void_p(self.ptr))
+            self.ptr = None
+
+    def __del__(self):
+        self.close()
 
 
 class Plan:
@@ -417,11 +441,13 @@ class State:
         _check(lib().sv_directory(self.h, C.byref(ptr), C.byref(n)))
         return ptr.value, n.value
 
-    def attach_host_pool(self, nbytes: int):
-        """Second memory level: a pinned host buffer of nbytes (0 detaches)."""
+    def attach_host_pool(self, nbytes: int, exact: bool = False):
+        """Second memory level: a pinned host buffer of nbytes (0 detaches);
+        a pinned torch tensor, or with exact an sv_host_alloc buffer of
+        exactly nbytes (torch's pinned allocator rounds up to a power of two)."""
         import torch
         if nbytes:
-            buf = torch.empty(int(nbytes), dtype=torch.uint8, pin_memory=True)
+            buf = HostBuffer(int(nbytes)) if exact else torch.empty(int(nbytes), dtype=torch.uint8, pin_memory=True)
             _check(lib().sv_attach_host_pool(self.h, C.c_void_p(buf.data_ptr()), int(nbytes)))
         else:
             buf = None
@@ -484,6 +510,9 @@ class State:
         if getattr(self, "h", None) and _lib is not None:
             _lib.sv_destroy(self.h)
             self.h = None
+        pool = getattr(self, "host_pool", None)
+        if isinstance(pool, HostBuffer):          # freed only once no state uses it
+            pool.close()
 
     def __del__(self):
         self.close()

@@ -1054,6 +1054,24 @@ int sv_attach_host_pool(sv_t *sv, void *host_pinned, uint64_t host_bytes)
     return SV_OK;
 }
 
+int sv_host_alloc(uint64_t bytes, void **ptr)
+{
+    if (!ptr) return fail(SV_ERR_INVALID, "ptr is NULL");
+    if (!bytes) return fail(SV_ERR_INVALID, "zero bytes");
+    *ptr = nullptr;
+    void *p = nullptr;
+    HIP_TRY(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+    *ptr = p;
+    return SV_OK;
+}
+
+int sv_host_free(void *ptr)
+{
+    if (!ptr) return SV_OK;
+    HIP_TRY(hipHostFree(ptr));
+    return SV_OK;
+}
+
 int sv_reset(sv_t *sv)
 {
     if (!sv) return fail(SV_ERR_INVALID, "state is NULL");

@@ -212,6 +212,12 @@ def test_plan_views_reject_bad_arguments(bmq):
     assert L.sv_check(None, C_.byref(nb)) == -1
     ptr, n = C_.c_void_p(), C_.c_uint64()
     assert L.sv_directory(None, C_.byref(ptr), C_.byref(n)) == -1
+    # exact pinned host allocations: bad arguments are refused before any
+    # HIP call and leave the output untouched; freeing NULL does nothing
+    p = C_.c_void_p(1)
+    assert L.sv_host_alloc(0, C_.byref(p)) == -1 and p.value == 1
+    assert L.sv_host_alloc(64, None) == -1
+    assert L.sv_host_free(None) == 0
 
 
 def test_admission_under_a_budget(bmq):

@@ -17,13 +17,13 @@ from paper_2410_14088_amd import circuits as C  # noqa: E402
 DEV = "cuda:0"
 
 
-def _run(gates, n, b, pool_bytes=0, host=0, flags=0, fuse=2, inner=2, tile=0, eb=1e-5):
+def _run(gates, n, b, pool_bytes=0, host=0, flags=0, fuse=2, inner=2, tile=0, eb=1e-5, exact=False):
     cfg = bmq.Config(n=n, b=b, inner=inner, fuse=fuse, domain=1, eb=eb, pool_bytes=pool_bytes, flags=flags,
                      tile=tile)
     plan = bmq.Plan(gates, cfg)
     sv = bmq.State(cfg, DEV)
     if host:
-        sv.attach_host_pool(host)
+        sv.attach_host_pool(host, exact=exact)
     stats = sv.apply(plan, stats=True)
     return sv, plan, stats
 
@@ -46,6 +46,23 @@ def test_host_spill_is_bit_exact():
     f = N.simulate(n, d["gates"])
     fr = torch.from_numpy(np.ascontiguousarray(f)).to(DEV)
     assert sv.fidelity(fr) == ref.fidelity(fr)
+
+
+def test_host_pool_of_exact_size_is_bit_exact():
+    # a host pool from sv_host_alloc, of a size that is no power of two
+    d = C.config(0)
+    n, b = d["n"], d["b"]
+    ref, _, st_ref = _run(d["gates"], n, b)
+    peak = max(s["bytes_out"] for s in st_ref)
+    host = 3 * peak + 4096 + 256
+    print(f"spill run: device pool {peak // 4} bytes, exact host pool {host} bytes", flush=True)
+    sv, _, st = _run(d["gates"], n, b, pool_bytes=peak // 4, host=host, exact=True)
+    assert isinstance(sv.host_pool, bmq.HostBuffer) and sv.host_pool.nbytes == host
+    assert max(s["bytes_out_host"] for s in st) > 0
+    for k in range(sv.n_blocks):
+        assert sv.block_stream(k) == ref.block_stream(k), k
+    sv.close()
+    assert sv.host_pool.ptr is None                # freed with the state
 
 
 def test_both_levels_full_reports_capacity():
