@@ -218,13 +218,15 @@ class HostBuffer:
         p = C.c_void_p()
         _check(lib().sv_host_alloc(int(nbytes), C.byref(p)))
         self.ptr, self.nbytes = p.value, int(nbytes)
+        # kept here: at interpreter exit the module's globals may already be gone
+        self._free, self._vp = lib().sv_host_free, C.c_void_p
 
     def data_ptr(self) -> int:
         return self.ptr
 
     def close(self):
-        if getattr(self, "ptr", None) and _lib is not None:
-            _lib.sv_host_free(C.c_void_p(self.ptr))
+        if getattr(self, "ptr", None):
+            self._free(self._vp(self.ptr))
             self.ptr = None
 
     def __del__(self):
@@ -511,7 +513,7 @@ class State:
             _lib.sv_destroy(self.h)
             self.h = None
         pool = getattr(self, "host_pool", None)
-        if isinstance(pool, HostBuffer):          # freed only once no state uses it
+        if pool is not None and hasattr(pool, "close"):   # a HostBuffer, freed once no state uses it
             pool.close()
 
     def __del__(self):
