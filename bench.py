@@ -136,7 +136,7 @@ def qft_ry_closed_form(n, theta, idx):
 # committed counter profiles of the pass kernel, per default workload:
 # (n, tile, fuse, flags) they were taken at and the file stem
 PROFILES = {"random": ((33, 12, 3, 32), "pass_kernel_random33"),
-            "qft": ((30, 12, 4, 0), "pass_kernel_qft30")}
+            "qft": ((30, 12, 4, 32), "pass_kernel_qft30")}
 
 
 def _profile_field(workload, key, n, tile, fuse, flags, field):
