@@ -39,10 +39,14 @@ struct OpDesc {
 // cursor and statistics, so that no single address takes every workgroup's
 // atomics.  A wave whose segment is full spills its bodies to the host pool
 // (second memory level) through one cursor, C_HOST_CURSOR of segment 0.
-// A launch's counter block is kSegments x C_NUM words; C_MODE0 packs the
-// ZERO | LZ counts, C_MODE0 + 2 the Q0 | VERBATIM counts (32 bits each).
+// A launch's counter block is kSegments x C_NUM words.  The statistics cost
+// a wave device-wide atomics only where the common case needs none: the
+// bytes a segment holds on the device are its cursor less C_SPILLED (bytes
+// of waves that found the segment full), C_MODE0 counts ZERO planes,
+// C_MODE0 + 2 packs the Q0 | VERBATIM counts (32 bits each), and the LZ
+// count is the rest of the pass's 2^(n-5) planes.
 enum Counter : int {
-    C_CURSOR = 0, C_OVERFLOW = 1, C_ZERO_CHUNKS = 2, C_MODE0 = 3, C_DEV_BYTES = 4, C_HOST_BYTES = 6,
+    C_CURSOR = 0, C_OVERFLOW = 1, C_ZERO_CHUNKS = 2, C_MODE0 = 3, C_SPILLED = 4, C_HOST_BYTES = 6,
     C_HOST_CURSOR = 7, C_NUM = 8
 };
 constexpr int kSegments = 256;

@@ -1074,16 +1074,19 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     uint64_t wave_off = (uint64_t)seg * a.seg_cap + b;       // directory offset of the wave's first body
     bool overflow = false;
     if (total && b + total > a.seg_cap) {
-        // segment full: the wave's bodies go to the host pool, or are lost
+        // segment full: the wave's bodies go to the host pool, or are lost;
+        // either way its share of the segment's cursor holds no bytes
         unsigned long long goth = 0;
         if (lane == 0 && a.host_cap) goth = atomicAdd(&a.counters[C_HOST_CURSOR], (unsigned long long)total);
         const uint64_t hb = uniform_u64(goth);
         overflow = !a.host_cap || hb + total > a.host_cap;
         wave_off = a.pool_cap + hb;
+        if (lane == 0) {
+            atomicAdd(&cnt[C_SPILLED], (unsigned long long)total);
+            if (!overflow) atomicAdd(&cnt[C_HOST_BYTES], (unsigned long long)total);
+        }
     }
     if (lane == 0 && overflow) atomicOr(&cnt[C_OVERFLOW], 1ull);
-    if (lane == 0 && total && !overflow)
-        atomicAdd(&cnt[wave_off < a.pool_cap ? C_DEV_BYTES : C_HOST_BYTES], (unsigned long long)total);
     const uint64_t off = wave_off + rel;
     if (!overflow && total) {
         // copy the staged stream out
@@ -1101,11 +1104,12 @@ __device__ __forceinline__ void pass_body(const A &a, uint32_t tile)
     const uint32_t hsum = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_add(hw), 63);
     const uint32_t zsum = (uint32_t)__builtin_amdgcn_readlane((int)wave_scan_add(zw), 63);
     // each wave adds its counts to its own segment's counters (no barrier:
-    // the waves of a tile finish independently)
+    // the waves of a tile finish independently); LZ planes are not counted
+    // (the runtime takes them as the rest), so a wave of LZ planes only, the
+    // common case, issues none of these atomics
     if (lane == 0) {
         if (zsum) atomicAdd(&cnt[C_ZERO_CHUNKS], (unsigned long long)zsum);
-        if (hsum & 0xFFFFu)
-            atomicAdd(&cnt[C_MODE0], (unsigned long long)(hsum & 0xFFu) | ((unsigned long long)((hsum >> 8) & 0xFFu) << 32));
+        if (hsum & 0xFFu) atomicAdd(&cnt[C_MODE0], (unsigned long long)(hsum & 0xFFu));
         if (hsum >> 16)
             atomicAdd(&cnt[C_MODE0 + 2], (unsigned long long)((hsum >> 16) & 0xFFu) | ((unsigned long long)(hsum >> 24) << 32));
     }

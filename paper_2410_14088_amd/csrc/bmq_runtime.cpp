@@ -1353,21 +1353,22 @@ int collect_stages(sv_t *sv, const sv_plan_t *p, size_t first, size_t batch,
         bool overflow = false;
         for (size_t pi = 0; pi < np; ++pi, ++li) {
             if (scratch && pi + 1 < np) continue;          // uncompressed intermediate pass
-            // per segment: cursor, overflow flag, zero chunks, device and host
-            // bytes, and the mode histogram packed two 32-bit counts per word
-            // (ZERO|LZ, Q0|VERBATIM)
+            // per segment: cursor, overflow flag, zero chunks, spilled and host
+            // bytes, the ZERO count and the Q0|VERBATIM counts packed two
+            // 32-bit counts per word; device bytes are the cursor less the
+            // spilled bytes, LZ planes the rest of the pass's 2 nch planes
             uint64_t dev = 0, host = 0, z = 0, m4[4] = {0, 0, 0, 0};
             for (int g = 0; g < bmq::kSegments; ++g) {
                 const unsigned long long *sg = &hc[li * kStageCounters + (size_t)g * bmq::C_NUM];
                 overflow |= sg[bmq::C_OVERFLOW] != 0;
-                dev += sg[bmq::C_DEV_BYTES];
+                dev += sg[bmq::C_CURSOR] - sg[bmq::C_SPILLED];
                 host += sg[bmq::C_HOST_BYTES];
                 z += sg[bmq::C_ZERO_CHUNKS];
-                m4[0] += sg[bmq::C_MODE0] & 0xFFFFFFFFull;
-                m4[1] += sg[bmq::C_MODE0] >> 32;
+                m4[0] += sg[bmq::C_MODE0];
                 m4[2] += sg[bmq::C_MODE0 + 2] & 0xFFFFFFFFull;
                 m4[3] += sg[bmq::C_MODE0 + 2] >> 32;
             }
+            m4[1] = 2 * nch - m4[0] - m4[2] - m4[3];
             if (pi + 1 < np) inter += 2 * (dev + host);
             out_dev = dev;
             out_host = host;
