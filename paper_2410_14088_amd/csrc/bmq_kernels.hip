@@ -702,9 +702,15 @@ __device__ __forceinline__ void decode_quad(uint32_t h, int32_t anchor, const ui
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         const uint32_t oj = o + (uint32_t)j * w;
-        uint64_t v;                                     // the two words holding the field, one load
-        __builtin_memcpy(&v, (const uint8_t *)pay + ((uint64_t)(oj >> 5) << 2), 8);
-        const uint32_t f = (uint32_t)(v >> (oj & 31u)) & fmask;
+        // word index through an opaque copy, so that the address is one
+        // shift and one scaled 64-bit add (left alone, the compiler turns
+        // (oj >> 5) * 4 into a shift and a mask before the add)
+        uint32_t wi = oj >> 5;
+        asm volatile("" : "+v"(wi));
+        uint32_t v[2];                                  // the two words holding the field, one load
+        __builtin_memcpy(v, pay + wi, 8);
+        // the pair shifted right by oj mod 32 (alignbit takes the low 5 bits)
+        const uint32_t f = __builtin_amdgcn_alignbit(v[1], v[0], oj) & fmask;
         k[j] = unzigzag(f);
     }
     if (mode == M_LZ) {
