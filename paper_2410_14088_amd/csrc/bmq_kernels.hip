@@ -819,7 +819,9 @@ __device__ __forceinline__ void stage_quad_payload(const QuadPlane &P, const Sta
     for (int j = 0; j < 16; ++j) {
         const uint32_t b = b0 + (uint32_t)j * w;
         const uint64_t t = (uint64_t)fld[j] << (b & 31u);
-        lds_u32 *const wp = pl + (b >> 5);
+        uint32_t wi = b >> 5;                           // opaque, as in the decoder: shift + scaled add
+        asm volatile("" : "+v"(wi));
+        lds_u32 *const wp = pl + wi;
         __hip_atomic_fetch_or(wp, (uint32_t)t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
         __hip_atomic_fetch_or(wp + 1, (uint32_t)(t >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
