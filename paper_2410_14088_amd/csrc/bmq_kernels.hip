@@ -447,6 +447,7 @@ __device__ __forceinline__ Layout layout_of(uint32_t h0, uint32_t h1)
 
 // DPP quad permutations: broadcast lane i of the quad, swap neighbours
 constexpr int QB0 = 0x00, QB1 = 0x55, QB2 = 0xAA, QB3 = 0xFF, QX1 = 0xB1, QX2 = 0x4E;
+constexpr int QPREV = 0x90;     // lane q takes lane q - 1 (lane 0 itself)
 
 template <int CTRL>
 __device__ __forceinline__ uint32_t qperm(uint32_t v)
@@ -589,18 +590,25 @@ __device__ __forceinline__ void encode_quad(const float *x, const CodecParams &c
     const bool allzero = log_dom ? !(f & 4u) : !(f & 2u);
     if (allzero) { P.hdr = M_ZERO; return; }
     // zeros take the code of the last non-zero value at or before them, else
-    // the chunk's first non-zero code: carry-in from the previous lanes
-    const uint32_t hs = seen ? 1u : 0u;
-    const uint32_t h0 = qperm<QB0>(hs), h1 = qperm<QB1>(hs), h2 = qperm<QB2>(hs);
-    const int32_t f0 = (int32_t)qperm<QB0>((uint32_t)first), f1 = (int32_t)qperm<QB1>((uint32_t)first);
-    const int32_t f2 = (int32_t)qperm<QB2>((uint32_t)first), f3 = (int32_t)qperm<QB3>((uint32_t)first);
-    const int32_t l0 = (int32_t)qperm<QB0>((uint32_t)last), l1 = (int32_t)qperm<QB1>((uint32_t)last);
-    const int32_t l2 = (int32_t)qperm<QB2>((uint32_t)last);
-    const int32_t cfirst = h0 ? f0 : (h1 ? f1 : (h2 ? f2 : f3));
-    int32_t carry = cfirst;
-    if (q >= 1 && h0) carry = l0;
-    if (q >= 2 && h1) carry = l1;
-    if (q >= 3 && h2) carry = l2;
+    // the chunk's first non-zero code: carry-in from the previous lanes.
+    // Waves whose planes hold no zero (a wave-uniform test) take the
+    // previous lane's last code directly (lane 0's carry is never used).
+    int32_t carry;
+    if (__builtin_amdgcn_ballot_w64(nzb != 0xFFFFu) == 0u) {
+        carry = (int32_t)qperm<QPREV>((uint32_t)last);
+    } else {
+        const uint32_t hs = seen ? 1u : 0u;
+        const uint32_t h0 = qperm<QB0>(hs), h1 = qperm<QB1>(hs), h2 = qperm<QB2>(hs);
+        const int32_t f0 = (int32_t)qperm<QB0>((uint32_t)first), f1 = (int32_t)qperm<QB1>((uint32_t)first);
+        const int32_t f2 = (int32_t)qperm<QB2>((uint32_t)first), f3 = (int32_t)qperm<QB3>((uint32_t)first);
+        const int32_t l0 = (int32_t)qperm<QB0>((uint32_t)last), l1 = (int32_t)qperm<QB1>((uint32_t)last);
+        const int32_t l2 = (int32_t)qperm<QB2>((uint32_t)last);
+        const int32_t cfirst = h0 ? f0 : (h1 ? f1 : (h2 ? f2 : f3));
+        carry = cfirst;
+        if (q >= 1 && h0) carry = l0;
+        if (q >= 2 && h1) carry = l1;
+        if (q >= 3 && h2) carry = l2;
+    }
     // zigzag(v) grows with |v| on each side of zero, so the widest field of a
     // mode is the zigzag of the smallest or of the largest value
     // from here on the lane keeps its Lorenzo residuals, zigzagged (the LZ
