@@ -328,3 +328,35 @@ def test_stream_matches_independent_parser_and_codes(domain):
                     assert p["zmask"] == zmask
                 else:
                     assert zmask == 0
+
+
+def _float_literals(text):
+    import re
+    return [float(v) for v in re.findall(r"(-?\d+\.\d+(?:e-?\d+)?)f\b", text)]
+
+
+def test_polynomial_coefficients_are_the_documented_fit():
+    """The oracle's and the device code's log2/exp2 coefficients are the
+    float32-rounded least-squares Chebyshev fits that
+    tests/golden/fit_codec_polys.py derives (same values on both sides)."""
+    import importlib.util
+    here = os.path.dirname(os.path.abspath(__file__))
+    spec = importlib.util.spec_from_file_location("fit_codec_polys", os.path.join(here, "golden", "fit_codec_polys.py"))
+    fitmod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(fitmod)
+    logc, expc = fitmod.log2_coefficients(), fitmod.exp2_coefficients()
+    assert len(logc) == 9 and len(expc) == 7
+    root = os.path.dirname(here)
+    oracle = open(os.path.join(root, "oracle", "codec_ref.c")).read()
+    c_log = _float_literals(oracle[oracle.index("static const float C[9]"):])[:9]
+    c_exp = _float_literals(oracle[oracle.index("static const float E[7]"):])[:7]
+    assert c_log == logc and c_exp == expc
+    # the device code evaluates the same polynomials by Horner's rule,
+    # highest coefficient first
+    dev = open(os.path.join(root, "paper_2410_14088_amd", "csrc", "bmq_kernels.hip")).read()
+    enc = dev[dev.index("float pp = "):]
+    d_log = _float_literals(enc[:enc.index("const uint32_t jb")])
+    dec = dev[dev.index("float log_decode_h"):]
+    d_exp = _float_literals(dec[dec.index("float p = "):dec.index("__builtin_amdgcn_ldexpf")])
+    assert d_log == logc[::-1]
+    assert d_exp[0] == expc[6] and d_exp[1:] == expc[5::-1] and len(d_exp) == 7
